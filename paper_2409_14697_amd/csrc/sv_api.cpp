@@ -1,0 +1,382 @@
+// C ABI of the state-vector core (declared in include/sv.h).
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "sv_host.h"
+
+namespace sv {
+
+static thread_local std::string g_error;
+
+sv_status fail(sv_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return st;
+}
+
+void clear_error() { g_error.clear(); }
+
+size_t elem_bytes(sv_dtype dt) { return dt == SV_C128 ? 16 : 8; }
+
+sv_status ensure_scratch(sv_state* s, size_t bytes) {
+  if (bytes <= s->scratch_bytes) return SV_OK;
+  if (s->scratch) {
+    SV_HIP_TRY(hipStreamSynchronize(s->stream));  // in-flight work may still read it
+    SV_HIP_TRY(hipFree(s->scratch));
+    s->scratch = nullptr;
+    s->scratch_bytes = 0;
+  }
+  if (hipMalloc(&s->scratch, bytes) != hipSuccess) {
+    s->scratch = nullptr;
+    return fail(SV_ERR_NOMEM, "cannot allocate %zu bytes of device scratch", bytes);
+  }
+  s->scratch_bytes = bytes;
+  return SV_OK;
+}
+
+sv_status upload(sv_state* s, const void* host, size_t bytes, void** dev) {
+  if (s->up_pending) {
+    // the staging buffer is rewritten below: wait until the last copy read it
+    SV_HIP_TRY(hipEventSynchronize(s->up_done));
+    s->up_pending = false;
+  }
+  if (bytes > s->up_bytes) {
+    if (s->up_dev) {
+      SV_HIP_TRY(hipStreamSynchronize(s->stream));
+      SV_HIP_TRY(hipFree(s->up_dev));
+      SV_HIP_TRY(hipHostFree(s->up_host));
+      s->up_dev = s->up_host = nullptr;
+      s->up_bytes = 0;
+    }
+    size_t cap = 1 << 16;
+    while (cap < bytes) cap <<= 1;
+    if (hipMalloc(&s->up_dev, cap) != hipSuccess) return fail(SV_ERR_NOMEM, "cannot allocate upload buffer");
+    if (hipHostMalloc(&s->up_host, cap, hipHostMallocDefault) != hipSuccess) {
+      (void)hipFree(s->up_dev);
+      s->up_dev = nullptr;
+      return fail(SV_ERR_NOMEM, "cannot allocate pinned staging buffer");
+    }
+    s->up_bytes = cap;
+  }
+  std::memcpy(s->up_host, host, bytes);
+  SV_HIP_TRY(hipMemcpyAsync(s->up_dev, s->up_host, bytes, hipMemcpyHostToDevice, s->stream));
+  SV_HIP_TRY(hipEventRecord(s->up_done, s->stream));
+  s->up_pending = true;
+  *dev = s->up_dev;
+  return SV_OK;
+}
+
+sv_status run_op_sweep(sv_state* s, const Op& op, const void* m_dev) {
+  if (op.nq <= 2) {
+    SweepArgs a;
+    sweep_args_for(op, &a);
+    SV_HIP_TRY(launch_sweep(s->dt, s->ptr, s->n, a, s->stream));
+    return SV_OK;
+  }
+  if (op.nq > s->n) return fail(SV_ERR_QUBIT, "op on %d qubits exceeds the state's %d", op.nq, s->n);
+  SV_HIP_TRY(launch_dense_kq(s->dt, s->ptr, s->n, op.nq, op.q, m_dev, s->stream));
+  return SV_OK;
+}
+
+static sv_status check_state(const sv_state* s) {
+  if (!s) return fail(SV_ERR_ARG, "null state");
+  return SV_OK;
+}
+
+static sv_status validate_opts(const sv_opts& o) {
+  if (o.max_fuse_qubits < 0 || o.max_fuse_qubits > SV_MAX_GATE_QUBITS)
+    return fail(SV_ERR_ARG, "max_fuse_qubits %d outside 0..%d", o.max_fuse_qubits, SV_MAX_GATE_QUBITS);
+  if (o.lds_qubits < 0 || o.lds_qubits > 16) return fail(SV_ERR_ARG, "lds_qubits %d outside 0..16", o.lds_qubits);
+  if (o.pinned_low_bits < 0 || o.pinned_low_bits > 8)
+    return fail(SV_ERR_ARG, "pinned_low_bits %d outside 0..8", o.pinned_low_bits);
+  if (o.renorm_interval < 0) return fail(SV_ERR_ARG, "negative renorm_interval");
+  if (o.mode < SV_MODE_AUTO || o.mode > SV_MODE_PASS) return fail(SV_ERR_ARG, "bad mode %d", o.mode);
+  return SV_OK;
+}
+
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+sv_status sv_default_opts(sv_opts* o) {
+  if (!o) return fail(SV_ERR_ARG, "null opts");
+  o->max_fuse_qubits = 5;
+  o->lds_qubits = 0;
+  o->pinned_low_bits = 0;
+  o->reorder = 1;
+  o->fp32_mfma = 1;
+  o->renorm_interval = 0;
+  o->mode = SV_MODE_AUTO;
+  return SV_OK;
+}
+
+sv_status sv_create(int n, sv_dtype dt, void* dev_ptr, void* stream, unsigned flags, sv_state** out) {
+  clear_error();
+  if (!out) return fail(SV_ERR_ARG, "null output handle");
+  *out = nullptr;
+  if (n < 1 || n > SV_MAX_QUBITS) return fail(SV_ERR_ARG, "n_qubits %d outside 1..%d", n, SV_MAX_QUBITS);
+  if (dt != SV_C64 && dt != SV_C128) return fail(SV_ERR_ARG, "bad dtype %d", (int)dt);
+  if (flags & ~SV_NO_INIT) return fail(SV_ERR_ARG, "unknown flags 0x%x", flags);
+  if (dev_ptr && ((uintptr_t)dev_ptr & 255u)) return fail(SV_ERR_ARG, "device buffer not 256-byte aligned");
+  sv_state* s = new (std::nothrow) sv_state();
+  if (!s) return fail(SV_ERR_NOMEM, "host allocation failed");
+  s->n = n;
+  s->dt = dt;
+  s->stream = (hipStream_t)stream;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(SV_ERR_DEVICE, "no HIP device");
+  }
+  if (hipEventCreateWithFlags(&s->up_done, hipEventDisableTiming) != hipSuccess) {
+    delete s;
+    return fail(SV_ERR_DEVICE, "hipEventCreate failed");
+  }
+  const size_t bytes = ((size_t)1 << n) * elem_bytes(dt);
+  if (dev_ptr) {
+    s->ptr = dev_ptr;
+  } else {
+    if (hipMalloc(&s->ptr, bytes) != hipSuccess) {
+      (void)hipEventDestroy(s->up_done);
+      delete s;
+      return fail(SV_ERR_NOMEM, "cannot allocate %zu bytes for the state", bytes);
+    }
+    s->owned = true;
+  }
+  if (!(flags & SV_NO_INIT)) {
+    hipError_t e = launch_init_basis(dt, s->ptr, n, 0, s->stream);
+    if (e != hipSuccess) {
+      sv_destroy(s);
+      return fail(SV_ERR_DEVICE, "init: %s", hipGetErrorString(e));
+    }
+  }
+  *out = s;
+  return SV_OK;
+}
+
+sv_status sv_destroy(sv_state* s) {
+  clear_error();
+  if (!s) return SV_OK;
+  sv_status st = SV_OK;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) st = fail(SV_ERR_DEVICE, "stream sync failed in destroy");
+  if (s->owned && s->ptr) (void)hipFree(s->ptr);
+  if (s->scratch) (void)hipFree(s->scratch);
+  if (s->up_dev) (void)hipFree(s->up_dev);
+  if (s->up_host) (void)hipHostFree(s->up_host);
+  if (s->up_done) (void)hipEventDestroy(s->up_done);
+  delete s;
+  return st;
+}
+
+sv_status sv_state_info(const sv_state* s, int* n, sv_dtype* dt, void** ptr) {
+  clear_error();
+  if (sv_status st = check_state(s)) return st;
+  if (n) *n = s->n;
+  if (dt) *dt = s->dt;
+  if (ptr) *ptr = s->ptr;
+  return SV_OK;
+}
+
+sv_status sv_set_stream(sv_state* s, void* stream) {
+  clear_error();
+  if (sv_status st = check_state(s)) return st;
+  s->stream = (hipStream_t)stream;
+  return SV_OK;
+}
+
+sv_status sv_init_basis(sv_state* s, uint64_t index) {
+  clear_error();
+  if (sv_status st = check_state(s)) return st;
+  if (index >= (1ull << s->n)) return fail(SV_ERR_ARG, "basis index out of range");
+  SV_HIP_TRY(launch_init_basis(s->dt, s->ptr, s->n, index, s->stream));
+  return SV_OK;
+}
+
+sv_status sv_apply_gate(sv_state* s, const sv_gate* g) {
+  clear_error();
+  if (sv_status st = check_state(s)) return st;
+  if (!g) return fail(SV_ERR_ARG, "null gate");
+  if (sv_status st = validate_gate(*g, s->n)) return st;
+  Op op = op_from_gate(*g);
+  if (op.nq <= 2) return run_op_sweep(s, op, nullptr);
+  const bool f32 = s->dt == SV_C64;
+  std::vector<unsigned char> host(op.m.size() * 2 * (f32 ? 4 : 8));
+  for (size_t e = 0; e < op.m.size(); ++e) {
+    if (f32) {
+      ((float*)host.data())[2 * e] = (float)op.m[e].real();
+      ((float*)host.data())[2 * e + 1] = (float)op.m[e].imag();
+    } else {
+      ((double*)host.data())[2 * e] = op.m[e].real();
+      ((double*)host.data())[2 * e + 1] = op.m[e].imag();
+    }
+  }
+  void* dev = nullptr;
+  if (sv_status st = upload(s, host.data(), host.size(), &dev)) return st;
+  return run_op_sweep(s, op, dev);
+}
+
+sv_status sv_fuse(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const sv_opts* o, sv_plan** out) {
+  clear_error();
+  if (!out) return fail(SV_ERR_ARG, "null output plan");
+  *out = nullptr;
+  if (n < 1 || n > SV_MAX_QUBITS) return fail(SV_ERR_ARG, "n_qubits %d outside 1..%d", n, SV_MAX_QUBITS);
+  if (dt != SV_C64 && dt != SV_C128) return fail(SV_ERR_ARG, "bad dtype %d", (int)dt);
+  if (n_gates && !g) return fail(SV_ERR_ARG, "null gate list");
+  sv_opts opts;
+  if (o) opts = *o;
+  else sv_default_opts(&opts);
+  if (sv_status st = validate_opts(opts)) return st;
+  for (size_t i = 0; i < n_gates; ++i) {
+    if (sv_status st = validate_gate(g[i], n)) {
+      std::string msg = sv_last_error();
+      return fail(st, "gate %zu: %s", i, msg.c_str());
+    }
+  }
+  sv_plan* p = new (std::nothrow) sv_plan();
+  if (!p) return fail(SV_ERR_NOMEM, "host allocation failed");
+  sv_status st = build_plan(n, dt, g, n_gates, opts, p);
+  if (st != SV_OK) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return SV_OK;
+}
+
+sv_status sv_plan_info(const sv_plan* p, size_t* n_ops, size_t* n_passes) {
+  clear_error();
+  if (!p) return fail(SV_ERR_ARG, "null plan");
+  if (n_ops) *n_ops = p->ops.size();
+  if (n_passes) *n_passes = p->passes.size();
+  return SV_OK;
+}
+
+sv_status sv_plan_export(const sv_plan* p, size_t op, int32_t* nq, int32_t q[SV_MAX_GATE_QUBITS], double* m,
+                         int32_t* pass) {
+  clear_error();
+  if (!p) return fail(SV_ERR_ARG, "null plan");
+  if (op >= p->ops.size()) return fail(SV_ERR_ARG, "op %zu out of range (%zu ops)", op, p->ops.size());
+  const Op& o = p->ops[op];
+  if (nq) *nq = o.nq;
+  if (q)
+    for (int i = 0; i < SV_MAX_GATE_QUBITS; ++i) q[i] = i < o.nq ? o.q[i] : -1;
+  if (m)
+    for (size_t e = 0; e < o.m.size(); ++e) {
+      m[2 * e] = o.m[e].real();
+      m[2 * e + 1] = o.m[e].imag();
+    }
+  if (pass) {
+    int32_t ps = -1;
+    for (size_t i = 0; i < p->passes.size(); ++i)
+      if ((int)op >= p->passes[i].first_op && (int)op < p->passes[i].first_op + p->passes[i].n_ops) ps = (int32_t)i;
+    *pass = ps;
+  }
+  return SV_OK;
+}
+
+sv_status sv_plan_pass_info(const sv_plan* p, size_t pass, int32_t* kind, int32_t* n_ops, int32_t* n_local) {
+  clear_error();
+  if (!p) return fail(SV_ERR_ARG, "null plan");
+  if (pass >= p->passes.size()) return fail(SV_ERR_ARG, "pass %zu out of range", pass);
+  const Pass& ps = p->passes[pass];
+  if (kind) *kind = ps.kind;
+  if (n_ops) *n_ops = ps.n_ops;
+  if (n_local) *n_local = ps.n_local;
+  return SV_OK;
+}
+
+sv_status sv_plan_destroy(sv_plan* p) {
+  clear_error();
+  delete p;
+  return SV_OK;
+}
+
+sv_status sv_apply_plan(sv_state* s, const sv_plan* p) {
+  clear_error();
+  if (sv_status st = check_state(s)) return st;
+  if (!p) return fail(SV_ERR_ARG, "null plan");
+  if (p->n != s->n || p->dt != s->dt)
+    return fail(SV_ERR_ARG, "plan built for n=%d dtype=%d, state has n=%d dtype=%d", p->n, (int)p->dt, s->n,
+                (int)s->dt);
+  return execute_plan(s, p);
+}
+
+sv_status sv_apply_circuit(sv_state* s, const sv_gate* g, size_t n_gates, const sv_opts* o) {
+  clear_error();
+  if (sv_status st = check_state(s)) return st;
+  sv_plan* p = nullptr;
+  if (sv_status st = sv_fuse(s->n, s->dt, g, n_gates, o, &p)) return st;
+  sv_status st = execute_plan(s, p);
+  delete p;
+  return st;
+}
+
+sv_status sv_permute_qubits(sv_state* s, const int32_t* dest) {
+  clear_error();
+  if (sv_status st = check_state(s)) return st;
+  if (!dest) return fail(SV_ERR_ARG, "null permutation");
+  return fail(SV_ERR_UNSUPPORTED, "sv_permute_qubits not available yet");
+}
+
+sv_status sv_measure_probs(sv_state* s, const int32_t* qubits, int m, double* out_dev) {
+  clear_error();
+  if (sv_status st = check_state(s)) return st;
+  if (m < 0 || m > s->n) return fail(SV_ERR_ARG, "m=%d outside 0..%d", m, s->n);
+  if (m > 0 && !qubits) return fail(SV_ERR_ARG, "null qubit list");
+  if (!out_dev) return fail(SV_ERR_ARG, "null output");
+  int qs[SV_MAX_QUBITS];
+  for (int r = 0; r < m; ++r) {
+    if (qubits[r] < 0 || qubits[r] >= s->n) return fail(SV_ERR_QUBIT, "qubit %d out of range", qubits[r]);
+    for (int j = 0; j < r; ++j)
+      if (qubits[j] == qubits[r]) return fail(SV_ERR_QUBIT, "qubit %d repeated", qubits[r]);
+    qs[r] = qubits[r];
+  }
+  const size_t need = probs_scratch_bytes(s->n, m, qs);
+  if (need)
+    if (sv_status st = ensure_scratch(s, need)) return st;
+  SV_HIP_TRY(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, s->scratch, s->stream));
+  return SV_OK;
+}
+
+sv_status sv_scale(sv_state* s, double scale) {
+  clear_error();
+  if (sv_status st = check_state(s)) return st;
+  SweepArgs a{};
+  a.op = SWEEP_SCALE;
+  a.g.nz = 0;
+  a.g.nv = 1;
+  a.m[0] = scale;
+  SV_HIP_TRY(launch_sweep(s->dt, s->ptr, s->n, a, s->stream));
+  return SV_OK;
+}
+
+sv_status sv_sync(sv_state* s) {
+  clear_error();
+  if (sv_status st = check_state(s)) return st;
+  SV_HIP_TRY(hipStreamSynchronize(s->stream));
+  SV_HIP_TRY(hipGetLastError());
+  return SV_OK;
+}
+
+const char* sv_last_error(void) { return g_error.c_str(); }
+
+const char* sv_version(void) { return "sv-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"
+
+#include "sv_util.h"
+
+extern "C" sv_status sv_util_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  clear_error();
+  if (!dst || !src) return fail(SV_ERR_ARG, "null buffer");
+  if (bytes % 16) return fail(SV_ERR_ARG, "size %zu is not a multiple of 16", bytes);
+  SV_HIP_TRY(launch_copy_bytes(dst, src, bytes, (hipStream_t)stream));
+  return SV_OK;
+}

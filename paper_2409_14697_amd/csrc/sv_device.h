@@ -1,0 +1,80 @@
+// Device-side helpers shared by the HIP kernels of the state-vector core.
+//
+// Storage: amplitude i of a 2^N state is element i of an array of interleaved
+// (re, im) pairs (Eq. 1 of QueenV2, Sec. II-A); qubit q is bit q of i.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sv {
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef float flt2 __attribute__((ext_vector_type(2)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Complex value in registers.
+template <typename R>
+struct cplx {
+  R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// acc + a * b
+template <typename R>
+__device__ __forceinline__ cplx<R> cfma(cplx<R> acc, cplx<R> a, cplx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+
+// Insert a zero bit at position b of k (bits >= b move up by one).
+__device__ __forceinline__ uint64_t insert0(uint64_t k, unsigned b) {
+  const uint64_t lo = k & ((1ull << b) - 1ull);
+  return ((k >> b) << (b + 1)) | lo;
+}
+
+// Memory element types: one load/store instruction moves one element.
+//   dbl2 : one complex128 amplitude (16 B)
+//   flt2 : one complex64 amplitude (8 B)
+//   flt4 : two consecutive complex64 amplitudes (16 B)
+template <typename E>
+struct elem_traits;
+template <>
+struct elem_traits<dbl2> {
+  typedef double R;
+  static constexpr int amps = 1;
+  static __device__ __forceinline__ cplx<R> get(const dbl2& e, int) { return {e.x, e.y}; }
+  static __device__ __forceinline__ void put(dbl2& e, int, cplx<R> v) { e.x = v.re; e.y = v.im; }
+};
+template <>
+struct elem_traits<flt2> {
+  typedef float R;
+  static constexpr int amps = 1;
+  static __device__ __forceinline__ cplx<R> get(const flt2& e, int) { return {e.x, e.y}; }
+  static __device__ __forceinline__ void put(flt2& e, int, cplx<R> v) { e.x = v.re; e.y = v.im; }
+};
+template <>
+struct elem_traits<flt4> {
+  typedef float R;
+  static constexpr int amps = 2;
+  static __device__ __forceinline__ cplx<R> get(const flt4& e, int h) {
+    return h ? cplx<R>{e.z, e.w} : cplx<R>{e.x, e.y};
+  }
+  static __device__ __forceinline__ void put(flt4& e, int h, cplx<R> v) {
+    if (h) { e.z = v.re; e.w = v.im; } else { e.x = v.re; e.y = v.im; }
+  }
+};
+
+// Streaming loads/stores: every byte of a sweep is touched once, so the
+// accesses are marked non-temporal.
+template <typename E>
+__device__ __forceinline__ E ld(const E* p) { return __builtin_nontemporal_load(p); }
+template <typename E>
+__device__ __forceinline__ void st(E* p, E v) { __builtin_nontemporal_store(v, p); }
+
+}  // namespace sv

@@ -1,0 +1,108 @@
+// Internal host-side declarations of the state-vector core (not part of the
+// C ABI).  The planner parts (gate ops, fusion, pass planning) use no HIP
+// call, so they run on machines without a GPU.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "sv.h"
+#include "sv_kernels.h"
+
+namespace sv {
+
+// ------------------------------------------------------------------ errors
+sv_status fail(sv_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define SV_HIP_TRY(expr)                                                               \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess) return ::sv::fail(SV_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+// ------------------------------------------------------------------ ops
+// One operation in logical qubits: a 2^nq x 2^nq matrix on q[0..nq-1]
+// (q[0] = most significant bit of the local index, as in Eq. 3).  `kind`
+// keeps the named kind of an unfused gate so that special kernels (swaps,
+// phases) can be used; fused or explicit matrices have kind SV_G_MATRIX.
+struct Op {
+  int kind = SV_G_MATRIX;
+  int nq = 0;
+  int q[SV_MAX_GATE_QUBITS] = {0, 0, 0, 0, 0, 0};
+  double theta = 0.0;
+  std::vector<cd> m;  // 4^nq entries, row-major
+  int n_gates = 1;    // gates merged into this op
+};
+
+// Validate one gate against an n-qubit state (host only).
+sv_status validate_gate(const sv_gate& g, int n);
+// Build the op (with its FP64 matrix) of a validated gate.
+Op op_from_gate(const sv_gate& g);
+// Named-gate matrices (textbook definitions, FP64).
+std::vector<cd> named_matrix(int kind, double theta);
+int gate_arity(int kind);
+
+// Structural class of an op, used by the kernels and the cost model.
+enum OpClass { CLS_DENSE = 0, CLS_DIAG = 1, CLS_PERM = 2 };
+OpClass classify(const Op& op);
+
+// Sweep kernel arguments for an op with nq <= 2 (returns false for nq >= 3).
+bool sweep_args_for(const Op& op, SweepArgs* out);
+
+// Fraction of amplitudes a single-op sweep reads and writes (touched subset).
+double touched_fraction(const Op& op);
+
+// ------------------------------------------------------------------ plan
+struct Pass {
+  int kind = 0;  // 0 sweep, 1 LDS tile pass, 2 dense fused kernel, 3 permutation
+  int first_op = 0, n_ops = 0;
+  int n_local = 0;
+};
+
+}  // namespace sv
+
+struct sv_plan {
+  int n = 0;
+  sv_dtype dt = SV_C128;
+  sv_opts opts{};
+  std::vector<sv::Op> ops;
+  std::vector<sv::Pass> passes;
+  size_t n_gates_in = 0;
+};
+
+struct sv_state {
+  int n = 0;
+  sv_dtype dt = SV_C128;
+  void* ptr = nullptr;
+  bool owned = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // device scratch (reduction partials)
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  // matrix uploads: pinned host staging + device buffer
+  void* up_host = nullptr;
+  void* up_dev = nullptr;
+  size_t up_bytes = 0;
+  hipEvent_t up_done = nullptr;
+  bool up_pending = false;
+};
+
+namespace sv {
+size_t elem_bytes(sv_dtype dt);
+sv_status ensure_scratch(sv_state* s, size_t bytes);
+// Copy `bytes` from host memory to the state's upload buffer (stream-ordered);
+// returns the device address.  The previous upload's device contents stay
+// valid for work enqueued before this call.
+sv_status upload(sv_state* s, const void* host, size_t bytes, void** dev);
+// Run one op as a full-state sweep (sweep kernels for nq <= 2, dense kernel
+// for nq >= 3 with the matrix at m_dev in the state's precision).
+sv_status run_op_sweep(sv_state* s, const Op& op, const void* m_dev);
+// Plan building (host only).
+sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const sv_opts& o, sv_plan* p);
+sv_status execute_plan(sv_state* s, const sv_plan* p);
+}  // namespace sv

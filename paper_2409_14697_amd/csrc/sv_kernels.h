@@ -1,0 +1,66 @@
+// Host-visible launchers of the HIP kernels.  Every launcher validates
+// nothing (the C ABI layer has done that), enqueues on `stream`, and returns
+// the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <complex>
+
+#include "sv.h"
+
+namespace sv {
+
+typedef std::complex<double> cd;
+
+// --- gate sweeps -----------------------------------------------------------
+// One sweep over the state; each work item owns one group of amplitudes
+// (Eq. 2 pairs, Eq. 3 quads, or a touched subset of them).  Geometry is given
+// in amplitude-index space:
+//   groups = all indices with zeros at positions z[0..nz-1] (ascending), OR'd
+//   with `set`; the members of a group sit at base + off[0..nv-1].
+struct GroupSpec {
+  int nz = 0;
+  unsigned z[3] = {0, 0, 0};
+  uint64_t set = 0;
+  int nv = 1;
+  uint64_t off[4] = {0, 0, 0, 0};
+};
+
+enum SweepOp {
+  SWEEP_DENSE1 = 0,  // nv=2: (a0,a1) <- M (a0,a1), M 2x2 (m[0..3] row-major)
+  SWEEP_DENSE2 = 1,  // nv=4: 4x4 matrix m[0..15]
+  SWEEP_SWAP = 2,    // nv=2: exchange a0 and a1 (X, CNOT, SWAP)
+  SWEEP_PHASE = 3,   // nv=1: a0 <- m[0] * a0 (phase on a fixed-bit subset)
+  SWEEP_DIAG = 4,    // nv=1: a <- d[local(bits)] * a, local index from bits
+                     //       b0 (MSB) [, b1]; m[0..3] = d
+  SWEEP_SCALE = 5    // nv=1: a <- m[0].real() * a
+};
+
+struct SweepArgs {
+  SweepOp op;
+  GroupSpec g;
+  cd m[16];
+  int diag_nbits = 0;
+  unsigned diag_b0 = 0, diag_b1 = 0;
+};
+
+hipError_t launch_sweep(sv_dtype dt, void* psi, int n, const SweepArgs& a, hipStream_t s);
+
+// --- dense k-qubit fused gate (3 <= k <= 6) ---------------------------------
+// m_dev: device copy of the 2^k x 2^k matrix, row-major interleaved, in the
+// state's precision (double for SV_C128, float for SV_C64).
+hipError_t launch_dense_kq(sv_dtype dt, void* psi, int n, int k, const int* q, const void* m_dev,
+                           hipStream_t s);
+
+// --- readout ----------------------------------------------------------------
+// Scratch bytes the marginal-probability reduction needs.
+size_t probs_scratch_bytes(int n, int m, const int* qubits);
+hipError_t launch_probs(sv_dtype dt, const void* psi, int n, const int* qubits, int m, double* out,
+                        void* scratch, hipStream_t s);
+
+// --- utilities --------------------------------------------------------------
+hipError_t launch_init_basis(sv_dtype dt, void* psi, int n, uint64_t index, hipStream_t s);
+hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+}  // namespace sv

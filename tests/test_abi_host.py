@@ -1,0 +1,126 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads and exports
+every function the headers declare; the planner (sv_fuse) validates its
+input and its exported plan, replayed by the oracle, reproduces the circuit.
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sv_oracle as so
+from paper_2409_14697_amd import binding as B
+from svgen import Gate, fused_haar_circuit, layered_circuit, qft_circuit, brickwork_circuit, gaussian_state_np
+
+
+def test_library_exports_every_header_symbol():
+    lib = B.load_library()
+    names = B.header_symbols()
+    assert "sv_create" in names and "sv_apply_gate" in names and "sv_measure_probs" in names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+
+
+def test_version_and_defaults():
+    assert "gfx950" in B.version()
+    o = B.make_opts(None)
+    assert o.max_fuse_qubits == 5 and o.reorder == 1 and o.fp32_mfma == 1 and o.mode == 0
+
+
+def _fuse_err(n, gates, opts=None, dtype="c128"):
+    with pytest.raises(B.SvError) as e:
+        B.Plan(n, dtype, gates, opts)
+    return e.value.status
+
+
+def test_validation_errors():
+    assert _fuse_err(4, [Gate("H", (4,))]) == B.SV_ERR_QUBIT
+    assert _fuse_err(4, [Gate("CNOT", (1, 1))]) == B.SV_ERR_QUBIT
+    assert _fuse_err(4, [Gate("H", (-1,))]) == B.SV_ERR_QUBIT
+    assert _fuse_err(4, [Gate("H", (0,))], {"max_fuse_qubits": 7}) == B.SV_ERR_ARG
+    assert _fuse_err(4, [Gate("H", (0,))], {"mode": 9}) == B.SV_ERR_ARG
+    assert _fuse_err(0, []) == B.SV_ERR_ARG
+    assert _fuse_err(35, []) == B.SV_ERR_ARG
+    with pytest.raises(ValueError):
+        B.Plan(4, "c32", [])
+    # raw ABI: bad kind, nq mismatch, matrix gate without matrix, too many qubits
+    lib = B.load_library()
+    arr = (B.SvGate * 1)()
+    h = ctypes.c_void_p()
+    for kind, nq, q in ((99, 1, [0]), (B.KIND["H"], 2, [0, 1]), (B.KIND["MATRIX"], 1, [0]),
+                        (B.KIND["MATRIX"], 7, [0, 1, 2, 3, 4, 5])):
+        arr[0].kind, arr[0].nq = kind, nq
+        for j in range(6):
+            arr[0].q[j] = q[j] if j < len(q) else -1
+        arr[0].m = None
+        st = lib.sv_fuse(8, B.SV_C128, arr, 1, None, ctypes.byref(h))
+        assert st == B.SV_ERR_ARG, (kind, nq, st)
+        assert lib.sv_last_error()
+    assert lib.sv_fuse(8, B.SV_C128, None, 1, None, ctypes.byref(h)) == B.SV_ERR_ARG
+    assert lib.sv_fuse(8, B.SV_C128, None, 0, None, None) == B.SV_ERR_ARG
+    assert lib.sv_plan_info(None, None, None) == B.SV_ERR_ARG
+    assert lib.sv_measure_probs(None, None, 0, None) == B.SV_ERR_ARG
+    assert lib.sv_apply_gate(None, None) == B.SV_ERR_ARG
+    assert lib.sv_destroy(None) == B.SV_OK
+
+
+def _replay(plan, n, psi):
+    ops = [(q, m) for q, m, _ in plan.export()]
+    return oracle.apply_ops(psi, ops)
+
+
+@pytest.mark.parametrize("kmax", [0, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fusion_plan_replays_circuit(kmax, dtype):
+    n = 10
+    gates = layered_circuit(n, n_gates=120, seed=31)
+    plan = B.Plan(n, dtype, gates, {"max_fuse_qubits": kmax})
+    n_ops, n_passes = plan.info()
+    assert n_ops <= len(gates)
+    if kmax <= 1:
+        assert n_ops == len(gates)
+    psi = gaussian_state_np(n, 5)
+    ref = oracle.run(gates, psi0=psi)
+    out = _replay(plan, n, psi)
+    assert np.max(np.abs(out - ref)) < 1e-13
+    for q, m, ps in plan.export():
+        assert len(q) <= max(kmax, 2) and len(set(q)) == len(q)
+        assert np.max(np.abs(m.conj().T @ m - np.eye(m.shape[0]))) < 1e-13
+        assert 0 <= ps < n_passes
+
+
+def test_fusion_reduces_ops():
+    gates = brickwork_circuit(12, 6, seed=3)
+    n5 = B.Plan(12, "c128", gates, {"max_fuse_qubits": 5}).info()[0]
+    n0 = B.Plan(12, "c128", gates, {"max_fuse_qubits": 0}).info()[0]
+    assert n0 == len(gates) and n5 < n0 / 3
+
+
+def test_fusion_qft_and_haar():
+    n = 9
+    for gates in (qft_circuit(n), fused_haar_circuit(n, 8, seed=2, ks=(3, 4, 5, 6))):
+        plan = B.Plan(n, "c128", gates, {"max_fuse_qubits": 6})
+        psi = gaussian_state_np(n, 1)
+        assert np.max(np.abs(_replay(plan, n, psi) - oracle.run(gates, psi0=psi))) < 1e-13
+
+
+def test_export_matches_input_when_unfused():
+    gates = [Gate("RX", (2,), 0.3), Gate("CNOT", (0, 3)), Gate("CPHASE", (1, 2), 1.1), Gate("RZZ", (0, 1), 0.7),
+             Gate("MATRIX", (3, 0, 1), matrix=np.eye(8)[::-1])]
+    plan = B.Plan(4, "c128", gates, {"max_fuse_qubits": 0})
+    ex = plan.export()
+    assert len(ex) == len(gates)
+    for g, (q, m, _) in zip(gates, ex):
+        assert q == g.qubits
+        assert np.max(np.abs(m - so.gate_matrix(g))) < 1e-15
+
+
+def test_named_gate_matrices_match_oracle_definitions():
+    # the library builds its own matrices (C++, FP64); compare them entrywise
+    for kind in ("H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "P", "CNOT", "CZ", "SWAP", "CPHASE", "RZZ"):
+        for theta in (0.0, 0.4, 2.9):
+            nq = 2 if kind in ("CNOT", "CZ", "SWAP", "CPHASE", "RZZ") else 1
+            g = Gate(kind, tuple(range(nq)), theta)
+            (q, m, _), = B.Plan(3, "c128", [g], {"max_fuse_qubits": 0}).export()
+            assert np.max(np.abs(m - so.gate_matrix(g))) < 1e-15, kind
