@@ -1,0 +1,258 @@
+"""Gate-sweep benchmark: HBM GB/s per gate at N=30 on one MI355X.
+
+Workload (the per-gate benchmark of QueenV2 Sec. IV-B, made concrete): a
+normalised complex Gaussian state of N=30 qubits in complex128 (16 GiB) and in
+complex64 (8 GiB), seeded; each of H, X, RZ, CNOT, CZ, SWAP, CPHASE applied on
+every target qubit 0..29 (two-qubit partners drawn at random), one gate per
+sv_apply_gate call.  One step = all 210 gates on the complex128 state and all
+210 on the complex64 state.
+
+value = algorithmic bytes / time over the timed steps, where a gate's
+algorithmic bytes are the bytes it must read and write: 2 * S * f, S the state
+size and f the fraction of 64-byte DRAM bursts that hold an amplitude the gate
+changes (1 for H/X/RZ; 1/2 or 1 for CNOT and SWAP; 1/4, 1/2 or 1 for CZ and
+CPHASE, depending on whether the gate's qubits lie above the burst).
+
+Every launch is bracketed by HIP events on the stream the library launches on
+(torch's current stream, handed to sv_create), so per-kernel average durations
+come from the same timed region.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+N_QUBITS = 30
+BURST = 64  # bytes per DRAM access granule (measured: FETCH_SIZE of sub-line gates)
+
+
+def burst_qubits(dtype: str) -> int:
+    """Qubits whose bit lies inside one 64-byte burst."""
+    return int(math.log2(BURST // (16 if dtype == "c128" else 8)))
+
+
+def touched_fraction(gate, dtype: str) -> float:
+    g = burst_qubits(dtype)
+    kind, qs = gate.kind, gate.qubits
+    if kind in ("H", "X", "RZ"):
+        return 1.0
+    if kind == "CNOT":
+        return 0.5 if qs[0] >= g else 1.0
+    if kind == "SWAP":
+        return 0.5 if (qs[0] >= g and qs[1] >= g) else 1.0
+    if kind in ("CZ", "CPHASE"):
+        return 2.0 ** -((qs[0] >= g) + (qs[1] >= g))
+    raise ValueError(kind)
+
+
+def kernel_of(gate, dtype: str) -> str:
+    """Name of the sweep kernel instantiation a gate runs (for the roofline and
+    for matching rocprofv3's per-kernel statistics)."""
+    fam = {"H": "dense1", "X": "swap1", "RZ": "diag", "CNOT": "swap2", "SWAP": "swap2", "CZ": "phase2",
+           "CPHASE": "phase2"}[gate.kind]
+    if dtype == "c128":
+        elem = "c128"
+    else:
+        uses0 = 0 in gate.qubits and gate.kind != "RZ"
+        elem = "c64x1" if uses0 else "c64x2"
+    return f"{fam}/{elem}"
+
+
+# Template instantiation names of the sweep kernel, as rocprofv3 lists them.
+KERNEL_SYMBOL = {
+    "dense1": "k_group<{E}, 1, 2, sv::(anonymous namespace)::OpDense1<{R}> >",
+    "swap1": "k_group<{E}, 1, 2, sv::(anonymous namespace)::OpSwap<{R}> >",
+    "diag": "k_group<{E}, 0, 1, sv::(anonymous namespace)::OpDiag<{R}> >",
+    "swap2": "k_group<{E}, 2, 2, sv::(anonymous namespace)::OpSwap<{R}> >",
+    "phase2": "k_group<{E}, 2, 1, sv::(anonymous namespace)::OpPhase<{R}> >",
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sv_sweep.hip", "sv_device.h", "sv_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2409_14697_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_key: str):
+    """HBM bytes per launch of `kernel_key` from the committed rocprofv3 counter
+    summary (FETCH_SIZE / WRITE_SIZE scaled by a copy kernel of known size);
+    None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "gate_sweep_counters_n30.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel_key)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(gates, n: int):
+    """The oracle (numpy, complex128) on a bounded sample of the same workload:
+    three gates of the set at N=30 on the host cores."""
+    import numpy as np
+
+    import oracle
+    from svgen import gaussian_state_np
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = 1
+    sample = [g for g in gates if (g.kind, g.qubits[-1]) in (("H", n - 1), ("CNOT", 0), ("CPHASE", n // 2))]
+    psi = gaussian_state_np(n, 2)
+    total_bytes, total_t = 0.0, 0.0
+    for g in sample:
+        t0 = time.perf_counter()
+        psi = oracle.apply_gate(psi, g)
+        total_t += time.perf_counter() - t0
+        total_bytes += 2.0 * (1 << n) * 16 * touched_fraction(g, "c128")
+    del psi
+    desc = ", ".join(f"{g.kind}{g.qubits}" for g in sample)
+    return {"value": total_bytes / total_t / 1e9, "unit": "GB/s", "cores": blas_threads, "kind": "oracle",
+            "sample": f"{len(sample)} gates of the set ({desc}) at N={n}, complex128, {total_t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=N_QUBITS)
+    ap.add_argument("--dtypes", default="c128,c64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-ceiling", action="store_true", help="also time the 16-byte copy kernel")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the state-vector hot path here runs on a single MI355X "
+              "(no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2409_14697_amd as sv
+    from svgen import gate_bench_set
+    from svgen.states import gaussian_state_torch
+
+    torch.cuda.set_device(0)
+    n = args.n
+    gates = gate_bench_set(n, seed=2)
+    dtypes = [d for d in args.dtypes.split(",") if d]
+    stream = torch.cuda.current_stream()
+    per_kernel = {}   # key -> [bytes, seconds, launches]
+    per_dtype = {}
+    total_bytes, total_s = 0.0, 0.0
+    for dtype in dtypes:
+        tdt = torch.complex128 if dtype == "c128" else torch.complex64
+        psi = gaussian_state_torch(n, 2, tdt)
+        st = sv.StateVector(n, dtype, tensor=psi, init=False, stream=stream)
+        S = psi.numel() * psi.element_size()
+        for _ in range(args.warmup):
+            for g in gates:
+                st.apply_gate(g)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in gates]
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        durations = [0.0] * len(gates)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(args.steps):
+            for i, g in enumerate(gates):
+                evs[i][0].record(stream)
+                st.apply_gate(g)
+                evs[i][1].record(stream)
+            stream.synchronize()
+            for i in range(len(gates)):
+                durations[i] += evs[i][0].elapsed_time(evs[i][1]) * 1e-3
+        stop.record(stream)
+        torch.cuda.synchronize()
+        wall = start.elapsed_time(stop) * 1e-3
+        dbytes = 0.0
+        for i, g in enumerate(gates):
+            b = 2.0 * S * touched_fraction(g, dtype) * args.steps
+            dbytes += b
+            key = kernel_of(g, dtype)
+            acc = per_kernel.setdefault(key, [0.0, 0.0, 0])
+            acc[0] += b
+            acc[1] += durations[i]
+            acc[2] += args.steps
+        kern_s = sum(durations)
+        per_dtype[dtype] = {"GB/s": round(dbytes / kern_s / 1e9, 1), "ms_per_step": round(1e3 * wall / args.steps, 3),
+                            "gates_per_step": len(gates)}
+        total_bytes += dbytes
+        total_s += kern_s
+        st.close()
+        del psi
+        torch.cuda.empty_cache()
+
+    copy_gbs = None
+    if args.copy_ceiling:
+        src = torch.empty(1 << (n - 1), dtype=torch.complex128, device="cuda")
+        dst = torch.empty_like(src)
+        sv.util_copy(dst, src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            sv.util_copy(dst, src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        copy_gbs = 2.0 * src.numel() * 16 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del src, dst
+
+    # dominant kernel = the one with the most time in the timed region
+    dom_key, (dbytes, dsec, dl) = max(per_kernel.items(), key=lambda kv: kv[1][1])
+    achieved = dbytes / dsec / 1e9
+    fam, elem = dom_key.split("/")
+    E = {"c128": "double __attribute__((ext_vector_type(2)))", "c64x2": "float __attribute__((ext_vector_type(4)))",
+         "c64x1": "float __attribute__((ext_vector_type(2)))"}[elem]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": load_traffic(dom_key),
+                "kernel": dom_key, "symbol": "sv::(anonymous namespace)::" + KERNEL_SYMBOL[fam].format(
+                    E=E, R="double" if elem == "c128" else "float"),
+                "launches": dl, "avg_ms": round(1e3 * dsec / dl, 4),
+                "algorithmic_bytes_per_launch": round(dbytes / dl)}
+    value = total_bytes / total_s / 1e9
+    out = {
+        "metric": "HBM GB/s per gate at N=30 (gate sweep benchmark)",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sum(v["ms_per_step"] for v in per_dtype.values()), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "+".join({"c128": "f64", "c64": "f32"}[d] for d in dtypes),
+        "data": "synthetic",
+        "config": {"workload": f"gate sweep benchmark: N={n}, {'+'.join(dtypes)} Gaussian state (seed 2), "
+                               f"H/X/RZ/CNOT/CZ/SWAP/CPHASE on every target (partners random, seed 2)",
+                   "n_qubits": n, "gates_per_step": len(gates) * len(dtypes)},
+        "by_dtype": per_dtype,
+        "per_kernel_GBs": {k: round(v[0] / v[1] / 1e9, 1) for k, v in sorted(per_kernel.items())},
+        "roofline": roofline,
+    }
+    if copy_gbs is not None:
+        out["copy_kernel_GBs"] = round(copy_gbs, 1)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(gates, n)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -12,6 +12,12 @@
 // complex64 states are processed two amplitudes (16 B) per access whenever bit
 // 0 is not one of the gate's positions; every group then has a twin at index
 // +1 and both are updated from one 16-byte load.
+//
+// Launch shape (measured on MI355X at 16 GiB): one group per lane and many
+// small blocks keep the most loads in flight -- more resident waves beat more
+// loads per lane.  Blocks are dispatched round-robin over the 8 XCDs; the
+// block index is remapped so that each XCD walks one contiguous eighth of the
+// state, which keeps each XCD's DRAM stream sequential.
 #include "sv_device.h"
 #include "sv_kernels.h"
 
@@ -19,6 +25,15 @@ namespace sv {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kXcds = 8;
+
+// Block index remapped so that XCD x (blocks x, x+8, ...) owns a contiguous
+// range; identity when the grid is not a multiple of the XCD count.
+__device__ __forceinline__ uint64_t xcd_block() {
+  const uint64_t b = blockIdx.x, nb = gridDim.x;
+  if (nb % kXcds) return b;
+  return (b % kXcds) * (nb / kXcds) + b / kXcds;
+}
 
 template <int NZ, int NV>
 struct Geo {
@@ -96,8 +111,8 @@ __global__ __launch_bounds__(kBlock) void k_group(E* __restrict__ psi, uint64_t 
                                                   Op op) {
   typedef elem_traits<E> TR;
   typedef typename TR::R R;
-  constexpr int ITEMS = (NV >= 4) ? 2 : (NV == 2 ? 4 : 8);
-  const uint64_t k0 = (uint64_t)blockIdx.x * (uint64_t)(kBlock * ITEMS) + threadIdx.x;
+  constexpr int ITEMS = 1;
+  const uint64_t k0 = xcd_block() * (uint64_t)(kBlock * ITEMS) + threadIdx.x;
   E v[ITEMS][NV];
   uint64_t base[ITEMS];
 #pragma unroll
@@ -139,7 +154,7 @@ cplx<R> to_dev(cd x) {
 
 template <typename E, int NZ, int NV, class Op>
 hipError_t run(void* psi, uint64_t ngroups, const GroupSpec& gs, unsigned shift, const Op& op, hipStream_t s) {
-  constexpr int ITEMS = (NV >= 4) ? 2 : (NV == 2 ? 4 : 8);
+  constexpr int ITEMS = 1;
   Geo<NZ, NV> g;
   for (int z = 0; z < NZ; ++z) g.z[z] = gs.z[z] - shift;
   g.set = gs.set >> shift;
@@ -229,8 +244,8 @@ __global__ __launch_bounds__(kBlock) void k_init_basis(E* __restrict__ psi, uint
 
 __global__ __launch_bounds__(kBlock) void k_copy16(flt4* __restrict__ dst, const flt4* __restrict__ src,
                                                    uint64_t count) {
-  constexpr int ITEMS = 8;
-  const uint64_t i0 = (uint64_t)blockIdx.x * (kBlock * ITEMS) + threadIdx.x;
+  constexpr int ITEMS = 1;
+  const uint64_t i0 = xcd_block() * (kBlock * ITEMS) + threadIdx.x;
   flt4 v[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
@@ -258,7 +273,7 @@ hipError_t launch_init_basis(sv_dtype dt, void* psi, int n, uint64_t index, hipS
 
 hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const uint64_t count = bytes / 16;
-  const uint64_t per_block = (uint64_t)kBlock * 8;
+  const uint64_t per_block = (uint64_t)kBlock;
   const uint64_t blocks = (count + per_block - 1) / per_block;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(kBlock), 0, s, (flt4*)dst, (const flt4*)src, count);
