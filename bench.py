@@ -9,9 +9,10 @@ sv_apply_gate call.  One step = all 210 gates on the complex128 state and all
 
 value = algorithmic bytes / time over the timed steps, where a gate's
 algorithmic bytes are the bytes it must read and write: 2 * S * f, S the state
-size and f the fraction of 64-byte DRAM bursts that hold an amplitude the gate
+size and f the fraction of 128-byte lines that hold an amplitude the gate
 changes (1 for H/X/RZ; 1/2 or 1 for CNOT and SWAP; 1/4, 1/2 or 1 for CZ and
-CPHASE, depending on whether the gate's qubits lie above the burst).
+CPHASE, depending on whether the gate's qubits lie above the line).  128 bytes
+is the read granularity FETCH_SIZE shows on MI355X.
 
 Every launch is bracketed by HIP events on the stream the library launches on
 (torch's current stream, handed to sv_create), so per-kernel average durations
@@ -32,16 +33,16 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 N_QUBITS = 30
-BURST = 64  # bytes per DRAM access granule (measured: FETCH_SIZE of sub-line gates)
+LINE = 128  # bytes per memory read granule (FETCH_SIZE of sub-line subsets)
 
 
-def burst_qubits(dtype: str) -> int:
-    """Qubits whose bit lies inside one 64-byte burst."""
-    return int(math.log2(BURST // (16 if dtype == "c128" else 8)))
+def line_qubits(dtype: str) -> int:
+    """Qubits whose bit lies inside one 128-byte line."""
+    return int(math.log2(LINE // (16 if dtype == "c128" else 8)))
 
 
 def touched_fraction(gate, dtype: str) -> float:
-    g = burst_qubits(dtype)
+    g = line_qubits(dtype)
     kind, qs = gate.kind, gate.qubits
     if kind in ("H", "X", "RZ"):
         return 1.0
@@ -54,32 +55,33 @@ def touched_fraction(gate, dtype: str) -> float:
     raise ValueError(kind)
 
 
-def kernel_of(gate, dtype: str) -> str:
-    """Name of the sweep kernel instantiation a gate runs (for the roofline and
-    for matching rocprofv3's per-kernel statistics)."""
-    fam = {"H": "dense1", "X": "swap1", "RZ": "diag", "CNOT": "swap2", "SWAP": "swap2", "CZ": "phase2",
-           "CPHASE": "phase2"}[gate.kind]
-    if dtype == "c128":
-        elem = "c128"
-    else:
-        uses0 = 0 in gate.qubits and gate.kind != "RZ"
-        elem = "c64x1" if uses0 else "c64x2"
-    return f"{fam}/{elem}"
+_ELEM = {"c128": "double __vector(2)", "c64x2": "float __vector(4)", "c64x1": "float __vector(2)",
+         "c64": "float __vector(4)"}
+_OPS = {"DENSE1": "OpDense1", "DENSE2": "OpDense2", "SWAP": "OpSwap", "PHASE": "OpPhase", "DIAG": "OpDiag",
+        "SCALE": "OpScale"}
+_KINDS = {"INTRA": 0, "LANE": 1, "REG": 2}
 
 
-# Template instantiation names of the sweep kernel, as rocprofv3 lists them.
-KERNEL_SYMBOL = {
-    "dense1": "k_group<{E}, 1, 2, sv::(anonymous namespace)::OpDense1<{R}> >",
-    "swap1": "k_group<{E}, 1, 2, sv::(anonymous namespace)::OpSwap<{R}> >",
-    "diag": "k_group<{E}, 0, 1, sv::(anonymous namespace)::OpDiag<{R}> >",
-    "swap2": "k_group<{E}, 2, 2, sv::(anonymous namespace)::OpSwap<{R}> >",
-    "phase2": "k_group<{E}, 2, 1, sv::(anonymous namespace)::OpPhase<{R}> >",
-}
+def kernel_symbol(key: str) -> str:
+    """Template instantiation of a kernel identifier returned by
+    sv_gate_kernel, as rocprofv3 lists it with namespaces removed."""
+    parts = key.split("/")
+    if parts[0] == "group":
+        el, op, zv = parts[1], parts[2], parts[3]
+        nz, nv = zv[1:].split("v")
+        real = "double" if el == "c128" else "float"
+        return f"k_group<{_ELEM[el]}, {nz}, {nv}, {_OPS[op]}<{real}> >"
+    if parts[0] == "lane":
+        el, k, kinds, z = parts[1], int(parts[2][1:]), parts[3].split("-"), int(parts[4][1:])
+        ka = _KINDS[kinds[0]]
+        kb = _KINDS[kinds[1]] if k == 2 else -1
+        return f"k_low<{_ELEM[el]}, {k}, {ka}, {kb}, {z}>"
+    return key
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sv_sweep.hip", "sv_device.h", "sv_kernels.h"):
+    for f in ("sv_sweep.hip", "sv_device.h", "sv_kernels.h", "sv_gates.cpp"):
         with open(os.path.join(ROOT, "paper_2409_14697_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -161,6 +163,7 @@ def main():
         psi = gaussian_state_torch(n, 2, tdt)
         st = sv.StateVector(n, dtype, tensor=psi, init=False, stream=stream)
         S = psi.numel() * psi.element_size()
+        kernels = [sv.gate_kernel(n, dtype, g) for g in gates]
         for _ in range(args.warmup):
             for g in gates:
                 st.apply_gate(g)
@@ -185,7 +188,7 @@ def main():
         for i, g in enumerate(gates):
             b = 2.0 * S * touched_fraction(g, dtype) * args.steps
             dbytes += b
-            key = kernel_of(g, dtype)
+            key = kernels[i]
             acc = per_kernel.setdefault(key, [0.0, 0.0, 0])
             acc[0] += b
             acc[1] += durations[i]
@@ -217,13 +220,9 @@ def main():
     # dominant kernel = the one with the most time in the timed region
     dom_key, (dbytes, dsec, dl) = max(per_kernel.items(), key=lambda kv: kv[1][1])
     achieved = dbytes / dsec / 1e9
-    fam, elem = dom_key.split("/")
-    E = {"c128": "double __attribute__((ext_vector_type(2)))", "c64x2": "float __attribute__((ext_vector_type(4)))",
-         "c64x1": "float __attribute__((ext_vector_type(2)))"}[elem]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": load_traffic(dom_key),
-                "kernel": dom_key, "symbol": "sv::(anonymous namespace)::" + KERNEL_SYMBOL[fam].format(
-                    E=E, R="double" if elem == "c128" else "float"),
+                "kernel": dom_key, "symbol": kernel_symbol(dom_key),
                 "launches": dl, "avg_ms": round(1e3 * dsec / dl, 4),
                 "algorithmic_bytes_per_launch": round(dbytes / dl)}
     value = total_bytes / total_s / 1e9
@@ -244,7 +243,8 @@ def main():
                                f"H/X/RZ/CNOT/CZ/SWAP/CPHASE on every target (partners random, seed 2)",
                    "n_qubits": n, "gates_per_step": len(gates) * len(dtypes)},
         "by_dtype": per_dtype,
-        "per_kernel_GBs": {k: round(v[0] / v[1] / 1e9, 1) for k, v in sorted(per_kernel.items())},
+        "per_kernel": {k: {"GB/s": round(v[0] / v[1] / 1e9, 1), "launches": v[2], "ms": round(1e3 * v[1], 2)}
+                       for k, v in sorted(per_kernel.items())},
         "roofline": roofline,
     }
     if copy_gbs is not None:

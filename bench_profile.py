@@ -1,0 +1,125 @@
+"""Summarise rocprofv3 output of bench.py into profiles/ (host side, no GPU).
+
+Inputs are the CSV directories of three profiled runs of bench.py:
+  --trace : rocprofv3 --kernel-trace --stats -f csv -d <dir> -o bench -- python bench.py
+  --fetch : rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o bench -- python bench.py --steps 1 --warmup 0
+            --no-cpu-baseline --copy-ceiling
+  --write : the same with --pmc WRITE_SIZE
+Outputs:
+  profiles/gate_sweep_n30.md              per-kernel durations (kernel trace) and
+                                          calibrated HBM traffic (counters)
+  profiles/gate_sweep_counters_n30.json   bytes per launch, read by bench.py's
+                                          roofline "traffic" field
+
+Calibration: the copy kernel (sv_util_copy) moves a known number of bytes
+(2^(N-1) complex128 elements read and written); FETCH_SIZE and WRITE_SIZE (KiB
+per dispatch) are each scaled by known bytes / counter value for that kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import json
+import os
+import statistics
+import sys
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def short(name: str) -> str:
+    """Kernel name without namespaces and argument list."""
+    n = name.replace("void ", "", 1)
+    n = n.replace("sv::(anonymous namespace)::", "")
+    depth, out = 0, []
+    for ch in n:
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def counters(d: str, counter: str):
+    rows = list(csv.DictReader(open(os.path.join(d, "bench_counter_collection.csv"))))
+    per = defaultdict(list)
+    for r in rows:
+        if r["Counter_Name"] == counter:
+            per[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return per
+
+
+def main():
+    import bench
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    args = ap.parse_args()
+
+    stats = list(csv.DictReader(open(os.path.join(args.trace, "bench_kernel_stats.csv"))))
+    fetch, write = counters(args.fetch, "FETCH_SIZE"), counters(args.write, "WRITE_SIZE")
+    copy = "k_copy16"
+    copy_bytes = float(1 << (args.n - 1)) * 16.0
+    f_fetch = copy_bytes / 1024.0 / statistics.mean(fetch[copy])
+    f_write = copy_bytes / 1024.0 / statistics.mean(write[copy])
+
+    import paper_2409_14697_amd as sv
+    from svgen import gate_bench_set
+    keys = sorted({sv.gate_kernel(args.n, dt, g) for dt in ("c128", "c64") for g in gate_bench_set(args.n, seed=2)})
+    sym2key = {bench.kernel_symbol(k): k for k in keys}
+
+    kernels = {}
+    for sym, vals in fetch.items():
+        if sym not in write or not sym.startswith("k_"):  # this library's kernels only
+            continue
+        key = sym2key.get(sym, sym)
+        fk, wk = statistics.mean(vals), statistics.mean(write[sym])
+        kernels[key] = {"symbol": sym, "launches": len(vals), "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+                        "bytes_per_launch": round((fk * f_fetch + wk * f_write) * 1024.0)}
+    os.makedirs(args.out, exist_ok=True)
+    with open(os.path.join(args.out, "gate_sweep_counters_n30.json"), "w") as f:
+        json.dump({"source_hash": bench.kernel_source_hash(), "n_qubits": args.n,
+                   "copy_calibration": {"fetch_factor": round(f_fetch, 4), "write_factor": round(f_write, 4),
+                                        "copy_bytes_each_way": copy_bytes},
+                   "kernels": kernels}, f, indent=1, sort_keys=True)
+
+    lines = ["# Gate-sweep benchmark, N=30 (complex128 + complex64): rocprofv3 summary", "",
+             "Commands (run from the repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "```",
+             "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o bench -- python bench.py",
+             "rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/prof_fetch -o bench -- python bench.py --steps 1 "
+             "--warmup 0 --no-cpu-baseline --copy-ceiling",
+             "rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/prof_write -o bench -- python bench.py --steps 1 "
+             "--warmup 0 --no-cpu-baseline --copy-ceiling",
+             "python bench_profile.py --trace gpurun_out/prof_trace --fetch gpurun_out/prof_fetch "
+             "--write gpurun_out/prof_write",
+             "```", "",
+             f"Kernel source hash: `{bench.kernel_source_hash()}`.", "",
+             "## Kernel trace (--stats), kernels above 0.5% of GPU time", "",
+             "| kernel | identifier | calls | avg ms | total % |", "|---|---|---:|---:|---:|"]
+    for r in stats:
+        if float(r["Percentage"]) < 0.5:
+            continue
+        sym = short(r["Name"])
+        lines.append(f"| `{sym}` | {sym2key.get(sym, '')} | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    lines += ["", "## HBM traffic per launch (FETCH_SIZE x %.3f + WRITE_SIZE x %.3f, calibrated on the copy kernel)"
+              % (f_fetch, f_write), "",
+              "| identifier | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes / launch |", "|---|---:|---:|---:|---:|"]
+    for key, k in sorted(kernels.items(), key=lambda kv: -kv[1]["bytes_per_launch"] * kv[1]["launches"]):
+        lines.append(f"| {key} | {k['launches']} | {k['fetch_kib']:.0f} | {k['write_kib']:.0f} | "
+                     f"{k['bytes_per_launch']:.4g} |")
+    with open(os.path.join(args.out, "gate_sweep_n30.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {args.out}/gate_sweep_n30.md and gate_sweep_counters_n30.json "
+          f"(fetch x{f_fetch:.3f}, write x{f_write:.3f})")
+
+
+if __name__ == "__main__":
+    main()

@@ -212,6 +212,14 @@ const char *sv_last_error(void);
 /* Library version string. */
 const char *sv_version(void);
 
+/* Which kernel sv_apply_gate would launch for gate g on an n-qubit state of
+ * type dt (host only; no device needed).  Writes a NUL-terminated identifier
+ * into buf (at most len bytes), e.g. "group/c128/SWAP/z2v2" (touched-subset
+ * group sweep), "lane/c64/K2/INTRA-REG/z1" (lane-exchange sweep) or
+ * "dense/c128/k5".  For attributing measured kernel time to gates.
+ * Errors: SV_ERR_ARG, SV_ERR_QUBIT (as sv_apply_gate). */
+sv_status sv_gate_kernel(int n_qubits, sv_dtype dt, const sv_gate *g, char *buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

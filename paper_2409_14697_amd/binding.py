@@ -54,7 +54,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
-                          f"(python -m paper_2409_14697_amd.build); there is no fallback")
+                          f"(python paper_2409_14697_amd/build.py); there is no fallback")
     # torch ships its own HIP runtime (same soname, libamdhip64.so.7).  Loading
     # torch first makes libsv.so bind to that runtime, so device pointers and
     # streams that torch hands over are valid in the library; loading libsv.so
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sv_last_error": (c_char_p, []),
         "sv_version": (c_char_p, []),
         "sv_util_copy": (S, [c_void_p, c_void_p, c_size_t, c_void_p]),
+        "sv_gate_kernel": (S, [c_int, c_int, POINTER(SvGate), c_char_p, c_size_t]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -305,6 +306,14 @@ def util_copy(dst, src, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     check(load_library().sv_util_copy(c_void_p(dst.data_ptr()), c_void_p(src.data_ptr()), nbytes,
                                       c_void_p(s.cuda_stream)))
+
+
+def gate_kernel(n: int, dtype, gate) -> str:
+    """Identifier of the kernel sv_apply_gate launches for `gate` (host only)."""
+    arr, keep = make_gates([gate])
+    buf = ctypes.create_string_buffer(128)
+    check(load_library().sv_gate_kernel(n, _dt_code(dtype), arr, buf, 128))
+    return buf.value.decode()
 
 
 def version() -> str:

@@ -1,6 +1,6 @@
 """Build libsv.so (HIP kernels for gfx950 + host C ABI) in-tree.
 
-    python -m paper_2409_14697_amd.build        # or __graft_entry__.build()
+    python paper_2409_14697_amd/build.py        # or __graft_entry__.build()
 
 Every source under csrc/ is compiled with hipcc for gfx950 and linked into
 paper_2409_14697_amd/libsv.so.  Packed FP32 instructions are disabled for the

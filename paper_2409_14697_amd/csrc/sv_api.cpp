@@ -75,7 +75,7 @@ sv_status upload(sv_state* s, const void* host, size_t bytes, void** dev) {
 sv_status run_op_sweep(sv_state* s, const Op& op, const void* m_dev) {
   if (op.nq <= 2) {
     SweepArgs a;
-    sweep_args_for(op, &a);
+    if (!low_args_for(op, s->dt, &a)) sweep_args_for(op, &a);
     SV_HIP_TRY(launch_sweep(s->dt, s->ptr, s->n, a, s->stream));
     return SV_OK;
   }
@@ -362,6 +362,37 @@ sv_status sv_sync(sv_state* s) {
   if (sv_status st = check_state(s)) return st;
   SV_HIP_TRY(hipStreamSynchronize(s->stream));
   SV_HIP_TRY(hipGetLastError());
+  return SV_OK;
+}
+
+sv_status sv_gate_kernel(int n, sv_dtype dt, const sv_gate* g, char* buf, size_t len) {
+  clear_error();
+  if (!g || !buf || len == 0) return fail(SV_ERR_ARG, "null argument");
+  if (n < 1 || n > SV_MAX_QUBITS) return fail(SV_ERR_ARG, "n_qubits %d outside 1..%d", n, SV_MAX_QUBITS);
+  if (dt != SV_C64 && dt != SV_C128) return fail(SV_ERR_ARG, "bad dtype %d", (int)dt);
+  if (sv_status st = validate_gate(*g, n)) return st;
+  const Op op = op_from_gate(*g);
+  const char* dts = dt == SV_C128 ? "c128" : "c64";
+  std::string name;
+  SweepArgs a;
+  if (op.nq >= 3) {
+    name = std::string("dense/") + dts + "/k" + std::to_string(op.nq);
+  } else if (low_args_for(op, dt, &a)) {
+    static const char* kn[] = {"INTRA", "LANE", "REG"};
+    name = std::string("lane/") + dts + "/K" + std::to_string(a.low_k) + "/" + kn[a.low_kind[0]];
+    if (a.low_k == 2) name += std::string("-") + kn[a.low_kind[1]];
+    name += "/z" + std::to_string(a.low_nz);
+  } else {
+    sweep_args_for(op, &a);
+    static const char* on[] = {"DENSE1", "DENSE2", "SWAP", "PHASE", "DIAG", "SCALE", "LOW"};
+    uint64_t used = a.g.set;
+    for (int i = 0; i < a.g.nz; ++i) used |= 1ull << a.g.z[i];
+    for (int i = 0; i < a.g.nv; ++i) used |= a.g.off[i];
+    const char* el = dt == SV_C128 ? "c128" : ((used & 1ull) ? "c64x1" : "c64x2");
+    name = std::string("group/") + el + "/" + on[a.op] + "/z" + std::to_string(a.g.nz) + "v" + std::to_string(a.g.nv);
+  }
+  if (name.size() + 1 > len) return fail(SV_ERR_ARG, "buffer of %zu bytes too small", len);
+  std::memcpy(buf, name.c_str(), name.size() + 1);
   return SV_OK;
 }
 

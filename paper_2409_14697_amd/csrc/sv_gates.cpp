@@ -205,6 +205,128 @@ bool sweep_args_for(const Op& op, SweepArgs* out) {
   return false;
 }
 
+// Position classes of a qubit for the sweep kernels, in units of 16-byte
+// elements (one complex128 amplitude, or a complex64 pair whose bit 0 is
+// inside the element):
+//   in_wave   -- the partner lies in the same row of 64 elements that one
+//                wave loads per instruction (element bit < 6): a target there
+//                is paired by lane exchange;
+//   sub_burst -- the bit lies inside one 64-byte DRAM burst (element bit < 2):
+//                a control or phase bit there cannot select a subset of
+//                bursts, so the whole row is read and the bit is handled in
+//                lanes; a higher control or phase bit restricts the sweep to
+//                the touched subset.
+static int elem_bit(int q, sv_dtype dt) { return dt == SV_C128 ? q : q - 1; }
+static bool in_wave(int q, sv_dtype dt) { return dt == SV_C64 && q == 0 ? true : elem_bit(q, dt) < 6; }
+static bool sub_burst(int q, sv_dtype dt) { return dt == SV_C64 && q == 0 ? true : elem_bit(q, dt) < 2; }
+static bool low_args_for_layout(const Op& op, sv_dtype dt, SweepArgs* out);
+
+bool plan_low(sv_dtype dt, SweepArgs* a) {
+  const bool pair = dt == SV_C64;
+  const unsigned shift = pair ? 1u : 0u;
+  unsigned epos[2] = {0, 0};
+  a->low_nz = 0;
+  a->low_set = 0;
+  a->low_off1 = 0;
+  for (int m = 0; m < a->low_k; ++m) {
+    const unsigned p = a->low_q[m];
+    if (pair && p == 0) {
+      a->low_kind[m] = LOW_INTRA;
+    } else if (p - shift < kLaneBits) {
+      a->low_kind[m] = LOW_LANE;
+      epos[m] = p - shift;
+    } else {
+      if (a->low_nz == 2) return false;
+      a->low_kind[m] = LOW_REG;
+      a->low_z[a->low_nz++] = p - shift;
+      a->low_off1 = 1ull << (p - shift);
+    }
+  }
+  for (unsigned p = 0; p < 64; ++p)
+    if ((a->low_fixed >> p) & 1ull) {
+      if (a->low_nz == 2 || (pair && p == 0)) return false;
+      a->low_z[a->low_nz++] = p - shift;
+      a->low_set |= 1ull << (p - shift);
+    }
+  if (a->low_nz > 1) return false;
+  // a lane holds element bits 0..5 minus the inserted positions below them
+  for (int m = 0; m < a->low_k; ++m)
+    if (a->low_kind[m] == LOW_LANE) {
+      unsigned below = 0;
+      for (int z = 0; z < a->low_nz; ++z) below += a->low_z[z] < epos[m] ? 1u : 0u;
+      a->low_lanebit[m] = epos[m] - below;
+    }
+  return true;
+}
+
+bool low_args_for(const Op& op, sv_dtype dt, SweepArgs* out) {
+  const bool ok = low_args_for_layout(op, dt, out);
+  return ok && plan_low(dt, out);
+}
+
+static bool low_args_for_layout(const Op& op, sv_dtype dt, SweepArgs* out) {
+  SweepArgs a{};
+  a.op = SWEEP_LOW;
+  if (op.nq == 1) {
+    const int t = op.q[0];
+    if (op.kind == SV_G_RZ) return false;  // elementwise sweep
+    const bool phase = op.kind == SV_G_Z || op.kind == SV_G_S || op.kind == SV_G_T || op.kind == SV_G_P;
+    if (phase ? !sub_burst(t, dt) : !in_wave(t, dt)) return false;
+    a.low_k = 1;
+    a.low_q[0] = (unsigned)t;
+    for (int i = 0; i < 4; ++i) a.m[i] = op.m[i];
+    *out = a;
+    return true;
+  }
+  if (op.nq != 2 || op.kind == SV_G_RZZ) return false;
+  const int q0 = op.q[0], q1 = op.q[1];
+  if (op.kind == SV_G_CNOT) {
+    const bool cfix = !sub_burst(q0, dt), tw = in_wave(q1, dt);
+    if (cfix && !tw) return false;
+    if (cfix) {  // control fixed to 1, X on the target
+      a.low_k = 1;
+      a.low_q[0] = (unsigned)q1;
+      a.low_fixed = 1ull << q0;
+      a.m[0] = 0.0; a.m[1] = 1.0; a.m[2] = 1.0; a.m[3] = 0.0;
+    } else {
+      a.low_k = 2;
+      a.low_q[0] = (unsigned)q0;
+      a.low_q[1] = (unsigned)q1;
+      for (int i = 0; i < 16; ++i) a.m[i] = op.m[i];
+    }
+    *out = a;
+    return true;
+  }
+  if (op.kind == SV_G_CZ || op.kind == SV_G_CPHASE) {
+    const bool s0 = sub_burst(q0, dt), s1 = sub_burst(q1, dt);
+    if (!s0 && !s1) return false;
+    if (s0 && s1) {
+      a.low_k = 2;
+      a.low_q[0] = (unsigned)q0;
+      a.low_q[1] = (unsigned)q1;
+      for (int i = 0; i < 16; ++i) a.m[i] = op.m[i];
+    } else {  // diag(1, phase) on the sub-burst qubit where the other is 1
+      a.low_k = 1;
+      a.low_q[0] = (unsigned)(s0 ? q0 : q1);
+      a.low_fixed = 1ull << (s0 ? q1 : q0);
+      a.m[0] = 1.0; a.m[1] = 0.0; a.m[2] = 0.0; a.m[3] = op.m[15];
+    }
+    *out = a;
+    return true;
+  }
+  // SWAP changes only the (0,1) and (1,0) members: it keeps the touched
+  // subset unless one qubit is inside a burst.  Dense two-qubit matrices
+  // change every amplitude: lane exchange whenever a qubit is in the row.
+  if (op.kind == SV_G_SWAP ? !(sub_burst(q0, dt) || sub_burst(q1, dt)) : !(in_wave(q0, dt) || in_wave(q1, dt)))
+    return false;
+  a.low_k = 2;
+  a.low_q[0] = (unsigned)q0;
+  a.low_q[1] = (unsigned)q1;
+  for (int i = 0; i < 16; ++i) a.m[i] = op.m[i];
+  *out = a;
+  return true;
+}
+
 double touched_fraction(const Op& op) {
   switch (op.kind) {
     case SV_G_Z: case SV_G_S: case SV_G_T: case SV_G_P: case SV_G_CNOT: case SV_G_SWAP:

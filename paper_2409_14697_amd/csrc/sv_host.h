@@ -52,6 +52,9 @@ OpClass classify(const Op& op);
 
 // Sweep kernel arguments for an op with nq <= 2 (returns false for nq >= 3).
 bool sweep_args_for(const Op& op, SweepArgs* out);
+// Lane-exchange kernel arguments when one of the op's qubits lies inside one
+// wave's row of 64 16-byte elements (returns false otherwise).
+bool low_args_for(const Op& op, sv_dtype dt, SweepArgs* out);
 
 // Fraction of amplitudes a single-op sweep reads and writes (touched subset).
 double touched_fraction(const Op& op);

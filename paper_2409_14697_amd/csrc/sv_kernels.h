@@ -34,7 +34,11 @@ enum SweepOp {
   SWEEP_PHASE = 3,   // nv=1: a0 <- m[0] * a0 (phase on a fixed-bit subset)
   SWEEP_DIAG = 4,    // nv=1: a <- d[local(bits)] * a, local index from bits
                      //       b0 (MSB) [, b1]; m[0..3] = d
-  SWEEP_SCALE = 5    // nv=1: a <- m[0].real() * a
+  SWEEP_SCALE = 5,   // nv=1: a <- m[0].real() * a
+  SWEEP_LOW = 6      // 1-/2-qubit matrix m (4^low_k entries) on qubits low_q
+                     // (low_q[0] = MSB), at least one of them inside a
+                     // 128-byte run; rows are exchanged between lanes.  Only
+                     // indices with all low_fixed bits set are visited.
 };
 
 struct SweepArgs {
@@ -43,7 +47,25 @@ struct SweepArgs {
   cd m[16];
   int diag_nbits = 0;
   unsigned diag_b0 = 0, diag_b1 = 0;
+  int low_k = 0;
+  unsigned low_q[2] = {0, 0};
+  uint64_t low_fixed = 0;
+  // filled by plan_low(): the lane-exchange layout in element space
+  int low_kind[2] = {-1, -1};      // LOW_INTRA / LOW_LANE / LOW_REG per matrix qubit
+  unsigned low_lanebit[2] = {0, 0};
+  int low_nz = 0;                  // zero-inserted element positions (REG target or fixed control)
+  unsigned low_z[2] = {0, 0};
+  uint64_t low_set = 0;            // element bits fixed to 1
+  uint64_t low_off1 = 0;           // element offset of the REG register
 };
+
+enum { LOW_INTRA = 0, LOW_LANE = 1, LOW_REG = 2 };
+constexpr unsigned kLaneBits = 6;  // element bits held across the 64 lanes of a wave
+
+// Element-space layout of a SWEEP_LOW op for dtype dt: qubit kinds, lane bits,
+// inserted positions.  Returns false if the op does not fit the kernel (at
+// most one REG target or one fixed control).
+bool plan_low(sv_dtype dt, SweepArgs* a);
 
 hipError_t launch_sweep(sv_dtype dt, void* psi, int n, const SweepArgs& a, hipStream_t s);
 

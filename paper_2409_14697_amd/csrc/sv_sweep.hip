@@ -147,20 +147,220 @@ __global__ __launch_bounds__(kBlock) void k_group(E* __restrict__ psi, uint64_t 
   }
 }
 
+// ---------------------------------------------------------------- lane exchange
+// Gates with a qubit inside one wave's 1 KiB row (element bit < 6, or bit 0 of
+// a complex64 element pair).  A wave reads 64 consecutive 16-byte elements per
+// load instruction -- whole bursts, never a strided subset -- and the partner
+// amplitudes of such a qubit are fetched from the lane that holds them
+// (ds_bpermute).  Each lane computes its own amplitudes y = sum_s U[rho][s] x_s
+// with rho the lane's row of the gate matrix.  A matrix qubit is INTRA (the
+// other half of a complex64 pair), LANE (lane bit = element bit p < 6), or REG
+// (a high target held in a second register, loaded from +2^p).  The kinds are
+// template parameters, so sources and coefficients resolve at compile time
+// except for the lane's own LANE bits, which select among kernel-argument
+// coefficients.  High controls are fixed to 1 by the group geometry.
+enum { QK_NONE = -1, QK_INTRA = LOW_INTRA, QK_LANE = LOW_LANE, QK_REG = LOW_REG };
+
+template <int NZ>
+struct LowGeo {
+  unsigned z[NZ > 0 ? NZ : 1];  // element-space zero positions (ascending)
+  uint64_t set;                 // element-space bits fixed to 1
+  uint64_t off1;                // element offset of register 1
+  unsigned lanebit[2];          // lane bit of a LANE qubit
+};
+
+template <typename R, int K>
+struct LowMat {
+  cplx<R> u[(1 << K) * (1 << K)];
+};
+
+__device__ __forceinline__ dbl2 shfl_xor_e(dbl2 v, unsigned m) {
+  dbl2 r;
+  r.x = __shfl_xor(v.x, (int)m);
+  r.y = __shfl_xor(v.y, (int)m);
+  return r;
+}
+__device__ __forceinline__ flt4 shfl_xor_e(flt4 v, unsigned m) {
+  flt4 r;
+  r.x = __shfl_xor(v.x, (int)m);
+  r.y = __shfl_xor(v.y, (int)m);
+  r.z = __shfl_xor(v.z, (int)m);
+  r.w = __shfl_xor(v.w, (int)m);
+  return r;
+}
+
+template <typename E, int K, int KA, int KB, int NZ>
+__global__ __launch_bounds__(kBlock) void k_low(E* __restrict__ psi, uint64_t ngroups, LowGeo<NZ> g,
+                                                LowMat<typename elem_traits<E>::R, K> u) {
+  typedef elem_traits<E> TR;
+  typedef typename TR::R R;
+  constexpr int D = 1 << K;
+  constexpr int A = TR::amps;
+  constexpr int kinds[2] = {KA, KB};
+  constexpr int NV = (KA == QK_REG || (K == 2 && KB == QK_REG)) ? 2 : 1;
+  // LANE qubits, in matrix order
+  constexpr int NL = (KA == QK_LANE) + (K == 2 && KB == QK_LANE);
+  const uint64_t k = xcd_block() * (uint64_t)kBlock + threadIdx.x;
+  const bool active = k < ngroups;
+  uint64_t b = k;
+#pragma unroll
+  for (int z = 0; z < NZ; ++z) b = insert0(b, g.z[z]);
+  b |= g.set;
+  E x[NV];
+#pragma unroll
+  for (int r = 0; r < NV; ++r) {
+    E v = {};
+    if (active) v = ld(psi + b + (r ? g.off1 : 0ull));
+    x[r] = v;
+  }
+  const unsigned lane = threadIdx.x & 63u;
+  // lane-bit values of the LANE qubits packed in matrix order, and the xor
+  // masks that flip each subset of them
+  unsigned lv = 0, lmask[4] = {0, 0, 0, 0};
+  {
+    int j = 0;
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+      if (kinds[m] == QK_LANE) {
+        lv |= ((lane >> g.lanebit[m]) & 1u) << (NL - 1 - j);
+        ++j;
+      }
+#pragma unroll
+    for (int f = 0; f < (1 << NL); ++f) {
+      int jj = 0;
+#pragma unroll
+      for (int m = 0; m < K; ++m)
+        if (kinds[m] == QK_LANE) {
+          if ((f >> (NL - 1 - jj)) & 1) lmask[f] |= 1u << g.lanebit[m];
+          ++jj;
+        }
+    }
+  }
+  // registers as seen from the lane that differs in each subset of LANE bits
+  E xs[1 << NL][NV];
+#pragma unroll
+  for (int f = 0; f < (1 << NL); ++f)
+#pragma unroll
+    for (int r = 0; r < NV; ++r) xs[f][r] = f ? shfl_xor_e(x[r], lmask[f]) : x[r];
+  E out[NV];
+#pragma unroll
+  for (int r = 0; r < NV; ++r) {
+#pragma unroll
+    for (int h = 0; h < A; ++h) {
+      cplx<R> y = {0, 0};
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        int rs = r, hs = h, f = 0, jj = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+          const int bit = (d >> (K - 1 - m)) & 1;
+          if (kinds[m] == QK_REG) rs ^= bit;
+          else if (kinds[m] == QK_INTRA) hs ^= bit;
+          if (kinds[m] == QK_LANE) {
+            f |= bit << (NL - 1 - jj);
+            ++jj;
+          }
+        }
+        // coefficient U[rho][rho ^ d]; rho's LANE bits come from lv
+        cplx<R> c = {0, 0};
+#pragma unroll
+        for (int v = 0; v < (1 << NL); ++v) {
+          int rho = 0, j2 = 0;
+#pragma unroll
+          for (int m = 0; m < K; ++m) {
+            int bit;
+            if (kinds[m] == QK_REG) bit = r;
+            else if (kinds[m] == QK_INTRA) bit = h;
+            else {
+              bit = (v >> (NL - 1 - j2)) & 1;
+              ++j2;
+            }
+            rho |= bit << (K - 1 - m);
+          }
+          const cplx<R> cand = u.u[rho * D + (rho ^ d)];
+          if (v == 0 || lv == (unsigned)v) c = cand;
+        }
+        y = cfma(y, c, TR::get(xs[f][rs], hs));
+      }
+      TR::put(out[r], h, y);
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < NV; ++r) st(psi + b + (r ? g.off1 : 0ull), out[r]);
+  }
+}
+
 template <typename R>
 cplx<R> to_dev(cd x) {
   return cplx<R>{(R)x.real(), (R)x.imag()};
 }
 
+template <typename E, int K, int KA, int KB, int NZ>
+hipError_t run_low(void* psi, uint64_t ngroups, const LowGeo<NZ>& g, const cd* m, hipStream_t s) {
+  typedef typename elem_traits<E>::R R;
+  LowMat<R, K> u;
+  for (int i = 0; i < (1 << K) * (1 << K); ++i) u.u[i] = to_dev<R>(m[i]);
+  const uint64_t blocks = (ngroups + kBlock - 1) / kBlock;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_low<E, K, KA, KB, NZ>), dim3((unsigned)blocks), dim3(kBlock), 0, s, (E*)psi, ngroups, g,
+                     u);
+  return hipGetLastError();
+}
+
+template <typename E, int K, int KA, int KB>
+hipError_t run_low_nz(void* psi, uint64_t ngroups, int nz, const unsigned* zs, uint64_t set, uint64_t off1,
+                      const unsigned* lanebit, const cd* m, hipStream_t s) {
+  if (nz == 0) {
+    LowGeo<0> g{};
+    g.set = set; g.off1 = off1; g.lanebit[0] = lanebit[0]; g.lanebit[1] = lanebit[1];
+    return run_low<E, K, KA, KB, 0>(psi, ngroups, g, m, s);
+  }
+  LowGeo<1> g{};
+  g.z[0] = zs[0]; g.set = set; g.off1 = off1; g.lanebit[0] = lanebit[0]; g.lanebit[1] = lanebit[1];
+  return run_low<E, K, KA, KB, 1>(psi, ngroups, g, m, s);
+}
+
+// Instantiate the lane-exchange kernel for the layout plan_low() chose.
+template <typename E>
+hipError_t dispatch_low(void* psi, int n, const SweepArgs& a, hipStream_t s) {
+  constexpr bool pair = elem_traits<E>::amps == 2;
+  const int nbits = n - (pair ? 1 : 0);
+  const int K = a.low_k;
+  const int* kind = a.low_kind;
+  const int nz = a.low_nz;
+  const unsigned* zs = a.low_z;
+  const uint64_t set = a.low_set, off1 = a.low_off1;
+  const unsigned* lanebit = a.low_lanebit;
+  const uint64_t ngroups = 1ull << (nbits - nz);
+#define SV_LOW(KK, A_, B_) return run_low_nz<E, KK, A_, B_>(psi, ngroups, nz, zs, set, off1, lanebit, a.m, s)
+  if (K == 1) {
+    if (kind[0] == QK_LANE) SV_LOW(1, QK_LANE, QK_NONE);
+    if constexpr (pair) {
+      if (kind[0] == QK_INTRA) SV_LOW(1, QK_INTRA, QK_NONE);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (kind[0] == QK_LANE && kind[1] == QK_LANE) SV_LOW(2, QK_LANE, QK_LANE);
+  if (kind[0] == QK_LANE && kind[1] == QK_REG) SV_LOW(2, QK_LANE, QK_REG);
+  if (kind[0] == QK_REG && kind[1] == QK_LANE) SV_LOW(2, QK_REG, QK_LANE);
+  if constexpr (pair) {
+    if (kind[0] == QK_INTRA && kind[1] == QK_LANE) SV_LOW(2, QK_INTRA, QK_LANE);
+    if (kind[0] == QK_LANE && kind[1] == QK_INTRA) SV_LOW(2, QK_LANE, QK_INTRA);
+    if (kind[0] == QK_INTRA && kind[1] == QK_REG) SV_LOW(2, QK_INTRA, QK_REG);
+    if (kind[0] == QK_REG && kind[1] == QK_INTRA) SV_LOW(2, QK_REG, QK_INTRA);
+  }
+#undef SV_LOW
+  return hipErrorInvalidValue;
+}
+
 template <typename E, int NZ, int NV, class Op>
 hipError_t run(void* psi, uint64_t ngroups, const GroupSpec& gs, unsigned shift, const Op& op, hipStream_t s) {
-  constexpr int ITEMS = 1;
   Geo<NZ, NV> g;
   for (int z = 0; z < NZ; ++z) g.z[z] = gs.z[z] - shift;
   g.set = gs.set >> shift;
   for (int r = 0; r < NV; ++r) g.off[r] = gs.off[r] >> shift;
-  const uint64_t per_block = (uint64_t)kBlock * ITEMS;
-  const uint64_t blocks = (ngroups + per_block - 1) / per_block;
+  const uint64_t blocks = (ngroups + kBlock - 1) / kBlock;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL((k_group<E, NZ, NV, Op>), dim3((unsigned)blocks), dim3(kBlock), 0, s, (E*)psi, ngroups, g,
                      op);
@@ -210,6 +410,8 @@ hipError_t dispatch(void* psi, int n, const SweepArgs& a, hipStream_t s) {
       op.s = (R)a.m[0].real();
       return run<E, 0, 1>(psi, ngroups, gs, shift, op, s);
     }
+    default:
+      break;
   }
   return hipErrorInvalidValue;
 }
@@ -224,6 +426,7 @@ bool uses_bit0(const GroupSpec& g) {
 }  // namespace
 
 hipError_t launch_sweep(sv_dtype dt, void* psi, int n, const SweepArgs& a, hipStream_t s) {
+  if (a.op == SWEEP_LOW) return dt == SV_C128 ? dispatch_low<dbl2>(psi, n, a, s) : dispatch_low<flt4>(psi, n, a, s);
   if (dt == SV_C128) return dispatch<dbl2>(psi, n, a, s);
   if (n >= 1 && !uses_bit0(a.g)) return dispatch<flt4>(psi, n, a, s);
   return dispatch<flt2>(psi, n, a, s);
