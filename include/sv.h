@@ -167,7 +167,8 @@ sv_status sv_plan_info(const sv_plan *p, size_t *n_ops, size_t *n_passes);
 /* Export fused op `op` (0-based, in execution order) in logical qubits:
  *   *nq, q[0..nq-1] (q[0] = MSB of the local index), the 2^nq x 2^nq matrix
  *   into m (row-major interleaved FP64; caller buffer of 2*64*64 doubles) and
- *   the pass it runs in.  Replaying all ops in order reproduces the circuit. */
+ *   the pass it runs in (-1: a SWAP realised by relabeling qubits, no data
+ *   moves).  Replaying all ops in order reproduces the circuit. */
 sv_status sv_plan_export(const sv_plan *p, size_t op, int32_t *nq, int32_t q[SV_MAX_GATE_QUBITS],
                          double *m, int32_t *pass);
 

@@ -272,12 +272,7 @@ sv_status sv_plan_export(const sv_plan* p, size_t op, int32_t* nq, int32_t q[SV_
       m[2 * e] = o.m[e].real();
       m[2 * e + 1] = o.m[e].imag();
     }
-  if (pass) {
-    int32_t ps = -1;
-    for (size_t i = 0; i < p->passes.size(); ++i)
-      if ((int)op >= p->passes[i].first_op && (int)op < p->passes[i].first_op + p->passes[i].n_ops) ps = (int32_t)i;
-    *pass = ps;
-  }
+  if (pass) *pass = op < p->op_pass.size() ? (int32_t)p->op_pass[op] : -1;
   return SV_OK;
 }
 

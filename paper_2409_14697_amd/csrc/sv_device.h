@@ -38,6 +38,28 @@ __device__ __forceinline__ uint64_t insert0(uint64_t k, unsigned b) {
   return ((k >> b) << (b + 1)) | lo;
 }
 
+// Deposit the low bits of x into the set bits of mask, lowest first (the
+// PDEP-like index map of Sec. III-B, done with shifts and masks).
+__device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t mask) {
+  uint64_t r = 0;
+  while (mask) {
+    const uint64_t low = mask & (~mask + 1ull);
+    if (x & 1ull) r |= low;
+    x >>= 1;
+    mask &= mask - 1ull;
+  }
+  return r;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of an MI355X; this index
+// makes XCD x (blocks x, x+8, ...) own one contiguous range of work items.
+// Identity when the grid is not a multiple of 8.
+__device__ __forceinline__ uint64_t xcd_block() {
+  const uint64_t b = blockIdx.x, nb = gridDim.x;
+  if (nb % 8) return b;
+  return (b % 8) * (nb / 8) + b / 8;
+}
+
 // Memory element types: one load/store instruction moves one element.
 //   dbl2 : one complex128 amplitude (16 B)
 //   flt2 : one complex64 amplitude (8 B)

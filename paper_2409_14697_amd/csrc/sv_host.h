@@ -60,10 +60,24 @@ bool low_args_for(const Op& op, sv_dtype dt, SweepArgs* out);
 double touched_fraction(const Op& op);
 
 // ------------------------------------------------------------------ plan
+enum PassKind { PASS_SWEEP = 0, PASS_TILE = 1, PASS_DENSE = 2, PASS_PERMUTE = 3 };
+
+struct StageHost {
+  uint32_t q[kPassRegBits] = {0, 0, 0, 0};  // local bit of each register bit
+  std::vector<PassOpDev> ops;               // .mat indexes this stage's `mats`
+  std::vector<cd> mats;
+};
+
 struct Pass {
-  int kind = 0;  // 0 sweep, 1 LDS tile pass, 2 dense fused kernel, 3 permutation
-  int first_op = 0, n_ops = 0;
+  int kind = PASS_SWEEP;
+  int first_op = 0, n_ops = 0;  // ops (execution order) this pass implements
   int n_local = 0;
+  // PASS_SWEEP / PASS_DENSE: the op in physical qubits
+  Op phys;
+  // PASS_TILE / PASS_PERMUTE
+  uint32_t lpos[16] = {0};
+  uint32_t wpos[16] = {0};
+  std::vector<StageHost> stages;
 };
 
 }  // namespace sv
@@ -72,9 +86,11 @@ struct sv_plan {
   int n = 0;
   sv_dtype dt = SV_C128;
   sv_opts opts{};
-  std::vector<sv::Op> ops;
+  std::vector<sv::Op> ops;        // logical qubits, execution order
+  std::vector<int> op_pass;       // pass of each op
   std::vector<sv::Pass> passes;
   size_t n_gates_in = 0;
+  double est_cost = 0.0;          // planner's estimate, in full-state sweeps
 };
 
 struct sv_state {
@@ -107,5 +123,15 @@ sv_status upload(sv_state* s, const void* host, size_t bytes, void** dev);
 sv_status run_op_sweep(sv_state* s, const Op& op, const void* m_dev);
 // Plan building (host only).
 sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const sv_opts& o, sv_plan* p);
+// Greedy fusion of an op list (ops no wider than kmax qubits; kmax <= 1
+// merges only one-qubit ops on the same qubit).
+std::vector<Op> fuse_ops(std::vector<Op> in, int n, sv_dtype dt, int kmax, bool mfma);
+// In-cache pass planning of an op list (logical qubits) into p->passes/ops.
+sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const sv_opts& o, sv_plan* p);
+// Cost of one op run as its own sweep, in full read+write sweeps of the state.
+double op_sweep_cost(const Op& op, sv_dtype dt, bool mfma);
+// Tile size defaults.
+int default_lds_qubits(sv_dtype dt);
+int default_pinned_bits(sv_dtype dt);
 sv_status execute_plan(sv_state* s, const sv_plan* p);
 }  // namespace sv

@@ -1,0 +1,476 @@
+// In-cache pass planner: groups ops into tile passes whose local qubits fit
+// one LDS tile (QueenV2 Sec. III-A tier 4 "in-rank gate blocks", found
+// greedily like Queen's findGB while considering control qubits), splits each
+// pass into register stages, and keeps the bidirectional logical<->physical
+// qubit map of Sec. III-A (qubit reordering, Sec. II-B): SWAP gates become
+// relabelings, and the map is brought back to the identity by permutations
+// fused into tile write-backs.  Host only.
+#include <algorithm>
+#include <cstring>
+
+#include "sv_host.h"
+
+namespace sv {
+
+int default_lds_qubits(sv_dtype dt) { return dt == SV_C128 ? 12 : 13; }  // 64 KiB tiles
+int default_pinned_bits(sv_dtype dt) { return dt == SV_C128 ? 3 : 4; }   // 128-byte runs
+
+namespace {
+
+bool is_diag(const Op& op) { return classify(op) == CLS_DIAG; }
+
+// Qubits that must be local when the op runs inside a tile pass: none for a
+// diagonal op (its phase depends only on bit values, which every amplitude
+// knows from its index), the target for a CNOT (the control only selects),
+// all of them otherwise.
+int locality(const Op& op, int* q) {
+  if (is_diag(op)) return 0;
+  if (op.kind == SV_G_CNOT) {
+    q[0] = op.q[1];
+    return 1;
+  }
+  for (int i = 0; i < op.nq; ++i) q[i] = op.q[i];
+  return op.nq;
+}
+
+Op to_physical(const Op& op, const std::vector<int>& phys) {
+  Op r = op;
+  for (int i = 0; i < op.nq; ++i) r.q[i] = phys[op.q[i]];
+  return r;
+}
+
+// Arithmetic per amplitude of one op inside a pass (real flops).
+double op_flops(const PassOpDev& od) {
+  switch (od.type) {
+    case POP_U1: return 16.0;
+    case POP_U2: return 32.0;
+    case POP_D1: case POP_D2: case POP_DG: return 6.0;
+    default: return 1.0;
+  }
+}
+
+struct StageBuilder {
+  const int* loc;  // physical bit -> local bit, or -1
+  int m;
+  std::vector<int> qs;   // register bits (local indices), in register order
+  std::vector<Op> ops;   // physical qubits
+
+  int reg(int physq) const {
+    const int l = loc[physq];
+    if (l < 0) return -1;
+    for (size_t r = 0; r < qs.size(); ++r)
+      if (qs[r] == l) return (int)r;
+    return -1;
+  }
+  uint32_t src(int physq) const {
+    const int l = loc[physq];
+    return l >= 0 ? (uint32_t)l : kPassTileSel + (uint32_t)physq;
+  }
+  void predicate(PassOpDev* od, int physq) const {
+    const int l = loc[physq];
+    if (l >= 0) od->lmask |= 1u << l;
+    else od->tmask |= 1ull << physq;
+  }
+
+  void encode(StageHost* sh) {
+    // pad the register bits with the lowest unused local bits
+    for (int l = 0; (int)qs.size() < kPassRegBits && l < m; ++l)
+      if (std::find(qs.begin(), qs.end(), l) == qs.end()) qs.push_back(l);
+    for (int r = 0; r < kPassRegBits; ++r) sh->q[r] = (uint32_t)qs[r];
+    for (const Op& op : ops) {
+      PassOpDev od{};
+      od.sa = od.sb = kPassNoSel;
+      od.mat = (uint32_t)sh->mats.size();
+      std::vector<cd> mv;
+      const bool diag = is_diag(op);
+      if (op.nq == 1) {
+        const int q = op.q[0], b = reg(q);
+        if (diag) {
+          const cd d0 = op.m[0], d1 = op.m[3];
+          if (b >= 0) {
+            od.type = POP_D1;
+            od.b0 = (uint32_t)b;
+            mv = {d0, d1};
+          } else if (d0 == cd(1.0, 0.0)) {
+            od.type = POP_DG;
+            predicate(&od, q);
+            mv = {d1};
+          } else {
+            od.type = POP_DG;
+            od.sa = src(q);
+            mv = {d0, d1};
+          }
+        } else if (op.kind == SV_G_X) {
+          od.type = POP_X;
+          od.b0 = (uint32_t)b;
+        } else {
+          od.type = POP_U1;
+          od.b0 = (uint32_t)b;
+          mv.assign(op.m.begin(), op.m.begin() + 4);
+        }
+      } else if (op.kind == SV_G_CNOT) {
+        const int c = op.q[0], t = op.q[1];
+        const int bt = reg(t), bc = reg(c);
+        if (bc >= 0) {
+          od.type = POP_CX;
+          od.b0 = (uint32_t)bc;
+          od.b1 = (uint32_t)bt;
+        } else {
+          od.type = POP_X;
+          od.b0 = (uint32_t)bt;
+          predicate(&od, c);
+        }
+      } else if (diag) {
+        const cd d[4] = {op.m[0], op.m[5], op.m[10], op.m[15]};
+        const int q0 = op.q[0], q1 = op.q[1];
+        const int r0 = reg(q0), r1 = reg(q1);
+        const cd one(1.0, 0.0);
+        const bool cz_like = d[0] == one && d[1] == one && d[2] == one;
+        if (r0 >= 0 && r1 >= 0) {
+          od.type = POP_D2;
+          od.b0 = (uint32_t)r0;
+          od.b1 = (uint32_t)r1;
+          mv = {d[0], d[1], d[2], d[3]};
+        } else if (r0 >= 0) {
+          od.type = POP_D1;
+          od.b0 = (uint32_t)r0;
+          if (cz_like) {
+            predicate(&od, q1);
+            mv = {one, d[3]};
+          } else {
+            od.sa = src(q1);  // variant = bit of q1
+            mv = {d[0], d[2], d[1], d[3]};
+          }
+        } else if (r1 >= 0) {
+          od.type = POP_D1;
+          od.b0 = (uint32_t)r1;
+          if (cz_like) {
+            predicate(&od, q0);
+            mv = {one, d[3]};
+          } else {
+            od.sa = src(q0);  // variant = bit of q0
+            mv = {d[0], d[1], d[2], d[3]};
+          }
+        } else {
+          od.type = POP_DG;
+          if (cz_like) {
+            predicate(&od, q0);
+            predicate(&od, q1);
+            mv = {d[3]};
+          } else {
+            od.sa = src(q0);
+            od.sb = src(q1);
+            mv = {d[0], d[1], d[2], d[3]};
+          }
+        }
+      } else {
+        od.type = POP_U2;
+        od.b0 = (uint32_t)reg(op.q[0]);
+        od.b1 = (uint32_t)reg(op.q[1]);
+        mv.assign(op.m.begin(), op.m.begin() + 16);
+      }
+      sh->mats.insert(sh->mats.end(), mv.begin(), mv.end());
+      sh->ops.push_back(od);
+    }
+  }
+};
+
+// Split the ops of one pass (physical qubits, program order) into stages of at
+// most kPassRegBits register bits.
+std::vector<StageHost> build_stages(const std::vector<Op>& ops, const int* loc, int m) {
+  std::vector<StageHost> out;
+  StageBuilder sb{loc, m, {}, {}};
+  for (const Op& op : ops) {
+    int q[SV_MAX_GATE_QUBITS];
+    const int k = locality(op, q);
+    std::vector<int> need;
+    for (int i = 0; i < k; ++i) {
+      const int l = loc[q[i]];
+      if (std::find(sb.qs.begin(), sb.qs.end(), l) == sb.qs.end() &&
+          std::find(need.begin(), need.end(), l) == need.end())
+        need.push_back(l);
+    }
+    if (sb.qs.size() + need.size() > (size_t)kPassRegBits) {
+      StageHost sh;
+      sb.encode(&sh);
+      out.push_back(std::move(sh));
+      sb.qs.clear();
+      sb.ops.clear();
+      need.clear();
+      for (int i = 0; i < k; ++i)
+        if (std::find(need.begin(), need.end(), loc[q[i]]) == need.end()) need.push_back(loc[q[i]]);
+    }
+    sb.qs.insert(sb.qs.end(), need.begin(), need.end());
+    sb.ops.push_back(op);
+  }
+  if (!sb.ops.empty()) {
+    StageHost sh;
+    sb.encode(&sh);
+    out.push_back(std::move(sh));
+  }
+  return out;
+}
+
+struct QubitMap {
+  std::vector<int> phys, logi;  // logical -> physical, physical -> logical
+  explicit QubitMap(int n) : phys(n), logi(n) {
+    for (int i = 0; i < n; ++i) phys[i] = logi[i] = i;
+  }
+  void relabel_swap(int a, int b) {
+    std::swap(phys[a], phys[b]);
+    logi[phys[a]] = a;
+    logi[phys[b]] = b;
+  }
+  bool identity() const {
+    for (size_t i = 0; i < phys.size(); ++i)
+      if (phys[i] != (int)i) return false;
+    return true;
+  }
+};
+
+// Fill a tile's local set up to m bits, lowest unused positions first (longest
+// contiguous runs), after the bits in `prefer`.
+void fill_local(std::vector<char>& in, int& count, int m, int n, const std::vector<int>& prefer) {
+  for (int b : prefer)
+    if (count < m && !in[b]) {
+      in[b] = 1;
+      ++count;
+    }
+  for (int b = 0; b < n && count < m; ++b)
+    if (!in[b]) {
+      in[b] = 1;
+      ++count;
+    }
+}
+
+// Cycles of the misplaced physical positions: data at x belongs at logi[x].
+std::vector<std::vector<int>> cycles_of(const QubitMap& mp) {
+  const int n = (int)mp.logi.size();
+  std::vector<char> seen(n, 0);
+  std::vector<std::vector<int>> cyc;
+  for (int x = 0; x < n; ++x) {
+    if (seen[x] || mp.logi[x] == x) continue;
+    std::vector<int> c;
+    for (int y = x; !seen[y]; y = mp.logi[y]) {
+      seen[y] = 1;
+      c.push_back(y);
+    }
+    cyc.push_back(c);
+  }
+  return cyc;
+}
+
+}  // namespace
+
+sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const sv_opts& o, sv_plan* p) {
+  int m = o.lds_qubits ? o.lds_qubits : default_lds_qubits(dt);
+  const int m_max = dt == SV_C128 ? 13 : 14;  // 128 KiB of the 160 KiB LDS
+  if (m > m_max) return fail(SV_ERR_ARG, "lds_qubits %d exceeds %d for this dtype", m, m_max);
+  if (m > n) m = n;
+  if (m <= kPassRegBits) return fail(SV_ERR_ARG, "tile of %d qubits is too small for %d register bits", m, kPassRegBits);
+  int pin = o.pinned_low_bits ? o.pinned_low_bits : default_pinned_bits(dt);
+  pin = std::min(pin, m - 2);
+  const bool reorder = o.reorder != 0;
+  const double flop_scale = dt == SV_C128 ? 314.0 : 157.0;  // flops/amp that take one sweep's time
+  const double stage_cost = 0.1;                              // LDS round trip of a tile, in sweeps
+
+  p->ops.clear();
+  p->op_pass.clear();
+  p->passes.clear();
+  p->est_cost = 0.0;
+  QubitMap mp(n);
+  std::vector<char> done(ops.size(), 0);
+  size_t first = 0;
+  auto emit_op = [&](const Op& op, int pass) {
+    p->ops.push_back(op);
+    p->op_pass.push_back(pass);
+  };
+
+  while (true) {
+    while (first < ops.size() && done[first]) ++first;
+    if (first == ops.size()) break;
+    const Op& head = ops[first];
+    if (reorder && head.kind == SV_G_SWAP) {  // relabel: no data moves
+      mp.relabel_swap(head.q[0], head.q[1]);
+      emit_op(head, -1);
+      done[first] = 1;
+      continue;
+    }
+    if (head.nq >= 3) {  // dense op: its own sweep
+      Pass ps;
+      ps.kind = PASS_DENSE;
+      ps.first_op = (int)p->ops.size();
+      ps.n_ops = 1;
+      ps.phys = to_physical(head, mp.phys);
+      emit_op(head, (int)p->passes.size());
+      p->est_cost += op_sweep_cost(head, dt, dt == SV_C64 && o.fp32_mfma);
+      p->passes.push_back(std::move(ps));
+      done[first] = 1;
+      continue;
+    }
+    // ---- one tile pass: gate-block search over the remaining ops
+    std::vector<char> in_l(n, 0), blocked(n, 0);
+    int count = 0;
+    for (int b = 0; b < pin; ++b) {
+      in_l[b] = 1;
+      ++count;
+    }
+    int n_blocked = 0;
+    std::vector<Op> members;  // physical qubits
+    const int pass_id = (int)p->passes.size();
+    const int first_op = (int)p->ops.size();
+    for (size_t j = first; j < ops.size() && n_blocked < n; ++j) {
+      if (done[j]) continue;
+      const Op& op = ops[j];
+      bool blk = op.nq >= 3;
+      for (int i = 0; i < op.nq; ++i) blk = blk || blocked[op.q[i]];
+      if (!blk && reorder && op.kind == SV_G_SWAP) {
+        mp.relabel_swap(op.q[0], op.q[1]);
+        emit_op(op, -1);
+        done[j] = 1;
+        continue;
+      }
+      if (!blk) {
+        int q[SV_MAX_GATE_QUBITS];
+        const int k = locality(op, q);
+        int extra = 0;
+        for (int i = 0; i < k; ++i) extra += in_l[mp.phys[q[i]]] ? 0 : 1;
+        if (count + extra <= m) {
+          for (int i = 0; i < k; ++i)
+            if (!in_l[mp.phys[q[i]]]) {
+              in_l[mp.phys[q[i]]] = 1;
+              ++count;
+            }
+          members.push_back(to_physical(op, mp.phys));
+          emit_op(op, pass_id);
+          done[j] = 1;
+          continue;
+        }
+      }
+      // deferred: every later op on these qubits must wait too
+      for (int i = 0; i < op.nq; ++i)
+        if (!blocked[op.q[i]]) {
+          blocked[op.q[i]] = 1;
+          ++n_blocked;
+        }
+    }
+    bool last = true;
+    for (size_t j = first; j < ops.size(); ++j) last = last && done[j];
+    // the last pass also takes the bits whose data must move back home
+    std::vector<int> prefer;
+    if (last && !mp.identity()) {
+      int room = m - count;
+      for (const auto& c : cycles_of(mp)) {
+        int extra = 0;
+        for (int x : c) extra += in_l[x] ? 0 : 1;
+        if (extra > room) continue;
+        room -= extra;
+        prefer.insert(prefer.end(), c.begin(), c.end());
+      }
+    }
+    fill_local(in_l, count, m, n, prefer);
+    Pass ps;
+    ps.kind = PASS_TILE;
+    ps.first_op = first_op;
+    ps.n_ops = (int)members.size();
+    ps.n_local = m;
+    int loc[64];
+    for (int b = 0; b < 64; ++b) loc[b] = -1;
+    int j = 0;
+    for (int b = 0; b < n; ++b)
+      if (in_l[b]) {
+        ps.lpos[j] = ps.wpos[j] = (uint32_t)b;
+        loc[b] = j++;
+      }
+    ps.stages = build_stages(members, loc, m);
+    // write-back: complete cycles of the map that lie inside the tile go home
+    if (last && !mp.identity()) {
+      for (const auto& c : cycles_of(mp)) {
+        bool inside = true;
+        for (int x : c) inside = inside && in_l[x];
+        if (!inside) continue;
+        for (int x : c) ps.wpos[loc[x]] = (uint32_t)mp.logi[x];
+      }
+      QubitMap nm = mp;
+      for (int jj = 0; jj < m; ++jj) {
+        const int l = mp.logi[ps.lpos[jj]];
+        nm.phys[l] = (int)ps.wpos[jj];
+        nm.logi[ps.wpos[jj]] = l;
+      }
+      mp = nm;
+    }
+    double alu = stage_cost * (double)ps.stages.size();
+    for (const StageHost& sh : ps.stages)
+      for (const PassOpDev& od : sh.ops) alu += op_flops(od) / flop_scale;
+    p->est_cost += std::max(1.0, alu);
+    p->passes.push_back(std::move(ps));
+  }
+
+  // ---- restore the logical order: permutation-only passes
+  while (!mp.identity()) {
+    std::vector<char> in_l(n, 0);
+    int count = 0;
+    for (int b = 0; b < pin; ++b) {
+      in_l[b] = 1;
+      ++count;
+    }
+    Pass ps;
+    ps.kind = PASS_PERMUTE;
+    ps.first_op = (int)p->ops.size();
+    ps.n_ops = 0;
+    ps.n_local = m;
+    // choose cycles (or a segment of one) that fit
+    std::vector<std::pair<int, int>> moves;  // (from, to)
+    for (const auto& c : cycles_of(mp)) {
+      int extra = 0;
+      for (int x : c) extra += in_l[x] ? 0 : 1;
+      if (count + extra <= m) {
+        for (int x : c) {
+          if (!in_l[x]) {
+            in_l[x] = 1;
+            ++count;
+          }
+          moves.push_back({x, mp.logi[x]});
+        }
+      } else if (moves.empty()) {
+        // segment x1..xc of a long cycle: x_i -> x_{i+1}, x_c -> x1
+        std::vector<int> seg;
+        for (int x : c) {
+          const int add = in_l[x] ? 0 : 1;
+          if (count + add > m) break;
+          if (add) {
+            in_l[x] = 1;
+            ++count;
+          }
+          seg.push_back(x);
+        }
+        if (seg.size() < 2) return fail(SV_ERR_UNSUPPORTED, "tile too small to restore the qubit order");
+        for (size_t i = 0; i + 1 < seg.size(); ++i) moves.push_back({seg[i], seg[i + 1]});
+        moves.push_back({seg.back(), seg[0]});
+        break;
+      }
+    }
+    fill_local(in_l, count, m, n, {});
+    int loc[64];
+    for (int b = 0; b < 64; ++b) loc[b] = -1;
+    int j = 0;
+    for (int b = 0; b < n; ++b)
+      if (in_l[b]) {
+        ps.lpos[j] = ps.wpos[j] = (uint32_t)b;
+        loc[b] = j++;
+      }
+    for (const auto& mv : moves) ps.wpos[loc[mv.first]] = (uint32_t)mv.second;
+    QubitMap nm = mp;
+    for (int jj = 0; jj < m; ++jj) {
+      const int l = mp.logi[ps.lpos[jj]];
+      nm.phys[l] = (int)ps.wpos[jj];
+      nm.logi[ps.wpos[jj]] = l;
+    }
+    mp = nm;
+    p->est_cost += 1.0;
+    p->passes.push_back(std::move(ps));
+  }
+  return SV_OK;
+}
+
+}  // namespace sv

@@ -100,88 +100,198 @@ int union_size(const Op& a, const Op& b) {
 
 }  // namespace
 
+std::vector<Op> fuse_ops(std::vector<Op> in, int n, sv_dtype dt, int kmax, bool mfma) {
+  std::vector<Op> out;
+  out.reserve(in.size());
+  std::vector<int> last(n, -1);  // index of the last op touching each qubit
+  const int width = kmax < 1 ? 0 : kmax;
+  for (Op& op : in) {
+    int cand = -1;
+    for (int j = 0; j < op.nq; ++j) cand = std::max(cand, last[op.q[j]]);
+    // Every op after `cand` shares no qubit with this one, so it may be moved
+    // up to just after `cand` and fused into it.
+    if (width >= 1 && cand >= 0 && union_size(out[cand], op) <= width &&
+        !(op.kind == SV_G_SWAP && width < 2)) {
+      Op& prev = out[cand];
+      Op m = merged(prev, op);
+      if (sweep_cost(m, dt, mfma) <= sweep_cost(prev, dt, mfma) + sweep_cost(op, dt, mfma) + 1e-12) {
+        prev = std::move(m);
+        // only this op's qubits move to `cand`; the other qubits of the fused
+        // op may already have later users
+        for (int j = 0; j < op.nq; ++j) last[op.q[j]] = cand;
+        continue;
+      }
+    }
+    out.push_back(std::move(op));
+    const int idx = (int)out.size() - 1;
+    for (int j = 0; j < out.back().nq; ++j) last[out.back().q[j]] = idx;
+  }
+  return out;
+}
+
+double op_sweep_cost(const Op& op, sv_dtype dt, bool mfma) { return sweep_cost(op, dt, mfma); }
+
 sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const sv_opts& o, sv_plan* p) {
   p->n = n;
   p->dt = dt;
   p->opts = o;
   p->n_gates_in = n_gates;
   p->ops.clear();
+  p->op_pass.clear();
   p->passes.clear();
-  const int kmax = o.max_fuse_qubits;
   const bool mfma = dt == SV_C64 && o.fp32_mfma;
-  std::vector<int> last(n, -1);  // index of the last op touching each qubit
-  for (size_t i = 0; i < n_gates; ++i) {
-    Op op = op_from_gate(g[i]);
-    int cand = -1;
-    for (int j = 0; j < op.nq; ++j) cand = std::max(cand, last[op.q[j]]);
-    // Every op after `cand` shares no qubit with this gate, so the gate may be
-    // moved up to just after `cand` and fused into it.
-    if (kmax >= 2 && cand >= 0 && union_size(p->ops[cand], op) <= kmax) {
-      Op& prev = p->ops[cand];
-      Op m = merged(prev, op);
-      if (sweep_cost(m, dt, mfma) <= sweep_cost(prev, dt, mfma) + sweep_cost(op, dt, mfma) + 1e-12) {
-        prev = std::move(m);
-        // only the gate's qubits move to `cand`; the other qubits of the fused
-        // op may already have later users
-        for (int j = 0; j < op.nq; ++j) last[op.q[j]] = cand;
-        continue;
-      }
+  std::vector<Op> raw;
+  raw.reserve(n_gates);
+  for (size_t i = 0; i < n_gates; ++i) raw.push_back(op_from_gate(g[i]));
+
+  // in-cache passes need a tile of at least 2^(register bits + 1) amplitudes
+  const bool tiles_ok = n > kPassRegBits;
+  if (o.mode != SV_MODE_SWEEP && tiles_ok) {
+    sv_plan tp;
+    tp.n = n;
+    tp.dt = dt;
+    tp.opts = o;
+    std::vector<Op> light = fuse_ops(raw, n, dt, std::min(o.max_fuse_qubits, 1), mfma);
+    sv_status st = plan_tile_passes(light, n, dt, o, &tp);
+    if (st != SV_OK) return st;
+    if (o.mode == SV_MODE_PASS) {
+      p->ops = std::move(tp.ops);
+      p->op_pass = std::move(tp.op_pass);
+      p->passes = std::move(tp.passes);
+      p->est_cost = tp.est_cost;
+      return SV_OK;
     }
-    p->ops.push_back(std::move(op));
-    const int idx = (int)p->ops.size() - 1;
-    for (int j = 0; j < p->ops.back().nq; ++j) last[p->ops.back().q[j]] = idx;
+    // SV_MODE_AUTO: keep the tile plan unless one-sweep-per-op is cheaper
+    std::vector<Op> fused = fuse_ops(raw, n, dt, o.max_fuse_qubits, mfma);
+    double sweep_total = 0.0;
+    for (const Op& op : fused) sweep_total += sweep_cost(op, dt, mfma);
+    if (tp.est_cost <= sweep_total) {
+      p->ops = std::move(tp.ops);
+      p->op_pass = std::move(tp.op_pass);
+      p->passes = std::move(tp.passes);
+      p->est_cost = tp.est_cost;
+      return SV_OK;
+    }
+    p->ops = std::move(fused);
+  } else {
+    p->ops = fuse_ops(raw, n, dt, o.max_fuse_qubits, mfma);
   }
-  // One sweep per op.
+  // one sweep per op
+  p->est_cost = 0.0;
   for (size_t i = 0; i < p->ops.size(); ++i) {
     Pass ps;
-    ps.kind = p->ops[i].nq >= 3 ? 2 : 0;
+    ps.kind = p->ops[i].nq >= 3 ? PASS_DENSE : PASS_SWEEP;
     ps.first_op = (int)i;
     ps.n_ops = 1;
-    p->passes.push_back(ps);
+    ps.phys = p->ops[i];
+    p->passes.push_back(std::move(ps));
+    p->op_pass.push_back((int)i);
+    p->est_cost += sweep_cost(p->ops[i], dt, mfma);
   }
   return SV_OK;
 }
 
 sv_status execute_plan(sv_state* s, const sv_plan* p) {
-  // Upload every matrix a dense kernel reads, in the state's precision, in one copy.
-  std::vector<size_t> offs(p->ops.size(), 0);
-  size_t total = 0;
   const bool f32 = s->dt == SV_C64;
   const size_t scal = f32 ? sizeof(float) : sizeof(double);
-  for (size_t i = 0; i < p->ops.size(); ++i) {
-    if (p->ops[i].nq >= 3) {
-      offs[i] = total;
-      total += p->ops[i].m.size() * 2 * scal;
-      total = (total + 255) & ~(size_t)255;
-    }
-  }
-  void* dev = nullptr;
-  if (total) {
-    std::vector<unsigned char> host(total);
-    for (size_t i = 0; i < p->ops.size(); ++i) {
-      if (p->ops[i].nq < 3) continue;
-      const std::vector<cd>& m = p->ops[i].m;
+  // One upload: dense matrices (state precision), then the tile-pass program.
+  std::vector<unsigned char> host;
+  auto align = [&](size_t a) { host.resize((host.size() + a - 1) / a * a); };
+  auto put_cd = [&](const cd* m, size_t count) {
+    const size_t at = host.size();
+    host.resize(at + count * 2 * scal);
+    for (size_t e = 0; e < count; ++e) {
       if (f32) {
-        float* dst = (float*)(host.data() + offs[i]);
-        for (size_t e = 0; e < m.size(); ++e) {
-          dst[2 * e] = (float)m[e].real();
-          dst[2 * e + 1] = (float)m[e].imag();
-        }
+        float* d = (float*)(host.data() + at);
+        d[2 * e] = (float)m[e].real();
+        d[2 * e + 1] = (float)m[e].imag();
       } else {
-        double* dst = (double*)(host.data() + offs[i]);
-        for (size_t e = 0; e < m.size(); ++e) {
-          dst[2 * e] = m[e].real();
-          dst[2 * e + 1] = m[e].imag();
-        }
+        double* d = (double*)(host.data() + at);
+        d[2 * e] = m[e].real();
+        d[2 * e + 1] = m[e].imag();
       }
     }
-    sv_status st = upload(s, host.data(), total, &dev);
+    return at;
+  };
+  std::vector<size_t> dense_off(p->passes.size(), 0);
+  std::vector<int> desc_index(p->passes.size(), -1);
+  std::vector<PassDescDev> descs;
+  std::vector<PassStageDev> stages;
+  std::vector<PassOpDev> pops;
+  std::vector<cd> pool;
+  for (size_t i = 0; i < p->passes.size(); ++i) {
+    const Pass& ps = p->passes[i];
+    if (ps.kind == PASS_DENSE) {
+      align(256);
+      dense_off[i] = put_cd(ps.phys.m.data(), ps.phys.m.size());
+    } else if (ps.kind == PASS_TILE || ps.kind == PASS_PERMUTE) {
+      PassDescDev d{};
+      d.m = (uint32_t)ps.n_local;
+      d.stage_first = (uint32_t)stages.size();
+      d.stage_count = (uint32_t)ps.stages.size();
+      d.lmask = 0;
+      for (int j = 0; j < ps.n_local; ++j) {
+        d.lpos[j] = ps.lpos[j];
+        d.wpos[j] = ps.wpos[j];
+        d.lmask |= 1ull << ps.lpos[j];
+      }
+      for (const StageHost& sh : ps.stages) {
+        PassStageDev sd{};
+        for (int r = 0; r < kPassRegBits; ++r) sd.q[r] = sh.q[r];
+        uint32_t srt[kPassRegBits];
+        for (int r = 0; r < kPassRegBits; ++r) srt[r] = sh.q[r];
+        std::sort(srt, srt + kPassRegBits);
+        for (int r = 0; r < kPassRegBits; ++r) sd.qsort[r] = srt[r];
+        sd.op_first = (uint32_t)pops.size();
+        sd.op_count = (uint32_t)sh.ops.size();
+        const uint32_t mbase = (uint32_t)pool.size();
+        for (PassOpDev od : sh.ops) {
+          od.mat += mbase;
+          pops.push_back(od);
+        }
+        pool.insert(pool.end(), sh.mats.begin(), sh.mats.end());
+        stages.push_back(sd);
+      }
+      desc_index[i] = (int)descs.size();
+      descs.push_back(d);
+    }
+  }
+  size_t off_desc = 0, off_stage = 0, off_ops = 0, off_pool = 0;
+  if (!descs.empty()) {
+    align(256);
+    off_desc = host.size();
+    host.insert(host.end(), (const unsigned char*)descs.data(),
+                (const unsigned char*)(descs.data() + descs.size()));
+    align(256);
+    off_stage = host.size();
+    host.insert(host.end(), (const unsigned char*)stages.data(),
+                (const unsigned char*)(stages.data() + stages.size()));
+    align(256);
+    off_ops = host.size();
+    host.insert(host.end(), (const unsigned char*)pops.data(), (const unsigned char*)(pops.data() + pops.size()));
+    align(256);
+    off_pool = pool.empty() ? host.size() : put_cd(pool.data(), pool.size());
+  }
+  void* dev = nullptr;
+  if (!host.empty()) {
+    align(256);
+    sv_status st = upload(s, host.data(), host.size(), &dev);
     if (st != SV_OK) return st;
   }
-  for (size_t i = 0; i < p->ops.size(); ++i) {
-    const void* mdev = p->ops[i].nq >= 3 ? (const void*)((const unsigned char*)dev + offs[i]) : nullptr;
-    sv_status st = run_op_sweep(s, p->ops[i], mdev);
-    if (st != SV_OK) return st;
+  unsigned char* db = (unsigned char*)dev;
+  for (size_t i = 0; i < p->passes.size(); ++i) {
+    const Pass& ps = p->passes[i];
+    if (ps.kind == PASS_SWEEP) {
+      sv_status st = run_op_sweep(s, ps.phys, nullptr);
+      if (st != SV_OK) return st;
+    } else if (ps.kind == PASS_DENSE) {
+      sv_status st = run_op_sweep(s, ps.phys, db + dense_off[i]);
+      if (st != SV_OK) return st;
+    } else {
+      SV_HIP_TRY(launch_pass(s->dt, s->ptr, s->n, ps.n_local, (const PassDescDev*)(db + off_desc), desc_index[i],
+                             (const PassStageDev*)(db + off_stage), (const PassOpDev*)(db + off_ops),
+                             db + off_pool, s->stream));
+    }
   }
   return SV_OK;
 }

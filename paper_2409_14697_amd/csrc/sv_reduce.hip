@@ -33,17 +33,6 @@ struct ProbGeo {
   int qpos[SV_MAX_QUBITS];  // qubits[r]
 };
 
-// deposit the low bits of x into the set bits of mask (ascending)
-__device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t mask) {
-  uint64_t r = 0;
-  while (mask) {
-    const uint64_t low = mask & (~mask + 1ull);
-    if (x & 1ull) r |= low;
-    x >>= 1;
-    mask &= mask - 1ull;
-  }
-  return r;
-}
 
 __device__ __forceinline__ double absq(dbl2 v) { return v.x * v.x + v.y * v.y; }
 __device__ __forceinline__ double absq(flt2 v) {

@@ -25,15 +25,6 @@ namespace sv {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kXcds = 8;
-
-// Block index remapped so that XCD x (blocks x, x+8, ...) owns a contiguous
-// range; identity when the grid is not a multiple of the XCD count.
-__device__ __forceinline__ uint64_t xcd_block() {
-  const uint64_t b = blockIdx.x, nb = gridDim.x;
-  if (nb % kXcds) return b;
-  return (b % kXcds) * (nb / kXcds) + b / kXcds;
-}
 
 template <int NZ, int NV>
 struct Geo {

@@ -92,9 +92,54 @@ def test_fusion_plan_replays_circuit(kmax, dtype):
 
 def test_fusion_reduces_ops():
     gates = brickwork_circuit(12, 6, seed=3)
-    n5 = B.Plan(12, "c128", gates, {"max_fuse_qubits": 5}).info()[0]
-    n0 = B.Plan(12, "c128", gates, {"max_fuse_qubits": 0}).info()[0]
+    n5 = B.Plan(12, "c128", gates, {"max_fuse_qubits": 5, "mode": "sweep"}).info()[0]
+    n0 = B.Plan(12, "c128", gates, {"max_fuse_qubits": 0, "mode": "sweep"}).info()[0]
     assert n0 == len(gates) and n5 < n0 / 3
+
+
+CIRCUITS = {
+    "layered": lambda n: layered_circuit(n, n_gates=160, seed=1),
+    "brickwork": lambda n: brickwork_circuit(n, 8, seed=3),
+    "qft": lambda n: qft_circuit(n),
+    "haar": lambda n: fused_haar_circuit(n, 5, seed=4, ks=(2, 3, 5)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CIRCUITS))
+@pytest.mark.parametrize("mode", ["pass", "auto", "sweep"])
+@pytest.mark.parametrize("lds", [0, 6, 9])
+def test_pass_plans_replay_circuit(name, mode, lds):
+    n = 12
+    gates = CIRCUITS[name](n)
+    plan = B.Plan(n, "c64", gates, {"mode": mode, "lds_qubits": lds})
+    psi = gaussian_state_np(n, 8)
+    assert np.max(np.abs(_replay(plan, n, psi) - oracle.run(gates, psi0=psi))) < 1e-13
+    n_ops, n_passes = plan.info()
+    passes = plan.passes()
+    assert len(passes) == n_passes
+    for kind, nops, nloc in passes:
+        assert kind in (0, 1, 2, 3)
+        if kind in (1, 3):
+            assert nloc == (lds or 12) or nloc == n
+
+
+def test_qft_swaps_become_relabels():
+    n = 14
+    plan = B.Plan(n, "c128", qft_circuit(n), {"mode": "pass", "lds_qubits": 8})
+    ex = plan.export()
+    swaps = [ps for q, m, ps in ex if len(q) == 2 and np.array_equal(m, so.named_matrix("SWAP"))]
+    assert len(swaps) == n // 2 and all(ps == -1 for ps in swaps)
+    kinds = [k for k, _, _ in plan.passes()]
+    assert 3 in kinds  # logical order restored by permutation-only passes
+    assert kinds.count(1) <= 4
+
+
+def test_pass_plan_needs_few_passes_for_diagonal_ladders():
+    # controlled phases need no locality: the QFT's passes are set by its H gates
+    n = 20
+    plan = B.Plan(n, "c64", qft_circuit(n), {"mode": "pass"})
+    kinds = [k for k, _, _ in plan.passes()]
+    assert kinds.count(1) <= 2
 
 
 def test_fusion_qft_and_haar():

@@ -1,0 +1,107 @@
+"""GPU parity of the in-cache tile passes (LDS stages, qubit relabeling, fused
+write-back permutations) and of the plan modes, against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from svgen import Gate, basis_state_np, brickwork_circuit, gaussian_state_np, layered_circuit, qft_circuit
+from tests.gpu_util import TOL, max_err, to_device, to_host
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = ["c128", "c64"]
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import paper_2409_14697_amd as sv
+    return sv
+
+
+def mixed_circuit(n, count, seed):
+    """Every gate kind, random qubits (controls and phase bits anywhere)."""
+    rng = np.random.default_rng(seed)
+    kinds1 = ["H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "P"]
+    kinds2 = ["CNOT", "CZ", "SWAP", "CPHASE", "RZZ"]
+    out = []
+    for _ in range(count):
+        if rng.random() < 0.5:
+            out.append(Gate(kinds1[int(rng.integers(len(kinds1)))], (int(rng.integers(n)),),
+                            float(rng.uniform(0, 2 * math.pi))))
+        else:
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            out.append(Gate(kinds2[int(rng.integers(len(kinds2)))], (a, b), float(rng.uniform(0, 2 * math.pi))))
+    return out
+
+
+def run_plan(sv, n, dtype, psi, gates, opts):
+    t, host_in = to_device(psi, dtype)
+    st = sv.StateVector(n, dtype, tensor=t, init=False)
+    st.apply_circuit(gates, opts)
+    st.sync()
+    out = to_host(t)
+    st.close()
+    return out, oracle.run(gates, psi0=host_in)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("lds", [0, 6, 9])
+@pytest.mark.parametrize("circuit", ["mixed", "layered", "brickwork", "qft"])
+def test_pass_mode_circuits(sv, dtype, lds, circuit):
+    n = 14
+    gates = {"mixed": lambda: mixed_circuit(n, 300, 7),
+             "layered": lambda: layered_circuit(n, n_gates=200, seed=1),
+             "brickwork": lambda: brickwork_circuit(n, 10, seed=3),
+             "qft": lambda: qft_circuit(n)}[circuit]()
+    out, ref = run_plan(sv, n, dtype, gaussian_state_np(n, 21), gates, {"mode": "pass", "lds_qubits": lds})
+    assert max_err(out, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_pass_whole_state_tile(sv, dtype):
+    """N at or below the tile size: one tile holds the whole state."""
+    for n in (5, 9, 12):
+        gates = mixed_circuit(n, 120, n)
+        out, ref = run_plan(sv, n, dtype, gaussian_state_np(n, 2), gates, {"mode": "pass"})
+        assert max_err(out, ref) <= TOL[dtype], n
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_pass_permutation_exact(sv, dtype):
+    """Only X, CNOT and SWAP: permutations of amplitudes, bitwise exact."""
+    n = 15
+    rng = np.random.default_rng(5)
+    gates = []
+    for _ in range(200):
+        k = int(rng.integers(3))
+        if k == 0:
+            gates.append(Gate("X", (int(rng.integers(n)),)))
+        else:
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            gates.append(Gate("CNOT" if k == 1 else "SWAP", (a, b)))
+    out, ref = run_plan(sv, n, dtype, gaussian_state_np(n, 3), gates, {"mode": "pass", "lds_qubits": 8})
+    assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_qft_pass_mode_n20(sv, dtype):
+    n = 20
+    psi = gaussian_state_np(n, 9)
+    t, host_in = to_device(psi, dtype)
+    st = sv.StateVector(n, dtype, tensor=t, init=False)
+    st.apply_circuit(qft_circuit(n), {"mode": "pass"})
+    st.sync()
+    ref = math.sqrt(1 << n) * np.fft.ifft(host_in)
+    assert max_err(to_host(t), ref) <= TOL[dtype]
+    st.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("mode", ["auto", "sweep", "pass"])
+def test_modes_agree_layered_n16(sv, dtype, mode):
+    n = 16
+    gates = layered_circuit(n, n_gates=200, seed=1)
+    out, ref = run_plan(sv, n, dtype, basis_state_np(n, 0), gates, {"mode": mode})
+    assert max_err(out, ref) <= TOL[dtype]
