@@ -129,6 +129,69 @@ def cpu_baseline(gates, n: int):
             "sample": f"{len(sample)} gates of the set ({desc}) at N={n}, complex128, {total_t:.1f} s"}
 
 
+def circuit_bench(args):
+    """Circuit benchmark: N=32 complex64 (32 GiB) random brickwork circuit of
+    depth 40 (1900 gates) and the N=32 QFT (544 gates), planned once (gate
+    fusion + in-cache tile passes) and applied `steps` times after `warmup`.
+    The QFT runs on a seeded basis state and is checked against its closed form
+    on 4096 sampled amplitudes."""
+    import numpy as np
+    import torch
+
+    import paper_2409_14697_amd as sv
+    from svgen import brickwork_circuit, qft_circuit
+
+    torch.cuda.set_device(0)
+    n = args.n if args.n != N_QUBITS else 32
+    dtype = "c64"
+    stream = torch.cuda.current_stream()
+    st = sv.StateVector(n, dtype, stream=stream)
+    S = (1 << n) * 8
+    out = {}
+    rng = np.random.default_rng(7)
+    x0 = int(rng.integers(0, 1 << n))
+    for name, gates in (("brickwork_d40", brickwork_circuit(n, 40, seed=3)), ("qft", qft_circuit(n))):
+        t0 = time.perf_counter()
+        plan = sv.Plan(n, dtype, gates, {"mode": args.mode})
+        plan_s = time.perf_counter() - t0
+        kinds = [k for k, _, _ in plan.passes()]
+        sweeps = len(kinds)
+        init = x0 if name == "qft" else 0
+        for _ in range(args.warmup):
+            st.init_basis(init)
+            st.apply_plan(plan)
+        times = []
+        for _ in range(args.steps):
+            st.init_basis(init)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            st.apply_plan(plan)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        sec = sum(times) / len(times)
+        rec = {"seconds": round(sec, 5), "min_s": round(min(times), 5), "gates": len(gates),
+               "ops": plan.info()[0], "passes": sweeps,
+               "pass_kinds": {str(k): kinds.count(k) for k in sorted(set(kinds))},
+               "plan_s": round(plan_s, 4), "sweep_GBs": round(sweeps * 2 * S / sec / 1e9, 1)}
+        if name == "qft":
+            ys = torch.from_numpy(rng.integers(0, 1 << n, size=4096)).cuda()
+            got = st.tensor[ys].cpu().numpy().astype(np.complex128)
+            y = ys.cpu().numpy().astype(np.float64)
+            ref = np.exp(2j * np.pi * ((x0 * y) % (1 << n)) / (1 << n)) / math.sqrt(1 << n)
+            rec["closed_form_max_err"] = float(np.max(np.abs(got - ref)))
+        out[name] = rec
+    st.close()
+    total = sum(v["seconds"] for v in out.values())
+    print(json.dumps({"metric": f"circuit seconds at N={n} (complex64)", "value": round(total, 5), "unit": "s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * total, 3),
+                      "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": f"circuit benchmark: N={n} complex64, brickwork depth 40 (seed 3) + QFT",
+                                 "mode": args.mode},
+                      "circuits": out}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,11 +201,17 @@ def main():
     ap.add_argument("--dtypes", default="c128,c64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ceiling", action="store_true", help="also time the 16-byte copy kernel")
+    ap.add_argument("--workload", default="gates", choices=["gates", "circuit"],
+                    help="gates: the per-gate sweep benchmark (default); circuit: N=32 circuits")
+    ap.add_argument("--mode", default="auto", choices=["auto", "pass", "sweep"], help="plan mode (circuit workload)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the state-vector hot path here runs on a single MI355X "
               "(no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "circuit":
+        circuit_bench(args)
+        return
 
     import torch
 

@@ -51,6 +51,11 @@ __device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t mask) {
   return r;
 }
 
+// A launch may hold at most 2^32 work-items; grids are capped at kMaxGrid
+// blocks and kernels loop over the remaining work blocks.
+constexpr uint64_t kMaxGrid = 1ull << 22;
+inline uint64_t capped_grid(uint64_t work_blocks) { return work_blocks < kMaxGrid ? work_blocks : kMaxGrid; }
+
 // Blocks are dispatched round-robin over the 8 XCDs of an MI355X; this index
 // makes XCD x (blocks x, x+8, ...) own one contiguous range of work items.
 // Identity when the grid is not a multiple of 8.

@@ -24,6 +24,8 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int RB = kPassRegBits;
 constexpr int NR = 1 << RB;
+constexpr int kBatchBits = 3;
+constexpr int kBatch = 1 << kBatchBits;  // global loads in flight per lane while gathering a tile
 
 template <int WB>
 __device__ __forceinline__ uint32_t swz(uint32_t x) {
@@ -124,8 +126,11 @@ __device__ __forceinline__ void op_d2(cplx<R>* v, const cplx<R>* M) {
     default: break;                                                     \
   }
 
+// M points at the op's first matrix entry (the same address in every lane, so
+// the entries come through scalar loads); `var` selects a variant per lane.
 template <typename R>
-__device__ __forceinline__ void apply_op(const PassOpDev& op, const cplx<R>* M, cplx<R>* v) {
+__device__ __forceinline__ void apply_op(const PassOpDev& op, const cplx<R>* __restrict__ M, uint32_t var,
+                                         cplx<R>* v) {
   const uint32_t pair = op.b0 * 4 + op.b1;
   switch (op.type) {
     case POP_U1: {
@@ -153,7 +158,15 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, const cplx<R>* M, 
       break;
     }
     case POP_D1: {
-#define F(B) op_d1<B>(v, M)
+      cplx<R> d[2] = {M[0], M[1]};
+      if (op.sa != kPassNoSel) {  // two variants, picked per lane
+        const cplx<R> e0 = M[2], e1 = M[3];
+        if (var) {
+          d[0] = e0;
+          d[1] = e1;
+        }
+      }
+#define F(B) op_d1<B>(v, d)
       SV_BIT_SWITCH(op.b0, F)
 #undef F
       break;
@@ -165,24 +178,27 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, const cplx<R>* M, 
       break;
     }
     case POP_DG: {
-      const cplx<R> p = M[0];
+      cplx<R> p = M[0];
+      if (op.sa != kPassNoSel) {
+        const cplx<R> p1 = M[1];
+        if (op.sb != kPassNoSel) {
+          const cplx<R> p2 = M[2], p3 = M[3];
+          // two-level select on the variant bits (kept as selects, not a table)
+          const bool hi = (var >> 1) & 1u, lo = var & 1u;
+          const R re0 = lo ? p1.re : p.re, im0 = lo ? p1.im : p.im;
+          const R re1 = lo ? p3.re : p2.re, im1 = lo ? p3.im : p2.im;
+          p.re = hi ? re1 : re0;
+          p.im = hi ? im1 : im0;
+        } else if (var) {
+          p = p1;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < NR; ++r) v[r] = cmul(p, v[r]);
       break;
     }
     default:
       break;
-  }
-}
-
-__device__ __forceinline__ uint32_t mat_size(uint32_t type) {
-  switch (type) {
-    case POP_U1: return 4;
-    case POP_U2: return 16;
-    case POP_D1: return 2;
-    case POP_D2: return 4;
-    case POP_DG: return 1;
-    default: return 0;
   }
 }
 
@@ -199,21 +215,45 @@ __global__ __launch_bounds__(kBlock) void k_pass(typename dev_elem<R>::E* __rest
   const uint32_t m = P.m;
   const uint32_t size = 1u << m;
   const uint64_t all = (1ull << n) - 1ull;
-  const uint64_t base = deposit(xcd_block(), all & ~P.lmask);
+  const uint64_t ntiles = 1ull << (n - m);
   const uint32_t t = threadIdx.x;
+  const uint32_t per = size >= (uint32_t)kBlock ? size / kBlock : 1u;  // elements per lane
+  const bool lane_on = t < size;
+  // physical offsets of the batch index u (local bits 8 .. 8 + log2(kBatch) - 1)
+  uint64_t u_in[kBatch], u_out[kBatch];
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u) {
+    u_in[u] = u_out[u] = 0;
+#pragma unroll
+    for (int b = 0; b < kBatchBits; ++b)
+      if (((u >> b) & 1) && 8u + b < m) {
+        u_in[u] |= 1ull << P.lpos[8 + b];
+        u_out[u] |= 1ull << P.wpos[8 + b];
+      }
+  }
+  for (uint64_t tile_id = xcd_block(); tile_id < ntiles; tile_id += gridDim.x) {
+  const uint64_t base = deposit(tile_id, all & ~P.lmask);
 
-  // gather: x = t + 256 j; the low 8 local bits come from t, the rest from j
+  // gather: x = t + 256 j; the low 8 local bits come from t, the rest from j.
+  // kBatch loads per lane are issued before any of them is written to LDS.
   uint64_t lo_in = 0, lo_out = 0;
   for (uint32_t j = 0; j < m && j < 8; ++j)
     if ((t >> j) & 1u) {
       lo_in |= 1ull << P.lpos[j];
       lo_out |= 1ull << P.wpos[j];
     }
-  for (uint32_t x = t; x < size; x += kBlock) {
-    uint64_t hi = 0;
-    for (uint32_t j = 8; j < m; ++j)
-      if ((x >> j) & 1u) hi |= 1ull << P.lpos[j];
-    tile[swz<WB>(x)] = ld(psi + (base | lo_in | hi));
+  for (uint32_t j0 = 0; j0 < per; j0 += kBatch) {
+    // local bits 8 + log2(kBatch) .. m-1 come from j0 (the same in every lane)
+    uint64_t hi_in = 0;
+    for (uint32_t b = 8 + kBatchBits; b < m; ++b)
+      if ((j0 >> (b - 8)) & 1u) hi_in |= 1ull << P.lpos[b];
+    E buf[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (j0 + u < per && lane_on) buf[u] = ld(psi + (base | lo_in | hi_in | u_in[u]));
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (j0 + u < per && lane_on) tile[swz<WB>(t + (j0 + u) * kBlock)] = buf[u];
   }
   __syncthreads();
 
@@ -252,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(typename dev_elem<R>::E* __rest
             var = (var << 1) |
                   (op.sb < kPassTileSel ? (xg >> op.sb) & 1u : (uint32_t)(base >> (op.sb - kPassTileSel)) & 1u);
         }
-        apply_op<R>(op, mats + op.mat + var * mat_size(op.type), v);
+        apply_op<R>(op, mats + op.mat, var, v);
       }
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -265,11 +305,19 @@ __global__ __launch_bounds__(kBlock) void k_pass(typename dev_elem<R>::E* __rest
     __syncthreads();
   }
 
-  for (uint32_t x = t; x < size; x += kBlock) {
-    uint64_t hi = 0;
-    for (uint32_t j = 8; j < m; ++j)
-      if ((x >> j) & 1u) hi |= 1ull << P.wpos[j];
-    st(psi + (base | lo_out | hi), tile[swz<WB>(x)]);
+  for (uint32_t j0 = 0; j0 < per; j0 += kBatch) {
+    uint64_t hi_out = 0;
+    for (uint32_t b = 8 + kBatchBits; b < m; ++b)
+      if ((j0 >> (b - 8)) & 1u) hi_out |= 1ull << P.wpos[b];
+    E buf[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (j0 + u < per && lane_on) buf[u] = tile[swz<WB>(t + (j0 + u) * kBlock)];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (j0 + u < per && lane_on) st(psi + (base | lo_out | hi_out | u_out[u]), buf[u]);
+  }
+  __syncthreads();  // the tile buffer is reused by the next tile
   }
 }
 
@@ -285,7 +333,7 @@ hipError_t run(void* psi, int n, int m, const PassDescDev* passes, int pass, con
     if (e != hipSuccess) return e;
     attr = lds;
   }
-  const uint64_t tiles = 1ull << (n - m);
+  const uint64_t tiles = capped_grid(1ull << (n - m));
   hipLaunchKernelGGL((k_pass<R, WB>), dim3((unsigned)tiles), dim3(kBlock), lds, s, (E*)psi, n, passes, pass, stages,
                      ops, (const cplx<R>*)mats);
   return hipGetLastError();

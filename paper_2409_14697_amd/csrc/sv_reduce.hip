@@ -30,6 +30,7 @@ struct ProbGeo {
   uint64_t rest_mask;    // unmeasured bits >= L
   uint64_t restlo_mask;  // unmeasured bits < L
   uint64_t chunk;        // rest values per block
+  uint64_t qhi_blocks;   // values of the measured high bits
   int qpos[SV_MAX_QUBITS];  // qubits[r]
 };
 
@@ -46,7 +47,8 @@ __global__ __launch_bounds__(kBlock) void k_probs_partial(const E* __restrict__ 
   __shared__ double red[kBlock];
   const unsigned t = threadIdx.x;
   const bool active = t < (1u << g.L);
-  const uint64_t qhi_bits = deposit(blockIdx.x, g.qhi_mask);
+  for (uint64_t qb = blockIdx.x; qb < g.qhi_blocks; qb += gridDim.x) {
+  const uint64_t qhi_bits = deposit(qb, g.qhi_mask);
   uint64_t cur = deposit((uint64_t)blockIdx.y * g.chunk, g.rest_mask);
   double acc = 0.0;
   if (active) {
@@ -80,6 +82,8 @@ __global__ __launch_bounds__(kBlock) void k_probs_partial(const E* __restrict__ 
     for (int r = 0; r < g.m; ++r) bin |= ((i >> g.qpos[r]) & 1ull) << (g.m - 1 - r);
     partial[(uint64_t)blockIdx.y * (1ull << g.m) + bin] = s;
   }
+  __syncthreads();  // red[] is reused by the next qhi value
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_probs_final(const double* __restrict__ partial, uint64_t nbins,
@@ -91,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_probs_final(const double* __restrict
   out[b] = s;
 }
 
-ProbGeo make_geo(int n, int m, const int* qubits, unsigned* chunks_out, unsigned* qhi_blocks_out) {
+ProbGeo make_geo(int n, int m, const int* qubits, unsigned* chunks_out, uint64_t* qhi_blocks_out) {
   ProbGeo g{};
   g.L = n < 8 ? n : 8;
   g.m = m;
@@ -111,15 +115,17 @@ ProbGeo make_geo(int n, int m, const int* qubits, unsigned* chunks_out, unsigned
   // aim for ~4096 blocks in total, bounded by the rest values and the partial buffer
   while ((chunks << mh) < 4096 && chunks < (1ull << nr) && ((chunks * 2) << m) <= kMaxPartialDoubles) chunks *= 2;
   g.chunk = (1ull << nr) / chunks;
+  g.qhi_blocks = 1ull << mh;
   *chunks_out = (unsigned)chunks;
-  *qhi_blocks_out = (unsigned)(1ull << mh);
+  *qhi_blocks_out = 1ull << mh;
   return g;
 }
 
 }  // namespace
 
 size_t probs_scratch_bytes(int n, int m, const int* qubits) {
-  unsigned chunks, qb;
+  unsigned chunks;
+  uint64_t qb;
   make_geo(n, m, qubits, &chunks, &qb);
   if (chunks == 1) return 0;  // a single chunk writes the output directly
   return (size_t)chunks * ((size_t)1 << m) * sizeof(double);
@@ -127,10 +133,11 @@ size_t probs_scratch_bytes(int n, int m, const int* qubits) {
 
 hipError_t launch_probs(sv_dtype dt, const void* psi, int n, const int* qubits, int m, double* out, void* scratch,
                         hipStream_t s) {
-  unsigned chunks, qb;
+  unsigned chunks;
+  uint64_t qb;
   ProbGeo g = make_geo(n, m, qubits, &chunks, &qb);
   double* partial = chunks == 1 ? out : (double*)scratch;
-  dim3 grid(qb, chunks);
+  dim3 grid((unsigned)capped_grid(qb), chunks);
   if (dt == SV_C128)
     hipLaunchKernelGGL(k_probs_partial<dbl2>, grid, dim3(kBlock), 0, s, (const dbl2*)psi, g, partial);
   else
@@ -138,7 +145,7 @@ hipError_t launch_probs(sv_dtype dt, const void* psi, int n, const int* qubits, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || chunks == 1) return e;
   const uint64_t nbins = 1ull << m;
-  const uint64_t blocks = (nbins + kBlock - 1) / kBlock;
+  const uint64_t blocks = (nbins + kBlock - 1) / kBlock;  // chunks > 1 only when 2^m partials fit 64 MiB
   hipLaunchKernelGGL(k_probs_final, dim3((unsigned)blocks), dim3(kBlock), 0, s, (const double*)partial, nbins,
                      chunks, out);
   return hipGetLastError();

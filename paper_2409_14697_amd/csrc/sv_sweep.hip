@@ -103,7 +103,9 @@ __global__ __launch_bounds__(kBlock) void k_group(E* __restrict__ psi, uint64_t 
   typedef elem_traits<E> TR;
   typedef typename TR::R R;
   constexpr int ITEMS = 1;
-  const uint64_t k0 = xcd_block() * (uint64_t)(kBlock * ITEMS) + threadIdx.x;
+  const uint64_t nwork = (ngroups + kBlock * ITEMS - 1) / (kBlock * ITEMS);
+  for (uint64_t wb = xcd_block(); wb < nwork; wb += gridDim.x) {
+  const uint64_t k0 = wb * (uint64_t)(kBlock * ITEMS) + threadIdx.x;
   E v[ITEMS][NV];
   uint64_t base[ITEMS];
 #pragma unroll
@@ -135,6 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_group(E* __restrict__ psi, uint64_t 
 #pragma unroll
       for (int r = 0; r < NV; ++r) st(psi + base[j] + g.off[r], v[j][r]);
     }
+  }
   }
 }
 
@@ -191,7 +194,9 @@ __global__ __launch_bounds__(kBlock) void k_low(E* __restrict__ psi, uint64_t ng
   constexpr int NV = (KA == QK_REG || (K == 2 && KB == QK_REG)) ? 2 : 1;
   // LANE qubits, in matrix order
   constexpr int NL = (KA == QK_LANE) + (K == 2 && KB == QK_LANE);
-  const uint64_t k = xcd_block() * (uint64_t)kBlock + threadIdx.x;
+  const uint64_t nwork = (ngroups + kBlock - 1) / kBlock;
+  for (uint64_t wb = xcd_block(); wb < nwork; wb += gridDim.x) {
+  const uint64_t k = wb * (uint64_t)kBlock + threadIdx.x;
   const bool active = k < ngroups;
   uint64_t b = k;
 #pragma unroll
@@ -280,6 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_low(E* __restrict__ psi, uint64_t ng
 #pragma unroll
     for (int r = 0; r < NV; ++r) st(psi + b + (r ? g.off1 : 0ull), out[r]);
   }
+  }
 }
 
 template <typename R>
@@ -292,7 +298,7 @@ hipError_t run_low(void* psi, uint64_t ngroups, const LowGeo<NZ>& g, const cd* m
   typedef typename elem_traits<E>::R R;
   LowMat<R, K> u;
   for (int i = 0; i < (1 << K) * (1 << K); ++i) u.u[i] = to_dev<R>(m[i]);
-  const uint64_t blocks = (ngroups + kBlock - 1) / kBlock;
+  const uint64_t blocks = capped_grid((ngroups + kBlock - 1) / kBlock);
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL((k_low<E, K, KA, KB, NZ>), dim3((unsigned)blocks), dim3(kBlock), 0, s, (E*)psi, ngroups, g,
                      u);
@@ -351,7 +357,7 @@ hipError_t run(void* psi, uint64_t ngroups, const GroupSpec& gs, unsigned shift,
   for (int z = 0; z < NZ; ++z) g.z[z] = gs.z[z] - shift;
   g.set = gs.set >> shift;
   for (int r = 0; r < NV; ++r) g.off[r] = gs.off[r] >> shift;
-  const uint64_t blocks = (ngroups + kBlock - 1) / kBlock;
+  const uint64_t blocks = capped_grid((ngroups + kBlock - 1) / kBlock);
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL((k_group<E, NZ, NV, Op>), dim3((unsigned)blocks), dim3(kBlock), 0, s, (E*)psi, ngroups, g,
                      op);
@@ -428,18 +434,18 @@ namespace {
 
 template <typename E>
 __global__ __launch_bounds__(kBlock) void k_init_basis(E* __restrict__ psi, uint64_t count, uint64_t index) {
-  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < count) {
+  for (uint64_t i = xcd_block() * kBlock + threadIdx.x; i < count; i += (uint64_t)gridDim.x * kBlock) {
     E v = {};
     if (i == index) v.x = 1;
-    psi[i] = v;
+    st(psi + i, v);
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy16(flt4* __restrict__ dst, const flt4* __restrict__ src,
                                                    uint64_t count) {
   constexpr int ITEMS = 1;
-  const uint64_t i0 = xcd_block() * (kBlock * ITEMS) + threadIdx.x;
+  for (uint64_t i0 = xcd_block() * (kBlock * ITEMS) + threadIdx.x; i0 < count;
+       i0 += (uint64_t)gridDim.x * kBlock * ITEMS) {
   flt4 v[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
@@ -451,13 +457,14 @@ __global__ __launch_bounds__(kBlock) void k_copy16(flt4* __restrict__ dst, const
     const uint64_t i = i0 + (uint64_t)j * kBlock;
     if (i < count) st(dst + i, v[j]);
   }
+  }
 }
 
 }  // namespace
 
 hipError_t launch_init_basis(sv_dtype dt, void* psi, int n, uint64_t index, hipStream_t s) {
   const uint64_t count = 1ull << n;
-  const uint64_t blocks = (count + kBlock - 1) / kBlock;
+  const uint64_t blocks = capped_grid((count + kBlock - 1) / kBlock);
   if (dt == SV_C128)
     hipLaunchKernelGGL(k_init_basis<dbl2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, (dbl2*)psi, count, index);
   else
@@ -468,7 +475,7 @@ hipError_t launch_init_basis(sv_dtype dt, void* psi, int n, uint64_t index, hipS
 hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const uint64_t count = bytes / 16;
   const uint64_t per_block = (uint64_t)kBlock;
-  const uint64_t blocks = (count + per_block - 1) / per_block;
+  const uint64_t blocks = capped_grid((count + per_block - 1) / per_block);
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(kBlock), 0, s, (flt4*)dst, (const flt4*)src, count);
   return hipGetLastError();
