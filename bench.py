@@ -192,6 +192,94 @@ def circuit_bench(args):
                       "circuits": out}))
 
 
+def _compare(a64, b128):
+    """FP64 error metrics of a complex64 state against a complex128 one
+    (chunked, on the device): max-abs, relative L2, infidelity, norm drift."""
+    import torch
+    step = 1 << 26
+    max_abs, diff2, ref2, own2 = 0.0, 0.0, 0.0, 0.0
+    inner = torch.zeros((), dtype=torch.complex128, device=b128.device)
+    for s0 in range(0, b128.numel(), step):
+        x = a64[s0:s0 + step].to(torch.complex128)
+        y = b128[s0:s0 + step]
+        d = x - y
+        max_abs = max(max_abs, float(d.abs().max()))
+        diff2 += float((d.real ** 2 + d.imag ** 2).sum())
+        ref2 += float((y.real ** 2 + y.imag ** 2).sum())
+        own2 += float((x.real ** 2 + x.imag ** 2).sum())
+        inner += torch.vdot(y, x)
+    fid = abs(complex(inner)) ** 2 / (ref2 * own2)
+    return {"max_abs": max_abs, "rel_l2": math.sqrt(diff2 / ref2), "infidelity": 1.0 - fid,
+            "norm_drift_fp32": own2 - 1.0, "norm_drift_fp64": ref2 - 1.0}
+
+
+def precision_bench(args):
+    """Precision form: N=30, 2000 Haar-random 5- and 6-qubit unitaries on
+    random ordered qubit sets; complex64 state with FP32 MFMA contractions
+    (FP32 accumulation, FP64 renormalisation every `renorm` ops) against a
+    complex128 state with the FP64 kernel, same GPU, same seeded input.
+    Errors are taken at checkpoints; one record per seed."""
+    import torch
+
+    import paper_2409_14697_amd as sv
+    from svgen import fused_haar_circuit
+    from svgen.states import gaussian_state_torch
+
+    torch.cuda.set_device(0)
+    n = args.n
+    stream = torch.cuda.current_stream()
+    records = []
+    t32_total = t64_total = 0.0
+    for seed in [int(x) for x in args.seeds.split(",")]:
+        gates = fused_haar_circuit(n, args.gates, seed=seed)
+        s128 = gaussian_state_torch(n, seed, torch.complex128)
+        s64 = s128.to(torch.complex64)
+        st64 = sv.StateVector(n, "c128", tensor=s128, init=False, stream=stream)
+        st32 = sv.StateVector(n, "c64", tensor=s64, init=False, stream=stream)
+        chk = args.checkpoint
+        rec = {"seed": seed, "gates": len(gates), "checkpoints": []}
+        t32 = t64 = 0.0
+        for g0 in range(0, len(gates), chk):
+            part = gates[g0:g0 + chk]
+            for st, dtype in ((st32, "c64"), (st64, "c128")):
+                opts = {"mode": "sweep", "max_fuse_qubits": 0}
+                if dtype == "c64":
+                    opts["renorm_interval"] = args.renorm
+                plan = sv.Plan(n, dtype, part, opts)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                st.apply_plan(plan)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                dt = e0.elapsed_time(e1) * 1e-3
+                if dtype == "c64":
+                    t32 += dt
+                else:
+                    t64 += dt
+            m = _compare(s64, s128)
+            m["after_gates"] = g0 + len(part)
+            rec["checkpoints"].append({k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in m.items()})
+        rec["fp32_mfma_s"] = round(t32, 4)
+        rec["fp64_s"] = round(t64, 4)
+        records.append(rec)
+        t32_total += t32
+        t64_total += t64
+        st32.close()
+        st64.close()
+        del s64, s128
+        torch.cuda.empty_cache()
+    final_err = max(r["checkpoints"][-1]["max_abs"] for r in records)
+    print(json.dumps({"metric": f"precision form: seconds for {args.gates} fused 5/6-qubit gates at N={n}, "
+                                "FP32 MFMA vs FP64", "value": round(t32_total / len(records), 4), "unit": "s",
+                      "n_gpus": 1, "steps": len(records), "warmup": 0,
+                      "ms_per_step": round(1e3 * t32_total / len(records), 3), "higher_is_better": False,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32 (vs f64)", "data": "synthetic",
+                      "config": {"workload": f"precision form: N={n}, {args.gates} Haar unitaries alternating "
+                                             f"k=5/6 (seeds {args.seeds}), renorm every {args.renorm}"},
+                      "fp64_seconds": round(t64_total / len(records), 4),
+                      "fp32_max_abs_error": final_err, "bar_max_abs": 1e-5, "records": records}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,8 +289,13 @@ def main():
     ap.add_argument("--dtypes", default="c128,c64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ceiling", action="store_true", help="also time the 16-byte copy kernel")
-    ap.add_argument("--workload", default="gates", choices=["gates", "circuit"],
-                    help="gates: the per-gate sweep benchmark (default); circuit: N=32 circuits")
+    ap.add_argument("--workload", default="gates", choices=["gates", "circuit", "precision"],
+                    help="gates: the per-gate sweep benchmark (default); circuit: N=32 circuits; "
+                         "precision: FP32 MFMA vs FP64 fused Haar gates")
+    ap.add_argument("--gates", type=int, default=2000, help="precision workload: number of fused gates")
+    ap.add_argument("--checkpoint", type=int, default=250, help="precision workload: gates between error checks")
+    ap.add_argument("--seeds", default="4,5,6", help="precision workload: circuit seeds")
+    ap.add_argument("--renorm", type=int, default=250, help="precision workload: FP64 renorm interval (0: off)")
     ap.add_argument("--mode", default="auto", choices=["auto", "pass", "sweep"], help="plan mode (circuit workload)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -211,6 +304,9 @@ def main():
         sys.exit(2)
     if args.workload == "circuit":
         circuit_bench(args)
+        return
+    if args.workload == "precision":
+        precision_bench(args)
         return
 
     import torch

@@ -72,7 +72,7 @@ sv_status upload(sv_state* s, const void* host, size_t bytes, void** dev) {
   return SV_OK;
 }
 
-sv_status run_op_sweep(sv_state* s, const Op& op, const void* m_dev) {
+sv_status run_op_sweep(sv_state* s, const Op& op, const void* m_dev, bool mfma) {
   if (op.nq <= 2) {
     SweepArgs a;
     if (!low_args_for(op, s->dt, &a)) sweep_args_for(op, &a);
@@ -80,7 +80,22 @@ sv_status run_op_sweep(sv_state* s, const Op& op, const void* m_dev) {
     return SV_OK;
   }
   if (op.nq > s->n) return fail(SV_ERR_QUBIT, "op on %d qubits exceeds the state's %d", op.nq, s->n);
-  SV_HIP_TRY(launch_dense_kq(s->dt, s->ptr, s->n, op.nq, op.q, m_dev, s->stream));
+  SV_HIP_TRY(launch_dense_kq(s->dt, s->ptr, s->n, op.nq, op.q, m_dev, mfma, s->stream));
+  return SV_OK;
+}
+
+sv_status renormalize(sv_state* s) {
+  // scratch: [squared norm][reduction partials]
+  const size_t part = probs_scratch_bytes(s->n, 0, nullptr);
+  if (sv_status st = ensure_scratch(s, 256 + part)) return st;
+  double* norm2 = (double*)s->scratch;
+  SV_HIP_TRY(launch_probs(s->dt, s->ptr, s->n, nullptr, 0, norm2, (unsigned char*)s->scratch + 256, s->stream));
+  SweepArgs a{};
+  a.op = SWEEP_SCALE_NORM;
+  a.g.nz = 0;
+  a.g.nv = 1;
+  a.norm2_dev = norm2;
+  SV_HIP_TRY(launch_sweep(s->dt, s->ptr, s->n, a, s->stream));
   return SV_OK;
 }
 
@@ -334,9 +349,8 @@ sv_status sv_measure_probs(sv_state* s, const int32_t* qubits, int m, double* ou
     qs[r] = qubits[r];
   }
   const size_t need = probs_scratch_bytes(s->n, m, qs);
-  if (need)
-    if (sv_status st = ensure_scratch(s, need)) return st;
-  SV_HIP_TRY(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, s->scratch, s->stream));
+  if (sv_status st = ensure_scratch(s, 256 + need)) return st;
+  SV_HIP_TRY(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, (unsigned char*)s->scratch + 256, s->stream));
   return SV_OK;
 }
 

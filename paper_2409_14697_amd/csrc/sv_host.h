@@ -119,8 +119,12 @@ sv_status ensure_scratch(sv_state* s, size_t bytes);
 // valid for work enqueued before this call.
 sv_status upload(sv_state* s, const void* host, size_t bytes, void** dev);
 // Run one op as a full-state sweep (sweep kernels for nq <= 2, dense kernel
-// for nq >= 3 with the matrix at m_dev in the state's precision).
-sv_status run_op_sweep(sv_state* s, const Op& op, const void* m_dev);
+// for nq >= 3 with the matrix at m_dev in the state's precision; mfma selects
+// the FP32 MFMA kernel for complex64 states and nq >= 4).
+sv_status run_op_sweep(sv_state* s, const Op& op, const void* m_dev, bool mfma = true);
+// Rescale the state to unit norm with an FP64 norm computed on the device
+// (stream-ordered; no host synchronisation).
+sv_status renormalize(sv_state* s);
 // Plan building (host only).
 sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const sv_opts& o, sv_plan* p);
 // Greedy fusion of an op list (ops no wider than kmax qubits; kmax <= 1

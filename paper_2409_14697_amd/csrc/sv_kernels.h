@@ -35,6 +35,7 @@ enum SweepOp {
   SWEEP_DIAG = 4,    // nv=1: a <- d[local(bits)] * a, local index from bits
                      //       b0 (MSB) [, b1]; m[0..3] = d
   SWEEP_SCALE = 5,   // nv=1: a <- m[0].real() * a
+  SWEEP_SCALE_NORM = 7,  // nv=1: a <- a / sqrt(*norm2_dev) (FP64 factor)
   SWEEP_LOW = 6      // 1-/2-qubit matrix m (4^low_k entries) on qubits low_q
                      // (low_q[0] = MSB), at least one of them inside a
                      // 128-byte run; rows are exchanged between lanes.  Only
@@ -47,6 +48,7 @@ struct SweepArgs {
   cd m[16];
   int diag_nbits = 0;
   unsigned diag_b0 = 0, diag_b1 = 0;
+  const double* norm2_dev = nullptr;  // SWEEP_SCALE_NORM
   int low_k = 0;
   unsigned low_q[2] = {0, 0};
   uint64_t low_fixed = 0;
@@ -122,8 +124,9 @@ hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* 
 
 // --- dense k-qubit fused gate (3 <= k <= 6) ---------------------------------
 // m_dev: device copy of the 2^k x 2^k matrix, row-major interleaved, in the
-// state's precision (double for SV_C128, float for SV_C64).
-hipError_t launch_dense_kq(sv_dtype dt, void* psi, int n, int k, const int* q, const void* m_dev,
+// state's precision (double for SV_C128, float for SV_C64).  mfma: complex64
+// states with k >= 4 use the FP32 MFMA kernel.
+hipError_t launch_dense_kq(sv_dtype dt, void* psi, int n, int k, const int* q, const void* m_dev, bool mfma,
                            hipStream_t s);
 
 // --- readout ----------------------------------------------------------------

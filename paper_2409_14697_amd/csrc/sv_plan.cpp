@@ -279,20 +279,28 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
     if (st != SV_OK) return st;
   }
   unsigned char* db = (unsigned char*)dev;
+  // complex64 states: FP64 renormalisation after every `renorm` dense ops
+  const int renorm = s->dt == SV_C64 ? p->opts.renorm_interval : 0;
+  int since = 0;
   for (size_t i = 0; i < p->passes.size(); ++i) {
     const Pass& ps = p->passes[i];
     if (ps.kind == PASS_SWEEP) {
       sv_status st = run_op_sweep(s, ps.phys, nullptr);
       if (st != SV_OK) return st;
     } else if (ps.kind == PASS_DENSE) {
-      sv_status st = run_op_sweep(s, ps.phys, db + dense_off[i]);
+      sv_status st = run_op_sweep(s, ps.phys, db + dense_off[i], p->opts.fp32_mfma != 0);
       if (st != SV_OK) return st;
+      if (renorm > 0 && ++since >= renorm) {
+        if (sv_status r = renormalize(s)) return r;
+        since = 0;
+      }
     } else {
       SV_HIP_TRY(launch_pass(s->dt, s->ptr, s->n, ps.n_local, (const PassDescDev*)(db + off_desc), desc_index[i],
                              (const PassStageDev*)(db + off_stage), (const PassOpDev*)(db + off_ops),
                              db + off_pool, s->stream));
     }
   }
+  if (renorm > 0 && since > 0) return renormalize(s);
   return SV_OK;
 }
 

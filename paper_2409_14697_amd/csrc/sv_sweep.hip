@@ -96,6 +96,18 @@ struct OpScale {
   }
 };
 
+// Renormalisation: the factor 1/sqrt(norm2) is formed in FP64 from the
+// device-resident squared norm (no host round trip).
+template <typename R>
+struct OpScaleNorm {
+  const double* norm2;
+  __device__ __forceinline__ void operator()(cplx<R>* a, uint64_t) const {
+    const R s = (R)(1.0 / sqrt(*norm2));
+    a[0].re *= s;
+    a[0].im *= s;
+  }
+};
+
 // ---------------------------------------------------------------- kernel
 template <typename E, int NZ, int NV, class Op>
 __global__ __launch_bounds__(kBlock) void k_group(E* __restrict__ psi, uint64_t ngroups, Geo<NZ, NV> g,
@@ -405,6 +417,11 @@ hipError_t dispatch(void* psi, int n, const SweepArgs& a, hipStream_t s) {
     case SWEEP_SCALE: {
       OpScale<R> op;
       op.s = (R)a.m[0].real();
+      return run<E, 0, 1>(psi, ngroups, gs, shift, op, s);
+    }
+    case SWEEP_SCALE_NORM: {
+      OpScaleNorm<R> op;
+      op.norm2 = a.norm2_dev;
       return run<E, 0, 1>(psi, ngroups, gs, shift, op, s);
     }
     default:
