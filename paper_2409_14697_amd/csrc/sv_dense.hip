@@ -99,81 +99,158 @@ hipError_t run(void* psi, int n, const DenseGeo& g, const void* m, hipStream_t s
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- FP32 MFMA
-// complex64 states, 4 <= k <= 6: Y = U X as a real GEMM on the interleaved
-// storage.  With rows of Y and X indexed 2*member + (0: re, 1: im), the
-// operator is the real 2D x 2D matrix A[2i+a][2j+b] = (Ur, -Ui; Ui, Ur)[a][b]
-// of U[i][j], so no de-interleaving is needed.  v_mfma_f32_32x32x2_f32 tiles:
-// A operand (32 x 2): lane l holds A[l % 32][l / 32]; B operand (2 x 32):
-// lane l holds B[l / 32][l % 32]; accumulator (32 x 32, 16 registers): lane l,
-// register r holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
-// FP32 inputs, FP32 accumulation.  A block of 4 waves covers all 2D rows and
-// 32 * 4 / (2D / 32) columns (groups); each wave keeps its 32 rows of A in
-// registers and streams X fragments from an LDS tile.
+// ---------------------------------------------------------------- MFMA
+// Y = U X as a real GEMM on the interleaved storage: with rows of Y and X
+// indexed 2*member + (0: re, 1: im), the operator is the real 2D x 2D matrix
+// A[2i+a][2j+b] = (Ur, -Ui; Ui, Ur)[a][b] of U[i][j], so the state is never
+// de-interleaved.  Matrix-core tiles (operand layouts of the instructions):
+//   FP32 (complex64):  v_mfma_f32_32x32x2_f32, BM = BN = 32, BK = 2
+//   FP64 (complex128): v_mfma_f64_16x16x4_f64, BM = BN = 16, BK = 4
+// A operand: lane l holds A[l % BM][l / BM]; B operand: lane l holds
+// B[l / BN][l % BN]; accumulator (BM x BN), column l % BN: FP32 register r of
+// lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, FP64 register r holds row
+// (l / 16) + 4 r (measured on gfx950 with one-hot operands).  The rows of a
+// block are assigned to (member, re/im) so that registers r, r + 1 of a lane
+// are the re and im parts of one output amplitude: FP32 blocks take real rows
+// in order; an FP64 block row rho = g + 4 r holds member 2 g + r / 2, part r % 2
+// of its 8 members.  Accumulation is in the input precision.
+// A block stages U (rows padded by one entry against LDS bank conflicts) once
+// and loops over column tiles of NC groups: each tile is gathered with all of
+// a lane's loads in flight, then the 4 waves share its (row block, column
+// block) output tiles.
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_dense_mfma(flt2* __restrict__ psi, uint64_t ngroups, DenseGeo g,
-                                                       const float* __restrict__ um) {
-  constexpr int D = 1 << K;          // members per group
-  constexpr int RB = (2 * D) / 32;   // 32-row blocks of the real operator
-  constexpr int CB = 4 / RB;         // 32-column blocks per block iteration
-  constexpr int NC = 32 * CB;        // groups per block iteration
-  __shared__ flt2 xs[D * NC];        // [member][column]
-  const int t = threadIdx.x, w = t / 64, l = t % 64;
-  const int rb = w % RB, cb = w / RB;
-  // this wave's rows of A for every k-step (K-dimension pairs = input members)
-  float a[D];
-#pragma unroll
-  for (int kk = 0; kk < D; ++kk) {
-    const int i = 32 * rb + (l % 32);  // real output row
-    const int oi = i >> 1, ar = i & 1, bi = l / 32;
-    const float ur = um[2 * (oi * D + kk)], ui = um[2 * (oi * D + kk) + 1];
-    a[kk] = ar == 0 ? (bi == 0 ? ur : -ui) : (bi == 0 ? ui : ur);
+template <typename R>
+struct mfma_shape;
+template <>
+struct mfma_shape<float> {
+  static constexpr int BM = 32, BN = 32, BK = 2, NACC = 16;
+  typedef floatx16 acc_t;
+  typedef flt2 E;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
   }
+  // block row -> (member within the block's 16, re/im)
+  static __device__ __forceinline__ void row_of(int rho, int* mem, int* part) {
+    *mem = rho >> 1;
+    *part = rho & 1;
+  }
+  // member (within the block) written by registers r, r + 1 of lane l (r even)
+  static __device__ __forceinline__ int out_member(int l, int r) { return (8 * (r / 4) + 4 * (l / 32) + (r % 4)) >> 1; }
+  static constexpr int MPB = 16;  // members per row block
+};
+template <>
+struct mfma_shape<double> {
+  static constexpr int BM = 16, BN = 16, BK = 4, NACC = 4;
+  typedef doublex4 acc_t;
+  typedef dbl2 E;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void row_of(int rho, int* mem, int* part) {
+    *mem = 2 * (rho % 4) + (rho / 4) / 2;
+    *part = (rho / 4) % 2;
+  }
+  static __device__ __forceinline__ int out_member(int l, int r) { return 2 * (l / 16) + r / 2; }
+  static constexpr int MPB = 8;
+};
+
+// groups per column tile: the X tile holds 2048 complex64 / 1024 complex128
+// amplitudes, and at least one column block
+template <typename R, int K>
+constexpr int mfma_cols() {
+  constexpr int target = (sizeof(R) == 4 ? 2048 : 1024) >> K;
+  return target < mfma_shape<R>::BN ? mfma_shape<R>::BN : target;
+}
+
+template <typename R, int K>
+constexpr size_t mfma_lds() {
+  return ((size_t)(1 << K) * ((1 << K) + 1) + (size_t)(1 << K) * mfma_cols<R, K>()) * 2 * sizeof(R);
+}
+
+template <typename R, int K>
+__global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E* __restrict__ psi,
+                                                       uint64_t ngroups, DenseGeo g, const R* __restrict__ um) {
+  typedef mfma_shape<R> MS;
+  typedef typename MS::E E;
+  constexpr int D = 1 << K, DP = D + 1;
+  constexpr int NC = mfma_cols<R, K>();
+  constexpr int RBLK = 2 * D / MS::BM, CBLK = NC / MS::BN, TILES = RBLK * CBLK;
+  constexpr int KSTEPS = 2 * D / MS::BK;
+  constexpr int PER = D * NC / kBlock;  // tile elements gathered per lane
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* us = reinterpret_cast<cplx<R>*>(smem);  // D x DP
+  E* xs = reinterpret_cast<E*>(us + D * DP);       // [member][NC]
+  const int t = threadIdx.x, w = t / 64, l = t % 64;
+  for (int e = t; e < D * D; e += kBlock) us[(e / D) * DP + (e % D)] = cplx<R>{um[2 * e], um[2 * e + 1]};
   const uint64_t nwork = (ngroups + NC - 1) / NC;
   for (uint64_t wb = xcd_block(); wb < nwork; wb += gridDim.x) {
     const uint64_t c0 = wb * NC;
-    __syncthreads();  // previous iteration's readers are done with xs
-    for (int e = t; e < D * NC; e += kBlock) {
-      const int c = e % NC, r = e / NC;
+    E buf[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + u * kBlock, c = e % NC, r = e / NC;
       const uint64_t col = c0 + c;
-      flt2 v = {0.f, 0.f};
-      if (col < ngroups) v = psi[group_base<K>(col, g) + member_off<K>(r, g)];
-      xs[e] = v;
+      E v = {};
+      if (col < ngroups) v = ld(psi + group_base<K>(col, g) + member_off<K>(r, g));
+      buf[u] = v;
     }
+    __syncthreads();  // U is staged and the previous tile's readers are done
+#pragma unroll
+    for (int u = 0; u < PER; ++u) xs[t + u * kBlock] = buf[u];
     __syncthreads();
-    floatx16 acc = {};
-    const int col = cb * 32 + (l % 32);
+    for (int tile = w; tile < TILES; tile += 4) {
+      const int rb = tile % RBLK, cb = tile / RBLK;
+      int ai, aa;  // output member and re/im of the A row this lane supplies
+      MS::row_of(l % MS::BM, &ai, &aa);
+      ai += MS::MPB * rb;
+      const int bcol = MS::BN * cb + l % MS::BN;
+      typename MS::acc_t acc = {};
+#pragma unroll 8
+      for (int ks = 0; ks < KSTEPS; ++ks) {
+        const int ak = MS::BK * ks + l / MS::BM;  // real column of A (= real row of B)
+        const cplx<R> u = us[ai * DP + (ak >> 1)];
+        const R a = aa == 0 ? ((ak & 1) == 0 ? u.re : -u.im) : ((ak & 1) == 0 ? u.im : u.re);
+        const int bk = MS::BK * ks + l / MS::BN;
+        const E xv = xs[(bk >> 1) * NC + bcol];
+        const R b = (bk & 1) ? xv.y : xv.x;
+        acc = MS::mma(a, b, acc);
+      }
+      const uint64_t gcol = c0 + bcol;
+      if (gcol < ngroups) {
+        const uint64_t gb = group_base<K>(gcol, g);
 #pragma unroll
-    for (int kk = 0; kk < D; ++kk) {
-      const flt2 xv = xs[kk * NC + col];
-      const float b = (l / 32) ? xv.y : xv.x;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kk], b, acc, 0, 0, 0);
-    }
-    const uint64_t gcol = c0 + col;
-    if (gcol < ngroups) {
-      const uint64_t gb = group_base<K>(gcol, g);
-#pragma unroll
-      for (int r = 0; r < 16; r += 2) {
-        const int i = 32 * rb + 8 * (r / 4) + 4 * (l / 32) + (r % 4);  // even real row: re, i + 1: im
-        flt2 y;
-        y.x = acc[r];
-        y.y = acc[r + 1];
-        psi[gb + member_off<K>(i >> 1, g)] = y;
+        for (int r = 0; r < MS::NACC; r += 2) {
+          const int mem = MS::MPB * rb + MS::out_member(l, r);
+          E y;
+          y.x = acc[r];
+          y.y = acc[r + 1];
+          st(psi + gb + member_off<K>(mem, g), y);
+        }
       }
     }
   }
 }
 
-template <int K>
+template <typename R, int K>
 hipError_t run_mfma(void* psi, int n, const DenseGeo& g, const void* m, hipStream_t s) {
-  constexpr int D = 1 << K;
-  constexpr int NC = 32 * (4 / ((2 * D) / 32));
+  constexpr int NC = mfma_cols<R, K>();
+  constexpr size_t lds = mfma_lds<R, K>();
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_dense_mfma<R, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
   const uint64_t ngroups = 1ull << (n - K);
-  const uint64_t blocks = capped_grid((ngroups + NC - 1) / NC);
-  hipLaunchKernelGGL((k_dense_mfma<K>), dim3((unsigned)blocks), dim3(kBlock), 0, s, (flt2*)psi, ngroups, g,
-                     (const float*)m);
+  const uint64_t tiles = (ngroups + NC - 1) / NC;
+  // persistent blocks: enough to fill the chip several times over, each
+  // amortising its staged U over many column tiles
+  const uint64_t blocks = tiles < 4096 ? tiles : 4096;
+  hipLaunchKernelGGL((k_dense_mfma<R, K>), dim3((unsigned)blocks), dim3(kBlock), lds, s,
+                     (typename mfma_shape<R>::E*)psi, ngroups, g, (const R*)m);
   return hipGetLastError();
 }
 
@@ -205,12 +282,20 @@ hipError_t launch_dense_kq(sv_dtype dt, void* psi, int n, int k, const int* q, c
       sorted[j - 1] = tmp;
     }
   for (int i = 0; i < k; ++i) g.zs[i] = (unsigned)sorted[i];
-  if (dt == SV_C128) return dispatch<dbl2>(psi, n, k, g, m_dev, s);
+  if (dt == SV_C128) {
+    switch (k) {
+      case 3: return run_mfma<double, 3>(psi, n, g, m_dev, s);
+      case 4: return run_mfma<double, 4>(psi, n, g, m_dev, s);
+      case 5: return run_mfma<double, 5>(psi, n, g, m_dev, s);
+      case 6: return run_mfma<double, 6>(psi, n, g, m_dev, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (mfma && k >= 4) {
     switch (k) {
-      case 4: return run_mfma<4>(psi, n, g, m_dev, s);
-      case 5: return run_mfma<5>(psi, n, g, m_dev, s);
-      case 6: return run_mfma<6>(psi, n, g, m_dev, s);
+      case 4: return run_mfma<float, 4>(psi, n, g, m_dev, s);
+      case 5: return run_mfma<float, 5>(psi, n, g, m_dev, s);
+      case 6: return run_mfma<float, 6>(psi, n, g, m_dev, s);
     }
   }
   return dispatch<flt2>(psi, n, k, g, m_dev, s);
