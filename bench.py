@@ -192,6 +192,128 @@ def circuit_bench(args):
                       "circuits": out}))
 
 
+def serve_cpu_baseline(requests, budget_s: float = 15.0):
+    """The oracle on a bounded sample of the serving mix: for one request of
+    each N in the mix, time its first few gates (at least 2, more while the
+    per-N share of `budget_s` allows), extrapolate linearly to the request's
+    full gate count, and weight by how often that N occurs.  Returns estimated
+    oracle circuits/s over the whole mix."""
+    import numpy as np
+
+    import oracle
+    from oracle import sv_oracle as so
+
+    by_n = {}
+    for r in requests:
+        by_n.setdefault(r.n, []).append(r)
+    per_n = budget_s / max(1, len(by_n))
+    total_s = 0.0
+    timed = 0
+    for n in sorted(by_n):
+        rs = by_n[n]
+        gates = rs[0].circuit()
+        psi = np.zeros(1 << n, dtype=np.complex128)
+        psi[0] = 1.0
+        t0 = time.perf_counter()
+        k = 0
+        while k < len(gates) and (k < 2 or time.perf_counter() - t0 < per_n):
+            psi = so.apply_gate(psi, gates[k])
+            k += 1
+        per_gate = (time.perf_counter() - t0) / k
+        timed += k
+        mean_gates = sum(r.depth * (r.n + r.n // 2) for r in rs) / len(rs)  # N rotations + N/2 CNOTs per pair
+        total_s += per_gate * mean_gates * len(rs)
+    return {"value": round(len(requests) / total_s, 4), "unit": "circuits/s", "cores": _cpu_threads(),
+            "kind": "oracle",
+            "sample": f"oracle (numpy complex128) timed on the first gates of one request per N "
+                      f"({timed} gates over N={min(by_n)}..{max(by_n)}), extrapolated linearly in gate count "
+                      f"to the {len(requests)}-request mix"}
+
+
+def _cpu_threads():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
+
+
+def serve_bench(args):
+    """Serving form: a stream of circuit requests (N ~ U{12..nmax}, depth ~
+    U{20..200} layer pairs of N rotations + N/2 CNOTs, Poisson arrivals) served
+    by the continuous-batching loop, in complex64 and complex128.  For each
+    dtype: a closed-loop run (all requests at t=0) measures the saturated
+    throughput X; the timed run replays the arrivals at rate 0.8 X.  The
+    reported value is the complex64 timed run's served circuits/s."""
+    from svgen import serving_requests
+    from paper_2409_14697_amd.serve import marshal_requests, jobs_from_marshalled
+
+    reqs = serving_requests(args.requests, seed=5, n_range=(12, args.nmax), depth_range=(20, 200))
+    t0 = time.perf_counter()
+    marshalled = marshal_requests(reqs, workers=min(16, _cpu_threads()))
+    prep_s = time.perf_counter() - t0
+
+    import torch
+
+    from paper_2409_14697_amd.serve import DeviceEngine, Server, free_budget
+
+    torch.cuda.set_device(0)
+    out = {}
+    dtypes = [d for d in args.dtypes.split(",") if d]
+    launch = {}
+    for dt in dtypes:
+        def run(rate, budget=None, timed=False):
+            eng = DeviceEngine(dt, time_launches=timed)
+            srv = Server(eng, budget or free_budget(0.8), max_active=args.max_active,
+                         plan_workers=min(16, _cpu_threads()))
+            res = srv.run(jobs_from_marshalled(reqs, marshalled, rate))
+            stats = eng.launch_stats() if timed else None
+            eng.close()
+            torch.cuda.synchronize()
+            return res, stats
+        # warm-up: allocator, kernels, planner threads
+        warm = max(1, min(32, len(reqs) // 8))
+        eng = DeviceEngine(dt)
+        Server(eng, free_budget(0.8), plan_workers=4).run(jobs_from_marshalled(reqs[:warm], marshalled[:warm], None))
+        eng.close()
+        closed, _ = run(None)
+        sat = closed.summary()["circuits_per_s"]
+        lam = args.rate_fraction * sat
+        timed, stats = run(lam, timed=True)
+        rec = {"closed_loop": _round(closed.summary()), "rate_per_s": round(lam, 3),
+               "poisson": _round(timed.summary()), "launch": _round(stats)}
+        if args.contention_gib > 0:
+            cont, _ = run(lam, budget=int(args.contention_gib * (1 << 30)))
+            rec["contention"] = dict(_round(cont.summary()), budget_gib=args.contention_gib)
+        out[dt] = rec
+        launch[dt] = stats
+        print(f"[serve] {dt}: closed {sat:.1f}/s, poisson {timed.summary()['circuits_per_s']:.1f}/s "
+              f"p99 {timed.summary()['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    main_dt = "c64" if "c64" in out else dtypes[0]
+    summ = out[main_dt]["poisson"]
+    st = launch[main_dt]
+    line = {"metric": "served circuits/s", "value": summ["circuits_per_s"], "unit": "circuits/s", "n_gpus": 1,
+            "steps": summ["completed"], "warmup": 1, "ms_per_step": round(1e3 / max(summ["circuits_per_s"], 1e-9), 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32" if main_dt == "c64" else "f64", "data": "synthetic",
+            "config": {"workload": f"serving: {len(reqs)} requests, N~U{{12..{args.nmax}}}, depth~U{{20..200}} layer "
+                                   f"pairs, Poisson arrivals at {args.rate_fraction} x closed-loop throughput, "
+                                   f"budget 0.8 x free HBM, {main_dt} timed run",
+                       "p99_ms": summ["p99_ms"], "p50_ms": summ["p50_ms"]},
+            "roofline": {"bound": "hbm", "achieved": round(st["GBs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(st["GBs"] / PEAK_HBM_GBS, 4), "traffic": None,
+                         "kernel": "k_pass_batch", "mean_launch_us": round(st["mean_launch_us"], 2)},
+            "serving": out, "prep_s": round(prep_s, 2)}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = serve_cpu_baseline(reqs)
+    print(json.dumps(line))
+
+
+def _round(d):
+    if d is None:
+        return None
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+
+
 def _compare(a64, b128):
     """FP64 error metrics of a complex64 state against a complex128 one
     (chunked, on the device): max-abs, relative L2, infidelity, norm drift."""
@@ -289,7 +411,13 @@ def main():
     ap.add_argument("--dtypes", default="c128,c64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ceiling", action="store_true", help="also time the 16-byte copy kernel")
-    ap.add_argument("--workload", default="gates", choices=["gates", "circuit", "precision"],
+    ap.add_argument("--requests", type=int, default=512, help="serve workload: number of requests")
+    ap.add_argument("--nmax", type=int, default=26, help="serve workload: largest request N")
+    ap.add_argument("--max-active", type=int, default=512, help="serve workload: slot cap")
+    ap.add_argument("--rate-fraction", type=float, default=0.8, help="serve workload: arrival rate / saturated rate")
+    ap.add_argument("--contention-gib", type=float, default=0.0,
+                    help="serve workload: also run with this HBM budget (GiB)")
+    ap.add_argument("--workload", default="gates", choices=["gates", "circuit", "precision", "serve"],
                     help="gates: the per-gate sweep benchmark (default); circuit: N=32 circuits; "
                          "precision: FP32 MFMA vs FP64 fused Haar gates")
     ap.add_argument("--gates", type=int, default=2000, help="precision workload: number of fused gates")
@@ -307,6 +435,9 @@ def main():
         return
     if args.workload == "precision":
         precision_bench(args)
+        return
+    if args.workload == "serve":
+        serve_bench(args)
         return
 
     import torch

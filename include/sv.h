@@ -117,6 +117,9 @@ typedef struct {
   int32_t renorm_interval;  /* complex64 states: rescale to unit norm (FP64
                                norm) every R dense ops; 0 = never; default 0   */
   int32_t mode;             /* sv_mode; default SV_MODE_AUTO                   */
+  int32_t max_pass_ops;     /* tile passes: at most this many ops per pass, so
+                               that passes of many states in one launch take
+                               similar times; 0 = no limit; default 0          */
 } sv_opts;
 
 /* Fill *o with the defaults.  Never fails for non-null o. */
@@ -136,8 +139,11 @@ sv_status sv_default_opts(sv_opts *o);
 sv_status sv_create(int n_qubits, sv_dtype dt, void *dev_ptr, void *hip_stream,
                     unsigned flags, sv_state **out);
 
-/* Destroy a state.  Waits for its stream; frees only memory the library
- * allocated.  NULL is accepted. */
+/* Destroy a state; frees only memory the library allocated.  When it frees
+ * device memory (an owned state buffer, reduction scratch, upload buffers) it
+ * first waits for the state's stream; a state on a borrowed buffer that never
+ * needed scratch returns at once, and the caller orders the reuse of its
+ * buffer after the work it queued.  NULL is accepted. */
 sv_status sv_destroy(sv_state *s);
 
 /* Query n, dtype and device pointer (any output may be NULL). */
@@ -209,6 +215,64 @@ sv_status sv_sync(sv_state *s);
 
 /* Message for the last failure on the calling thread ("" if none). */
 const char *sv_last_error(void);
+
+/* ---- Serving: device-resident programs and batched passes ---------------
+ * A request loop keeps many states resident and advances all of them with one
+ * kernel launch per step (continuous batching): each launch runs the next
+ * in-cache tile pass of every active state, so requests admitted later join
+ * the next launch and their work overlaps with older ones on the device. */
+typedef struct sv_program sv_program;  /* tile-pass program of one plan, in device memory */
+typedef struct sv_batcher sv_batcher;  /* launches one pass of many states at once        */
+
+/* Device bytes a program of plan p occupies (for a caller-owned buffer).
+ * Errors: SV_ERR_ARG, SV_ERR_UNSUPPORTED (see sv_program_create). */
+sv_status sv_program_bytes(const sv_plan *p, size_t *bytes);
+
+/* Upload the tile-pass program of plan p, stream-ordered on hip_stream (NULL
+ * = null stream).  The plan must consist only of in-cache tile passes (mode
+ * SV_MODE_PASS, n >= 5, gates of at most 2 qubits); otherwise
+ * SV_ERR_UNSUPPORTED.
+ *   dev_buf : NULL -> the library allocates the device copy and frees it in
+ *             sv_program_destroy; otherwise caller device memory of at least
+ *             sv_program_bytes(p) bytes, 256-byte aligned, kept alive while
+ *             work that uses the program may run.
+ * The program keeps its own host copy; the plan may be destroyed at once.
+ * Errors: SV_ERR_ARG, SV_ERR_UNSUPPORTED, SV_ERR_NOMEM, SV_ERR_DEVICE. */
+sv_status sv_program_create(const sv_plan *p, void *dev_buf, size_t buf_bytes, void *hip_stream,
+                            sv_program **out);
+
+/* Qubits, dtype and number of passes of a program (outputs may be NULL). */
+sv_status sv_program_info(const sv_program *prog, int32_t *n_qubits, sv_dtype *dt, int32_t *n_passes);
+
+/* Free a program.  When the library owns its device copy it first waits for
+ * the upload stream; with a caller buffer it waits only for the program's
+ * own upload (so that its host copy may be freed) and the caller orders the
+ * reuse of the buffer after the work that reads it.  NULL is accepted. */
+sv_status sv_program_destroy(sv_program *prog);
+
+/* A batcher owns its stream and small descriptor buffers. */
+sv_status sv_batcher_create(void *hip_stream, sv_batcher **out);
+
+/* One launch: for every i < count, run pass pass_index[i] of programs[i] on
+ * states[i].  All states and programs must share one dtype; states[i] must
+ * have programs[i]'s qubit count; a state may appear at most once.  Work is
+ * enqueued on the batcher's stream: the caller orders it against other work
+ * on the states (e.g. by creating the states on the same stream).  A state's
+ * result depends only on its own program -- bitwise the same in any batch.
+ * Errors: SV_ERR_ARG (count, null entries, mismatched n/dtype, pass index out
+ * of range), SV_ERR_NOMEM, SV_ERR_DEVICE. */
+sv_status sv_batcher_run(sv_batcher *b, int count, sv_state *const *states, const sv_program *const *programs,
+                         const int32_t *pass_index);
+
+/* Marginal probabilities of one state as sv_measure_probs defines them, but
+ * enqueued on the batcher's stream with reduction scratch the batcher owns,
+ * so that serving loops allocate nothing per request.  out_dev: device
+ * memory for 2^m doubles.  Errors: SV_ERR_ARG, SV_ERR_QUBIT, SV_ERR_NOMEM,
+ * SV_ERR_DEVICE. */
+sv_status sv_batcher_probs(sv_batcher *b, const sv_state *s, const int32_t *qubits, int m, double *out_dev);
+
+/* Free a batcher (waits for its stream).  NULL is accepted. */
+sv_status sv_batcher_destroy(sv_batcher *b);
 
 /* Library version string. */
 const char *sv_version(void);

@@ -42,7 +42,8 @@ class SvGate(ctypes.Structure):
 
 class SvOpts(ctypes.Structure):
     _fields_ = [("max_fuse_qubits", c_int32), ("lds_qubits", c_int32), ("pinned_low_bits", c_int32),
-                ("reorder", c_int32), ("fp32_mfma", c_int32), ("renorm_interval", c_int32), ("mode", c_int32)]
+                ("reorder", c_int32), ("fp32_mfma", c_int32), ("renorm_interval", c_int32), ("mode", c_int32),
+                ("max_pass_ops", c_int32)]
 
 
 _lib = None
@@ -86,6 +87,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sv_version": (c_char_p, []),
         "sv_util_copy": (S, [c_void_p, c_void_p, c_size_t, c_void_p]),
         "sv_gate_kernel": (S, [c_int, c_int, POINTER(SvGate), c_char_p, c_size_t]),
+        "sv_program_bytes": (S, [c_void_p, POINTER(c_size_t)]),
+        "sv_program_create": (S, [c_void_p, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
+        "sv_program_info": (S, [c_void_p, POINTER(c_int32), POINTER(c_int), POINTER(c_int32)]),
+        "sv_program_destroy": (S, [c_void_p]),
+        "sv_batcher_create": (S, [c_void_p, POINTER(c_void_p)]),
+        "sv_batcher_run": (S, [c_void_p, c_int, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_int32)]),
+        "sv_batcher_probs": (S, [c_void_p, c_void_p, POINTER(c_int32), c_int, c_void_p]),
+        "sv_batcher_destroy": (S, [c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -163,9 +172,27 @@ class Plan:
         self._h = h
         self.n, self.dtype = n, dtype
 
+    @classmethod
+    def from_array(cls, n: int, dtype: str, marshalled: tuple, n_gates: int, opts: Optional[dict] = None) -> "Plan":
+        """Plan from gates already marshalled by make_gates (array, keepalive)."""
+        self = cls.__new__(cls)
+        arr, _ = marshalled
+        o = make_opts(opts)
+        h = c_void_p()
+        check(load_library().sv_fuse(n, _dt_code(dtype), arr, n_gates, byref(o), byref(h)))
+        self._h = h
+        self.n, self.dtype = n, dtype
+        return self
+
     @property
     def handle(self):
         return self._h
+
+    def program_bytes(self) -> int:
+        """Device bytes of this plan's tile-pass program (sv_program_bytes)."""
+        nb = c_size_t()
+        check(load_library().sv_program_bytes(self._h, byref(nb)))
+        return nb.value
 
     def info(self):
         a, b = c_size_t(), c_size_t()
@@ -291,6 +318,86 @@ class StateVector:
     def close(self):
         if getattr(self, "_h", None):
             load_library().sv_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ serving
+class Program:
+    """A plan's tile-pass program resident in device memory (sv_program_*).
+
+    With buffer=None the program's bytes live in a uint8 torch tensor of the
+    caching allocator (no hipMalloc once the allocator is warm); the tensor is
+    kept alive by this object."""
+
+    def __init__(self, plan: Plan, stream=None, buffer=None):
+        import torch
+        lib = load_library()
+        nb = c_size_t()
+        check(lib.sv_program_bytes(plan.handle, byref(nb)))
+        self.nbytes = nb.value
+        if buffer is None:
+            buffer = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device="cuda")
+        self.buffer = buffer
+        s = stream if stream is not None else torch.cuda.current_stream()
+        h = c_void_p()
+        check(lib.sv_program_create(plan.handle, c_void_p(buffer.data_ptr()), buffer.numel(),
+                                    c_void_p(s.cuda_stream), byref(h)))
+        self._h = h
+        n, dt, npass = c_int32(), c_int(), c_int32()
+        check(lib.sv_program_info(h, byref(n), byref(dt), byref(npass)))
+        self.n, self.n_passes = n.value, npass.value
+        self.dtype = "c128" if dt.value == SV_C128 else "c64"
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().sv_program_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batcher:
+    """One kernel launch runs one tile pass of many states (sv_batcher_*)."""
+
+    def __init__(self, stream=None):
+        import torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = c_void_p()
+        check(load_library().sv_batcher_create(c_void_p(self.stream.cuda_stream), byref(h)))
+        self._h = h
+
+    def run(self, states: Sequence[StateVector], programs: Sequence[Program], pass_index: Sequence[int]):
+        k = len(states)
+        if len(programs) != k or len(pass_index) != k:
+            raise ValueError("states, programs and pass_index differ in length")
+        sa = (c_void_p * max(k, 1))(*[st.handle.value for st in states])
+        pa = (c_void_p * max(k, 1))(*[pr.handle.value for pr in programs])
+        ia = (c_int32 * max(k, 1))(*[int(i) for i in pass_index])
+        check(load_library().sv_batcher_run(self._h, k, sa, pa, ia))
+
+    def probs(self, state: StateVector, qubits: Sequence[int], out):
+        qs = [int(q) for q in qubits]
+        qa = (c_int32 * max(1, len(qs)))(*qs)
+        check(load_library().sv_batcher_probs(self._h, state.handle, qa, len(qs), c_void_p(out.data_ptr())))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().sv_batcher_destroy(self._h)
             self._h = c_void_p()
 
     def __del__(self):

@@ -99,6 +99,19 @@ sv_status renormalize(sv_state* s) {
   return SV_OK;
 }
 
+sv_status probs_args(int n, const int32_t* qubits, int m, const double* out_dev, int* qs) {
+  if (m < 0 || m > n) return fail(SV_ERR_ARG, "m=%d outside 0..%d", m, n);
+  if (m > 0 && !qubits) return fail(SV_ERR_ARG, "null qubit list");
+  if (!out_dev) return fail(SV_ERR_ARG, "null output");
+  for (int r = 0; r < m; ++r) {
+    if (qubits[r] < 0 || qubits[r] >= n) return fail(SV_ERR_QUBIT, "qubit %d out of range", qubits[r]);
+    for (int j = 0; j < r; ++j)
+      if (qubits[j] == qubits[r]) return fail(SV_ERR_QUBIT, "qubit %d repeated", qubits[r]);
+    qs[r] = qubits[r];
+  }
+  return SV_OK;
+}
+
 static sv_status check_state(const sv_state* s) {
   if (!s) return fail(SV_ERR_ARG, "null state");
   return SV_OK;
@@ -112,6 +125,7 @@ static sv_status validate_opts(const sv_opts& o) {
     return fail(SV_ERR_ARG, "pinned_low_bits %d outside 0..8", o.pinned_low_bits);
   if (o.renorm_interval < 0) return fail(SV_ERR_ARG, "negative renorm_interval");
   if (o.mode < SV_MODE_AUTO || o.mode > SV_MODE_PASS) return fail(SV_ERR_ARG, "bad mode %d", o.mode);
+  if (o.max_pass_ops < 0) return fail(SV_ERR_ARG, "negative max_pass_ops");
   return SV_OK;
 }
 
@@ -130,6 +144,7 @@ sv_status sv_default_opts(sv_opts* o) {
   o->fp32_mfma = 1;
   o->renorm_interval = 0;
   o->mode = SV_MODE_AUTO;
+  o->max_pass_ops = 0;
   return SV_OK;
 }
 
@@ -180,7 +195,8 @@ sv_status sv_destroy(sv_state* s) {
   clear_error();
   if (!s) return SV_OK;
   sv_status st = SV_OK;
-  if (hipStreamSynchronize(s->stream) != hipSuccess) st = fail(SV_ERR_DEVICE, "stream sync failed in destroy");
+  const bool frees = (s->owned && s->ptr) || s->scratch || s->up_dev || s->up_host;
+  if (frees && hipStreamSynchronize(s->stream) != hipSuccess) st = fail(SV_ERR_DEVICE, "stream sync failed in destroy");
   if (s->owned && s->ptr) (void)hipFree(s->ptr);
   if (s->scratch) (void)hipFree(s->scratch);
   if (s->up_dev) (void)hipFree(s->up_dev);
@@ -338,16 +354,8 @@ sv_status sv_permute_qubits(sv_state* s, const int32_t* dest) {
 sv_status sv_measure_probs(sv_state* s, const int32_t* qubits, int m, double* out_dev) {
   clear_error();
   if (sv_status st = check_state(s)) return st;
-  if (m < 0 || m > s->n) return fail(SV_ERR_ARG, "m=%d outside 0..%d", m, s->n);
-  if (m > 0 && !qubits) return fail(SV_ERR_ARG, "null qubit list");
-  if (!out_dev) return fail(SV_ERR_ARG, "null output");
   int qs[SV_MAX_QUBITS];
-  for (int r = 0; r < m; ++r) {
-    if (qubits[r] < 0 || qubits[r] >= s->n) return fail(SV_ERR_QUBIT, "qubit %d out of range", qubits[r]);
-    for (int j = 0; j < r; ++j)
-      if (qubits[j] == qubits[r]) return fail(SV_ERR_QUBIT, "qubit %d repeated", qubits[r]);
-    qs[r] = qubits[r];
-  }
+  if (sv_status st = probs_args(s->n, qubits, m, out_dev, qs)) return st;
   const size_t need = probs_scratch_bytes(s->n, m, qs);
   if (sv_status st = ensure_scratch(s, 256 + need)) return st;
   SV_HIP_TRY(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, (unsigned char*)s->scratch + 256, s->stream));

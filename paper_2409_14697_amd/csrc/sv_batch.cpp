@@ -1,0 +1,307 @@
+// Serving support: device-resident tile-pass programs and the batcher that
+// runs one pass of many states per kernel launch (continuous batching).
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "sv_host.h"
+
+struct sv_program {
+  int n = 0;
+  sv_dtype dt = SV_C128;
+  int n_passes = 0;
+  int max_m = 0;
+  std::vector<int> pass_m;  // local qubits of each pass
+  std::vector<unsigned char> host;  // [descs][stages][ops][pool], kept for the async upload
+  void* dev = nullptr;
+  bool owned = false;
+  hipEvent_t uploaded = nullptr;  // after the upload: the host copy may be freed
+  size_t off_desc = 0, off_stage = 0, off_ops = 0, off_pool = 0;
+  hipStream_t stream = nullptr;
+};
+
+struct sv_batcher {
+  hipStream_t stream = nullptr;
+  static constexpr int kSlots = 4;  // descriptor buffers in flight
+  void* host[kSlots] = {nullptr, nullptr, nullptr, nullptr};
+  void* dev[kSlots] = {nullptr, nullptr, nullptr, nullptr};
+  size_t cap[kSlots] = {0, 0, 0, 0};
+  hipEvent_t done[kSlots] = {nullptr, nullptr, nullptr, nullptr};
+  bool used[kSlots] = {false, false, false, false};
+  int next = 0;
+  void* scratch = nullptr;  // reduction partials of sv_batcher_probs
+  size_t scratch_bytes = 0;
+};
+
+namespace sv {
+namespace {
+
+// Pack the plan's tile passes into prog->host (offsets 256-byte aligned).
+sv_status pack_program(const sv_plan* p, sv_program* prog) {
+  if (!p || (p->dt != SV_C64 && p->dt != SV_C128)) return fail(SV_ERR_ARG, "bad plan");
+  const bool f32 = p->dt == SV_C64;
+  const size_t scal = f32 ? sizeof(float) : sizeof(double);
+  std::vector<PassDescDev> descs;
+  std::vector<PassStageDev> stages;
+  std::vector<PassOpDev> pops;
+  std::vector<cd> pool;
+  for (const Pass& ps : p->passes) {
+    if (ps.kind != PASS_TILE && ps.kind != PASS_PERMUTE)
+      return fail(SV_ERR_UNSUPPORTED, "program needs a plan of in-cache tile passes only (build it with mode PASS)");
+    PassDescDev d{};
+    d.m = (uint32_t)ps.n_local;
+    d.stage_first = (uint32_t)stages.size();
+    d.stage_count = (uint32_t)ps.stages.size();
+    for (int j = 0; j < ps.n_local; ++j) {
+      d.lpos[j] = ps.lpos[j];
+      d.wpos[j] = ps.wpos[j];
+      d.lmask |= 1ull << ps.lpos[j];
+    }
+    for (const StageHost& sh : ps.stages) {
+      PassStageDev sd{};
+      uint32_t srt[kPassRegBits];
+      for (int r = 0; r < kPassRegBits; ++r) sd.q[r] = srt[r] = sh.q[r];
+      std::sort(srt, srt + kPassRegBits);
+      for (int r = 0; r < kPassRegBits; ++r) sd.qsort[r] = srt[r];
+      sd.op_first = (uint32_t)pops.size();
+      sd.op_count = (uint32_t)sh.ops.size();
+      const uint32_t mbase = (uint32_t)pool.size();
+      for (PassOpDev od : sh.ops) {
+        od.mat += mbase;
+        pops.push_back(od);
+      }
+      pool.insert(pool.end(), sh.mats.begin(), sh.mats.end());
+      stages.push_back(sd);
+    }
+    descs.push_back(d);
+    prog->pass_m.push_back(ps.n_local);
+    prog->max_m = std::max(prog->max_m, ps.n_local);
+  }
+  std::vector<unsigned char>& host = prog->host;
+  host.clear();
+  auto align = [&]() { host.resize((host.size() + 255) / 256 * 256); };
+  auto put = [&](const void* src, size_t bytes) {
+    align();
+    const size_t at = host.size();
+    host.resize(at + bytes);
+    if (bytes) std::memcpy(host.data() + at, src, bytes);
+    return at;
+  };
+  prog->off_desc = put(descs.data(), descs.size() * sizeof(PassDescDev));
+  prog->off_stage = put(stages.data(), stages.size() * sizeof(PassStageDev));
+  prog->off_ops = put(pops.data(), pops.size() * sizeof(PassOpDev));
+  align();
+  prog->off_pool = host.size();
+  host.resize(host.size() + pool.size() * 2 * scal);
+  for (size_t e = 0; e < pool.size(); ++e) {
+    if (f32) {
+      float* d = (float*)(host.data() + prog->off_pool);
+      d[2 * e] = (float)pool[e].real();
+      d[2 * e + 1] = (float)pool[e].imag();
+    } else {
+      double* d = (double*)(host.data() + prog->off_pool);
+      d[2 * e] = pool[e].real();
+      d[2 * e + 1] = pool[e].imag();
+    }
+  }
+  align();
+  prog->n = p->n;
+  prog->dt = p->dt;
+  prog->n_passes = (int)descs.size();
+  return SV_OK;
+}
+
+}  // namespace
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+sv_status sv_program_bytes(const sv_plan* p, size_t* bytes) {
+  clear_error();
+  if (!p || !bytes) return fail(SV_ERR_ARG, "null argument");
+  sv_program tmp;
+  if (sv_status st = pack_program(p, &tmp)) return st;
+  *bytes = tmp.host.size();
+  return SV_OK;
+}
+
+sv_status sv_program_create(const sv_plan* p, void* dev_buf, size_t buf_bytes, void* stream, sv_program** out) {
+  clear_error();
+  if (!p || !out) return fail(SV_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (dev_buf && ((uintptr_t)dev_buf & 255u)) return fail(SV_ERR_ARG, "program buffer not 256-byte aligned");
+  sv_program* prog = new (std::nothrow) sv_program();
+  if (!prog) return fail(SV_ERR_NOMEM, "host allocation failed");
+  prog->stream = (hipStream_t)stream;
+  sv_status st = pack_program(p, prog);
+  if (st == SV_OK) {
+    const size_t bytes = prog->host.size();
+    if (dev_buf) {
+      if (buf_bytes < bytes) st = fail(SV_ERR_ARG, "program buffer of %zu bytes, %zu needed", buf_bytes, bytes);
+      prog->dev = dev_buf;
+    } else if (hipMalloc(&prog->dev, bytes) != hipSuccess) {
+      prog->dev = nullptr;
+      st = fail(SV_ERR_NOMEM, "cannot allocate %zu bytes for the program", bytes);
+    } else {
+      prog->owned = true;
+    }
+  }
+  if (st == SV_OK && hipEventCreateWithFlags(&prog->uploaded, hipEventDisableTiming) != hipSuccess) {
+    prog->uploaded = nullptr;
+    st = fail(SV_ERR_DEVICE, "hipEventCreate failed");
+  }
+  if (st == SV_OK && (hipMemcpyAsync(prog->dev, prog->host.data(), prog->host.size(), hipMemcpyHostToDevice,
+                                     prog->stream) != hipSuccess ||
+                      hipEventRecord(prog->uploaded, prog->stream) != hipSuccess))
+    st = fail(SV_ERR_DEVICE, "program upload failed");
+  if (st != SV_OK) {
+    (void)hipStreamSynchronize(prog->stream);
+    if (prog->owned) (void)hipFree(prog->dev);
+    if (prog->uploaded) (void)hipEventDestroy(prog->uploaded);
+    delete prog;
+    return st;
+  }
+  *out = prog;
+  return SV_OK;
+}
+
+sv_status sv_program_info(const sv_program* prog, int32_t* n, sv_dtype* dt, int32_t* n_passes) {
+  clear_error();
+  if (!prog) return fail(SV_ERR_ARG, "null program");
+  if (n) *n = prog->n;
+  if (dt) *dt = prog->dt;
+  if (n_passes) *n_passes = prog->n_passes;
+  return SV_OK;
+}
+
+sv_status sv_program_destroy(sv_program* prog) {
+  clear_error();
+  if (!prog) return SV_OK;
+  sv_status st = SV_OK;
+  if (prog->owned) {
+    if (hipStreamSynchronize(prog->stream) != hipSuccess) st = fail(SV_ERR_DEVICE, "stream sync failed");
+    (void)hipFree(prog->dev);
+  } else if (hipEventSynchronize(prog->uploaded) != hipSuccess) {  // the upload may still read the host copy
+    st = fail(SV_ERR_DEVICE, "event sync failed");
+  }
+  (void)hipEventDestroy(prog->uploaded);
+  delete prog;
+  return st;
+}
+
+sv_status sv_batcher_create(void* stream, sv_batcher** out) {
+  clear_error();
+  if (!out) return fail(SV_ERR_ARG, "null output");
+  sv_batcher* b = new (std::nothrow) sv_batcher();
+  if (!b) return fail(SV_ERR_NOMEM, "host allocation failed");
+  b->stream = (hipStream_t)stream;
+  for (int i = 0; i < sv_batcher::kSlots; ++i)
+    if (hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming) != hipSuccess) {
+      sv_batcher_destroy(b);
+      return fail(SV_ERR_DEVICE, "hipEventCreate failed");
+    }
+  *out = b;
+  return SV_OK;
+}
+
+sv_status sv_batcher_run(sv_batcher* b, int count, sv_state* const* states, const sv_program* const* programs,
+                         const int32_t* pass_index) {
+  clear_error();
+  if (!b) return fail(SV_ERR_ARG, "null batcher");
+  if (count <= 0) return count == 0 ? SV_OK : fail(SV_ERR_ARG, "negative count");
+  if (!states || !programs || !pass_index) return fail(SV_ERR_ARG, "null array");
+  std::vector<BatchItemDev> items((size_t)count);
+  uint64_t tiles = 0;
+  int max_m = 0;
+  sv_dtype dt = SV_C128;
+  for (int i = 0; i < count; ++i) {
+    const sv_state* s = states[i];
+    const sv_program* p = programs[i];
+    if (!s || !p) return fail(SV_ERR_ARG, "null state or program at %d", i);
+    if (i == 0) dt = s->dt;
+    if (s->dt != dt || p->dt != dt) return fail(SV_ERR_ARG, "item %d: mixed dtypes in one batch", i);
+    if (p->n != s->n) return fail(SV_ERR_ARG, "item %d: program for %d qubits, state has %d", i, p->n, s->n);
+    if (pass_index[i] < 0 || pass_index[i] >= p->n_passes)
+      return fail(SV_ERR_ARG, "item %d: pass %d out of range (%d passes)", i, pass_index[i], p->n_passes);
+    for (int j = 0; j < i; ++j)
+      if (states[j] == s) return fail(SV_ERR_ARG, "state %d appears twice in one batch", i);
+    const int m = p->pass_m[pass_index[i]];
+    BatchItemDev& it = items[i];
+    unsigned char* pd = (unsigned char*)p->dev;
+    it.psi = s->ptr;
+    it.passes = (const PassDescDev*)(pd + p->off_desc);
+    it.stages = (const PassStageDev*)(pd + p->off_stage);
+    it.ops = (const PassOpDev*)(pd + p->off_ops);
+    it.mats = pd + p->off_pool;
+    it.tile_begin = tiles;
+    it.n = s->n;
+    it.pass = pass_index[i];
+    tiles += 1ull << (s->n - m);
+    max_m = std::max(max_m, m);
+  }
+  const size_t bytes = items.size() * sizeof(BatchItemDev);
+  const int k = b->next;
+  b->next = (b->next + 1) % sv_batcher::kSlots;
+  if (b->used[k]) SV_HIP_TRY(hipEventSynchronize(b->done[k]));  // slot's last launch has read it
+  if (bytes > b->cap[k]) {
+    if (b->dev[k]) {
+      SV_HIP_TRY(hipFree(b->dev[k]));
+      SV_HIP_TRY(hipHostFree(b->host[k]));
+      b->dev[k] = b->host[k] = nullptr;
+    }
+    size_t cap = 4096;
+    while (cap < bytes) cap <<= 1;
+    if (hipMalloc(&b->dev[k], cap) != hipSuccess) return fail(SV_ERR_NOMEM, "batch descriptor buffer");
+    if (hipHostMalloc(&b->host[k], cap, hipHostMallocDefault) != hipSuccess)
+      return fail(SV_ERR_NOMEM, "pinned batch descriptor buffer");
+    b->cap[k] = cap;
+  }
+  std::memcpy(b->host[k], items.data(), bytes);
+  SV_HIP_TRY(hipMemcpyAsync(b->dev[k], b->host[k], bytes, hipMemcpyHostToDevice, b->stream));
+  SV_HIP_TRY(launch_pass_batch(dt, (const BatchItemDev*)b->dev[k], count, tiles, max_m, b->stream));
+  SV_HIP_TRY(hipEventRecord(b->done[k], b->stream));
+  b->used[k] = true;
+  return SV_OK;
+}
+
+sv_status sv_batcher_probs(sv_batcher* b, const sv_state* s, const int32_t* qubits, int m, double* out_dev) {
+  clear_error();
+  if (!b || !s) return fail(SV_ERR_ARG, "null batcher or state");
+  int qs[SV_MAX_QUBITS];
+  if (sv_status st = probs_args(s->n, qubits, m, out_dev, qs)) return st;
+  const size_t need = std::max<size_t>(probs_scratch_bytes(s->n, m, qs), 256);
+  if (need > b->scratch_bytes) {
+    if (b->scratch) {
+      SV_HIP_TRY(hipStreamSynchronize(b->stream));  // earlier reductions may still use it
+      SV_HIP_TRY(hipFree(b->scratch));
+      b->scratch = nullptr;
+      b->scratch_bytes = 0;
+    }
+    if (hipMalloc(&b->scratch, need) != hipSuccess) {
+      b->scratch = nullptr;
+      return fail(SV_ERR_NOMEM, "cannot allocate %zu bytes of reduction scratch", need);
+    }
+    b->scratch_bytes = need;
+  }
+  SV_HIP_TRY(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, b->scratch, b->stream));
+  return SV_OK;
+}
+
+sv_status sv_batcher_destroy(sv_batcher* b) {
+  clear_error();
+  if (!b) return SV_OK;
+  sv_status st = SV_OK;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) st = fail(SV_ERR_DEVICE, "stream sync failed");
+  for (int i = 0; i < sv_batcher::kSlots; ++i) {
+    if (b->dev[i]) (void)hipFree(b->dev[i]);
+    if (b->host[i]) (void)hipHostFree(b->host[i]);
+    if (b->done[i]) (void)hipEventDestroy(b->done[i]);
+  }
+  if (b->scratch) (void)hipFree(b->scratch);
+  delete b;
+  return st;
+}
+
+}  // extern "C"

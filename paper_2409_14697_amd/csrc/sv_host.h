@@ -114,6 +114,8 @@ struct sv_state {
 namespace sv {
 size_t elem_bytes(sv_dtype dt);
 sv_status ensure_scratch(sv_state* s, size_t bytes);
+// Validate a marginal's qubit list (sv_measure_probs rules); copies it to qs.
+sv_status probs_args(int n, const int32_t* qubits, int m, const double* out_dev, int* qs);
 // Copy `bytes` from host memory to the state's upload buffer (stream-ordered);
 // returns the device address.  The previous upload's device contents stay
 // valid for work enqueued before this call.

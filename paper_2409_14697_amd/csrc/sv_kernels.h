@@ -118,6 +118,22 @@ struct alignas(16) PassDescDev {
   uint32_t wpos[16];             // physical position of local bit j on store
 };
 
+// One state in a batched pass launch (device-resident array).
+struct alignas(16) BatchItemDev {
+  void* psi;                      // state amplitudes
+  const PassDescDev* passes;      // the state's program
+  const PassStageDev* stages;
+  const PassOpDev* ops;
+  const void* mats;
+  uint64_t tile_begin;            // first global tile of this item (ascending)
+  int32_t n;                      // qubits
+  int32_t pass;                   // pass of the program to run
+};
+
+// Run pass items[i].pass of every item in one launch (all items share dt).
+hipError_t launch_pass_batch(sv_dtype dt, const BatchItemDev* items, int count, uint64_t total_tiles, int max_m,
+                             hipStream_t s);
+
 // Launch pass `pass` of a program already resident in device memory.
 hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* passes, int pass,
                        const PassStageDev* stages, const PassOpDev* ops, const void* mats, hipStream_t s);

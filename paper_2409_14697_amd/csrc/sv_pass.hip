@@ -202,36 +202,39 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, const cplx<R>* __r
   }
 }
 
+// Per-lane physical offsets of the batch index u (local bits 8 .. 8 + log2(kBatch) - 1).
+struct BatchOffsets {
+  uint64_t in[kBatch], out[kBatch];
+};
+
+__device__ __forceinline__ void batch_offsets(const PassDescDev& P, BatchOffsets* bo) {
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u) {
+    bo->in[u] = bo->out[u] = 0;
+#pragma unroll
+    for (int b = 0; b < kBatchBits; ++b)
+      if (((u >> b) & 1) && 8u + b < P.m) {
+        bo->in[u] |= 1ull << P.lpos[8 + b];
+        bo->out[u] |= 1ull << P.wpos[8 + b];
+      }
+  }
+}
+
+// One tile of one pass: gather, run the stages, scatter.  `tile` is the LDS
+// buffer of 2^m elements; every thread of the block calls this.
 template <typename R, int WB>
-__global__ __launch_bounds__(kBlock) void k_pass(typename dev_elem<R>::E* __restrict__ psi, int n,
-                                                 const PassDescDev* __restrict__ passes, int pi,
-                                                 const PassStageDev* __restrict__ stages,
-                                                 const PassOpDev* __restrict__ ops,
-                                                 const cplx<R>* __restrict__ mats) {
+__device__ __forceinline__ void tile_pass(typename dev_elem<R>::E* __restrict__ psi, int n, const PassDescDev& P,
+                                          const PassStageDev* __restrict__ stages,
+                                          const PassOpDev* __restrict__ ops, const cplx<R>* __restrict__ mats,
+                                          uint64_t tile_id, typename dev_elem<R>::E* tile,
+                                          const BatchOffsets& bo) {
   typedef typename dev_elem<R>::E E;
-  extern __shared__ __align__(16) unsigned char smem[];
-  E* tile = reinterpret_cast<E*>(smem);
-  const PassDescDev& P = passes[pi];
   const uint32_t m = P.m;
   const uint32_t size = 1u << m;
   const uint64_t all = (1ull << n) - 1ull;
-  const uint64_t ntiles = 1ull << (n - m);
   const uint32_t t = threadIdx.x;
   const uint32_t per = size >= (uint32_t)kBlock ? size / kBlock : 1u;  // elements per lane
   const bool lane_on = t < size;
-  // physical offsets of the batch index u (local bits 8 .. 8 + log2(kBatch) - 1)
-  uint64_t u_in[kBatch], u_out[kBatch];
-#pragma unroll
-  for (int u = 0; u < kBatch; ++u) {
-    u_in[u] = u_out[u] = 0;
-#pragma unroll
-    for (int b = 0; b < kBatchBits; ++b)
-      if (((u >> b) & 1) && 8u + b < m) {
-        u_in[u] |= 1ull << P.lpos[8 + b];
-        u_out[u] |= 1ull << P.wpos[8 + b];
-      }
-  }
-  for (uint64_t tile_id = xcd_block(); tile_id < ntiles; tile_id += gridDim.x) {
   const uint64_t base = deposit(tile_id, all & ~P.lmask);
 
   // gather: x = t + 256 j; the low 8 local bits come from t, the rest from j.
@@ -250,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(typename dev_elem<R>::E* __rest
     E buf[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u)
-      if (j0 + u < per && lane_on) buf[u] = ld(psi + (base | lo_in | hi_in | u_in[u]));
+      if (j0 + u < per && lane_on) buf[u] = ld(psi + (base | lo_in | hi_in | bo.in[u]));
 #pragma unroll
     for (int u = 0; u < kBatch; ++u)
       if (j0 + u < per && lane_on) tile[swz<WB>(t + (j0 + u) * kBlock)] = buf[u];
@@ -315,9 +318,54 @@ __global__ __launch_bounds__(kBlock) void k_pass(typename dev_elem<R>::E* __rest
       if (j0 + u < per && lane_on) buf[u] = tile[swz<WB>(t + (j0 + u) * kBlock)];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u)
-      if (j0 + u < per && lane_on) st(psi + (base | lo_out | hi_out | u_out[u]), buf[u]);
+      if (j0 + u < per && lane_on) st(psi + (base | lo_out | hi_out | bo.out[u]), buf[u]);
   }
   __syncthreads();  // the tile buffer is reused by the next tile
+}
+
+template <typename R, int WB>
+__global__ __launch_bounds__(kBlock) void k_pass(typename dev_elem<R>::E* __restrict__ psi, int n,
+                                                 const PassDescDev* __restrict__ passes, int pi,
+                                                 const PassStageDev* __restrict__ stages,
+                                                 const PassOpDev* __restrict__ ops,
+                                                 const cplx<R>* __restrict__ mats) {
+  typedef typename dev_elem<R>::E E;
+  extern __shared__ __align__(16) unsigned char smem[];
+  E* tile = reinterpret_cast<E*>(smem);
+  const PassDescDev& P = passes[pi];
+  BatchOffsets bo;
+  batch_offsets(P, &bo);
+  const uint64_t ntiles = 1ull << (n - P.m);
+  for (uint64_t tile_id = xcd_block(); tile_id < ntiles; tile_id += gridDim.x)
+    tile_pass<R, WB>(psi, n, P, stages, ops, mats, tile_id, tile, bo);
+}
+
+// Many states in one launch: work item i runs pass `pass` of its own program
+// over its own tiles; global tile g belongs to the item whose [tile_begin,
+// tile_begin + tiles) range holds g.  No item reads another's state, so each
+// result is independent of the batch it ran in.
+template <typename R, int WB>
+__global__ __launch_bounds__(kBlock) void k_pass_batch(const BatchItemDev* __restrict__ items, int count,
+                                                       uint64_t total_tiles) {
+  typedef typename dev_elem<R>::E E;
+  extern __shared__ __align__(16) unsigned char smem[];
+  E* tile = reinterpret_cast<E*>(smem);
+  int cur = -1;
+  BatchOffsets bo;
+  for (uint64_t g = xcd_block(); g < total_tiles; g += gridDim.x) {
+    int lo = 0, hi = count - 1;  // last item with tile_begin <= g
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].tile_begin <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchItemDev& it = items[lo];
+    const PassDescDev& P = it.passes[it.pass];
+    if (lo != cur) {
+      batch_offsets(P, &bo);
+      cur = lo;
+    }
+    tile_pass<R, WB>((E*)it.psi, it.n, P, it.stages, it.ops, (const cplx<R>*)it.mats, g - it.tile_begin, tile, bo);
   }
 }
 
@@ -339,12 +387,35 @@ hipError_t run(void* psi, int n, int m, const PassDescDev* passes, int pass, con
   return hipGetLastError();
 }
 
+template <typename R, int WB>
+hipError_t run_batch(const BatchItemDev* items, int count, uint64_t total_tiles, int max_m, hipStream_t s) {
+  typedef typename dev_elem<R>::E E;
+  const size_t lds = ((size_t)1 << max_m) * sizeof(E);
+  static size_t attr = 0;
+  if (lds > attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_pass_batch<R, WB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = lds;
+  }
+  const uint64_t blocks = capped_grid(total_tiles);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_pass_batch<R, WB>), dim3((unsigned)blocks), dim3(kBlock), lds, s, items, count, total_tiles);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* passes, int pass,
                        const PassStageDev* stages, const PassOpDev* ops, const void* mats, hipStream_t s) {
   if (dt == SV_C128) return run<double, 3>(psi, n, m, passes, pass, stages, ops, mats, s);
   return run<float, 4>(psi, n, m, passes, pass, stages, ops, mats, s);
+}
+
+hipError_t launch_pass_batch(sv_dtype dt, const BatchItemDev* items, int count, uint64_t total_tiles, int max_m,
+                             hipStream_t s) {
+  if (dt == SV_C128) return run_batch<double, 3>(items, count, total_tiles, max_m, s);
+  return run_batch<float, 4>(items, count, total_tiles, max_m, s);
 }
 
 }  // namespace sv

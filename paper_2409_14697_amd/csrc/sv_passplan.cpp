@@ -319,7 +319,8 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
     std::vector<Op> members;  // physical qubits
     const int pass_id = (int)p->passes.size();
     const int first_op = (int)p->ops.size();
-    for (size_t j = first; j < ops.size() && n_blocked < n; ++j) {
+    const size_t cap = o.max_pass_ops > 0 ? (size_t)o.max_pass_ops : ops.size();
+    for (size_t j = first; j < ops.size() && n_blocked < n && members.size() < cap; ++j) {
       if (done[j]) continue;
       const Op& op = ops[j];
       bool blk = op.nq >= 3;

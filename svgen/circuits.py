@@ -80,10 +80,11 @@ def layered_circuit(n: int, n_gates: Optional[int] = None, n_layer_pairs: Option
     while True:
         if n_layer_pairs is not None and pairs_done == n_layer_pairs:
             break
+        ks = rng.integers(0, 4, size=n)
+        ths = rng.uniform(0.0, 2.0 * math.pi, size=n)
         for q in range(n):
-            kind = kinds[int(rng.integers(0, 4))]
-            theta = float(rng.uniform(0.0, 2.0 * math.pi))
-            gates.append(Gate(kind, (q,), theta if kind != "H" else 0.0))
+            kind = kinds[int(ks[q])]
+            gates.append(Gate(kind, (q,), float(ths[q]) if kind != "H" else 0.0))
         for c, t in random_matching(n, rng):
             gates.append(Gate("CNOT", (c, t)))
         pairs_done += 1

@@ -169,3 +169,18 @@ def test_named_gate_matrices_match_oracle_definitions():
             g = Gate(kind, tuple(range(nq)), theta)
             (q, m, _), = B.Plan(3, "c128", [g], {"max_fuse_qubits": 0}).export()
             assert np.max(np.abs(m - so.gate_matrix(g))) < 1e-15, kind
+
+
+@pytest.mark.parametrize("cap", [1, 7, 32])
+def test_pass_op_cap_splits_passes_and_replays(cap):
+    n = 12
+    gates = layered_circuit(n, n_gates=300, seed=9)
+    plan = B.Plan(n, "c128", gates, {"mode": "pass", "max_pass_ops": cap})
+    psi = gaussian_state_np(n, 3)
+    assert np.max(np.abs(_replay(plan, n, psi) - oracle.run(gates, psi0=psi))) < 1e-13
+    for kind, nops, nloc in plan.passes():
+        assert kind in (1, 3) and nops <= cap
+    uncapped = B.Plan(n, "c128", gates, {"mode": "pass"}).info()[1]
+    assert plan.info()[1] >= max(uncapped, len(gates) // cap)
+    with pytest.raises(B.SvError):
+        B.Plan(n, "c128", gates, {"mode": "pass", "max_pass_ops": -1})

@@ -1,0 +1,148 @@
+"""GPU tests of the serving form: the batched pass launch (sv_batcher_run) and
+the continuous-batching loop.  Every served state is checked against the
+oracle, and a request's result is the same whether it ran alone or in a mix
+(the batched kernel reads only the request's own program and state)."""
+import numpy as np
+import pytest
+
+import oracle
+from svgen import layered_circuit, serving_requests
+from tests.gpu_util import TOL, max_err, to_host
+
+pytestmark = pytest.mark.gpu
+
+PROB_TOL = {"c128": 1e-12, "c64": 4e-5}
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import paper_2409_14697_amd as sv
+    return sv
+
+
+def low_probs_ref(psi, n, k=16):
+    k = min(n, k)
+    return oracle.probs(psi, list(range(k - 1, -1, -1)))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batched_pass_launch_matches_oracle_and_single_plans(sv, dtype):
+    import torch
+    ns = [6, 9, 12, 13, 14, 16, 17]
+    circuits = {n: layered_circuit(n, n_layer_pairs=5, seed=n) for n in ns}
+    plans = {n: sv.Plan(n, dtype, circuits[n], {"mode": "pass", "max_pass_ops": 16}) for n in ns}
+    progs = {n: sv.Program(plans[n]) for n in ns}
+    states = {n: sv.StateVector(n, dtype) for n in ns}
+    batcher = sv.Batcher()
+    step = 0
+    while True:
+        live = [n for n in ns if step < progs[n].n_passes]
+        if not live:
+            break
+        batcher.run([states[n] for n in live], [progs[n] for n in live], [step] * len(live))
+        step += 1
+    torch.cuda.synchronize()
+    for n in ns:
+        out = to_host(states[n].tensor)
+        ref = oracle.run(circuits[n], n=n)
+        assert max_err(out, ref) <= TOL[dtype], n
+        # the unbatched pass kernel (sv_apply_plan) on the same plan
+        single = sv.StateVector(n, dtype)
+        single.apply_plan(plans[n])
+        single.sync()
+        assert max_err(to_host(single.tensor), out) <= TOL[dtype], n
+        single.close()
+    for n in ns:
+        states[n].close()
+        progs[n].close()
+    batcher.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batcher_rejects_bad_batches(sv, dtype):
+    from paper_2409_14697_amd import binding as B
+    other = "c64" if dtype == "c128" else "c128"
+    pa = sv.Program(sv.Plan(8, dtype, layered_circuit(8, n_layer_pairs=2, seed=1), {"mode": "pass"}))
+    pb = sv.Program(sv.Plan(8, other, layered_circuit(8, n_layer_pairs=2, seed=1), {"mode": "pass"}))
+    s8, s9 = sv.StateVector(8, dtype), sv.StateVector(9, dtype)
+    s8o = sv.StateVector(8, other)
+    before = to_host(s8.tensor)
+    b = sv.Batcher()
+    cases = [([s9], [pa], [0]),                       # program for 8 qubits, state of 9
+             ([s8, s8o], [pa, pb], [0, 0]),           # mixed dtypes
+             ([s8, s8], [pa, pa], [0, 0]),            # a state twice
+             ([s8], [pa], [pa.n_passes]),             # pass index out of range
+             ([s8], [pa], [-1])]
+    for st, pr, ix in cases:
+        with pytest.raises(B.SvError) as e:
+            b.run(st, pr, ix)
+        assert e.value.status == B.SV_ERR_ARG
+    b.run([], [], [])  # an empty batch is a no-op
+    import torch
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(s8.tensor), before)
+    # a plan with a dense sweep pass cannot become a program
+    with pytest.raises(B.SvError) as e:
+        sv.Program(sv.Plan(8, dtype, layered_circuit(8, n_layer_pairs=2, seed=1), {"mode": "sweep"}))
+    assert e.value.status == B.SV_ERR_UNSUPPORTED
+    for x in (s8, s9, s8o, pa, pb, b):
+        x.close()
+
+
+def _serve(sv, dtype, requests, rate, budget=None, keep_states=True, max_active=64):
+    from paper_2409_14697_amd import binding as B
+    from paper_2409_14697_amd.serve import DeviceEngine, Server, free_budget, make_jobs
+    jobs = make_jobs(requests, rate, B.make_gates)
+    eng = DeviceEngine(dtype, keep_states=keep_states, max_pass_ops=24)
+    srv = Server(eng, budget or free_budget(0.5), max_active=max_active, plan_workers=4)
+    res = srv.run(jobs)
+    eng.close()
+    return res, jobs
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("rate", [None, 3000.0])
+def test_serving_loop_results_match_oracle(sv, dtype, rate):
+    reqs = serving_requests(24, seed=11, n_range=(6, 15), depth_range=(2, 12))
+    res, jobs = _serve(sv, dtype, reqs, rate)
+    s = res.summary()
+    assert s["completed"] == len(reqs) and s["errors"] == 0 and s["rejected"] == 0
+    assert s["p99_ms"] >= s["p50_ms"] > 0
+    for r, j in zip(reqs, jobs):
+        ref = oracle.run(r.circuit(), n=r.n)
+        assert max_err(to_host(j.handle["tensor"]), ref) <= TOL[dtype], (r.rid, r.n)
+        assert max_err(j.probs, low_probs_ref(ref, r.n)) <= PROB_TOL[dtype], (r.rid, r.n)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_serving_alone_equals_in_mix_bitwise(sv, dtype):
+    reqs = serving_requests(16, seed=12, n_range=(6, 17), depth_range=(2, 10))
+    _, mixed = _serve(sv, dtype, reqs, None)
+    for r, j in zip(reqs[:8], mixed[:8]):
+        _, alone = _serve(sv, dtype, [r], None)
+        a = alone[0].handle["tensor"].cpu().numpy()
+        b = j.handle["tensor"].cpu().numpy()
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), r.rid
+        assert np.array_equal(alone[0].probs, j.probs), r.rid
+
+
+def test_serving_under_a_tight_budget(sv):
+    # a budget that holds only a few of the states at once forces queueing
+    reqs = serving_requests(20, seed=13, n_range=(10, 16), depth_range=(2, 6))
+    budget = 3 * (1 << 16) * 8 + (4 << 20)
+    res, jobs = _serve(sv, "c64", reqs, 5000.0, budget=budget)
+    s = res.summary()
+    assert s["completed"] == len(reqs)
+    assert res.peak_used <= budget
+    for r, j in zip(reqs, jobs):
+        assert max_err(to_host(j.handle["tensor"]), oracle.run(r.circuit(), n=r.n)) <= TOL["c64"]
+
+
+def test_serving_rejects_a_request_larger_than_the_budget(sv):
+    reqs = serving_requests(6, seed=14, n_range=(8, 10), depth_range=(2, 4))
+    big = serving_requests(1, seed=15, n_range=(20, 20), depth_range=(2, 2))[0]
+    big.rid = 99
+    res, jobs = _serve(sv, "c64", reqs + [big], None, budget=64 << 20 >> 4)
+    by = {j.rid: j for j in jobs}
+    assert by[99].status == "rejected"
+    assert all(by[r.rid].status == "done" for r in reqs)
