@@ -81,7 +81,7 @@ def kernel_symbol(key: str) -> str:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sv_sweep.hip", "sv_device.h", "sv_kernels.h", "sv_gates.cpp"):
+    for f in ("sv_sweep.hip", "sv_device.h", "sv_kernels.h", "sv_gates.cpp"):  # the gate-sweep kernels and their arguments
         with open(os.path.join(ROOT, "paper_2409_14697_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -52,7 +52,46 @@ def counters(d: str, counter: str):
     return per
 
 
+def trace_summary(argv):
+    """Kernel-trace summary of any profiled bench.py run:
+    bench_profile.py trace --dir D --out profiles/NAME.md --title T --cmd "C" [--result R.json]"""
+    ap = argparse.ArgumentParser(prog="bench_profile.py trace")
+    ap.add_argument("--dir", required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--cmd", required=True, help="the profiled command, as run from the repository root")
+    ap.add_argument("--result", help="the JSON line the profiled run printed (figures quoted in the summary)")
+    ap.add_argument("--min-pct", type=float, default=0.5)
+    args = ap.parse_args(argv)
+    stats = list(csv.DictReader(open(os.path.join(args.dir, "bench_kernel_stats.csv"))))
+    lines = [f"# {args.title}: rocprofv3 kernel trace", "",
+             "Command (from the repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "```", args.cmd, "```", "",
+             f"## Kernels above {args.min_pct}% of GPU time", "",
+             "| kernel | calls | avg us | min us | max us | total ms | total % |", "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in stats:
+        if float(r["Percentage"]) < args.min_pct:
+            continue
+        lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    if args.result:
+        with open(args.result) as f:
+            line = [l for l in f.read().splitlines() if l.startswith("{")][-1]
+        res = json.loads(line)
+        lines += ["", "## The profiled run's own report", "", "```",
+                  json.dumps({k: res[k] for k in ("metric", "value", "unit", "roofline") if k in res}, indent=1),
+                  "```"]
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {args.out}")
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "trace":
+        trace_summary(sys.argv[2:])
+        return
     import bench
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)

@@ -11,6 +11,7 @@
 // column-fastest, so consecutive lanes read consecutive groups.
 #include "sv_device.h"
 #include "sv_kernels.h"
+#include "sv_tile_kernels.h"
 
 namespace sv {
 namespace {

@@ -11,6 +11,7 @@
 
 #include "sv.h"
 #include "sv_kernels.h"
+#include "sv_tile_kernels.h"
 
 namespace sv {
 

@@ -1,6 +1,6 @@
-// Host-visible launchers of the HIP kernels.  Every launcher validates
-// nothing (the C ABI layer has done that), enqueues on `stream`, and returns
-// the launch status.
+// Host-visible launchers of the gate-sweep, readout and utility kernels.
+// Every launcher validates nothing (the C ABI layer has done that), enqueues
+// on `stream`, and returns the launch status.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -70,80 +70,6 @@ constexpr unsigned kLaneBits = 6;  // element bits held across the 64 lanes of a
 bool plan_low(sv_dtype dt, SweepArgs* a);
 
 hipError_t launch_sweep(sv_dtype dt, void* psi, int n, const SweepArgs& a, hipStream_t s);
-
-// --- in-cache tile passes (LDS) --------------------------------------------
-// A pass loads tiles of 2^m amplitudes (local bits = physical positions
-// lpos[0..m-1], ascending), runs its stages on each tile in LDS and
-// registers, and stores local bit j to physical position wpos[j] (a
-// permutation of lpos: qubit reordering fused into the write-back).
-// A stage holds 2^kPassRegBits register amplitudes per group: register bit r
-// is local bit q[r]; groups enumerate the other local bits.
-constexpr int kPassRegBits = 4;
-
-enum PassOpType : uint32_t {
-  POP_U1 = 0,  // 2x2 on register bit b0                        (4 entries)
-  POP_U2 = 1,  // 4x4 on register bits (b0 = MSB, b1)           (16 entries)
-  POP_X = 2,   // exchange register pairs on bit b0              (0 entries)
-  POP_CX = 3,  // exchange pairs on bit b1 where bit b0 is 1     (0 entries)
-  POP_D1 = 4,  // diag(d0, d1) on register bit b0                (2 entries)
-  POP_D2 = 5,  // diag(d0..d3) on register bits (b0 = MSB, b1)   (4 entries)
-  POP_DG = 6   // one phase for the whole group                  (1 entry)
-};
-constexpr uint32_t kPassNoSel = 0xffffffffu;
-constexpr uint32_t kPassTileSel = 64;  // select codes >= 64 name tile (non-local) physical bits
-
-struct alignas(16) PassOpDev {
-  uint32_t type;   // PassOpType
-  uint32_t b0, b1; // register bits
-  uint32_t mat;    // first complex entry in the matrix pool
-  uint32_t lmask;  // local bits (outside the stage's register bits) that must all be 1
-  uint32_t sa, sb; // matrix-variant selectors: local bit (< 64) or 64 + tile physical bit;
-                   // variant = bit(sa) [*2 + bit(sb)]; entries of variant v at mat + v * size
-  uint32_t pad;
-  uint64_t tmask;  // tile (non-local) physical bits that must all be 1
-};
-
-struct PassStageDev {
-  uint32_t q[kPassRegBits];      // local bit of register bit r
-  uint32_t qsort[kPassRegBits];  // the same bits, ascending (group enumeration)
-  uint32_t op_first, op_count;
-};
-
-struct alignas(16) PassDescDev {
-  uint32_t m;                    // local bits per tile
-  uint32_t stage_first, stage_count;
-  uint32_t pad;
-  uint64_t lmask;                // physical mask of the local bits
-  uint32_t lpos[16];             // physical position of local bit j on load (ascending)
-  uint32_t wpos[16];             // physical position of local bit j on store
-};
-
-// One state in a batched pass launch (device-resident array).
-struct alignas(16) BatchItemDev {
-  void* psi;                      // state amplitudes
-  const PassDescDev* passes;      // the state's program
-  const PassStageDev* stages;
-  const PassOpDev* ops;
-  const void* mats;
-  uint64_t tile_begin;            // first global tile of this item (ascending)
-  int32_t n;                      // qubits
-  int32_t pass;                   // pass of the program to run
-};
-
-// Run pass items[i].pass of every item in one launch (all items share dt).
-hipError_t launch_pass_batch(sv_dtype dt, const BatchItemDev* items, int count, uint64_t total_tiles, int max_m,
-                             hipStream_t s);
-
-// Launch pass `pass` of a program already resident in device memory.
-hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* passes, int pass,
-                       const PassStageDev* stages, const PassOpDev* ops, const void* mats, hipStream_t s);
-
-// --- dense k-qubit fused gate (3 <= k <= 6) ---------------------------------
-// m_dev: device copy of the 2^k x 2^k matrix, row-major interleaved, in the
-// state's precision (double for SV_C128, float for SV_C64).  mfma: complex64
-// states with k >= 4 use the FP32 MFMA kernel.
-hipError_t launch_dense_kq(sv_dtype dt, void* psi, int n, int k, const int* q, const void* m_dev, bool mfma,
-                           hipStream_t s);
 
 // --- readout ----------------------------------------------------------------
 // Scratch bytes the marginal-probability reduction needs.

@@ -17,6 +17,7 @@
 // lanes of a wave fall into distinct banks.
 #include "sv_device.h"
 #include "sv_kernels.h"
+#include "sv_tile_kernels.h"
 
 namespace sv {
 namespace {
