@@ -106,7 +106,8 @@ typedef struct {
   int32_t max_fuse_qubits;  /* general gate fusion width (Sec. II-B, III-A
                                tier 5); 0 or 1 disables dense fusion; <= 6.
                                default 5                                      */
-  int32_t lds_qubits;       /* local qubits per in-cache tile; 0 = auto       */
+  int32_t lds_qubits;       /* local qubits per in-cache tile, 5..12 (complex128)
+                               or 5..13 (complex64); 0 = auto (the maximum)   */
   int32_t pinned_low_bits;  /* low index bits always inside a tile (memory
                                coalescing); 0 = auto                          */
   int32_t reorder;          /* 1 = let passes move qubits (Sec. II-B qubit
@@ -179,10 +180,11 @@ sv_status sv_plan_export(const sv_plan *p, size_t op, int32_t *nq, int32_t q[SV_
                          double *m, int32_t *pass);
 
 /* Describe pass `pass`: kind (0 = sweep kernel, 1 = LDS in-cache tile pass,
- * 2 = dense fused kernel, 3 = permutation), number of ops, and the number of
- * local qubits of its tile (0 for sweeps). */
+ * 2 = dense fused kernel, 3 = permutation), number of ops, the number of
+ * local qubits of its tile (0 for sweeps) and of register stages (LDS round
+ * trips of the tile; 0 for sweeps).  Outputs may be NULL. */
 sv_status sv_plan_pass_info(const sv_plan *p, size_t pass, int32_t *kind, int32_t *n_ops,
-                            int32_t *n_local);
+                            int32_t *n_local, int32_t *n_stages);
 
 sv_status sv_plan_destroy(sv_plan *p);
 
@@ -195,7 +197,11 @@ sv_status sv_apply_circuit(sv_state *s, const sv_gate *g, size_t n_gates, const 
 
 /* Physically reorder qubits (Sec. II-B qubit reordering / in-memory
  * swapping): the amplitude at index i moves to the index whose bit dest[q]
- * equals bit q of i.  dest is a permutation of 0..n-1.  Async. */
+ * equals bit q of i.  dest is a permutation of 0..n-1 (n entries).  Runs as
+ * in-cache permutation passes (bitwise exact; a few full read+write sweeps
+ * of the state at most).  Async.  Errors: SV_ERR_ARG (null), SV_ERR_QUBIT
+ * (entry out of range or repeated; the state is untouched), SV_ERR_NOMEM,
+ * SV_ERR_DEVICE. */
 sv_status sv_permute_qubits(sv_state *s, const int32_t *dest);
 
 /* Marginal probabilities over m qubits (0 <= m <= n, distinct):

@@ -75,7 +75,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sv_plan_info": (S, [c_void_p, POINTER(c_size_t), POINTER(c_size_t)]),
         "sv_plan_export": (S, [c_void_p, c_size_t, POINTER(c_int32), POINTER(c_int32), POINTER(c_double),
                                POINTER(c_int32)]),
-        "sv_plan_pass_info": (S, [c_void_p, c_size_t, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
+        "sv_plan_pass_info": (S, [c_void_p, c_size_t, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                                  POINTER(c_int32)]),
         "sv_plan_destroy": (S, [c_void_p]),
         "sv_apply_plan": (S, [c_void_p, c_void_p]),
         "sv_apply_circuit": (S, [c_void_p, POINTER(SvGate), c_size_t, POINTER(SvOpts)]),
@@ -214,14 +215,16 @@ class Plan:
             out.append((tuple(q[j] for j in range(nq.value)), m, ps.value))
         return out
 
-    def passes(self):
+    def passes(self, stages: bool = False):
+        """(kind, n_ops, n_local) per pass; with stages=True also n_stages."""
         lib = load_library()
         _, n_passes = self.info()
         out = []
         for i in range(n_passes):
-            kind, nops, nloc = c_int32(), c_int32(), c_int32()
-            check(lib.sv_plan_pass_info(self._h, i, byref(kind), byref(nops), byref(nloc)))
-            out.append((kind.value, nops.value, nloc.value))
+            kind, nops, nloc, nst = c_int32(), c_int32(), c_int32(), c_int32()
+            check(lib.sv_plan_pass_info(self._h, i, byref(kind), byref(nops), byref(nloc), byref(nst)))
+            out.append((kind.value, nops.value, nloc.value, nst.value) if stages else
+                       (kind.value, nops.value, nloc.value))
         return out
 
     def close(self):

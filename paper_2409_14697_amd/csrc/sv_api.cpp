@@ -307,7 +307,8 @@ sv_status sv_plan_export(const sv_plan* p, size_t op, int32_t* nq, int32_t q[SV_
   return SV_OK;
 }
 
-sv_status sv_plan_pass_info(const sv_plan* p, size_t pass, int32_t* kind, int32_t* n_ops, int32_t* n_local) {
+sv_status sv_plan_pass_info(const sv_plan* p, size_t pass, int32_t* kind, int32_t* n_ops, int32_t* n_local,
+                            int32_t* n_stages) {
   clear_error();
   if (!p) return fail(SV_ERR_ARG, "null plan");
   if (pass >= p->passes.size()) return fail(SV_ERR_ARG, "pass %zu out of range", pass);
@@ -315,6 +316,7 @@ sv_status sv_plan_pass_info(const sv_plan* p, size_t pass, int32_t* kind, int32_
   if (kind) *kind = ps.kind;
   if (n_ops) *n_ops = ps.n_ops;
   if (n_local) *n_local = ps.n_local;
+  if (n_stages) *n_stages = (int32_t)ps.stages.size();
   return SV_OK;
 }
 
@@ -348,7 +350,40 @@ sv_status sv_permute_qubits(sv_state* s, const int32_t* dest) {
   clear_error();
   if (sv_status st = check_state(s)) return st;
   if (!dest) return fail(SV_ERR_ARG, "null permutation");
-  return fail(SV_ERR_UNSUPPORTED, "sv_permute_qubits not available yet");
+  const int n = s->n;
+  std::vector<int> target(n, -1);  // target[p]: the old qubit whose bit ends at position p
+  for (int q = 0; q < n; ++q) {
+    if (dest[q] < 0 || dest[q] >= n) return fail(SV_ERR_QUBIT, "dest[%d] = %d out of range", q, dest[q]);
+    if (target[dest[q]] >= 0) return fail(SV_ERR_QUBIT, "dest is not a permutation (%d repeated)", dest[q]);
+    target[dest[q]] = q;
+  }
+  // The permutation as transpositions of index bits (selection order, at most
+  // n-1 SWAPs).  Planned in tile-pass mode, each SWAP only relabels qubits and
+  // the data moves once, in the permutation passes that restore the labels.
+  std::vector<int> cur(n);
+  for (int p = 0; p < n; ++p) cur[p] = p;
+  std::vector<sv_gate> swaps;
+  for (int p = 0; p < n; ++p) {
+    if (cur[p] == target[p]) continue;
+    int j = p + 1;
+    while (cur[j] != target[p]) ++j;
+    sv_gate g{};
+    g.kind = SV_G_SWAP;
+    g.nq = 2;
+    g.q[0] = p;
+    g.q[1] = j;
+    for (int r = 2; r < SV_MAX_GATE_QUBITS; ++r) g.q[r] = -1;
+    swaps.push_back(g);
+    std::swap(cur[p], cur[j]);
+  }
+  if (swaps.empty()) return SV_OK;
+  sv_opts o;
+  sv_default_opts(&o);
+  o.max_fuse_qubits = 0;
+  o.reorder = 1;
+  // tiles need more local bits than one stage's registers; tiny states use SWAP sweeps
+  o.mode = n > kPassRegBits + 1 ? SV_MODE_PASS : SV_MODE_SWEEP;
+  return sv_apply_circuit(s, swaps.data(), swaps.size(), &o);
 }
 
 sv_status sv_measure_probs(sv_state* s, const int32_t* qubits, int m, double* out_dev) {

@@ -6,9 +6,12 @@
 // most significant bit of the local index).  Viewed as a matrix product
 // Y = U X, column c of X is group c.
 //
-// A block stages U and a tile of C columns (2^k x C amplitudes) in LDS, then
-// every lane produces output elements straight from LDS.  Lanes load the tile
-// column-fastest, so consecutive lanes read consecutive groups.
+// A block works on tiles of C consecutive groups (2^k x C amplitudes).  A
+// tile is a set of 2^(k + log2 C) indices: the gate's bits plus the lowest
+// log2 C other bits vary, the remaining bits are the tile's base (the
+// PDEP-like deposit of Sec. III-B).  Lanes walk a tile in address order, so
+// every load and store instruction covers whole 128-byte lines whatever the
+// gate's qubits are; LDS holds the tile as X[member][column].
 #include "sv_device.h"
 #include "sv_kernels.h"
 #include "sv_tile_kernels.h"
@@ -18,65 +21,122 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Address map of a tile: tile-local index e has bit j at physical position
+// pos[j] (ascending; 64 = a column bit beyond the state, for states with
+// fewer groups than a tile has columns) and contributes lds[j] to the tile's
+// LDS index member * C + column.  The tile's base deposits the work-block
+// number into `rest`.
 struct DenseGeo {
-  unsigned zs[SV_MAX_GATE_QUBITS];  // gate bits, ascending (zero-insert order)
-  unsigned q[SV_MAX_GATE_QUBITS];   // gate bits in local order (q[0] = MSB)
+  uint64_t rest;
+  uint32_t nbits;
+  uint32_t inv;       // tile-local bits with no physical position
+  uint32_t pos[16];
+  uint32_t lds[16];
 };
 
-template <int K>
-__device__ __forceinline__ uint64_t group_base(uint64_t c, const DenseGeo& g) {
+// Per-lane part of the map: tile-local bits 0..7 come from the lane.
+struct LaneMap {
+  uint64_t addr;
+  uint32_t lds;
+  bool on;
+};
+
+__device__ __forceinline__ LaneMap lane_map(uint32_t t, const DenseGeo& g) {
+  LaneMap m{0, 0, (t & g.inv) == 0};
 #pragma unroll
-  for (int z = 0; z < K; ++z) c = insert0(c, g.zs[z]);
-  return c;
+  for (int j = 0; j < 8; ++j)
+    if ((t >> j) & 1u) {
+      if (g.pos[j] < 64) m.addr |= 1ull << g.pos[j];
+      m.lds |= g.lds[j];
+    }
+  return m;
 }
 
-template <int K>
-__device__ __forceinline__ uint64_t member_off(int r, const DenseGeo& g) {
-  uint64_t o = 0;
+// Uniform part for element u of a lane (tile-local bits 8 ..).
+template <int U>
+__device__ __forceinline__ void elem_map(const DenseGeo& g, uint64_t* addr, uint32_t* lds, bool* on) {
+  uint64_t a = 0;
+  uint32_t l = 0;
 #pragma unroll
-  for (int m = 0; m < K; ++m) o |= (uint64_t)((r >> (K - 1 - m)) & 1) << g.q[m];
-  return o;
+  for (int b = 0; b < 8; ++b)
+    if ((U >> b) & 1) {
+      if (g.pos[8 + b] < 64) a |= 1ull << g.pos[8 + b];
+      l |= g.lds[8 + b];
+    }
+  *addr = a;
+  *lds = l;
+  *on = (((uint32_t)U << 8) & g.inv) == 0;
 }
 
-// Tile columns per block: the tile holds 2048 amplitudes.
+#define SV_FOR_U(PER, F)                                                  \
+  F(0) if (PER > 1) { F(1) } if (PER > 2) { F(2) F(3) }                   \
+  if (PER > 4) { F(4) F(5) F(6) F(7) }                                    \
+  if (PER > 8) { F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) }
+
+// Tile columns of the VALU kernel: the tile holds 2048 amplitudes.
 template <int K>
 constexpr int tile_cols() {
   return 2048 >> K;
 }
 
 template <typename E, int K>
-__global__ __launch_bounds__(kBlock) void k_dense(E* __restrict__ psi, uint64_t ngroups, DenseGeo g,
+__global__ __launch_bounds__(kBlock) void k_dense(E* __restrict__ psi, uint64_t nwork, DenseGeo g,
                                                   const typename elem_traits<E>::R* __restrict__ um) {
   typedef typename elem_traits<E>::R R;
   constexpr int D = 1 << K;
   constexpr int C = tile_cols<K>();
+  constexpr int PER = D * C / kBlock;
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* us = reinterpret_cast<cplx<R>*>(smem);  // D x D
   cplx<R>* xs = us + D * D;                          // D x C, row r = member r
   const int t = threadIdx.x;
   for (int e = t; e < D * D; e += kBlock) us[e] = cplx<R>{um[2 * e], um[2 * e + 1]};
-  const uint64_t c0 = (uint64_t)blockIdx.x * C;
-  for (int e = t; e < D * C; e += kBlock) {
-    const int c = e % C, r = e / C;
-    const uint64_t col = c0 + c;
-    if (col < ngroups) {
-      const E v = psi[group_base<K>(col, g) + member_off<K>(r, g)];
-      xs[e] = cplx<R>{v.x, v.y};
+  const LaneMap lm = lane_map((uint32_t)t, g);
+  for (uint64_t wb = xcd_block(); wb < nwork; wb += gridDim.x) {
+    const uint64_t base = deposit(wb, g.rest) | lm.addr;
+    E buf[PER];
+#define SV_LD(U)                                                  \
+    {                                                             \
+      uint64_t a;                                                 \
+      uint32_t l;                                                 \
+      bool on;                                                    \
+      elem_map<U>(g, &a, &l, &on);                                \
+      if (on && lm.on) buf[U] = ld(psi + (base | a));             \
     }
-  }
-  __syncthreads();
-  for (int e = t; e < D * C; e += kBlock) {
-    const int c = e % C, r = e / C;
-    const uint64_t col = c0 + c;
-    if (col >= ngroups) continue;
-    cplx<R> y = {0, 0};
-    const cplx<R>* urow = us + r * D;
-#pragma unroll 8
-    for (int s = 0; s < D; ++s) y = cfma(y, urow[s], xs[s * C + c]);
-    E out;
-    out.x = y.re;
-    out.y = y.im;
-    psi[group_base<K>(col, g) + member_off<K>(r, g)] = out;
+    SV_FOR_U(PER, SV_LD)
+#undef SV_LD
+    __syncthreads();  // U is staged and the previous tile's readers are done
+#define SV_LDS(U)                                                 \
+    {                                                             \
+      uint64_t a;                                                 \
+      uint32_t l;                                                 \
+      bool on;                                                    \
+      elem_map<U>(g, &a, &l, &on);                                \
+      if (on && lm.on) xs[lm.lds | l] = cplx<R>{buf[U].x, buf[U].y}; \
+    }
+    SV_FOR_U(PER, SV_LDS)
+#undef SV_LDS
+    __syncthreads();
+#define SV_OUT(U)                                                 \
+    {                                                             \
+      uint64_t a;                                                 \
+      uint32_t l;                                                 \
+      bool on;                                                    \
+      elem_map<U>(g, &a, &l, &on);                                \
+      if (on && lm.on) {                                          \
+        const uint32_t li = lm.lds | l, r = li / C, c = li % C;   \
+        cplx<R> y = {0, 0};                                       \
+        const cplx<R>* urow = us + r * D;                         \
+        _Pragma("unroll 8")                                       \
+        for (int s = 0; s < D; ++s) y = cfma(y, urow[s], xs[s * C + c]); \
+        E o;                                                      \
+        o.x = y.re;                                               \
+        o.y = y.im;                                               \
+        st(psi + (base | a), o);                                  \
+      }                                                           \
+    }
+    SV_FOR_U(PER, SV_OUT)
+#undef SV_OUT
   }
 }
 
@@ -94,8 +154,8 @@ hipError_t run(void* psi, int n, const DenseGeo& g, const void* m, hipStream_t s
     attr_set = true;
   }
   const uint64_t ngroups = 1ull << (n - K);
-  const uint64_t blocks = (ngroups + C - 1) / C;
-  hipLaunchKernelGGL((k_dense<E, K>), dim3((unsigned)blocks), dim3(kBlock), lds, s, (E*)psi, ngroups, g,
+  const uint64_t nwork = (ngroups + C - 1) / C;
+  hipLaunchKernelGGL((k_dense<E, K>), dim3((unsigned)capped_grid(nwork)), dim3(kBlock), lds, s, (E*)psi, nwork, g,
                      (const R*)m);
   return hipGetLastError();
 }
@@ -171,43 +231,60 @@ constexpr size_t mfma_lds() {
 }
 
 template <typename R, int K>
-__global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E* __restrict__ psi,
-                                                       uint64_t ngroups, DenseGeo g, const R* __restrict__ um) {
+__global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E* __restrict__ psi, uint64_t nwork,
+                                                       DenseGeo g, const R* __restrict__ um) {
   typedef mfma_shape<R> MS;
   typedef typename MS::E E;
   constexpr int D = 1 << K, DP = D + 1;
   constexpr int NC = mfma_cols<R, K>();
   constexpr int RBLK = 2 * D / MS::BM, CBLK = NC / MS::BN, TILES = RBLK * CBLK;
+  constexpr int TPW = (TILES + 3) / 4;  // output tiles per wave
   constexpr int KSTEPS = 2 * D / MS::BK;
-  constexpr int PER = D * NC / kBlock;  // tile elements gathered per lane
+  constexpr int PER = D * NC / kBlock;  // tile elements per lane
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* us = reinterpret_cast<cplx<R>*>(smem);  // D x DP
   E* xs = reinterpret_cast<E*>(us + D * DP);       // [member][NC]
   const int t = threadIdx.x, w = t / 64, l = t % 64;
   for (int e = t; e < D * D; e += kBlock) us[(e / D) * DP + (e % D)] = cplx<R>{um[2 * e], um[2 * e + 1]};
-  const uint64_t nwork = (ngroups + NC - 1) / NC;
+  const LaneMap lm = lane_map((uint32_t)t, g);
   for (uint64_t wb = xcd_block(); wb < nwork; wb += gridDim.x) {
-    const uint64_t c0 = wb * NC;
+    const uint64_t base = deposit(wb, g.rest) | lm.addr;
+    // gather in address order, all loads of a lane in flight
     E buf[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = t + u * kBlock, c = e % NC, r = e / NC;
-      const uint64_t col = c0 + c;
-      E v = {};
-      if (col < ngroups) v = ld(psi + group_base<K>(col, g) + member_off<K>(r, g));
-      buf[u] = v;
+#define SV_LD(U)                                                  \
+    {                                                             \
+      uint64_t a;                                                 \
+      uint32_t li;                                                \
+      bool on;                                                    \
+      elem_map<U>(g, &a, &li, &on);                               \
+      if (on && lm.on) buf[U] = ld(psi + (base | a));             \
     }
-    __syncthreads();  // U is staged and the previous tile's readers are done
-#pragma unroll
-    for (int u = 0; u < PER; ++u) xs[t + u * kBlock] = buf[u];
+    SV_FOR_U(PER, SV_LD)
+#undef SV_LD
+    __syncthreads();  // U is staged and the previous tile's store phase is done
+#define SV_LDS(U)                                                 \
+    {                                                             \
+      uint64_t a;                                                 \
+      uint32_t li;                                                \
+      bool on;                                                    \
+      elem_map<U>(g, &a, &li, &on);                               \
+      if (on && lm.on) xs[lm.lds | li] = buf[U];                  \
+    }
+    SV_FOR_U(PER, SV_LDS)
+#undef SV_LDS
     __syncthreads();
-    for (int tile = w; tile < TILES; tile += 4) {
+    // each wave computes up to TPW (row block, column block) output tiles
+    typename MS::acc_t acc[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int tile = w + 4 * i;
+      acc[i] = typename MS::acc_t{};
+      if (tile >= TILES) continue;
       const int rb = tile % RBLK, cb = tile / RBLK;
       int ai, aa;  // output member and re/im of the A row this lane supplies
       MS::row_of(l % MS::BM, &ai, &aa);
       ai += MS::MPB * rb;
       const int bcol = MS::BN * cb + l % MS::BN;
-      typename MS::acc_t acc = {};
 #pragma unroll 8
       for (int ks = 0; ks < KSTEPS; ++ks) {
         const int ak = MS::BK * ks + l / MS::BM;  // real column of A (= real row of B)
@@ -216,21 +293,37 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
         const int bk = MS::BK * ks + l / MS::BN;
         const E xv = xs[(bk >> 1) * NC + bcol];
         const R b = (bk & 1) ? xv.y : xv.x;
-        acc = MS::mma(a, b, acc);
-      }
-      const uint64_t gcol = c0 + bcol;
-      if (gcol < ngroups) {
-        const uint64_t gb = group_base<K>(gcol, g);
-#pragma unroll
-        for (int r = 0; r < MS::NACC; r += 2) {
-          const int mem = MS::MPB * rb + MS::out_member(l, r);
-          E y;
-          y.x = acc[r];
-          y.y = acc[r + 1];
-          st(psi + gb + member_off<K>(mem, g), y);
-        }
+        acc[i] = MS::mma(a, b, acc[i]);
       }
     }
+    __syncthreads();  // every wave has read X: the outputs replace it in LDS
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int tile = w + 4 * i;
+      if (tile >= TILES) continue;
+      const int rb = tile % RBLK, cb = tile / RBLK;
+      const int bcol = MS::BN * cb + l % MS::BN;
+#pragma unroll
+      for (int r = 0; r < MS::NACC; r += 2) {
+        const int mem = MS::MPB * rb + MS::out_member(l, r);
+        E y;
+        y.x = acc[i][r];
+        y.y = acc[i][r + 1];
+        xs[mem * NC + bcol] = y;
+      }
+    }
+    __syncthreads();
+    // store in address order
+#define SV_ST(U)                                                  \
+    {                                                             \
+      uint64_t a;                                                 \
+      uint32_t li;                                                \
+      bool on;                                                    \
+      elem_map<U>(g, &a, &li, &on);                               \
+      if (on && lm.on) st(psi + (base | a), xs[lm.lds | li]);     \
+    }
+    SV_FOR_U(PER, SV_ST)
+#undef SV_ST
   }
 }
 
@@ -246,60 +339,80 @@ hipError_t run_mfma(void* psi, int n, const DenseGeo& g, const void* m, hipStrea
     attr_set = true;
   }
   const uint64_t ngroups = 1ull << (n - K);
-  const uint64_t tiles = (ngroups + NC - 1) / NC;
+  const uint64_t nwork = (ngroups + NC - 1) / NC;
   // persistent blocks: enough to fill the chip several times over, each
   // amortising its staged U over many column tiles
-  const uint64_t blocks = tiles < 4096 ? tiles : 4096;
+  const uint64_t blocks = nwork < 4096 ? nwork : 4096;
   hipLaunchKernelGGL((k_dense_mfma<R, K>), dim3((unsigned)blocks), dim3(kBlock), lds, s,
-                     (typename mfma_shape<R>::E*)psi, ngroups, g, (const R*)m);
+                     (typename mfma_shape<R>::E*)psi, nwork, g, (const R*)m);
   return hipGetLastError();
 }
 
-template <typename E>
-hipError_t dispatch(void* psi, int n, int k, const DenseGeo& g, const void* m, hipStream_t s) {
-  switch (k) {
-    case 3: return run<E, 3>(psi, n, g, m, s);
-    case 4: return run<E, 4>(psi, n, g, m, s);
-    case 5: return run<E, 5>(psi, n, g, m, s);
-    case 6: return run<E, 6>(psi, n, g, m, s);
+// Tile map of a k-qubit gate q[0..k-1] (q[0] = MSB of the member index)
+// with nc columns per tile (a power of two), for an n-qubit state.
+DenseGeo make_geo(int n, int k, const int* q, int nc) {
+  int cb = 0;
+  while ((1 << cb) < nc) ++cb;
+  struct Bit {
+    uint32_t pos, lds;
+  } bits[16];
+  int nb = 0;
+  uint64_t gate = 0;
+  for (int i = 0; i < k; ++i) {
+    bits[nb++] = {(uint32_t)q[i], (1u << (k - 1 - i)) << cb};
+    gate |= 1ull << q[i];
   }
-  return hipErrorInvalidValue;
+  int col = 0;
+  for (int p = 0; p < n && col < cb; ++p)
+    if (!((gate >> p) & 1)) bits[nb++] = {(uint32_t)p, 1u << col++};
+  uint64_t tilemask = gate;
+  for (int i = k; i < nb; ++i) tilemask |= 1ull << bits[i].pos;
+  for (; col < cb; ++col) bits[nb++] = {64u, 1u << col};  // beyond the state
+  for (int i = 1; i < nb; ++i)
+    for (int j = i; j > 0 && bits[j - 1].pos > bits[j].pos; --j) {
+      const Bit tmp = bits[j];
+      bits[j] = bits[j - 1];
+      bits[j - 1] = tmp;
+    }
+  DenseGeo g{};
+  g.nbits = (uint32_t)nb;
+  for (int j = 0; j < nb; ++j) {
+    g.pos[j] = bits[j].pos;
+    g.lds[j] = bits[j].lds;
+    if (bits[j].pos == 64u) g.inv |= 1u << j;
+  }
+  const uint64_t all = n >= 64 ? ~0ull : (1ull << n) - 1ull;
+  g.rest = all & ~tilemask;
+  return g;
 }
 
 }  // namespace
 
 hipError_t launch_dense_kq(sv_dtype dt, void* psi, int n, int k, const int* q, const void* m_dev, bool mfma,
                            hipStream_t s) {
-  DenseGeo g{};
-  int sorted[SV_MAX_GATE_QUBITS];
-  for (int i = 0; i < k; ++i) {
-    g.q[i] = (unsigned)q[i];
-    sorted[i] = q[i];
-  }
-  for (int i = 1; i < k; ++i)
-    for (int j = i; j > 0 && sorted[j - 1] > sorted[j]; --j) {
-      int tmp = sorted[j];
-      sorted[j] = sorted[j - 1];
-      sorted[j - 1] = tmp;
-    }
-  for (int i = 0; i < k; ++i) g.zs[i] = (unsigned)sorted[i];
   if (dt == SV_C128) {
     switch (k) {
-      case 3: return run_mfma<double, 3>(psi, n, g, m_dev, s);
-      case 4: return run_mfma<double, 4>(psi, n, g, m_dev, s);
-      case 5: return run_mfma<double, 5>(psi, n, g, m_dev, s);
-      case 6: return run_mfma<double, 6>(psi, n, g, m_dev, s);
+      case 3: return run_mfma<double, 3>(psi, n, make_geo(n, k, q, mfma_cols<double, 3>()), m_dev, s);
+      case 4: return run_mfma<double, 4>(psi, n, make_geo(n, k, q, mfma_cols<double, 4>()), m_dev, s);
+      case 5: return run_mfma<double, 5>(psi, n, make_geo(n, k, q, mfma_cols<double, 5>()), m_dev, s);
+      case 6: return run_mfma<double, 6>(psi, n, make_geo(n, k, q, mfma_cols<double, 6>()), m_dev, s);
     }
     return hipErrorInvalidValue;
   }
   if (mfma && k >= 4) {
     switch (k) {
-      case 4: return run_mfma<float, 4>(psi, n, g, m_dev, s);
-      case 5: return run_mfma<float, 5>(psi, n, g, m_dev, s);
-      case 6: return run_mfma<float, 6>(psi, n, g, m_dev, s);
+      case 4: return run_mfma<float, 4>(psi, n, make_geo(n, k, q, mfma_cols<float, 4>()), m_dev, s);
+      case 5: return run_mfma<float, 5>(psi, n, make_geo(n, k, q, mfma_cols<float, 5>()), m_dev, s);
+      case 6: return run_mfma<float, 6>(psi, n, make_geo(n, k, q, mfma_cols<float, 6>()), m_dev, s);
     }
   }
-  return dispatch<flt2>(psi, n, k, g, m_dev, s);
+  switch (k) {
+    case 3: return run<flt2, 3>(psi, n, make_geo(n, k, q, tile_cols<3>()), m_dev, s);
+    case 4: return run<flt2, 4>(psi, n, make_geo(n, k, q, tile_cols<4>()), m_dev, s);
+    case 5: return run<flt2, 5>(psi, n, make_geo(n, k, q, tile_cols<5>()), m_dev, s);
+    case 6: return run<flt2, 6>(psi, n, make_geo(n, k, q, tile_cols<6>()), m_dev, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace sv

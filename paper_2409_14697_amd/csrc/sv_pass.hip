@@ -25,8 +25,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int RB = kPassRegBits;
 constexpr int NR = 1 << RB;
-constexpr int kBatchBits = 3;
-constexpr int kBatch = 1 << kBatchBits;  // global loads in flight per lane while gathering a tile
 
 template <int WB>
 __device__ __forceinline__ uint32_t swz(uint32_t x) {
@@ -47,9 +45,65 @@ struct dev_elem<float> {
   typedef flt2 E;
 };
 
+// Program memory (pass descriptors, stages, ops, matrices, batch items) is
+// read-only while a pass kernel runs.  Reading it through the constant
+// address space lets uniform reads go through scalar loads even where the
+// compiler cannot prove that the state's stores do not alias it (the batched
+// kernel takes the state and program pointers from one descriptor array).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+// The state lives in global memory; saying so keeps its loads and stores
+// global (not flat) after its pointer passed through scalar registers.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ T ldg(gptr<const T> p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void stg(gptr<T> p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)p;
+}
+// A value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+template <typename P>
+__device__ __forceinline__ P uniform_ptr(P p) {
+  return (P)uniform64((uint64_t)p);
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cget(cptr<cplx<R>> M, uint32_t i) {
+  return cplx<R>{M[i].re, M[i].im};
+}
+// Copy a program struct out of constant memory (dword by dword: the
+// implicit copy constructor cannot read another address space).
+template <typename T>
+__device__ __forceinline__ T cload(cptr<T> p) {
+  static_assert(sizeof(T) % 4 == 0, "program structs are dword multiples");
+  T out;
+  const __attribute__((address_space(4))) uint32_t* src = (const __attribute__((address_space(4))) uint32_t*)p;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
+  return out;
+}
+
 template <int B, typename R>
-__device__ __forceinline__ void op_u1(cplx<R>* v, const cplx<R>* M) {
-  const cplx<R> m0 = M[0], m1 = M[1], m2 = M[2], m3 = M[3];
+__device__ __forceinline__ void op_u1(cplx<R>* v, cptr<cplx<R>> M) {
+  const cplx<R> m0 = cget(M, 0), m1 = cget(M, 1), m2 = cget(M, 2), m3 = cget(M, 3);
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (!((r >> B) & 1)) {
@@ -60,7 +114,7 @@ __device__ __forceinline__ void op_u1(cplx<R>* v, const cplx<R>* M) {
 }
 
 template <int B0, int B1, typename R>
-__device__ __forceinline__ void op_u2(cplx<R>* v, const cplx<R>* M) {
+__device__ __forceinline__ void op_u2(cplx<R>* v, cptr<cplx<R>> M) {
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (!((r >> B0) & 1) && !((r >> B1) & 1)) {
@@ -68,13 +122,54 @@ __device__ __forceinline__ void op_u2(cplx<R>* v, const cplx<R>* M) {
       const cplx<R> x0 = v[i[0]], x1 = v[i[1]], x2 = v[i[2]], x3 = v[i[3]];
 #pragma unroll
       for (int o = 0; o < 4; ++o) {
-        cplx<R> y = cmul(M[4 * o], x0);
-        y = cfma(y, M[4 * o + 1], x1);
-        y = cfma(y, M[4 * o + 2], x2);
-        y = cfma(y, M[4 * o + 3], x3);
+        cplx<R> y = cmul(cget(M, 4 * o), x0);
+        y = cfma(y, cget(M, 4 * o + 1), x1);
+        y = cfma(y, cget(M, 4 * o + 2), x2);
+        y = cfma(y, cget(M, 4 * o + 3), x3);
         v[i[o]] = y;
       }
     }
+}
+
+// Real 2x2 (H, RY): two real scalars per output, 4 multiply-adds per amplitude.
+template <int B, typename R>
+__device__ __forceinline__ void op_ur(cplx<R>* v, cptr<cplx<R>> M) {
+  const R m0 = cget(M, 0).re, m1 = cget(M, 1).re, m2 = cget(M, 2).re, m3 = cget(M, 3).re;
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    if (!((r >> B) & 1)) {
+      const cplx<R> a0 = v[r], a1 = v[r | (1 << B)];
+      v[r] = cplx<R>{fma(m1, a1.re, m0 * a0.re), fma(m1, a1.im, m0 * a0.im)};
+      v[r | (1 << B)] = cplx<R>{fma(m3, a1.re, m2 * a0.re), fma(m3, a1.im, m2 * a0.im)};
+    }
+}
+
+// Real diagonal, imaginary off-diagonal (RX): (x + i y) * (i s) = -s y + i s x.
+template <int B, typename R>
+__device__ __forceinline__ void op_ui(cplx<R>* v, cptr<cplx<R>> M) {
+  const R m0 = cget(M, 0).re, s1 = cget(M, 1).im, s2 = cget(M, 2).im, m3 = cget(M, 3).re;
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    if (!((r >> B) & 1)) {
+      const cplx<R> a0 = v[r], a1 = v[r | (1 << B)];
+      v[r] = cplx<R>{fma(-s1, a1.im, m0 * a0.re), fma(s1, a1.re, m0 * a0.im)};
+      v[r | (1 << B)] = cplx<R>{fma(-s2, a0.im, m3 * a1.re), fma(s2, a0.re, m3 * a1.im)};
+    }
+}
+
+// Phase on the amplitudes whose register bit B is 1 (controlled phases).
+template <int B, typename R>
+__device__ __forceinline__ void op_p1(cplx<R>* v, cplx<R> p) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    if ((r >> B) & 1) v[r] = cmul(p, v[r]);
+}
+
+template <int B0, int B1, typename R>
+__device__ __forceinline__ void op_p2(cplx<R>* v, cplx<R> p) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    if (((r >> B0) & 1) && ((r >> B1) & 1)) v[r] = cmul(p, v[r]);
 }
 
 template <int B, typename R>
@@ -107,8 +202,8 @@ __device__ __forceinline__ void op_d1(cplx<R>* v, const cplx<R>* M) {
 }
 
 template <int B0, int B1, typename R>
-__device__ __forceinline__ void op_d2(cplx<R>* v, const cplx<R>* M) {
-  const cplx<R> d[4] = {M[0], M[1], M[2], M[3]};
+__device__ __forceinline__ void op_d2(cplx<R>* v, cptr<cplx<R>> M) {
+  const cplx<R> d[4] = {cget(M, 0), cget(M, 1), cget(M, 2), cget(M, 3)};
 #pragma unroll
   for (int r = 0; r < NR; ++r) v[r] = cmul(d[(((r >> B0) & 1) << 1) | ((r >> B1) & 1)], v[r]);
 }
@@ -130,7 +225,7 @@ __device__ __forceinline__ void op_d2(cplx<R>* v, const cplx<R>* M) {
 // M points at the op's first matrix entry (the same address in every lane, so
 // the entries come through scalar loads); `var` selects a variant per lane.
 template <typename R>
-__device__ __forceinline__ void apply_op(const PassOpDev& op, const cplx<R>* __restrict__ M, uint32_t var,
+__device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, uint32_t var,
                                          cplx<R>* v) {
   const uint32_t pair = op.b0 * 4 + op.b1;
   switch (op.type) {
@@ -159,13 +254,13 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, const cplx<R>* __r
       break;
     }
     case POP_D1: {
-      cplx<R> d[2] = {M[0], M[1]};
-      if (op.sa != kPassNoSel) {  // two variants, picked per lane
-        const cplx<R> e0 = M[2], e1 = M[3];
-        if (var) {
-          d[0] = e0;
-          d[1] = e1;
-        }
+      cplx<R> d[2] = {cget(M, 0), cget(M, 1)};
+      if (op.sa != kPassNoSel) {  // two variants, picked per lane (value selects: the loads stay uniform)
+        const cplx<R> e0 = cget(M, 2), e1 = cget(M, 3);
+        d[0].re = var ? e0.re : d[0].re;
+        d[0].im = var ? e0.im : d[0].im;
+        d[1].re = var ? e1.re : d[1].re;
+        d[1].im = var ? e1.im : d[1].im;
       }
 #define F(B) op_d1<B>(v, d)
       SV_BIT_SWITCH(op.b0, F)
@@ -178,12 +273,43 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, const cplx<R>* __r
 #undef F
       break;
     }
+    case POP_UR: {
+#define F(B) op_ur<B>(v, M)
+      SV_BIT_SWITCH(op.b0, F)
+#undef F
+      break;
+    }
+    case POP_UI: {
+#define F(B) op_ui<B>(v, M)
+      SV_BIT_SWITCH(op.b0, F)
+#undef F
+      break;
+    }
+    case POP_P1: {
+      cplx<R> p = cget(M, 0);
+      if (op.sa != kPassNoSel) {  // two variants, picked per lane
+        const cplx<R> p1 = cget(M, 1);
+        p.re = var ? p1.re : p.re;
+        p.im = var ? p1.im : p.im;
+      }
+#define F(B) op_p1<B>(v, p)
+      SV_BIT_SWITCH(op.b0, F)
+#undef F
+      break;
+    }
+    case POP_P2: {
+      const cplx<R> p = cget(M, 0);
+#define F(A, B) op_p2<A, B>(v, p)
+      SV_PAIR_SWITCH(pair, F)
+#undef F
+      break;
+    }
     case POP_DG: {
-      cplx<R> p = M[0];
+      cplx<R> p = cget(M, 0);
       if (op.sa != kPassNoSel) {
-        const cplx<R> p1 = M[1];
+        const cplx<R> p1 = cget(M, 1);
         if (op.sb != kPassNoSel) {
-          const cplx<R> p2 = M[2], p3 = M[3];
+          const cplx<R> p2 = cget(M, 2), p3 = cget(M, 3);
           // two-level select on the variant bits (kept as selects, not a table)
           const bool hi = (var >> 1) & 1u, lo = var & 1u;
           const R re0 = lo ? p1.re : p.re, im0 = lo ? p1.im : p.im;
@@ -203,75 +329,166 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, const cplx<R>* __r
   }
 }
 
-// Per-lane physical offsets of the batch index u (local bits 8 .. 8 + log2(kBatch) - 1).
-struct BatchOffsets {
-  uint64_t in[kBatch], out[kBatch];
+// Global memory is moved in 16-byte elements: one complex128 amplitude, or a
+// pair of complex64 amplitudes whose local bit 0 (always physical bit 0: the
+// low bits are pinned) lies inside the element.
+template <typename R>
+struct gelem;
+template <>
+struct gelem<double> {
+  typedef dbl2 G;
+  static constexpr int LB = 0;  // local bits inside one element
+};
+template <>
+struct gelem<float> {
+  typedef flt4 G;
+  static constexpr int LB = 1;
 };
 
-__device__ __forceinline__ void batch_offsets(const PassDescDev& P, BatchOffsets* bo) {
+// Uniform physical offsets of the per-lane element counter: bit b of the
+// counter is local bit LB + 8 + b; h[0..3] cover a batch of 16, the rest the
+// batch number.
+struct PassOffsets {
+  uint64_t in[4], out[4];
+};
+
+template <int LB>
+__device__ __forceinline__ void pass_offsets(cptr<PassDescDev> P, PassOffsets* po) {
 #pragma unroll
-  for (int u = 0; u < kBatch; ++u) {
-    bo->in[u] = bo->out[u] = 0;
-#pragma unroll
-    for (int b = 0; b < kBatchBits; ++b)
-      if (((u >> b) & 1) && 8u + b < P.m) {
-        bo->in[u] |= 1ull << P.lpos[8 + b];
-        bo->out[u] |= 1ull << P.wpos[8 + b];
-      }
+  for (int b = 0; b < 4; ++b) {
+    const uint32_t l = LB + 8 + b;
+    po->in[b] = l < P->m ? 1ull << P->lpos[l] : 0ull;
+    po->out[b] = l < P->m ? 1ull << P->wpos[l] : 0ull;
   }
 }
 
-// One tile of one pass: gather, run the stages, scatter.  `tile` is the LDS
-// buffer of 2^m elements; every thread of the block calls this.
-template <typename R, int WB>
-__device__ __forceinline__ void tile_pass(typename dev_elem<R>::E* __restrict__ psi, int n, const PassDescDev& P,
-                                          const PassStageDev* __restrict__ stages,
-                                          const PassOpDev* __restrict__ ops, const cplx<R>* __restrict__ mats,
-                                          uint64_t tile_id, typename dev_elem<R>::E* tile,
-                                          const BatchOffsets& bo) {
-  typedef typename dev_elem<R>::E E;
-  const uint32_t m = P.m;
-  const uint32_t size = 1u << m;
-  const uint64_t all = (1ull << n) - 1ull;
-  const uint32_t t = threadIdx.x;
-  const uint32_t per = size >= (uint32_t)kBlock ? size / kBlock : 1u;  // elements per lane
-  const bool lane_on = t < size;
-  const uint64_t base = deposit(tile_id, all & ~P.lmask);
+template <int U>
+__device__ __forceinline__ uint64_t batch_bits(const uint64_t* h) {
+  return ((U & 1) ? h[0] : 0ull) | ((U & 2) ? h[1] : 0ull) | ((U & 4) ? h[2] : 0ull) | ((U & 8) ? h[3] : 0ull);
+}
 
-  // gather: x = t + 256 j; the low 8 local bits come from t, the rest from j.
-  // kBatch loads per lane are issued before any of them is written to LDS.
-  uint64_t lo_in = 0, lo_out = 0;
-  for (uint32_t j = 0; j < m && j < 8; ++j)
-    if ((t >> j) & 1u) {
-      lo_in |= 1ull << P.lpos[j];
-      lo_out |= 1ull << P.wpos[j];
-    }
-  for (uint32_t j0 = 0; j0 < per; j0 += kBatch) {
-    // local bits 8 + log2(kBatch) .. m-1 come from j0 (the same in every lane)
-    uint64_t hi_in = 0;
-    for (uint32_t b = 8 + kBatchBits; b < m; ++b)
-      if ((j0 >> (b - 8)) & 1u) hi_in |= 1ull << P.lpos[b];
-    E buf[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (j0 + u < per && lane_on) buf[u] = ld(psi + (base | lo_in | hi_in | bo.in[u]));
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (j0 + u < per && lane_on) tile[swz<WB>(t + (j0 + u) * kBlock)] = buf[u];
+// Everything a lane needs to move one tile: the pass, the state, the tile's
+// base index and the uniform offsets of its element counter.
+template <typename R>
+struct TileRef {
+  typename dev_elem<R>::E* psi;
+  cptr<PassDescDev> P;
+  cptr<PassStageDev> stages;
+  cptr<PassOpDev> ops;
+  cptr<cplx<R>> mats;
+  uint64_t base;
+};
+
+template <typename R>
+__device__ __forceinline__ TileRef<R> tile_ref(typename dev_elem<R>::E* psi, int n, cptr<PassDescDev> P,
+                                               cptr<PassStageDev> stages, cptr<PassOpDev> ops,
+                                               cptr<cplx<R>> mats, uint64_t tile_id) {
+  TileRef<R> r;
+  r.psi = uniform_ptr(psi);
+  r.P = uniform_ptr(P);
+  r.stages = uniform_ptr(stages);
+  r.ops = uniform_ptr(ops);
+  r.mats = uniform_ptr(mats);
+  r.base = uniform64(deposit(tile_id, ((1ull << n) - 1ull) & ~r.P->lmask));
+  return r;
+}
+
+constexpr int kBatch = 16;  // 16-byte loads in flight per lane
+
+// Lane geometry of a tile: element e = t + 256 j holds local index
+// x = e << LB; local bits LB .. LB+7 come from the lane, the rest from j.
+struct LaneGeo {
+  uint32_t per;
+  bool on;
+};
+
+template <int LB>
+__device__ __forceinline__ LaneGeo lane_geo(uint32_t m) {
+  const uint32_t elems = (1u << m) >> LB;
+  return {elems >= (uint32_t)kBlock ? elems / kBlock : 1u, threadIdx.x < elems};
+}
+
+template <int LB>
+__device__ __forceinline__ uint64_t lane_bits(cptr<uint32_t> pos, uint32_t m) {
+  uint64_t r = 0;
+  for (uint32_t j = 0; j < 8 && LB + j < m; ++j)
+    if ((threadIdx.x >> j) & 1u) r |= 1ull << pos[LB + j];
+  return r;
+}
+
+// Issue the loads of the whole tile into buf (no wait).
+template <typename R>
+__device__ __forceinline__ void tile_load(const TileRef<R>& T, typename gelem<R>::G* buf) {
+  typedef typename gelem<R>::G G;
+  constexpr int LB = gelem<R>::LB;
+  const cptr<PassDescDev> P = T.P;
+  const LaneGeo lg = lane_geo<LB>(P->m);
+  const gptr<const G> gpsi = as_global(reinterpret_cast<const G*>(T.psi));
+  const uint64_t a0 = T.base | lane_bits<LB>(P->lpos, P->m);
+  PassOffsets po;
+  pass_offsets<LB>(P, &po);
+  // unpredicated: elements past the tile (small tiles) re-read the tile base,
+  // so the loads need no branches (and no waits between them)
+#define SV_LD(U)                                                                        \
+  {                                                                                     \
+    const uint64_t ad = (U < lg.per && lg.on) ? (a0 | batch_bits<U>(po.in)) : T.base;  \
+    buf[U] = ldg<G>(gpsi + (ad >> LB));                                                 \
   }
-  __syncthreads();
+  SV_LD(0) SV_LD(1) SV_LD(2) SV_LD(3) SV_LD(4) SV_LD(5) SV_LD(6) SV_LD(7)
+  SV_LD(8) SV_LD(9) SV_LD(10) SV_LD(11) SV_LD(12) SV_LD(13) SV_LD(14) SV_LD(15)
+#undef SV_LD
+}
 
-  for (uint32_t si = 0; si < P.stage_count; ++si) {
-    const PassStageDev& S = stages[P.stage_first + si];
+template <typename R, int WB>
+__device__ __forceinline__ void batch_to_lds(const typename gelem<R>::G* buf, uint32_t j0, const LaneGeo& lg,
+                                             typename dev_elem<R>::E* tile) {
+  typedef typename dev_elem<R>::E E;
+  constexpr int LB = gelem<R>::LB;
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u)
+    if (j0 + u < lg.per && lg.on) {
+      const uint32_t x = (threadIdx.x + (j0 + u) * kBlock) << LB;
+      if constexpr (LB == 1) {
+        tile[swz<WB>(x)] = E{buf[u].x, buf[u].y};
+        tile[swz<WB>(x | 1u)] = E{buf[u].z, buf[u].w};
+      } else {
+        tile[swz<WB>(x)] = buf[u];
+      }
+    }
+}
+
+// Write the loaded tile (at most 16 elements per lane: 64 KiB tiles) to LDS.
+template <typename R, int WB>
+__device__ __forceinline__ void tile_fill(const TileRef<R>& T, const typename gelem<R>::G* buf,
+                                          typename dev_elem<R>::E* tile) {
+  const LaneGeo lg = lane_geo<gelem<R>::LB>(T.P->m);
+  batch_to_lds<R, WB>(buf, 0, lg, tile);
+}
+
+// The pass's register stages on the tile in LDS (ends with a barrier).
+template <typename R, int WB>
+__device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_elem<R>::E* tile) {
+  typedef typename dev_elem<R>::E E;
+  const cptr<PassDescDev> P = T.P;
+  const cptr<PassStageDev> stages = T.stages;
+  const cptr<PassOpDev> ops = T.ops;
+  const cptr<cplx<R>> mats = T.mats;
+  const uint64_t base = T.base;
+  const uint32_t size = 1u << P->m;
+  const uint32_t t = threadIdx.x;
+  for (uint32_t si = 0; si < P->stage_count; ++si) {
+    const PassStageDev S = cload(stages + (P->stage_first + si));
     const uint32_t groups = size >> RB;
-    uint32_t off[NR];
+    // swz is linear over XOR and xg shares no bit with a register offset, so
+    // swz(xg | off) = swz(xg) ^ swz(off): the 16 offsets are swizzled once
+    uint32_t soff[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       uint32_t o = 0;
 #pragma unroll
       for (int b = 0; b < RB; ++b)
         if ((r >> b) & 1) o |= 1u << S.q[b];
-      off[r] = o;
+      soff[r] = swz<WB>(o);
     }
     for (uint32_t gi = t; gi < groups; gi += kBlock) {
       uint32_t xg = gi;
@@ -280,14 +497,15 @@ __device__ __forceinline__ void tile_pass(typename dev_elem<R>::E* __restrict__ 
         const uint32_t q = S.qsort[b];
         xg = ((xg >> q) << (q + 1)) | (xg & ((1u << q) - 1u));
       }
+      const uint32_t sx = swz<WB>(xg);
       cplx<R> v[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const E e = tile[swz<WB>(xg | off[r])];
+        const E e = tile[sx ^ soff[r]];
         v[r] = cplx<R>{e.x, e.y};
       }
       for (uint32_t o = 0; o < S.op_count; ++o) {
-        const PassOpDev op = ops[S.op_first + o];
+        const PassOpDev op = cload(ops + (S.op_first + o));
         if ((xg & op.lmask) != op.lmask || (base & op.tmask) != op.tmask) continue;
         uint32_t var = 0;
         if (op.sa != kPassNoSel) {
@@ -303,26 +521,102 @@ __device__ __forceinline__ void tile_pass(typename dev_elem<R>::E* __restrict__ 
         E e;
         e.x = v[r].re;
         e.y = v[r].im;
-        tile[swz<WB>(xg | off[r])] = e;
+        tile[sx ^ soff[r]] = e;
       }
     }
     __syncthreads();
   }
 
-  for (uint32_t j0 = 0; j0 < per; j0 += kBatch) {
-    uint64_t hi_out = 0;
-    for (uint32_t b = 8 + kBatchBits; b < m; ++b)
-      if ((j0 >> (b - 8)) & 1u) hi_out |= 1ull << P.wpos[b];
-    E buf[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (j0 + u < per && lane_on) buf[u] = tile[swz<WB>(t + (j0 + u) * kBlock)];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (j0 + u < per && lane_on) st(psi + (base | lo_out | hi_out | bo.out[u]), buf[u]);
-  }
-  __syncthreads();  // the tile buffer is reused by the next tile
 }
+
+// Store the tile: local bit j goes to physical position wpos[j]; complex64
+// pairs stay 16-byte elements when local bit 0 is written back to bit 0.
+template <typename R, int WB>
+__device__ __forceinline__ void tile_store(const TileRef<R>& T, const typename dev_elem<R>::E* tile) {
+  typedef typename dev_elem<R>::E E;
+  typedef typename gelem<R>::G G;
+  constexpr int LB = gelem<R>::LB;
+  const cptr<PassDescDev> P = T.P;
+  const LaneGeo lg = lane_geo<LB>(P->m);
+  const gptr<G> gpsi = as_global(reinterpret_cast<G*>(T.psi));
+  const gptr<E> epsi = as_global(T.psi);
+  const bool pair_store = LB == 0 || P->wpos[0] == 0;
+  const uint64_t lo = T.base | lane_bits<LB>(P->wpos, P->m);
+  PassOffsets po;
+  pass_offsets<LB>(P, &po);
+  {
+    constexpr uint32_t j0 = 0;
+    const uint64_t a0 = lo;
+    G buf[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (j0 + u < lg.per && lg.on) {
+        const uint32_t x = (threadIdx.x + (j0 + u) * kBlock) << LB;
+        if constexpr (LB == 1) {
+          const E e0 = tile[swz<WB>(x)], e1 = tile[swz<WB>(x | 1u)];
+          buf[u] = G{e0.x, e0.y, e1.x, e1.y};
+        } else {
+          buf[u] = tile[swz<WB>(x)];
+        }
+      }
+    if (pair_store) {
+#define SV_ST(U) \
+      if (j0 + U < lg.per && lg.on) stg<G>(gpsi + ((a0 | batch_bits<U>(po.out)) >> LB), buf[U]);
+      SV_ST(0) SV_ST(1) SV_ST(2) SV_ST(3) SV_ST(4) SV_ST(5) SV_ST(6) SV_ST(7)
+      SV_ST(8) SV_ST(9) SV_ST(10) SV_ST(11) SV_ST(12) SV_ST(13) SV_ST(14) SV_ST(15)
+#undef SV_ST
+    } else if constexpr (LB == 1) {
+      // the pair splits: amplitude x | 1 goes to bit wpos[0]
+      const uint64_t b0 = 1ull << P->wpos[0];
+#define SV_ST2(U)                                                   \
+      if (j0 + U < lg.per && lg.on) {                               \
+        const uint64_t ad = a0 | batch_bits<U>(po.out);             \
+        stg<E>(epsi + ad, E{buf[U].x, buf[U].y});                   \
+        stg<E>(epsi + (ad | b0), E{buf[U].z, buf[U].w});            \
+      }
+      SV_ST2(0) SV_ST2(1) SV_ST2(2) SV_ST2(3) SV_ST2(4) SV_ST2(5) SV_ST2(6) SV_ST2(7)
+      SV_ST2(8) SV_ST2(9) SV_ST2(10) SV_ST2(11) SV_ST2(12) SV_ST2(13) SV_ST2(14) SV_ST2(15)
+#undef SV_ST2
+    }
+  }
+}
+
+// Persistent loop over tiles, software-pipelined: the next tile's loads are
+// in flight while the current tile runs its stages and is stored.  `next`
+// maps a global tile number to its TileRef.
+template <typename R, int WB, typename Src>
+__device__ __forceinline__ void tile_loop(uint64_t total, const Src& src, typename dev_elem<R>::E* tile) {
+  typedef typename gelem<R>::G G;
+  uint64_t g = xcd_block();
+  if (g >= total) return;
+  G buf[kBatch];
+  tile_load<R>(src(g), buf);
+  while (true) {
+    const uint64_t ng = g + gridDim.x;
+    const TileRef<R> cur = src(g);  // recomputed, not carried: fewer live registers
+    __syncthreads();  // the previous tile's store has read the buffer
+    tile_fill<R, WB>(cur, buf, tile);
+    __syncthreads();
+    if (ng < total) tile_load<R>(src(ng), buf);
+    tile_stages<R, WB>(cur, tile);
+    tile_store<R, WB>(cur, tile);
+    if (ng >= total) break;
+    g = ng;
+  }
+}
+
+template <typename R>
+struct SingleSrc {
+  typename dev_elem<R>::E* psi;
+  int n;
+  cptr<PassDescDev> P;
+  cptr<PassStageDev> stages;
+  cptr<PassOpDev> ops;
+  cptr<cplx<R>> mats;
+  __device__ __forceinline__ TileRef<R> operator()(uint64_t g) const {
+    return tile_ref<R>(psi, n, P, stages, ops, mats, g);
+  }
+};
 
 template <typename R, int WB>
 __global__ __launch_bounds__(kBlock) void k_pass(typename dev_elem<R>::E* __restrict__ psi, int n,
@@ -333,41 +627,55 @@ __global__ __launch_bounds__(kBlock) void k_pass(typename dev_elem<R>::E* __rest
   typedef typename dev_elem<R>::E E;
   extern __shared__ __align__(16) unsigned char smem[];
   E* tile = reinterpret_cast<E*>(smem);
-  const PassDescDev& P = passes[pi];
-  BatchOffsets bo;
-  batch_offsets(P, &bo);
-  const uint64_t ntiles = 1ull << (n - P.m);
-  for (uint64_t tile_id = xcd_block(); tile_id < ntiles; tile_id += gridDim.x)
-    tile_pass<R, WB>(psi, n, P, stages, ops, mats, tile_id, tile, bo);
+  const cptr<PassDescDev> P = as_const(passes + pi);
+  const SingleSrc<R> src{psi, n, P, as_const(stages), as_const(ops), as_const(mats)};
+  tile_loop<R, WB>(1ull << (n - P->m), src, tile);
 }
 
 // Many states in one launch: work item i runs pass `pass` of its own program
 // over its own tiles; global tile g belongs to the item whose [tile_begin,
 // tile_begin + tiles) range holds g.  No item reads another's state, so each
 // result is independent of the batch it ran in.
-template <typename R, int WB>
-__global__ __launch_bounds__(kBlock) void k_pass_batch(const BatchItemDev* __restrict__ items, int count,
-                                                       uint64_t total_tiles) {
-  typedef typename dev_elem<R>::E E;
-  extern __shared__ __align__(16) unsigned char smem[];
-  E* tile = reinterpret_cast<E*>(smem);
-  int cur = -1;
-  BatchOffsets bo;
-  for (uint64_t g = xcd_block(); g < total_tiles; g += gridDim.x) {
+template <typename R>
+struct BatchSrc {
+  cptr<BatchItemDev> items;
+  int count;
+  __device__ __forceinline__ TileRef<R> operator()(uint64_t g) const {
     int lo = 0, hi = count - 1;  // last item with tile_begin <= g
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (items[mid].tile_begin <= g) lo = mid;
       else hi = mid - 1;
     }
-    const BatchItemDev& it = items[lo];
-    const PassDescDev& P = it.passes[it.pass];
-    if (lo != cur) {
-      batch_offsets(P, &bo);
-      cur = lo;
-    }
-    tile_pass<R, WB>((E*)it.psi, it.n, P, it.stages, it.ops, (const cplx<R>*)it.mats, g - it.tile_begin, tile, bo);
+    lo = __builtin_amdgcn_readfirstlane(lo);  // the same in every lane
+    const cptr<BatchItemDev> it = items + lo;  // fields read one by one: scalar loads
+    return tile_ref<R>((typename dev_elem<R>::E*)it->psi, it->n, as_const(it->passes + it->pass),
+                       as_const(it->stages), as_const(it->ops), as_const((const cplx<R>*)it->mats),
+                       g - it->tile_begin);
   }
+};
+
+template <typename R, int WB>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pass_batch(const BatchItemDev* __restrict__ items, int count,
+                                                       uint64_t total_tiles) {
+  typedef typename dev_elem<R>::E E;
+  extern __shared__ __align__(16) unsigned char smem[];
+  E* tile = reinterpret_cast<E*>(smem);
+  const BatchSrc<R> src{as_const(items), count};
+  tile_loop<R, WB>(total_tiles, src, tile);
+}
+
+// Blocks that fit on the device at once for `kernel` with `lds` bytes of
+// dynamic LDS (the persistent grid of the pipelined tile loop).
+template <typename F>
+uint64_t resident_blocks(F kernel, size_t lds, uint64_t* cache) {
+  int nb = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, lds) != hipSuccess || nb < 1) nb = 1;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  *cache = (uint64_t)nb * (uint64_t)cus;
+  return *cache;
 }
 
 template <typename R, int WB>
@@ -375,15 +683,18 @@ hipError_t run(void* psi, int n, int m, const PassDescDev* passes, int pass, con
                const PassOpDev* ops, const void* mats, hipStream_t s) {
   typedef typename dev_elem<R>::E E;
   const size_t lds = ((size_t)1 << m) * sizeof(E);
-  static size_t attr = 0;  // largest dynamic LDS size requested so far
+  static size_t attr = 0;            // largest dynamic LDS size requested so far
+  static uint64_t resident[17] = {};  // per tile size
   if (lds > attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_pass<R, WB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
     attr = lds;
   }
-  const uint64_t tiles = capped_grid(1ull << (n - m));
-  hipLaunchKernelGGL((k_pass<R, WB>), dim3((unsigned)tiles), dim3(kBlock), lds, s, (E*)psi, n, passes, pass, stages,
+  if (!resident[m]) resident_blocks(k_pass<R, WB>, lds, &resident[m]);
+  const uint64_t tiles = 1ull << (n - m);
+  const uint64_t blocks = tiles < resident[m] ? tiles : resident[m];
+  hipLaunchKernelGGL((k_pass<R, WB>), dim3((unsigned)blocks), dim3(kBlock), lds, s, (E*)psi, n, passes, pass, stages,
                      ops, (const cplx<R>*)mats);
   return hipGetLastError();
 }
@@ -393,14 +704,16 @@ hipError_t run_batch(const BatchItemDev* items, int count, uint64_t total_tiles,
   typedef typename dev_elem<R>::E E;
   const size_t lds = ((size_t)1 << max_m) * sizeof(E);
   static size_t attr = 0;
+  static uint64_t resident[17] = {};
   if (lds > attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_pass_batch<R, WB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr = lds;
   }
-  const uint64_t blocks = capped_grid(total_tiles);
-  if (blocks == 0) return hipSuccess;
+  if (total_tiles == 0) return hipSuccess;
+  if (!resident[max_m]) resident_blocks(k_pass_batch<R, WB>, lds, &resident[max_m]);
+  const uint64_t blocks = total_tiles < resident[max_m] ? total_tiles : resident[max_m];
   hipLaunchKernelGGL((k_pass_batch<R, WB>), dim3((unsigned)blocks), dim3(kBlock), lds, s, items, count, total_tiles);
   return hipGetLastError();
 }

@@ -44,9 +44,23 @@ double op_flops(const PassOpDev& od) {
   switch (od.type) {
     case POP_U1: return 16.0;
     case POP_U2: return 32.0;
+    case POP_UR: case POP_UI: return 8.0;
     case POP_D1: case POP_D2: case POP_DG: return 6.0;
+    case POP_P1: return 3.0;
+    case POP_P2: return 1.5;
     default: return 1.0;
   }
+}
+
+bool all_real(const cd* m, int count) {
+  for (int i = 0; i < count; ++i)
+    if (m[i].imag() != 0.0) return false;
+  return true;
+}
+
+// Real diagonal and imaginary off-diagonal (RX, Y).
+bool real_diag_imag_offdiag(const cd* m) {
+  return m[0].imag() == 0.0 && m[3].imag() == 0.0 && m[1].real() == 0.0 && m[2].real() == 0.0;
 }
 
 struct StageBuilder {
@@ -87,7 +101,11 @@ struct StageBuilder {
         const int q = op.q[0], b = reg(q);
         if (diag) {
           const cd d0 = op.m[0], d1 = op.m[3];
-          if (b >= 0) {
+          if (b >= 0 && d0 == cd(1.0, 0.0)) {
+            od.type = POP_P1;
+            od.b0 = (uint32_t)b;
+            mv = {d1};
+          } else if (b >= 0) {
             od.type = POP_D1;
             od.b0 = (uint32_t)b;
             mv = {d0, d1};
@@ -104,7 +122,7 @@ struct StageBuilder {
           od.type = POP_X;
           od.b0 = (uint32_t)b;
         } else {
-          od.type = POP_U1;
+          od.type = all_real(op.m.data(), 4) ? POP_UR : real_diag_imag_offdiag(op.m.data()) ? POP_UI : POP_U1;
           od.b0 = (uint32_t)b;
           mv.assign(op.m.begin(), op.m.begin() + 4);
         }
@@ -126,30 +144,36 @@ struct StageBuilder {
         const int r0 = reg(q0), r1 = reg(q1);
         const cd one(1.0, 0.0);
         const bool cz_like = d[0] == one && d[1] == one && d[2] == one;
-        if (r0 >= 0 && r1 >= 0) {
+        if (r0 >= 0 && r1 >= 0 && cz_like) {
+          od.type = POP_P2;
+          od.b0 = (uint32_t)r0;
+          od.b1 = (uint32_t)r1;
+          mv = {d[3]};
+        } else if (r0 >= 0 && r1 >= 0) {
           od.type = POP_D2;
           od.b0 = (uint32_t)r0;
           od.b1 = (uint32_t)r1;
           mv = {d[0], d[1], d[2], d[3]};
-        } else if (r0 >= 0) {
-          od.type = POP_D1;
-          od.b0 = (uint32_t)r0;
+        } else if (r0 >= 0 || r1 >= 0) {
+          // one qubit in registers (bit b of the register index), the other
+          // (o) selects: entries by (bit of o, bit b)
+          const bool first = r0 >= 0;
+          const int b = first ? r0 : r1, o = first ? q1 : q0;
+          const cd e00 = first ? d[0] : d[0], e01 = first ? d[2] : d[1];  // o = 0: b = 0, 1
+          const cd e10 = first ? d[1] : d[2], e11 = first ? d[3] : d[3];  // o = 1: b = 0, 1
+          od.b0 = (uint32_t)b;
           if (cz_like) {
-            predicate(&od, q1);
-            mv = {one, d[3]};
+            od.type = POP_P1;
+            predicate(&od, o);
+            mv = {d[3]};
+          } else if (e00 == one && e10 == one) {
+            od.type = POP_P1;  // only the b = 1 half changes
+            od.sa = src(o);
+            mv = {e01, e11};
           } else {
-            od.sa = src(q1);  // variant = bit of q1
-            mv = {d[0], d[2], d[1], d[3]};
-          }
-        } else if (r1 >= 0) {
-          od.type = POP_D1;
-          od.b0 = (uint32_t)r1;
-          if (cz_like) {
-            predicate(&od, q0);
-            mv = {one, d[3]};
-          } else {
-            od.sa = src(q0);  // variant = bit of q0
-            mv = {d[0], d[1], d[2], d[3]};
+            od.type = POP_D1;
+            od.sa = src(o);
+            mv = {e00, e01, e10, e11};
           }
         } else {
           od.type = POP_DG;
@@ -264,7 +288,8 @@ std::vector<std::vector<int>> cycles_of(const QubitMap& mp) {
 
 sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const sv_opts& o, sv_plan* p) {
   int m = o.lds_qubits ? o.lds_qubits : default_lds_qubits(dt);
-  const int m_max = dt == SV_C128 ? 13 : 14;  // 128 KiB of the 160 KiB LDS
+  // 64 KiB tiles: two blocks per CU, and 16 elements of 16 bytes per lane
+  const int m_max = dt == SV_C128 ? 12 : 13;
   if (m > m_max) return fail(SV_ERR_ARG, "lds_qubits %d exceeds %d for this dtype", m, m_max);
   if (m > n) m = n;
   if (m <= kPassRegBits) return fail(SV_ERR_ARG, "tile of %d qubits is too small for %d register bits", m, kPassRegBits);
@@ -471,6 +496,11 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
     p->est_cost += 1.0;
     p->passes.push_back(std::move(ps));
   }
+  // the pass kernels move complex64 amplitudes in pairs on physical bit 0,
+  // which the pinned low bits keep local as local bit 0
+  for (const Pass& ps : p->passes)
+    if ((ps.kind == PASS_TILE || ps.kind == PASS_PERMUTE) && ps.lpos[0] != 0)
+      return fail(SV_ERR_UNSUPPORTED, "internal: a tile pass without physical bit 0 local");
   return SV_OK;
 }
 

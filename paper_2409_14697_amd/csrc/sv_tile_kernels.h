@@ -25,7 +25,12 @@ enum PassOpType : uint32_t {
   POP_CX = 3,  // exchange pairs on bit b1 where bit b0 is 1     (0 entries)
   POP_D1 = 4,  // diag(d0, d1) on register bit b0                (2 entries)
   POP_D2 = 5,  // diag(d0..d3) on register bits (b0 = MSB, b1)   (4 entries)
-  POP_DG = 6   // one phase for the whole group                  (1 entry)
+  POP_DG = 6,  // one phase for the whole group                  (1 entry)
+  POP_UR = 7,  // real 2x2 on register bit b0 (H, RY)            (4 entries, real parts used)
+  POP_UI = 8,  // 2x2 with real diagonal and imaginary off-diagonal
+               // on register bit b0 (RX)                        (4 entries: re, im, im, re used)
+  POP_P1 = 9,  // phase on the amplitudes whose bit b0 is 1     (1 entry)
+  POP_P2 = 10  // phase on the amplitudes whose bits b0, b1 are 1 (1 entry)
 };
 constexpr uint32_t kPassNoSel = 0xffffffffu;
 constexpr uint32_t kPassTileSel = 64;  // select codes >= 64 name tile (non-local) physical bits

@@ -105,3 +105,28 @@ def test_modes_agree_layered_n16(sv, dtype, mode):
     gates = layered_circuit(n, n_gates=200, seed=1)
     out, ref = run_plan(sv, n, dtype, basis_state_np(n, 0), gates, {"mode": mode})
     assert max_err(out, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_permute_qubits_bitwise(sv, dtype):
+    """sv_permute_qubits against the oracle's index-bit permutation: random
+    permutations, a reversal, a cyclic shift and the identity; bitwise."""
+    from paper_2409_14697_amd import binding as B
+    rng = np.random.default_rng(17)
+    for n in (1, 2, 4, 5, 6, 9, 13, 14, 17, 20):
+        perms = [list(rng.permutation(n)) for _ in range(2)]
+        perms += [list(range(n - 1, -1, -1)), [(q + 1) % n for q in range(n)], list(range(n))]
+        for dest in perms:
+            t, host_in = to_device(gaussian_state_np(n, n), dtype)
+            st = sv.StateVector(n, dtype, tensor=t, init=False)
+            st.permute_qubits(dest)
+            st.sync()
+            ref = oracle.permute_qubits(host_in, dest)
+            assert np.array_equal(to_host(t), ref), (n, dest)
+            st.close()
+    st = sv.StateVector(5, dtype)
+    for bad in ([0, 1, 2, 3, 3], [0, 1, 2, 3, 5], [0, 1, 2, 3, -1]):
+        with pytest.raises(B.SvError) as e:
+            st.permute_qubits(bad)
+        assert e.value.status == B.SV_ERR_QUBIT
+    st.close()
