@@ -32,6 +32,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# vector (VALU) peaks: 256 CUs x 2.4 GHz; FP32 counts packed math, FP64 does not
+PEAK_VALU_TFLOPS = {"c64": 157.3, "c128": 78.6}
 N_QUBITS = 30
 LINE = 128  # bytes per memory read granule (FETCH_SIZE of sub-line subsets)
 
@@ -299,13 +301,26 @@ def serve_bench(args):
                                    f"pairs, Poisson arrivals at {args.rate_fraction} x closed-loop throughput, "
                                    f"budget 0.8 x free HBM, {main_dt} timed run",
                        "p99_ms": summ["p99_ms"], "p50_ms": summ["p50_ms"]},
-            "roofline": {"bound": "hbm", "achieved": round(st["GBs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": round(st["GBs"] / PEAK_HBM_GBS, 4), "traffic": None,
-                         "kernel": "k_pass_batch", "mean_launch_us": round(st["mean_launch_us"], 2)},
+            "roofline": serve_roofline(st, main_dt),
             "serving": out, "prep_s": round(prep_s, 2)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = serve_cpu_baseline(reqs)
     print(json.dumps(line))
+
+
+def serve_roofline(st, dt):
+    """Roofline of the batched pass kernel: whichever of HBM bytes and VALU
+    flops (both algorithmic, per second of launch time) is nearer its peak."""
+    peak_flops = PEAK_VALU_TFLOPS[dt]
+    hbm = st["GBs"] / PEAK_HBM_GBS
+    alu = st["TFLOPs"] / peak_flops
+    common = {"kernel": "k_pass_batch", "mean_launch_us": round(st["mean_launch_us"], 2),
+              "hbm_frac": round(hbm, 4), "alu_frac": round(alu, 4)}
+    if alu > hbm:
+        return dict({"bound": "alu", "achieved": round(st["TFLOPs"], 2), "peak": peak_flops, "unit": "TFLOP/s",
+                     "frac": round(alu, 4), "traffic": None}, **common)
+    return dict({"bound": "hbm", "achieved": round(st["GBs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                 "frac": round(hbm, 4), "traffic": None}, **common)
 
 
 def _round(d):

@@ -186,6 +186,12 @@ sv_status sv_plan_export(const sv_plan *p, size_t op, int32_t *nq, int32_t q[SV_
 sv_status sv_plan_pass_info(const sv_plan *p, size_t pass, int32_t *kind, int32_t *n_ops,
                             int32_t *n_local, int32_t *n_stages);
 
+/* Algorithmic arithmetic of pass `pass`, in real flops per amplitude of the
+ * state: the sum over its ops of 8 * 2^k for a dense k-qubit op (one complex
+ * multiply-add per matrix entry), 6 for a diagonal op (one complex multiply)
+ * and 0 for a permutation.  Errors: SV_ERR_ARG. */
+sv_status sv_plan_pass_flops(const sv_plan *p, size_t pass, double *flops_per_amp);
+
 sv_status sv_plan_destroy(sv_plan *p);
 
 /* Execute a plan built for this state's n and dtype.  Async.  The state is

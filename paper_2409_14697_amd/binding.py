@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sv_plan_pass_info": (S, [c_void_p, c_size_t, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                   POINTER(c_int32)]),
         "sv_plan_destroy": (S, [c_void_p]),
+        "sv_plan_pass_flops": (S, [c_void_p, c_size_t, POINTER(c_double)]),
         "sv_apply_plan": (S, [c_void_p, c_void_p]),
         "sv_apply_circuit": (S, [c_void_p, POINTER(SvGate), c_size_t, POINTER(SvOpts)]),
         "sv_permute_qubits": (S, [c_void_p, POINTER(c_int32)]),
@@ -225,6 +226,17 @@ class Plan:
             check(lib.sv_plan_pass_info(self._h, i, byref(kind), byref(nops), byref(nloc), byref(nst)))
             out.append((kind.value, nops.value, nloc.value, nst.value) if stages else
                        (kind.value, nops.value, nloc.value))
+        return out
+
+    def pass_flops(self) -> List[float]:
+        """Algorithmic real flops per amplitude of every pass (sv_plan_pass_flops)."""
+        lib = load_library()
+        _, n_passes = self.info()
+        out = []
+        f = c_double()
+        for i in range(n_passes):
+            check(lib.sv_plan_pass_flops(self._h, i, byref(f)))
+            out.append(f.value)
         return out
 
     def close(self):

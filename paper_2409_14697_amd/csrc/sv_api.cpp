@@ -320,6 +320,20 @@ sv_status sv_plan_pass_info(const sv_plan* p, size_t pass, int32_t* kind, int32_
   return SV_OK;
 }
 
+sv_status sv_plan_pass_flops(const sv_plan* p, size_t pass, double* flops_per_amp) {
+  clear_error();
+  if (!p || !flops_per_amp) return fail(SV_ERR_ARG, "null argument");
+  if (pass >= p->passes.size()) return fail(SV_ERR_ARG, "pass %zu out of range", pass);
+  double f = 0.0;
+  for (size_t i = 0; i < p->ops.size(); ++i) {
+    if (p->op_pass[i] != (int)pass) continue;
+    const OpClass c = classify(p->ops[i]);
+    f += c == CLS_PERM ? 0.0 : c == CLS_DIAG ? 6.0 : 8.0 * (double)(1 << p->ops[i].nq);
+  }
+  *flops_per_amp = f;
+  return SV_OK;
+}
+
 sv_status sv_plan_destroy(sv_plan* p) {
   clear_error();
   delete p;

@@ -227,73 +227,101 @@ constexpr int mfma_cols() {
 
 template <typename R, int K>
 constexpr size_t mfma_lds() {
-  return ((size_t)(1 << K) * ((1 << K) + 1) + (size_t)(1 << K) * mfma_cols<R, K>()) * 2 * sizeof(R);
+  return (size_t)(1 << K) * mfma_cols<R, K>() * 2 * sizeof(R);
 }
+
+// Waves own row blocks: wave w computes the output tiles w, w + 4, ... of the
+// (row block, column block) grid, tile = rb + RBLK * cb, so it only ever
+// needs the row blocks (w + 4 i) mod RBLK.  Their A fragments (the embedded
+// U) are loop-invariant over column tiles and stay in registers.
+template <typename R, int K>
+struct mfma_plan {
+  typedef mfma_shape<R> MS;
+  static constexpr int D = 1 << K;
+  static constexpr int NC = mfma_cols<R, K>();
+  static constexpr int RBLK = 2 * D / MS::BM, CBLK = NC / MS::BN, TILES = RBLK * CBLK;
+  static constexpr int TPW = (TILES + 3) / 4;                 // output tiles per wave
+  static constexpr int NRB = RBLK >= 4 ? RBLK / 4 : 1;         // distinct row blocks per wave
+  static constexpr int KSTEPS = 2 * D / MS::BK;
+};
 
 template <typename R, int K>
 __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E* __restrict__ psi, uint64_t nwork,
                                                        DenseGeo g, const R* __restrict__ um) {
   typedef mfma_shape<R> MS;
+  typedef mfma_plan<R, K> MP;
   typedef typename MS::E E;
-  constexpr int D = 1 << K, DP = D + 1;
-  constexpr int NC = mfma_cols<R, K>();
-  constexpr int RBLK = 2 * D / MS::BM, CBLK = NC / MS::BN, TILES = RBLK * CBLK;
-  constexpr int TPW = (TILES + 3) / 4;  // output tiles per wave
-  constexpr int KSTEPS = 2 * D / MS::BK;
+  constexpr int D = MP::D, NC = MP::NC, RBLK = MP::RBLK, TILES = MP::TILES, TPW = MP::TPW, NRB = MP::NRB;
+  constexpr int KSTEPS = MP::KSTEPS;
   constexpr int PER = D * NC / kBlock;  // tile elements per lane
   extern __shared__ __align__(16) unsigned char smem[];
-  cplx<R>* us = reinterpret_cast<cplx<R>*>(smem);  // D x DP
-  E* xs = reinterpret_cast<E*>(us + D * DP);       // [member][NC]
+  E* xs = reinterpret_cast<E*>(smem);  // [member][NC]
   const int t = threadIdx.x, w = t / 64, l = t % 64;
-  for (int e = t; e < D * D; e += kBlock) us[(e / D) * DP + (e % D)] = cplx<R>{um[2 * e], um[2 * e + 1]};
-  const LaneMap lm = lane_map((uint32_t)t, g);
-  for (uint64_t wb = xcd_block(); wb < nwork; wb += gridDim.x) {
-    const uint64_t base = deposit(wb, g.rest) | lm.addr;
-    // gather in address order, all loads of a lane in flight
-    E buf[PER];
-#define SV_LD(U)                                                  \
-    {                                                             \
-      uint64_t a;                                                 \
-      uint32_t li;                                                \
-      bool on;                                                    \
-      elem_map<U>(g, &a, &li, &on);                               \
-      if (on && lm.on) buf[U] = ld(psi + (base | a));             \
+  // A fragments of this wave's row blocks: lane l supplies A[l % BM][BK ks + l / BM]
+  R afrag[NRB][KSTEPS];
+#pragma unroll
+  for (int i = 0; i < NRB; ++i) {
+    const int rb = (w + 4 * i) % RBLK;
+    int ai, aa;  // output member and re/im of the A row this lane supplies
+    MS::row_of(l % MS::BM, &ai, &aa);
+    ai += MS::MPB * rb;
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+      const int ak = MS::BK * ks + l / MS::BM;  // real column of A (= real row of B)
+      const R ur = um[2 * (ai * D + (ak >> 1))], ui = um[2 * (ai * D + (ak >> 1)) + 1];
+      afrag[i][ks] = aa == 0 ? ((ak & 1) == 0 ? ur : -ui) : ((ak & 1) == 0 ? ui : ur);
     }
+  }
+  const LaneMap lm = lane_map((uint32_t)t, g);
+  // software-pipelined over column tiles: the next tile's loads are in flight
+  // while the current tile runs on the matrix cores and is stored
+  uint64_t wb = xcd_block();
+  if (wb >= nwork) return;
+  E buf[PER];
+#define SV_LD(U)                                                      \
+  {                                                                   \
+    uint64_t a;                                                       \
+    uint32_t li;                                                      \
+    bool on;                                                          \
+    elem_map<U>(g, &a, &li, &on);                                     \
+    buf[U] = ld(psi + ((on && lm.on) ? (ldbase | a) : ldbase));       \
+  }
+  {
+    const uint64_t ldbase = deposit(wb, g.rest) | lm.addr;
     SV_FOR_U(PER, SV_LD)
-#undef SV_LD
-    __syncthreads();  // U is staged and the previous tile's store phase is done
-#define SV_LDS(U)                                                 \
-    {                                                             \
-      uint64_t a;                                                 \
-      uint32_t li;                                                \
-      bool on;                                                    \
-      elem_map<U>(g, &a, &li, &on);                               \
-      if (on && lm.on) xs[lm.lds | li] = buf[U];                  \
+  }
+  while (true) {
+    const uint64_t nb = wb + gridDim.x;
+    const uint64_t base = deposit(wb, g.rest) | lm.addr;
+    __syncthreads();  // the previous tile's store phase is done with LDS
+#define SV_LDS(U)                                                     \
+    {                                                                 \
+      uint64_t a;                                                     \
+      uint32_t li;                                                    \
+      bool on;                                                        \
+      elem_map<U>(g, &a, &li, &on);                                   \
+      if (on && lm.on) xs[lm.lds | li] = buf[U];                      \
     }
     SV_FOR_U(PER, SV_LDS)
 #undef SV_LDS
     __syncthreads();
-    // each wave computes up to TPW (row block, column block) output tiles
+    if (nb < nwork) {
+      const uint64_t ldbase = deposit(nb, g.rest) | lm.addr;
+      SV_FOR_U(PER, SV_LD)
+    }
     typename MS::acc_t acc[TPW];
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int tile = w + 4 * i;
       acc[i] = typename MS::acc_t{};
       if (tile >= TILES) continue;
-      const int rb = tile % RBLK, cb = tile / RBLK;
-      int ai, aa;  // output member and re/im of the A row this lane supplies
-      MS::row_of(l % MS::BM, &ai, &aa);
-      ai += MS::MPB * rb;
-      const int bcol = MS::BN * cb + l % MS::BN;
-#pragma unroll 8
+      const int bcol = MS::BN * (tile / RBLK) + l % MS::BN;
+#pragma unroll
       for (int ks = 0; ks < KSTEPS; ++ks) {
-        const int ak = MS::BK * ks + l / MS::BM;  // real column of A (= real row of B)
-        const cplx<R> u = us[ai * DP + (ak >> 1)];
-        const R a = aa == 0 ? ((ak & 1) == 0 ? u.re : -u.im) : ((ak & 1) == 0 ? u.im : u.re);
         const int bk = MS::BK * ks + l / MS::BN;
         const E xv = xs[(bk >> 1) * NC + bcol];
         const R b = (bk & 1) ? xv.y : xv.x;
-        acc[i] = MS::mma(a, b, acc[i]);
+        acc[i] = MS::mma(afrag[i % NRB][ks], b, acc[i]);  // row block (w + 4 i) % RBLK
       }
     }
     __syncthreads();  // every wave has read X: the outputs replace it in LDS
@@ -314,17 +342,20 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
     }
     __syncthreads();
     // store in address order
-#define SV_ST(U)                                                  \
-    {                                                             \
-      uint64_t a;                                                 \
-      uint32_t li;                                                \
-      bool on;                                                    \
-      elem_map<U>(g, &a, &li, &on);                               \
-      if (on && lm.on) st(psi + (base | a), xs[lm.lds | li]);     \
+#define SV_ST(U)                                                      \
+    {                                                                 \
+      uint64_t a;                                                     \
+      uint32_t li;                                                    \
+      bool on;                                                        \
+      elem_map<U>(g, &a, &li, &on);                                   \
+      if (on && lm.on) st(psi + (base | a), xs[lm.lds | li]);         \
     }
     SV_FOR_U(PER, SV_ST)
 #undef SV_ST
+    if (nb >= nwork) break;
+    wb = nb;
   }
+#undef SV_LD
 }
 
 template <typename R, int K>
@@ -341,7 +372,7 @@ hipError_t run_mfma(void* psi, int n, const DenseGeo& g, const void* m, hipStrea
   const uint64_t ngroups = 1ull << (n - K);
   const uint64_t nwork = (ngroups + NC - 1) / NC;
   // persistent blocks: enough to fill the chip several times over, each
-  // amortising its staged U over many column tiles
+  // amortising its A fragments (loaded once) over many column tiles
   const uint64_t blocks = nwork < 4096 ? nwork : 4096;
   hipLaunchKernelGGL((k_dense_mfma<R, K>), dim3((unsigned)blocks), dim3(kBlock), lds, s,
                      (typename mfma_shape<R>::E*)psi, nwork, g, (const R*)m);

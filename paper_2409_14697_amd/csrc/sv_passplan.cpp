@@ -46,8 +46,9 @@ double op_flops(const PassOpDev& od) {
     case POP_U2: return 32.0;
     case POP_UR: case POP_UI: return 8.0;
     case POP_D1: case POP_D2: case POP_DG: return 6.0;
-    case POP_P1: return 3.0;
+    case POP_P1: return od.lmask ? 8.0 : 3.0;  // a per-lane predicate costs register copies
     case POP_P2: return 1.5;
+    case POP_X: return od.lmask ? 6.0 : 1.0;
     default: return 1.0;
   }
 }
@@ -296,8 +297,13 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
   int pin = o.pinned_low_bits ? o.pinned_low_bits : default_pinned_bits(dt);
   pin = std::min(pin, m - 2);
   const bool reorder = o.reorder != 0;
-  const double flop_scale = dt == SV_C128 ? 314.0 : 157.0;  // flops/amp that take one sweep's time
-  const double stage_cost = 0.1;                              // LDS round trip of a tile, in sweeps
+  // Cost of a tile pass in full-state sweeps (measured on MI355X at N=30):
+  // the data movement alone takes ~1.2 sweeps and hides ~0.3 sweeps of
+  // arithmetic; beyond that the stages and ops add up.  flop_scale: op flops
+  // per amplitude that take one sweep's time; stage_cost: one LDS round trip.
+  const double flop_scale = dt == SV_C128 ? 180.0 : 100.0;
+  const double stage_cost = 0.08;
+  const double pass_base = 1.2, hidden = 0.3;
 
   p->ops.clear();
   p->op_pass.clear();
@@ -428,7 +434,7 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
     double alu = stage_cost * (double)ps.stages.size();
     for (const StageHost& sh : ps.stages)
       for (const PassOpDev& od : sh.ops) alu += op_flops(od) / flop_scale;
-    p->est_cost += std::max(1.0, alu);
+    p->est_cost += pass_base + std::max(0.0, alu - hidden);
     p->passes.push_back(std::move(ps));
   }
 
@@ -493,7 +499,7 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
       nm.logi[ps.wpos[jj]] = l;
     }
     mp = nm;
-    p->est_cost += 1.0;
+    p->est_cost += pass_base;
     p->passes.push_back(std::move(ps));
   }
   // the pass kernels move complex64 amplitudes in pairs on physical bit 0,

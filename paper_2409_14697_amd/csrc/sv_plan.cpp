@@ -14,6 +14,15 @@ namespace {
 // fraction; arithmetic time with the dense flops per amplitude (8 * 2^k for a
 // complex 2^k x 2^k product) over the flop/byte ridge of the precision.
 double sweep_cost(const Op& op, sv_dtype dt, bool mfma) {
+  if (op.nq >= 3) {
+    // dense k-qubit kernels, in sweeps of the state (measured on MI355X at
+    // N=30): HBM-bound up to k = 5, matrix-core bound at k = 6
+    static const double c64_mfma[7] = {0, 0, 0, 1.15, 1.26, 1.26, 1.87};
+    static const double c64_valu[7] = {0, 0, 0, 1.15, 1.4, 2.1, 4.2};
+    static const double c128[7] = {0, 0, 0, 1.27, 1.27, 1.3, 3.2};
+    const int k = op.nq > 6 ? 6 : op.nq;
+    return dt == SV_C128 ? c128[k] : (mfma ? c64_mfma[k] : c64_valu[k]);
+  }
   const double bytes_per_amp = 2.0 * (double)elem_bytes(dt);
   double ridge;  // flops per byte at which compute time equals memory time
   if (dt == SV_C128) ridge = 78.6 / 8.0;

@@ -299,7 +299,7 @@ class DeviceEngine:
     def prepare(self, job: Job) -> Job:
         B = self.B
         plan = B.Plan.from_array(job.n, self.dtype, job.gates, job.n_gates, self.opts)
-        job.handle = {"plan": plan}
+        job.handle = {"plan": plan, "flops": plan.pass_flops() if self.time_launches else None}
         job.n_passes = plan.info()[1]
         job.footprint = (1 << job.n) * self.elem_bytes + _round_up(plan.program_bytes(), 512) \
             + (8 << min(job.n, self.probs_qubits))
@@ -325,23 +325,28 @@ class DeviceEngine:
         ev = self.torch.cuda.Event(enable_timing=self.time_launches)
         ev.record(self.stream)
         if t0 is not None:
-            self.timed.append((t0, ev, sum(2 * (1 << j.n) * self.elem_bytes for j in active), len(active)))
+            nbytes = sum(2 * (1 << j.n) * self.elem_bytes for j in active)
+            flops = sum(j.handle["flops"][j.next_pass] * (1 << j.n) for j in active)
+            self.timed.append((t0, ev, nbytes, len(active), flops))
         self.launch_events.append(ev)
         while len(self.launch_events) > self.inflight:
             self.launch_events.popleft().synchronize()
 
     def launch_stats(self) -> Dict:
         """Batched-pass launches timed with HIP events on the serving stream:
-        count, mean duration, and algorithmic bytes (read + write of every
-        state in the launch) per second of launch time."""
+        count, mean duration, algorithmic bytes (read + write of every state in
+        the launch) and algorithmic flops (sv_plan_pass_flops x amplitudes)
+        per second of launch time."""
         self.torch.cuda.synchronize()
         if not self.timed:
             return {"launches": 0}
-        secs = [a.elapsed_time(b) * 1e-3 for a, b, _, _ in self.timed]
-        nbytes = sum(x for _, _, x, _ in self.timed)
-        items = sum(k for _, _, _, k in self.timed)
+        secs = [rec[0].elapsed_time(rec[1]) * 1e-3 for rec in self.timed]
+        nbytes = sum(rec[2] for rec in self.timed)
+        items = sum(rec[3] for rec in self.timed)
+        flops = sum(rec[4] for rec in self.timed)
         return {"launches": len(secs), "mean_launch_us": 1e6 * sum(secs) / len(secs),
                 "busy_s": sum(secs), "bytes": nbytes, "GBs": nbytes / sum(secs) / 1e9,
+                "flops": flops, "TFLOPs": flops / sum(secs) / 1e12,
                 "mean_states_per_launch": items / len(secs)}
 
     def finish(self, job: Job) -> None:

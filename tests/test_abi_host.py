@@ -184,3 +184,16 @@ def test_pass_op_cap_splits_passes_and_replays(cap):
     assert plan.info()[1] >= max(uncapped, len(gates) // cap)
     with pytest.raises(B.SvError):
         B.Plan(n, "c128", gates, {"mode": "pass", "max_pass_ops": -1})
+
+
+def test_planning_time_is_bounded():
+    # host planning must stay far below device time: ~8k gates at N=26 in well under a second
+    import time
+    from svgen import Request
+    gates = Request(0, 26, 200, 7, 0.0).circuit()
+    for mode in ("pass", "auto", "sweep"):
+        t0 = time.perf_counter()
+        plan = B.Plan(26, "c64", gates, {"mode": mode})
+        dt = time.perf_counter() - t0
+        assert plan.info()[0] > 0
+        assert dt < 2.0, (mode, dt)
