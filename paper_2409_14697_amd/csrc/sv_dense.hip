@@ -34,38 +34,42 @@ struct DenseGeo {
   uint32_t lds[16];
 };
 
-// Per-lane part of the map: tile-local bits 0..7 come from the lane.
+// Per-lane part of the map: tile-local bits LB .. LB+7 come from the lane.
+// LB = 1 moves complex64 amplitudes in 16-byte pairs: tile-local bit 0 is
+// always physical bit 0 (the lowest bit is a gate bit or a column bit), so
+// an element and its bit-0 partner are adjacent in memory.
 struct LaneMap {
   uint64_t addr;
   uint32_t lds;
   bool on;
 };
 
+template <int LB>
 __device__ __forceinline__ LaneMap lane_map(uint32_t t, const DenseGeo& g) {
-  LaneMap m{0, 0, (t & g.inv) == 0};
+  LaneMap m{0, 0, ((t << LB) & g.inv) == 0};
 #pragma unroll
   for (int j = 0; j < 8; ++j)
     if ((t >> j) & 1u) {
-      if (g.pos[j] < 64) m.addr |= 1ull << g.pos[j];
-      m.lds |= g.lds[j];
+      if (g.pos[LB + j] < 64) m.addr |= 1ull << g.pos[LB + j];
+      m.lds |= g.lds[LB + j];
     }
   return m;
 }
 
-// Uniform part for element u of a lane (tile-local bits 8 ..).
-template <int U>
+// Uniform part for element u of a lane (tile-local bits LB+8 ..).
+template <int LB, int U>
 __device__ __forceinline__ void elem_map(const DenseGeo& g, uint64_t* addr, uint32_t* lds, bool* on) {
   uint64_t a = 0;
   uint32_t l = 0;
 #pragma unroll
   for (int b = 0; b < 8; ++b)
     if ((U >> b) & 1) {
-      if (g.pos[8 + b] < 64) a |= 1ull << g.pos[8 + b];
-      l |= g.lds[8 + b];
+      if (g.pos[LB + 8 + b] < 64) a |= 1ull << g.pos[LB + 8 + b];
+      l |= g.lds[LB + 8 + b];
     }
   *addr = a;
   *lds = l;
-  *on = (((uint32_t)U << 8) & g.inv) == 0;
+  *on = (((uint32_t)U << (8 + LB)) & g.inv) == 0;
 }
 
 #define SV_FOR_U(PER, F)                                                  \
@@ -85,23 +89,25 @@ __global__ __launch_bounds__(kBlock) void k_dense(E* __restrict__ psi, uint64_t 
   typedef typename elem_traits<E>::R R;
   constexpr int D = 1 << K;
   constexpr int C = tile_cols<K>();
-  constexpr int PER = D * C / kBlock;
+  constexpr int PER = D * C / kBlock / 2;  // 16-byte pairs per lane
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* us = reinterpret_cast<cplx<R>*>(smem);  // D x D
   cplx<R>* xs = us + D * D;                          // D x C, row r = member r
+  flt4* pairs = reinterpret_cast<flt4*>(psi);
   const int t = threadIdx.x;
   for (int e = t; e < D * D; e += kBlock) us[e] = cplx<R>{um[2 * e], um[2 * e + 1]};
-  const LaneMap lm = lane_map((uint32_t)t, g);
+  const LaneMap lm = lane_map<1>((uint32_t)t, g);
+  const uint32_t l0 = g.lds[0];  // LDS offset of the bit-0 partner
   for (uint64_t wb = xcd_block(); wb < nwork; wb += gridDim.x) {
     const uint64_t base = deposit(wb, g.rest) | lm.addr;
-    E buf[PER];
+    flt4 buf[PER];
 #define SV_LD(U)                                                  \
     {                                                             \
       uint64_t a;                                                 \
       uint32_t l;                                                 \
       bool on;                                                    \
-      elem_map<U>(g, &a, &l, &on);                                \
-      if (on && lm.on) buf[U] = ld(psi + (base | a));             \
+      elem_map<1, U>(g, &a, &l, &on);                             \
+      if (on && lm.on) buf[U] = ld(pairs + ((base | a) >> 1));    \
     }
     SV_FOR_U(PER, SV_LD)
 #undef SV_LD
@@ -111,8 +117,11 @@ __global__ __launch_bounds__(kBlock) void k_dense(E* __restrict__ psi, uint64_t 
       uint64_t a;                                                 \
       uint32_t l;                                                 \
       bool on;                                                    \
-      elem_map<U>(g, &a, &l, &on);                                \
-      if (on && lm.on) xs[lm.lds | l] = cplx<R>{buf[U].x, buf[U].y}; \
+      elem_map<1, U>(g, &a, &l, &on);                             \
+      if (on && lm.on) {                                          \
+        xs[lm.lds | l] = cplx<R>{buf[U].x, buf[U].y};             \
+        xs[lm.lds | l | l0] = cplx<R>{buf[U].z, buf[U].w};        \
+      }                                                           \
     }
     SV_FOR_U(PER, SV_LDS)
 #undef SV_LDS
@@ -122,17 +131,19 @@ __global__ __launch_bounds__(kBlock) void k_dense(E* __restrict__ psi, uint64_t 
       uint64_t a;                                                 \
       uint32_t l;                                                 \
       bool on;                                                    \
-      elem_map<U>(g, &a, &l, &on);                                \
+      elem_map<1, U>(g, &a, &l, &on);                             \
       if (on && lm.on) {                                          \
-        const uint32_t li = lm.lds | l, r = li / C, c = li % C;   \
-        cplx<R> y = {0, 0};                                       \
-        const cplx<R>* urow = us + r * D;                         \
-        _Pragma("unroll 8")                                       \
-        for (int s = 0; s < D; ++s) y = cfma(y, urow[s], xs[s * C + c]); \
-        E o;                                                      \
-        o.x = y.re;                                               \
-        o.y = y.im;                                               \
-        st(psi + (base | a), o);                                  \
+        flt4 o;                                                   \
+        _Pragma("unroll")                                         \
+        for (int h = 0; h < 2; ++h) {                             \
+          const uint32_t li = lm.lds | l | (h ? l0 : 0u), r = li / C, c = li % C; \
+          cplx<R> y = {0, 0};                                     \
+          const cplx<R>* urow = us + r * D;                       \
+          _Pragma("unroll 8")                                     \
+          for (int s = 0; s < D; ++s) y = cfma(y, urow[s], xs[s * C + c]); \
+          if (h) { o.z = y.re; o.w = y.im; } else { o.x = y.re; o.y = y.im; } \
+        }                                                         \
+        st(pairs + ((base | a) >> 1), o);                         \
       }                                                           \
     }
     SV_FOR_U(PER, SV_OUT)
@@ -200,6 +211,16 @@ struct mfma_shape<float> {
   // member (within the block) written by registers r, r + 1 of lane l (r even)
   static __device__ __forceinline__ int out_member(int l, int r) { return (8 * (r / 4) + 4 * (l / 32) + (r % 4)) >> 1; }
   static constexpr int MPB = 16;  // members per row block
+  // global 16-byte element: a complex64 pair (LDS entries li and li | l0)
+  typedef flt4 G;
+  static __device__ __forceinline__ void to_lds(E* xs, uint32_t li, uint32_t l0, G v) {
+    xs[li] = E{v.x, v.y};
+    xs[li | l0] = E{v.z, v.w};
+  }
+  static __device__ __forceinline__ G from_lds(const E* xs, uint32_t li, uint32_t l0) {
+    const E a = xs[li], b = xs[li | l0];
+    return G{a.x, a.y, b.x, b.y};
+  }
 };
 template <>
 struct mfma_shape<double> {
@@ -215,13 +236,16 @@ struct mfma_shape<double> {
   }
   static __device__ __forceinline__ int out_member(int l, int r) { return 2 * (l / 16) + r / 2; }
   static constexpr int MPB = 8;
+  typedef dbl2 G;  // one complex128 amplitude
+  static __device__ __forceinline__ void to_lds(E* xs, uint32_t li, uint32_t, G v) { xs[li] = v; }
+  static __device__ __forceinline__ G from_lds(const E* xs, uint32_t li, uint32_t) { return xs[li]; }
 };
 
-// groups per column tile: the X tile holds 2048 complex64 / 1024 complex128
-// amplitudes, and at least one column block
+// groups per column tile: the X tile holds 4096 complex64 / 1024 complex128
+// amplitudes (32 / 16 KiB), and at least one column block
 template <typename R, int K>
 constexpr int mfma_cols() {
-  constexpr int target = (sizeof(R) == 4 ? 2048 : 1024) >> K;
+  constexpr int target = (sizeof(R) == 4 ? 4096 : 1024) >> K;
   return target < mfma_shape<R>::BN ? mfma_shape<R>::BN : target;
 }
 
@@ -253,7 +277,11 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
   typedef typename MS::E E;
   constexpr int D = MP::D, NC = MP::NC, RBLK = MP::RBLK, TILES = MP::TILES, TPW = MP::TPW, NRB = MP::NRB;
   constexpr int KSTEPS = MP::KSTEPS;
-  constexpr int PER = D * NC / kBlock;  // tile elements per lane
+  // global memory moves in 16-byte elements: complex128 amplitudes, or
+  // complex64 pairs on tile-local bit 0 (LB = 1)
+  constexpr int LB = sizeof(R) == 4 ? 1 : 0;
+  typedef typename mfma_shape<R>::G G;
+  constexpr int PER = (D * NC / kBlock) >> LB;  // 16-byte elements per lane
   extern __shared__ __align__(16) unsigned char smem[];
   E* xs = reinterpret_cast<E*>(smem);  // [member][NC]
   const int t = threadIdx.x, w = t / 64, l = t % 64;
@@ -272,19 +300,21 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
       afrag[i][ks] = aa == 0 ? ((ak & 1) == 0 ? ur : -ui) : ((ak & 1) == 0 ? ui : ur);
     }
   }
-  const LaneMap lm = lane_map((uint32_t)t, g);
+  const LaneMap lm = lane_map<LB>((uint32_t)t, g);
+  const uint32_t l0 = g.lds[0];  // LDS offset of the bit-0 partner (LB = 1)
+  G* gp = reinterpret_cast<G*>(psi);
   // software-pipelined over column tiles: the next tile's loads are in flight
   // while the current tile runs on the matrix cores and is stored
   uint64_t wb = xcd_block();
   if (wb >= nwork) return;
-  E buf[PER];
+  G buf[PER];
 #define SV_LD(U)                                                      \
   {                                                                   \
     uint64_t a;                                                       \
     uint32_t li;                                                      \
     bool on;                                                          \
-    elem_map<U>(g, &a, &li, &on);                                     \
-    buf[U] = ld(psi + ((on && lm.on) ? (ldbase | a) : ldbase));       \
+    elem_map<LB, U>(g, &a, &li, &on);                                 \
+    buf[U] = ld(gp + (((on && lm.on) ? (ldbase | a) : ldbase) >> LB)); \
   }
   {
     const uint64_t ldbase = deposit(wb, g.rest) | lm.addr;
@@ -299,8 +329,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
       uint64_t a;                                                     \
       uint32_t li;                                                    \
       bool on;                                                        \
-      elem_map<U>(g, &a, &li, &on);                                   \
-      if (on && lm.on) xs[lm.lds | li] = buf[U];                      \
+      elem_map<LB, U>(g, &a, &li, &on);                               \
+      if (on && lm.on) mfma_shape<R>::to_lds(xs, lm.lds | li, l0, buf[U]); \
     }
     SV_FOR_U(PER, SV_LDS)
 #undef SV_LDS
@@ -347,8 +377,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
       uint64_t a;                                                     \
       uint32_t li;                                                    \
       bool on;                                                        \
-      elem_map<U>(g, &a, &li, &on);                                   \
-      if (on && lm.on) st(psi + (base | a), xs[lm.lds | li]);         \
+      elem_map<LB, U>(g, &a, &li, &on);                               \
+      if (on && lm.on) st(gp + ((base | a) >> LB), mfma_shape<R>::from_lds(xs, lm.lds | li, l0)); \
     }
     SV_FOR_U(PER, SV_ST)
 #undef SV_ST
