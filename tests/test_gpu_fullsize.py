@@ -1,0 +1,170 @@
+"""Parity at the benchmark sizes, in the launch configurations bench.py times.
+
+The oracle cannot hold a 2^30 or 2^32 state, so these tests compare sampled
+outputs it computes one group at a time (Eq. 2/3 on the sampled group's
+amplitudes, read from the device right before the gate), or properties that
+hold at any size: the QFT's closed form on a basis state, a circuit followed
+by its inverse returning the start state, and the norm."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sv_oracle as so
+from svgen import Gate, brickwork_circuit, gate_bench_set, haar_unitary, qft_circuit, serving_requests
+from svgen.states import gaussian_state_torch
+from tests.gpu_util import TOL, max_err, torch_dtype
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+SAMPLES = 512
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import paper_2409_14697_amd as sv
+    return sv
+
+
+def sampled_groups(n, qubits, count, rng):
+    """Indices (count x 2^k) of random groups of the gate's qubits (oracle order)."""
+    mask = 0
+    for q in qubits:
+        mask |= 1 << q
+    bases = rng.integers(0, 1 << n, size=count, dtype=np.int64) & ~np.int64(mask)
+    return np.stack([so.group_indices(int(b), qubits) for b in bases])
+
+
+def read(t, idx):
+    import torch
+    flat = torch.from_numpy(idx.reshape(-1)).to(t.device)
+    return t[flat].cpu().numpy().astype(np.complex128).reshape(idx.shape)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_gate_benchmark_n30_sampled(sv, dtype):
+    """Every gate of the N=30 gate benchmark, applied with sv_apply_gate to the
+    benchmark's Gaussian state; each gate checked on 512 sampled groups."""
+    import torch
+    n = 30
+    t = gaussian_state_torch(n, 2, torch_dtype(dtype))
+    st = sv.StateVector(n, dtype, tensor=t, init=False)
+    rng = np.random.default_rng(11)
+    for g in gate_bench_set(n, seed=2):
+        idx = sampled_groups(n, g.qubits, SAMPLES, rng)
+        before = read(t, idx)
+        st.apply_gate(g)
+        st.sync()
+        after = read(t, idx)
+        expected = oracle.apply_to_group(so.gate_matrix(g), before.T).T
+        assert max_err(after, expected) <= TOL[dtype], (g.kind, g.qubits)
+    st.close()
+    del t
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_dense_k5_k6_n30_sampled(sv, dtype):
+    """The precision form's fused gates (k = 5, 6; FP64 MFMA for complex128,
+    FP32 MFMA for complex64) at N=30, on sampled groups, with low, high and
+    random qubit placements."""
+    import torch
+    n = 30
+    t = gaussian_state_torch(n, 4, torch_dtype(dtype))
+    st = sv.StateVector(n, dtype, tensor=t, init=False)
+    rng = np.random.default_rng(12)
+    opts = {"mode": "sweep", "max_fuse_qubits": 0, "fp32_mfma": 1}
+    for k in (5, 6):
+        for qs in (tuple(range(k - 1, -1, -1)), tuple(range(n - k, n)),
+                   tuple(int(x) for x in rng.choice(n, k, replace=False))):
+            g = Gate("MATRIX", qs, matrix=haar_unitary(1 << k, rng))
+            idx = sampled_groups(n, qs, SAMPLES, rng)
+            before = read(t, idx)
+            st.apply_circuit([g], opts)
+            st.sync()
+            after = read(t, idx)
+            expected = oracle.apply_to_group(g.matrix, before.T).T
+            assert max_err(after, expected) <= TOL[dtype], (k, qs)
+    st.close()
+    del t
+    torch.cuda.empty_cache()
+
+
+def inverse(gates):
+    out = []
+    for g in reversed(gates):
+        if g.kind in ("RX", "RY", "RZ", "P", "CPHASE", "RZZ"):
+            out.append(Gate(g.kind, g.qubits, -g.theta))
+        elif g.kind in ("H", "X", "Y", "Z", "CNOT", "CZ", "SWAP"):
+            out.append(Gate(g.kind, g.qubits, g.theta))
+        else:
+            raise ValueError(g.kind)
+    return out
+
+
+def test_circuit_benchmark_n32_properties(sv):
+    """N=32 complex64 with the circuit benchmark's plans (mode auto): the QFT
+    matches its closed form on sampled amplitudes; brickwork followed by its
+    inverse returns |0..0>; the FP64 norm stays 1."""
+    import torch
+    n, dtype = 32, "c64"
+    st = sv.StateVector(n, dtype)
+    rng = np.random.default_rng(7)
+    x0 = int(rng.integers(0, 1 << n))
+    st.init_basis(x0)
+    st.apply_circuit(qft_circuit(n), {"mode": "auto"})
+    st.sync()
+    ys = rng.integers(0, 1 << n, size=4096, dtype=np.int64)
+    got = read(st.tensor, ys)
+    ref = np.exp(2j * np.pi * ((x0 * ys.astype(np.float64)) % (1 << n)) / (1 << n)) / math.sqrt(1 << n)
+    # complex64 amplitudes of size 2^-16 accumulate ~1e-7 relative rounding per pass
+    assert max_err(got, ref) <= 1e-9
+    assert abs(st.norm2() - 1.0) < 1e-5
+    brick = brickwork_circuit(n, 40, seed=3)
+    st.init_basis(0)
+    st.apply_circuit(brick, {"mode": "auto"})
+    assert abs(st.norm2() - 1.0) < 1e-4
+    st.apply_circuit(inverse(brick), {"mode": "auto"})
+    st.sync()
+    idx = np.concatenate([[0], rng.integers(1, 1 << n, size=4095, dtype=np.int64)])
+    got = read(st.tensor, idx)
+    ref = np.zeros(idx.shape, dtype=np.complex128)
+    ref[0] = 1.0
+    assert max_err(got, ref) <= 1e-4
+    st.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_serving_large_requests(sv, dtype):
+    """Requests of N = 22..26 served in a mix with small ones: unit FP64 norm
+    and marginals, and each large result bitwise equal to the same request
+    served alone."""
+    from paper_2409_14697_amd import binding as B
+    from paper_2409_14697_amd.serve import DeviceEngine, Server, free_budget, make_jobs
+    big = serving_requests(4, seed=21, n_range=(22, 26), depth_range=(20, 30))
+    small = serving_requests(8, seed=22, n_range=(12, 16), depth_range=(20, 30))
+    for i, r in enumerate(small):
+        r.rid = 100 + i
+    reqs = big + small
+
+    def serve(rs):
+        jobs = make_jobs(rs, None, B.make_gates)
+        eng = DeviceEngine(dtype, keep_states=True)
+        Server(eng, free_budget(0.5), plan_workers=4).run(jobs)
+        eng.close()
+        return {j.rid: j for j in jobs}
+
+    mixed = serve(reqs)
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    for r in reqs:
+        j = mixed[r.rid]
+        assert j.status == "done"
+        assert abs(float(j.probs.sum()) - 1.0) < tol * 10, r.rid
+    for r in big[:2]:
+        alone = serve([r])[r.rid]
+        a = alone.handle["tensor"].cpu().numpy()
+        b = mixed[r.rid].handle["tensor"].cpu().numpy()
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), r.rid
+        assert np.array_equal(alone.probs, mixed[r.rid].probs)
