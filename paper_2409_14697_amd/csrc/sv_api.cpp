@@ -396,7 +396,7 @@ sv_status sv_permute_qubits(sv_state* s, const int32_t* dest) {
   o.max_fuse_qubits = 0;
   o.reorder = 1;
   // tiles need more local bits than one stage's registers; tiny states use SWAP sweeps
-  o.mode = n > kPassRegBits + 1 ? SV_MODE_PASS : SV_MODE_SWEEP;
+  o.mode = n > pass_reg_bits(s->dt) ? SV_MODE_PASS : SV_MODE_SWEEP;
   return sv_apply_circuit(s, swaps.data(), swaps.size(), &o);
 }
 

@@ -59,10 +59,11 @@ sv_status pack_program(const sv_plan* p, sv_program* prog) {
     }
     for (const StageHost& sh : ps.stages) {
       PassStageDev sd{};
-      uint32_t srt[kPassRegBits];
-      for (int r = 0; r < kPassRegBits; ++r) sd.q[r] = srt[r] = sh.q[r];
-      std::sort(srt, srt + kPassRegBits);
-      for (int r = 0; r < kPassRegBits; ++r) sd.qsort[r] = srt[r];
+      const int rb = pass_reg_bits(p->dt);
+      uint32_t srt[kPassRegBitsMax];
+      for (int r = 0; r < rb; ++r) sd.q[r] = srt[r] = sh.q[r];
+      std::sort(srt, srt + rb);
+      for (int r = 0; r < rb; ++r) sd.qsort[r] = srt[r];
       sd.op_first = (uint32_t)pops.size();
       sd.op_count = (uint32_t)sh.ops.size();
       const uint32_t mbase = (uint32_t)pool.size();

@@ -64,7 +64,7 @@ double touched_fraction(const Op& op);
 enum PassKind { PASS_SWEEP = 0, PASS_TILE = 1, PASS_DENSE = 2, PASS_PERMUTE = 3 };
 
 struct StageHost {
-  uint32_t q[kPassRegBits] = {0, 0, 0, 0};  // local bit of each register bit
+  uint32_t q[kPassRegBitsMax] = {0, 0, 0, 0, 0};  // local bit of each register bit
   std::vector<PassOpDev> ops;               // .mat indexes this stage's `mats`
   std::vector<cd> mats;
 };

@@ -23,8 +23,13 @@ namespace sv {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int RB = kPassRegBits;
-constexpr int NR = 1 << RB;
+
+// Register bits of a stage: 32 complex64 or 16 complex128 amplitudes per lane.
+template <typename R>
+struct Regs {
+  static constexpr int RB = sizeof(R) == 4 ? 5 : 4;
+  static constexpr int NR = 1 << RB;
+};
 
 template <int WB>
 __device__ __forceinline__ uint32_t swz(uint32_t x) {
@@ -103,6 +108,7 @@ __device__ __forceinline__ T cload(cptr<T> p) {
 
 template <int B, typename R>
 __device__ __forceinline__ void op_u1(cplx<R>* v, cptr<cplx<R>> M) {
+  constexpr int NR = Regs<R>::NR;
   const cplx<R> m0 = cget(M, 0), m1 = cget(M, 1), m2 = cget(M, 2), m3 = cget(M, 3);
 #pragma unroll
   for (int r = 0; r < NR; ++r)
@@ -115,6 +121,7 @@ __device__ __forceinline__ void op_u1(cplx<R>* v, cptr<cplx<R>> M) {
 
 template <int B0, int B1, typename R>
 __device__ __forceinline__ void op_u2(cplx<R>* v, cptr<cplx<R>> M) {
+  constexpr int NR = Regs<R>::NR;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (!((r >> B0) & 1) && !((r >> B1) & 1)) {
@@ -134,6 +141,7 @@ __device__ __forceinline__ void op_u2(cplx<R>* v, cptr<cplx<R>> M) {
 // Real 2x2 (H, RY): two real scalars per output, 4 multiply-adds per amplitude.
 template <int B, typename R>
 __device__ __forceinline__ void op_ur(cplx<R>* v, cptr<cplx<R>> M) {
+  constexpr int NR = Regs<R>::NR;
   const R m0 = cget(M, 0).re, m1 = cget(M, 1).re, m2 = cget(M, 2).re, m3 = cget(M, 3).re;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
@@ -147,6 +155,7 @@ __device__ __forceinline__ void op_ur(cplx<R>* v, cptr<cplx<R>> M) {
 // Real diagonal, imaginary off-diagonal (RX): (x + i y) * (i s) = -s y + i s x.
 template <int B, typename R>
 __device__ __forceinline__ void op_ui(cplx<R>* v, cptr<cplx<R>> M) {
+  constexpr int NR = Regs<R>::NR;
   const R m0 = cget(M, 0).re, s1 = cget(M, 1).im, s2 = cget(M, 2).im, m3 = cget(M, 3).re;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
@@ -160,6 +169,7 @@ __device__ __forceinline__ void op_ui(cplx<R>* v, cptr<cplx<R>> M) {
 // Phase on the amplitudes whose register bit B is 1 (controlled phases).
 template <int B, typename R>
 __device__ __forceinline__ void op_p1(cplx<R>* v, cplx<R> p) {
+  constexpr int NR = Regs<R>::NR;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if ((r >> B) & 1) v[r] = cmul(p, v[r]);
@@ -167,6 +177,7 @@ __device__ __forceinline__ void op_p1(cplx<R>* v, cplx<R> p) {
 
 template <int B0, int B1, typename R>
 __device__ __forceinline__ void op_p2(cplx<R>* v, cplx<R> p) {
+  constexpr int NR = Regs<R>::NR;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (((r >> B0) & 1) && ((r >> B1) & 1)) v[r] = cmul(p, v[r]);
@@ -174,6 +185,7 @@ __device__ __forceinline__ void op_p2(cplx<R>* v, cplx<R> p) {
 
 template <int B, typename R>
 __device__ __forceinline__ void op_x(cplx<R>* v) {
+  constexpr int NR = Regs<R>::NR;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (!((r >> B) & 1)) {
@@ -185,6 +197,7 @@ __device__ __forceinline__ void op_x(cplx<R>* v) {
 
 template <int BC, int BT, typename R>
 __device__ __forceinline__ void op_cx(cplx<R>* v) {
+  constexpr int NR = Regs<R>::NR;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (((r >> BC) & 1) && !((r >> BT) & 1)) {
@@ -196,6 +209,7 @@ __device__ __forceinline__ void op_cx(cplx<R>* v) {
 
 template <int B, typename R>
 __device__ __forceinline__ void op_d1(cplx<R>* v, const cplx<R>* M) {
+  constexpr int NR = Regs<R>::NR;
   const cplx<R> d0 = M[0], d1 = M[1];
 #pragma unroll
   for (int r = 0; r < NR; ++r) v[r] = cmul(((r >> B) & 1) ? d1 : d0, v[r]);
@@ -203,23 +217,30 @@ __device__ __forceinline__ void op_d1(cplx<R>* v, const cplx<R>* M) {
 
 template <int B0, int B1, typename R>
 __device__ __forceinline__ void op_d2(cplx<R>* v, cptr<cplx<R>> M) {
+  constexpr int NR = Regs<R>::NR;
   const cplx<R> d[4] = {cget(M, 0), cget(M, 1), cget(M, 2), cget(M, 3)};
 #pragma unroll
   for (int r = 0; r < NR; ++r) v[r] = cmul(d[(((r >> B0) & 1) << 1) | ((r >> B1) & 1)], v[r]);
 }
 
-#define SV_PAIR_SWITCH(code, F)                                         \
-  switch (code) {                                                       \
-    case 1: F(0, 1); break;  case 2: F(0, 2); break;  case 3: F(0, 3); break; \
-    case 4: F(1, 0); break;  case 6: F(1, 2); break;  case 7: F(1, 3); break; \
-    case 8: F(2, 0); break;  case 9: F(2, 1); break;  case 11: F(2, 3); break; \
-    case 12: F(3, 0); break; case 13: F(3, 1); break; case 14: F(3, 2); break; \
-    default: break;                                                     \
+// Dispatch on register bits; bit 4 exists only with 5 register bits (H5).
+#define SV_PAIR_SWITCH(code, F, H5)                                                          \
+  switch (code) {                                                                            \
+    case 1: F(0, 1); break;   case 2: F(0, 2); break;   case 3: F(0, 3); break;             \
+    case 8: F(1, 0); break;   case 10: F(1, 2); break;  case 11: F(1, 3); break;            \
+    case 16: F(2, 0); break;  case 17: F(2, 1); break;  case 19: F(2, 3); break;            \
+    case 24: F(3, 0); break;  case 25: F(3, 1); break;  case 26: F(3, 2); break;            \
+    case 4: if constexpr (H5) F(0, 4); break;   case 12: if constexpr (H5) F(1, 4); break;  \
+    case 20: if constexpr (H5) F(2, 4); break;  case 28: if constexpr (H5) F(3, 4); break;  \
+    case 32: if constexpr (H5) F(4, 0); break;  case 33: if constexpr (H5) F(4, 1); break;  \
+    case 34: if constexpr (H5) F(4, 2); break;  case 35: if constexpr (H5) F(4, 3); break;  \
+    default: break;                                                                          \
   }
-#define SV_BIT_SWITCH(b, F)                                             \
-  switch (b) {                                                          \
-    case 0: F(0); break; case 1: F(1); break; case 2: F(2); break; case 3: F(3); break; \
-    default: break;                                                     \
+#define SV_BIT_SWITCH(b, F, H5)                                                              \
+  switch (b) {                                                                               \
+    case 0: F(0); break; case 1: F(1); break; case 2: F(2); break; case 3: F(3); break;     \
+    case 4: if constexpr (H5) F(4); break;                                                   \
+    default: break;                                                                          \
   }
 
 // M points at the op's first matrix entry (the same address in every lane, so
@@ -227,29 +248,30 @@ __device__ __forceinline__ void op_d2(cplx<R>* v, cptr<cplx<R>> M) {
 template <typename R>
 __device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, uint32_t var,
                                          cplx<R>* v) {
-  const uint32_t pair = op.b0 * 4 + op.b1;
+  const uint32_t pair = op.b0 * 8 + op.b1;
+  constexpr bool H5 = Regs<R>::RB > 4;
   switch (op.type) {
     case POP_U1: {
 #define F(B) op_u1<B>(v, M)
-      SV_BIT_SWITCH(op.b0, F)
+      SV_BIT_SWITCH(op.b0, F, H5)
 #undef F
       break;
     }
     case POP_U2: {
 #define F(A, B) op_u2<A, B>(v, M)
-      SV_PAIR_SWITCH(pair, F)
+      SV_PAIR_SWITCH(pair, F, H5)
 #undef F
       break;
     }
     case POP_X: {
 #define F(B) op_x<B>(v)
-      SV_BIT_SWITCH(op.b0, F)
+      SV_BIT_SWITCH(op.b0, F, H5)
 #undef F
       break;
     }
     case POP_CX: {
 #define F(A, B) op_cx<A, B>(v)
-      SV_PAIR_SWITCH(pair, F)
+      SV_PAIR_SWITCH(pair, F, H5)
 #undef F
       break;
     }
@@ -263,25 +285,25 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, u
         d[1].im = var ? e1.im : d[1].im;
       }
 #define F(B) op_d1<B>(v, d)
-      SV_BIT_SWITCH(op.b0, F)
+      SV_BIT_SWITCH(op.b0, F, H5)
 #undef F
       break;
     }
     case POP_D2: {
 #define F(A, B) op_d2<A, B>(v, M)
-      SV_PAIR_SWITCH(pair, F)
+      SV_PAIR_SWITCH(pair, F, H5)
 #undef F
       break;
     }
     case POP_UR: {
 #define F(B) op_ur<B>(v, M)
-      SV_BIT_SWITCH(op.b0, F)
+      SV_BIT_SWITCH(op.b0, F, H5)
 #undef F
       break;
     }
     case POP_UI: {
 #define F(B) op_ui<B>(v, M)
-      SV_BIT_SWITCH(op.b0, F)
+      SV_BIT_SWITCH(op.b0, F, H5)
 #undef F
       break;
     }
@@ -293,14 +315,14 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, u
         p.im = var ? p1.im : p.im;
       }
 #define F(B) op_p1<B>(v, p)
-      SV_BIT_SWITCH(op.b0, F)
+      SV_BIT_SWITCH(op.b0, F, H5)
 #undef F
       break;
     }
     case POP_P2: {
       const cplx<R> p = cget(M, 0);
 #define F(A, B) op_p2<A, B>(v, p)
-      SV_PAIR_SWITCH(pair, F)
+      SV_PAIR_SWITCH(pair, F, H5)
 #undef F
       break;
     }
@@ -321,7 +343,7 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, u
         }
       }
 #pragma unroll
-      for (int r = 0; r < NR; ++r) v[r] = cmul(p, v[r]);
+      for (int r = 0; r < Regs<R>::NR; ++r) v[r] = cmul(p, v[r]);
       break;
     }
     default:
@@ -476,6 +498,7 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
   const uint64_t base = T.base;
   const uint32_t size = 1u << P->m;
   const uint32_t t = threadIdx.x;
+  constexpr int RB = Regs<R>::RB, NR = Regs<R>::NR;
   for (uint32_t si = 0; si < P->stage_count; ++si) {
     const PassStageDev S = cload(stages + (P->stage_first + si));
     const uint32_t groups = size >> RB;
@@ -619,7 +642,7 @@ struct SingleSrc {
 };
 
 template <typename R, int WB>
-__global__ __launch_bounds__(kBlock) void k_pass(typename dev_elem<R>::E* __restrict__ psi, int n,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pass(typename dev_elem<R>::E* __restrict__ psi, int n,
                                                  const PassDescDev* __restrict__ passes, int pi,
                                                  const PassStageDev* __restrict__ stages,
                                                  const PassOpDev* __restrict__ ops,

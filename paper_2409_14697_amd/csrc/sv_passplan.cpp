@@ -67,6 +67,7 @@ bool real_diag_imag_offdiag(const cd* m) {
 struct StageBuilder {
   const int* loc;  // physical bit -> local bit, or -1
   int m;
+  int rb;          // register bits per stage
   std::vector<int> qs;   // register bits (local indices), in register order
   std::vector<Op> ops;   // physical qubits
 
@@ -89,9 +90,9 @@ struct StageBuilder {
 
   void encode(StageHost* sh) {
     // pad the register bits with the lowest unused local bits
-    for (int l = 0; (int)qs.size() < kPassRegBits && l < m; ++l)
+    for (int l = 0; (int)qs.size() < rb && l < m; ++l)
       if (std::find(qs.begin(), qs.end(), l) == qs.end()) qs.push_back(l);
-    for (int r = 0; r < kPassRegBits; ++r) sh->q[r] = (uint32_t)qs[r];
+    for (int r = 0; r < rb; ++r) sh->q[r] = (uint32_t)qs[r];
     for (const Op& op : ops) {
       PassOpDev od{};
       od.sa = od.sb = kPassNoSel;
@@ -201,10 +202,10 @@ struct StageBuilder {
 };
 
 // Split the ops of one pass (physical qubits, program order) into stages of at
-// most kPassRegBits register bits.
-std::vector<StageHost> build_stages(const std::vector<Op>& ops, const int* loc, int m) {
+// most rb register bits.
+std::vector<StageHost> build_stages(const std::vector<Op>& ops, const int* loc, int m, int rb) {
   std::vector<StageHost> out;
-  StageBuilder sb{loc, m, {}, {}};
+  StageBuilder sb{loc, m, rb, {}, {}};
   for (const Op& op : ops) {
     int q[SV_MAX_GATE_QUBITS];
     const int k = locality(op, q);
@@ -215,7 +216,7 @@ std::vector<StageHost> build_stages(const std::vector<Op>& ops, const int* loc, 
           std::find(need.begin(), need.end(), l) == need.end())
         need.push_back(l);
     }
-    if (sb.qs.size() + need.size() > (size_t)kPassRegBits) {
+    if (sb.qs.size() + need.size() > (size_t)rb) {
       StageHost sh;
       sb.encode(&sh);
       out.push_back(std::move(sh));
@@ -293,7 +294,8 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
   const int m_max = dt == SV_C128 ? 12 : 13;
   if (m > m_max) return fail(SV_ERR_ARG, "lds_qubits %d exceeds %d for this dtype", m, m_max);
   if (m > n) m = n;
-  if (m <= kPassRegBits) return fail(SV_ERR_ARG, "tile of %d qubits is too small for %d register bits", m, kPassRegBits);
+  const int rb = pass_reg_bits(dt);
+  if (m < rb) return fail(SV_ERR_ARG, "tile of %d qubits is too small for %d register bits", m, rb);
   int pin = o.pinned_low_bits ? o.pinned_low_bits : default_pinned_bits(dt);
   pin = std::min(pin, m - 2);
   const bool reorder = o.reorder != 0;
@@ -414,7 +416,7 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
         ps.lpos[j] = ps.wpos[j] = (uint32_t)b;
         loc[b] = j++;
       }
-    ps.stages = build_stages(members, loc, m);
+    ps.stages = build_stages(members, loc, m, rb);
     // write-back: complete cycles of the map that lie inside the tile go home
     if (last && !mp.identity()) {
       for (const auto& c : cycles_of(mp)) {

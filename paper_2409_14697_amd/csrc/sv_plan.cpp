@@ -154,7 +154,7 @@ sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const
   for (size_t i = 0; i < n_gates; ++i) raw.push_back(op_from_gate(g[i]));
 
   // in-cache passes need a tile of at least 2^(register bits + 1) amplitudes
-  const bool tiles_ok = n > kPassRegBits;
+  const bool tiles_ok = n > pass_reg_bits(dt);
   if (o.mode != SV_MODE_SWEEP && tiles_ok) {
     sv_plan tp;
     tp.n = n;
@@ -246,11 +246,12 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
       }
       for (const StageHost& sh : ps.stages) {
         PassStageDev sd{};
-        for (int r = 0; r < kPassRegBits; ++r) sd.q[r] = sh.q[r];
-        uint32_t srt[kPassRegBits];
-        for (int r = 0; r < kPassRegBits; ++r) srt[r] = sh.q[r];
-        std::sort(srt, srt + kPassRegBits);
-        for (int r = 0; r < kPassRegBits; ++r) sd.qsort[r] = srt[r];
+        const int rb = pass_reg_bits(s->dt);
+        for (int r = 0; r < rb; ++r) sd.q[r] = sh.q[r];
+        uint32_t srt[kPassRegBitsMax];
+        for (int r = 0; r < rb; ++r) srt[r] = sh.q[r];
+        std::sort(srt, srt + rb);
+        for (int r = 0; r < rb; ++r) sd.qsort[r] = srt[r];
         sd.op_first = (uint32_t)pops.size();
         sd.op_count = (uint32_t)sh.ops.size();
         const uint32_t mbase = (uint32_t)pool.size();

@@ -14,9 +14,11 @@ namespace sv {
 // lpos[0..m-1], ascending), runs its stages on each tile in LDS and
 // registers, and stores local bit j to physical position wpos[j] (a
 // permutation of lpos: qubit reordering fused into the write-back).
-// A stage holds 2^kPassRegBits register amplitudes per group: register bit r
-// is local bit q[r]; groups enumerate the other local bits.
-constexpr int kPassRegBits = 4;
+// A stage holds 2^rb register amplitudes per group (rb = pass_reg_bits:
+// 5 for complex64, 4 for complex128): register bit r is local bit q[r];
+// groups enumerate the other local bits.
+constexpr int kPassRegBitsMax = 5;
+inline constexpr int pass_reg_bits(sv_dtype dt) { return dt == SV_C64 ? 5 : 4; }
 
 enum PassOpType : uint32_t {
   POP_U1 = 0,  // 2x2 on register bit b0                        (4 entries)
@@ -47,8 +49,8 @@ struct alignas(16) PassOpDev {
 };
 
 struct PassStageDev {
-  uint32_t q[kPassRegBits];      // local bit of register bit r
-  uint32_t qsort[kPassRegBits];  // the same bits, ascending (group enumeration)
+  uint32_t q[kPassRegBitsMax];      // local bit of register bit r (r < rb)
+  uint32_t qsort[kPassRegBitsMax];  // the same bits, ascending (group enumeration)
   uint32_t op_first, op_count;
 };
 
