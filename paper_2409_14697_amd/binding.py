@@ -356,10 +356,11 @@ class Program:
         nb = c_size_t()
         check(lib.sv_program_bytes(plan.handle, byref(nb)))
         self.nbytes = nb.value
-        if buffer is None:
-            buffer = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device="cuda")
-        self.buffer = buffer
         s = stream if stream is not None else torch.cuda.current_stream()
+        if buffer is None:
+            with torch.cuda.stream(s):  # the caching allocator ties the block to the upload stream
+                buffer = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device="cuda")
+        self.buffer = buffer
         h = c_void_p()
         check(lib.sv_program_create(plan.handle, c_void_p(buffer.data_ptr()), buffer.numel(),
                                     c_void_p(s.cuda_stream), byref(h)))

@@ -247,16 +247,23 @@ sv_status sv_batcher_run(sv_batcher* b, int count, sv_state* const* states, cons
   b->next = (b->next + 1) % sv_batcher::kSlots;
   if (b->used[k]) SV_HIP_TRY(hipEventSynchronize(b->done[k]));  // slot's last launch has read it
   if (bytes > b->cap[k]) {
-    if (b->dev[k]) {
-      SV_HIP_TRY(hipFree(b->dev[k]));
-      SV_HIP_TRY(hipHostFree(b->host[k]));
-      b->dev[k] = b->host[k] = nullptr;
-    }
+    // the slot's last launch has finished (waited above): its buffers can go
+    if (b->dev[k]) (void)hipFree(b->dev[k]);
+    if (b->host[k]) (void)hipHostFree(b->host[k]);
+    b->dev[k] = b->host[k] = nullptr;
+    b->cap[k] = 0;
     size_t cap = 4096;
     while (cap < bytes) cap <<= 1;
-    if (hipMalloc(&b->dev[k], cap) != hipSuccess) return fail(SV_ERR_NOMEM, "batch descriptor buffer");
-    if (hipHostMalloc(&b->host[k], cap, hipHostMallocDefault) != hipSuccess)
+    if (hipMalloc(&b->dev[k], cap) != hipSuccess) {
+      b->dev[k] = nullptr;
+      return fail(SV_ERR_NOMEM, "batch descriptor buffer");
+    }
+    if (hipHostMalloc(&b->host[k], cap, hipHostMallocDefault) != hipSuccess) {
+      b->host[k] = nullptr;
+      (void)hipFree(b->dev[k]);
+      b->dev[k] = nullptr;
       return fail(SV_ERR_NOMEM, "pinned batch descriptor buffer");
+    }
     b->cap[k] = cap;
   }
   std::memcpy(b->host[k], items.data(), bytes);

@@ -309,7 +309,8 @@ class DeviceEngine:
         torch, B = self.torch, self.B
         h = job.handle
         tdt = torch.complex64 if self.dtype == "c64" else torch.complex128
-        h["tensor"] = torch.empty(1 << job.n, dtype=tdt, device="cuda")
+        with torch.cuda.stream(self.stream):  # allocations belong to the serving stream
+            h["tensor"] = torch.empty(1 << job.n, dtype=tdt, device="cuda")
         h["state"] = B.StateVector(job.n, self.dtype, tensor=h["tensor"], stream=self.stream, init=True)
         h["program"] = B.Program(h["plan"], stream=self.stream)
         h["plan"].close()
@@ -353,10 +354,12 @@ class DeviceEngine:
         torch = self.torch
         h = job.handle
         k = min(job.n, self.probs_qubits)
-        dev = torch.empty(1 << k, dtype=torch.float64, device="cuda")
+        with torch.cuda.stream(self.stream):
+            dev = torch.empty(1 << k, dtype=torch.float64, device="cuda")
         self.batcher.probs(h["state"], list(range(k - 1, -1, -1)), dev)
         host = torch.empty(1 << k, dtype=torch.float64, pin_memory=True)
-        host.copy_(dev, non_blocking=True)
+        with torch.cuda.stream(self.stream):  # ordered after the reduction
+            host.copy_(dev, non_blocking=True)
         ev = torch.cuda.Event()
         ev.record(self.stream)
         h["probs_dev"], h["probs_host"], h["done"] = dev, host, ev
