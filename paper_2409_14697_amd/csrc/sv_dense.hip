@@ -44,11 +44,11 @@ struct LaneMap {
   bool on;
 };
 
-template <int LB>
+template <int LB, int TB = 8>
 __device__ __forceinline__ LaneMap lane_map(uint32_t t, const DenseGeo& g) {
   LaneMap m{0, 0, ((t << LB) & g.inv) == 0};
 #pragma unroll
-  for (int j = 0; j < 8; ++j)
+  for (int j = 0; j < TB; ++j)
     if ((t >> j) & 1u) {
       if (g.pos[LB + j] < 64) m.addr |= 1ull << g.pos[LB + j];
       m.lds |= g.lds[LB + j];
@@ -56,26 +56,26 @@ __device__ __forceinline__ LaneMap lane_map(uint32_t t, const DenseGeo& g) {
   return m;
 }
 
-// Uniform part for element u of a lane (tile-local bits LB+8 ..).
-template <int LB, int U>
+// Uniform part for element u of a lane (tile-local bits LB+TB ..; TB lane bits).
+template <int LB, int U, int TB = 8>
 __device__ __forceinline__ void elem_map(const DenseGeo& g, uint64_t* addr, uint32_t* lds, bool* on) {
   uint64_t a = 0;
   uint32_t l = 0;
 #pragma unroll
   for (int b = 0; b < 8; ++b)
     if ((U >> b) & 1) {
-      if (g.pos[LB + 8 + b] < 64) a |= 1ull << g.pos[LB + 8 + b];
-      l |= g.lds[LB + 8 + b];
+      if (g.pos[LB + TB + b] < 64) a |= 1ull << g.pos[LB + TB + b];
+      l |= g.lds[LB + TB + b];
     }
   *addr = a;
   *lds = l;
-  *on = (((uint32_t)U << (8 + LB)) & g.inv) == 0;
+  *on = (((uint32_t)U << (TB + LB)) & g.inv) == 0;
 }
 
 #define SV_FOR_U(PER, F)                                                  \
-  F(0) if (PER > 1) { F(1) } if (PER > 2) { F(2) F(3) }                   \
-  if (PER > 4) { F(4) F(5) F(6) F(7) }                                    \
-  if (PER > 8) { F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) }
+  F(0) if constexpr (PER > 1) { F(1) } if constexpr (PER > 2) { F(2) F(3) } \
+  if constexpr (PER > 4) { F(4) F(5) F(6) F(7) }                           \
+  if constexpr (PER > 8) { F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) }
 
 // Tile columns of the VALU kernel: the tile holds 2048 amplitudes.
 template <int K>
@@ -241,11 +241,11 @@ struct mfma_shape<double> {
   static __device__ __forceinline__ G from_lds(const E* xs, uint32_t li, uint32_t) { return xs[li]; }
 };
 
-// groups per column tile: the X tile holds 4096 complex64 / 1024 complex128
-// amplitudes (32 / 16 KiB), and at least one column block
+// groups per column tile: the X tile holds 4096 complex64 / 2048 complex128
+// amplitudes (32 KiB), and at least one column block
 template <typename R, int K>
 constexpr int mfma_cols() {
-  constexpr int target = (sizeof(R) == 4 ? 4096 : 1024) >> K;
+  constexpr int target = (sizeof(R) == 4 ? 4096 : 2048) >> K;
   return target < mfma_shape<R>::BN ? mfma_shape<R>::BN : target;
 }
 
@@ -254,34 +254,39 @@ constexpr size_t mfma_lds() {
   return (size_t)(1 << K) * mfma_cols<R, K>() * 2 * sizeof(R);
 }
 
-// Waves own row blocks: wave w computes the output tiles w, w + 4, ... of the
-// (row block, column block) grid, tile = rb + RBLK * cb, so it only ever
-// needs the row blocks (w + 4 i) mod RBLK.  Their A fragments (the embedded
-// U) are loop-invariant over column tiles and stay in registers.
+// Waves own row blocks: wave w computes the output tiles w, w + W, ... of
+// the (row block, column block) grid, tile = rb + RBLK * cb, so it only ever
+// needs the row blocks (w + W i) mod RBLK.  Their A fragments (the embedded
+// U) are loop-invariant over column tiles and stay in registers.  W = 4
+// waves per block, 8 for complex128 k = 6 (one row block of A per wave, so a
+// block fits two waves per SIMD).
 template <typename R, int K>
 struct mfma_plan {
   typedef mfma_shape<R> MS;
   static constexpr int D = 1 << K;
   static constexpr int NC = mfma_cols<R, K>();
+  static constexpr int W = (sizeof(R) == 8 && K == 6) ? 8 : 4;
+  static constexpr int THREADS = 64 * W, TB = W == 8 ? 9 : 8;
   static constexpr int RBLK = 2 * D / MS::BM, CBLK = NC / MS::BN, TILES = RBLK * CBLK;
-  static constexpr int TPW = (TILES + 3) / 4;                 // output tiles per wave
-  static constexpr int NRB = RBLK >= 4 ? RBLK / 4 : 1;         // distinct row blocks per wave
+  static constexpr int TPW = (TILES + W - 1) / W;              // output tiles per wave
+  static constexpr int NRB = RBLK >= W ? RBLK / W : 1;         // distinct row blocks per wave
   static constexpr int KSTEPS = 2 * D / MS::BK;
+  static_assert(RBLK < W || RBLK % W == 0, "row blocks split evenly over the waves");
 };
 
 template <typename R, int K>
-__global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E* __restrict__ psi, uint64_t nwork,
+__global__ __launch_bounds__((mfma_plan<R, K>::THREADS)) void k_dense_mfma(typename mfma_shape<R>::E* __restrict__ psi, uint64_t nwork,
                                                        DenseGeo g, const R* __restrict__ um) {
   typedef mfma_shape<R> MS;
   typedef mfma_plan<R, K> MP;
   typedef typename MS::E E;
   constexpr int D = MP::D, NC = MP::NC, RBLK = MP::RBLK, TILES = MP::TILES, TPW = MP::TPW, NRB = MP::NRB;
-  constexpr int KSTEPS = MP::KSTEPS;
+  constexpr int KSTEPS = MP::KSTEPS, W = MP::W, TB = MP::TB;
   // global memory moves in 16-byte elements: complex128 amplitudes, or
   // complex64 pairs on tile-local bit 0 (LB = 1)
   constexpr int LB = sizeof(R) == 4 ? 1 : 0;
   typedef typename mfma_shape<R>::G G;
-  constexpr int PER = (D * NC / kBlock) >> LB;  // 16-byte elements per lane
+  constexpr int PER = (D * NC / MP::THREADS) >> LB;  // 16-byte elements per lane
   extern __shared__ __align__(16) unsigned char smem[];
   E* xs = reinterpret_cast<E*>(smem);  // [member][NC]
   const int t = threadIdx.x, w = t / 64, l = t % 64;
@@ -289,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
   R afrag[NRB][KSTEPS];
 #pragma unroll
   for (int i = 0; i < NRB; ++i) {
-    const int rb = (w + 4 * i) % RBLK;
+    const int rb = (w + W * i) % RBLK;
     int ai, aa;  // output member and re/im of the A row this lane supplies
     MS::row_of(l % MS::BM, &ai, &aa);
     ai += MS::MPB * rb;
@@ -300,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
       afrag[i][ks] = aa == 0 ? ((ak & 1) == 0 ? ur : -ui) : ((ak & 1) == 0 ? ui : ur);
     }
   }
-  const LaneMap lm = lane_map<LB>((uint32_t)t, g);
+  const LaneMap lm = lane_map<LB, TB>((uint32_t)t, g);
   const uint32_t l0 = g.lds[0];  // LDS offset of the bit-0 partner (LB = 1)
   G* gp = reinterpret_cast<G*>(psi);
   // software-pipelined over column tiles: the next tile's loads are in flight
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
     uint64_t a;                                                       \
     uint32_t li;                                                      \
     bool on;                                                          \
-    elem_map<LB, U>(g, &a, &li, &on);                                 \
+    elem_map<LB, U, TB>(g, &a, &li, &on);                                 \
     buf[U] = ld(gp + (((on && lm.on) ? (ldbase | a) : ldbase) >> LB)); \
   }
   {
@@ -329,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
       uint64_t a;                                                     \
       uint32_t li;                                                    \
       bool on;                                                        \
-      elem_map<LB, U>(g, &a, &li, &on);                               \
+      elem_map<LB, U, TB>(g, &a, &li, &on);                               \
       if (on && lm.on) mfma_shape<R>::to_lds(xs, lm.lds | li, l0, buf[U]); \
     }
     SV_FOR_U(PER, SV_LDS)
@@ -342,7 +347,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
     typename MS::acc_t acc[TPW];
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
-      const int tile = w + 4 * i;
+      const int tile = w + W * i;
       acc[i] = typename MS::acc_t{};
       if (tile >= TILES) continue;
       const int bcol = MS::BN * (tile / RBLK) + l % MS::BN;
@@ -351,13 +356,13 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
         const int bk = MS::BK * ks + l / MS::BN;
         const E xv = xs[(bk >> 1) * NC + bcol];
         const R b = (bk & 1) ? xv.y : xv.x;
-        acc[i] = MS::mma(afrag[i % NRB][ks], b, acc[i]);  // row block (w + 4 i) % RBLK
+        acc[i] = MS::mma(afrag[i % NRB][ks], b, acc[i]);  // row block (w + W i) % RBLK
       }
     }
     __syncthreads();  // every wave has read X: the outputs replace it in LDS
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
-      const int tile = w + 4 * i;
+      const int tile = w + W * i;
       if (tile >= TILES) continue;
       const int rb = tile % RBLK, cb = tile / RBLK;
       const int bcol = MS::BN * cb + l % MS::BN;
@@ -377,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_mfma(typename mfma_shape<R>::E
       uint64_t a;                                                     \
       uint32_t li;                                                    \
       bool on;                                                        \
-      elem_map<LB, U>(g, &a, &li, &on);                               \
+      elem_map<LB, U, TB>(g, &a, &li, &on);                               \
       if (on && lm.on) st(gp + ((base | a) >> LB), mfma_shape<R>::from_lds(xs, lm.lds | li, l0)); \
     }
     SV_FOR_U(PER, SV_ST)
@@ -404,7 +409,7 @@ hipError_t run_mfma(void* psi, int n, const DenseGeo& g, const void* m, hipStrea
   // persistent blocks: enough to fill the chip several times over, each
   // amortising its A fragments (loaded once) over many column tiles
   const uint64_t blocks = nwork < 4096 ? nwork : 4096;
-  hipLaunchKernelGGL((k_dense_mfma<R, K>), dim3((unsigned)blocks), dim3(kBlock), lds, s,
+  hipLaunchKernelGGL((k_dense_mfma<R, K>), dim3((unsigned)blocks), dim3(mfma_plan<R, K>::THREADS), lds, s,
                      (typename mfma_shape<R>::E*)psi, nwork, g, (const R*)m);
   return hipGetLastError();
 }
