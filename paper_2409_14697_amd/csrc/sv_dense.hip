@@ -245,7 +245,7 @@ struct mfma_shape<double> {
 // amplitudes (32 KiB), and at least one column block
 template <typename R, int K>
 constexpr int mfma_cols() {
-  constexpr int target = (sizeof(R) == 4 ? 4096 : 2048) >> K;
+  constexpr int target = (sizeof(R) == 4 ? 4096 : (K == 6 ? 4096 : 2048)) >> K;
   return target < mfma_shape<R>::BN ? mfma_shape<R>::BN : target;
 }
 
