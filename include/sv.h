@@ -95,7 +95,8 @@ typedef struct sv_plan sv_plan;    /* opaque: host-only executable schedule   */
 
 /* Execution strategy of a plan. */
 typedef enum {
-  SV_MODE_AUTO = 0,   /* cost model chooses per pass                        */
+  SV_MODE_AUTO = 0,   /* cost model picks the cheaper of a tile-pass plan and
+                         a one-sweep-per-fused-op plan                       */
   SV_MODE_SWEEP = 1,  /* one full-state sweep per (fused) op                */
   SV_MODE_PASS = 2    /* LDS in-cache passes that apply many ops per sweep  */
 } sv_mode;
