@@ -225,11 +225,19 @@ def serve_cpu_baseline(requests, budget_s: float = 15.0):
         timed += k
         mean_gates = sum(r.depth * (r.n + r.n // 2) for r in rs) / len(rs)  # N rotations + N/2 CNOTs per pair
         total_s += per_gate * mean_gates * len(rs)
-    return {"value": round(len(requests) / total_s, 4), "unit": "circuits/s", "cores": _cpu_threads(),
+    return {"value": round(len(requests) / total_s, 4), "unit": "circuits/s", "cores": _blas_threads(),
             "kind": "oracle",
             "sample": f"oracle (numpy complex128) timed on the first gates of one request per N "
                       f"({timed} gates over N={min(by_n)}..{max(by_n)}), extrapolated linearly in gate count "
                       f"to the {len(requests)}-request mix"}
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        return 1
 
 
 def _cpu_threads():

@@ -102,7 +102,8 @@ template <typename R>
 struct OpScaleNorm {
   const double* norm2;
   __device__ __forceinline__ void operator()(cplx<R>* a, uint64_t) const {
-    const R s = (R)(1.0 / sqrt(*norm2));
+    const double n2 = *norm2;
+    const R s = n2 > 0.0 ? (R)(1.0 / sqrt(n2)) : R(1);  // a zero state stays as it is
     a[0].re *= s;
     a[0].im *= s;
   }

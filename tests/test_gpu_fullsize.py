@@ -168,3 +168,40 @@ def test_serving_large_requests(sv, dtype):
         b = mixed[r.rid].handle["tensor"].cpu().numpy()
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), r.rid
         assert np.array_equal(alone.probs, mixed[r.rid].probs)
+
+
+@pytest.mark.parametrize("dtype,n", [("c64", 34), ("c128", 33)])
+def test_maximum_state_size(sv, dtype, n):
+    """The largest states (128 GiB): a sweep gate, a lane-exchange gate, a
+    fused dense gate on the top qubits and a tile pass, checked on sampled
+    groups; marginals over the top 16 qubits sum to 1."""
+    import torch
+    st = sv.StateVector(n, dtype)
+    t = st.tensor
+    rng = np.random.default_rng(31)
+    st.init_basis(0)
+    st.apply_gate(Gate("H", (n - 1,)))
+    st.apply_gate(Gate("CNOT", (n - 1, 0)))
+    st.sync()
+    got = read(t, np.array([0, 1, 1 << (n - 1), (1 << (n - 1)) + 1], dtype=np.int64))
+    r2 = 1 / math.sqrt(2)
+    assert max_err(got, [r2, 0, 0, r2]) <= TOL[dtype]
+    # spread the state over every qubit, then check gates on sampled groups
+    st.apply_circuit([Gate("H", (q,)) for q in range(n)], {"mode": "sweep"})
+    k = 5
+    qs = tuple(range(n - 1, n - 1 - k, -1))
+    for g, opts in ((Gate("MATRIX", qs, matrix=haar_unitary(1 << k, rng)), {"mode": "sweep", "max_fuse_qubits": 0}),
+                    (Gate("RX", (3,), 0.7), {"mode": "sweep"}),
+                    (Gate("CPHASE", (n - 1, 2), 1.3), {"mode": "pass"})):
+        idx = sampled_groups(n, g.qubits, SAMPLES, rng)
+        before = read(t, idx)
+        st.apply_circuit([g], opts)
+        st.sync()
+        after = read(t, idx)
+        assert max_err(after, oracle.apply_to_group(so.gate_matrix(g), before.T).T) <= TOL[dtype], g.kind
+    p = st.measure_probs(list(range(n - 1, n - 17, -1)))
+    st.sync()
+    assert abs(float(p.sum().item()) - 1.0) < (1e-10 if dtype == "c128" else 1e-4)
+    st.close()
+    del t
+    torch.cuda.empty_cache()

@@ -207,3 +207,30 @@ def test_invalid_gate_leaves_state_untouched(sv):
     st.sync()
     assert np.array_equal(to_host(t), host_in)
     st.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_degenerate_inputs(sv, dtype):
+    """Empty circuits and plans change nothing; a state that is all zeros stays
+    zero under renormalisation; n above the maximum is rejected."""
+    from paper_2409_14697_amd import binding as B
+    n = 7
+    t, host_in = to_device(gaussian_state_np(n, 5), dtype)
+    st = sv.StateVector(n, dtype, tensor=t, init=False)
+    before = to_host(t)
+    for mode in ("auto", "sweep", "pass"):
+        st.apply_circuit([], {"mode": mode})
+    st.apply_plan(sv.Plan(n, dtype, [], {"mode": "pass"}))
+    st.sync()
+    assert np.array_equal(to_host(t), before)
+    t.zero_()
+    st.apply_circuit([Gate("MATRIX", (0, 1, 2), matrix=np.eye(8))],
+                     {"mode": "sweep", "max_fuse_qubits": 0, "renorm_interval": 1})
+    st.sync()
+    assert np.array_equal(to_host(t), np.zeros(1 << n))
+    st.close()
+    import ctypes
+    h = ctypes.c_void_p()
+    code = B.SV_C128 if dtype == "c128" else B.SV_C64
+    assert B.load_library().sv_create(35, code, None, None, 0, ctypes.byref(h)) == B.SV_ERR_ARG  # before allocating
+    assert B.load_library().sv_create(0, code, None, None, 0, ctypes.byref(h)) == B.SV_ERR_ARG
