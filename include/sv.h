@@ -193,6 +193,14 @@ sv_status sv_plan_pass_info(const sv_plan *p, size_t pass, int32_t *kind, int32_
  * and 0 for a permutation.  Errors: SV_ERR_ARG. */
 sv_status sv_plan_pass_flops(const sv_plan *p, size_t pass, double *flops_per_amp);
 
+/* Kernel ops of tile pass `pass` after register staging: *n_ops ops in
+ * total, *n_ladders of them phase ladders (a run of phase gates and
+ * controlled phases that share one qubit, applied as one op with a
+ * fixed-point angle sum; Sec. III-A's gate grouping inside a tile).  Both 0
+ * for passes that are not tile passes.  Outputs may be NULL.
+ * Errors: SV_ERR_ARG. */
+sv_status sv_plan_pass_ops(const sv_plan *p, size_t pass, int32_t *n_ops, int32_t *n_ladders);
+
 sv_status sv_plan_destroy(sv_plan *p);
 
 /* Execute a plan built for this state's n and dtype.  Async.  The state is

@@ -11,7 +11,7 @@ import ctypes
 import os
 import re
 from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int32, c_size_t, c_uint, c_uint64, c_void_p
-from typing import Iterable, List, Optional, Sequence
+from typing import Iterable, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   POINTER(c_int32)]),
         "sv_plan_destroy": (S, [c_void_p]),
         "sv_plan_pass_flops": (S, [c_void_p, c_size_t, POINTER(c_double)]),
+        "sv_plan_pass_ops": (S, [c_void_p, c_size_t, POINTER(c_int32), POINTER(c_int32)]),
         "sv_apply_plan": (S, [c_void_p, c_void_p]),
         "sv_apply_circuit": (S, [c_void_p, POINTER(SvGate), c_size_t, POINTER(SvOpts)]),
         "sv_permute_qubits": (S, [c_void_p, POINTER(c_int32)]),
@@ -226,6 +227,17 @@ class Plan:
             check(lib.sv_plan_pass_info(self._h, i, byref(kind), byref(nops), byref(nloc), byref(nst)))
             out.append((kind.value, nops.value, nloc.value, nst.value) if stages else
                        (kind.value, nops.value, nloc.value))
+        return out
+
+    def kernel_ops(self) -> List[Tuple[int, int]]:
+        """(kernel ops, phase ladders among them) per pass (sv_plan_pass_ops)."""
+        lib = load_library()
+        _, n_passes = self.info()
+        out = []
+        a, b = c_int32(), c_int32()
+        for i in range(n_passes):
+            check(lib.sv_plan_pass_ops(self._h, i, byref(a), byref(b)))
+            out.append((a.value, b.value))
         return out
 
     def pass_flops(self) -> List[float]:

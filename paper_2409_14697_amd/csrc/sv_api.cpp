@@ -334,6 +334,21 @@ sv_status sv_plan_pass_flops(const sv_plan* p, size_t pass, double* flops_per_am
   return SV_OK;
 }
 
+sv_status sv_plan_pass_ops(const sv_plan* p, size_t pass, int32_t* n_ops, int32_t* n_ladders) {
+  clear_error();
+  if (!p) return fail(SV_ERR_ARG, "null plan");
+  if (pass >= p->passes.size()) return fail(SV_ERR_ARG, "pass %zu out of range", pass);
+  int32_t ops = 0, ladders = 0;
+  for (const StageHost& sh : p->passes[pass].stages)
+    for (const PassOpDev& od : sh.ops) {
+      ++ops;
+      ladders += od.type == POP_LP;
+    }
+  if (n_ops) *n_ops = ops;
+  if (n_ladders) *n_ladders = ladders;
+  return SV_OK;
+}
+
 sv_status sv_plan_destroy(sv_plan* p) {
   clear_error();
   delete p;

@@ -12,6 +12,7 @@ struct sv_program {
   int n_passes = 0;
   int max_m = 0;
   std::vector<int> pass_m;  // local qubits of each pass
+  std::vector<char> pass_lp;  // the pass holds phase-ladder ops
   std::vector<unsigned char> host;  // [descs][stages][ops][pool], kept for the async upload
   void* dev = nullptr;
   bool owned = false;
@@ -45,6 +46,7 @@ sv_status pack_program(const sv_plan* p, sv_program* prog) {
   std::vector<PassStageDev> stages;
   std::vector<PassOpDev> pops;
   std::vector<cd> pool;
+  std::vector<uint8_t> pool_raw;
   for (const Pass& ps : p->passes) {
     if (ps.kind != PASS_TILE && ps.kind != PASS_PERMUTE)
       return fail(SV_ERR_UNSUPPORTED, "program needs a plan of in-cache tile passes only (build it with mode PASS)");
@@ -72,10 +74,12 @@ sv_status pack_program(const sv_plan* p, sv_program* prog) {
         pops.push_back(od);
       }
       pool.insert(pool.end(), sh.mats.begin(), sh.mats.end());
+      pool_raw.insert(pool_raw.end(), sh.raw.begin(), sh.raw.end());
       stages.push_back(sd);
     }
     descs.push_back(d);
     prog->pass_m.push_back(ps.n_local);
+    prog->pass_lp.push_back(pass_has_ladders(ps) ? 1 : 0);
     prog->max_m = std::max(prog->max_m, ps.n_local);
   }
   std::vector<unsigned char>& host = prog->host;
@@ -94,17 +98,7 @@ sv_status pack_program(const sv_plan* p, sv_program* prog) {
   align();
   prog->off_pool = host.size();
   host.resize(host.size() + pool.size() * 2 * scal);
-  for (size_t e = 0; e < pool.size(); ++e) {
-    if (f32) {
-      float* d = (float*)(host.data() + prog->off_pool);
-      d[2 * e] = (float)pool[e].real();
-      d[2 * e + 1] = (float)pool[e].imag();
-    } else {
-      double* d = (double*)(host.data() + prog->off_pool);
-      d[2 * e] = pool[e].real();
-      d[2 * e + 1] = pool[e].imag();
-    }
-  }
+  write_pool(host.data() + prog->off_pool, pool.data(), pool_raw.data(), pool.size(), f32);
   align();
   prog->n = p->n;
   prog->dt = p->dt;
@@ -216,6 +210,7 @@ sv_status sv_batcher_run(sv_batcher* b, int count, sv_state* const* states, cons
   std::vector<BatchItemDev> items((size_t)count);
   uint64_t tiles = 0;
   int max_m = 0;
+  bool ladders = false;
   sv_dtype dt = SV_C128;
   for (int i = 0; i < count; ++i) {
     const sv_state* s = states[i];
@@ -241,6 +236,7 @@ sv_status sv_batcher_run(sv_batcher* b, int count, sv_state* const* states, cons
     it.pass = pass_index[i];
     tiles += 1ull << (s->n - m);
     max_m = std::max(max_m, m);
+    ladders = ladders || p->pass_lp[pass_index[i]];
   }
   const size_t bytes = items.size() * sizeof(BatchItemDev);
   const int k = b->next;
@@ -268,7 +264,7 @@ sv_status sv_batcher_run(sv_batcher* b, int count, sv_state* const* states, cons
   }
   std::memcpy(b->host[k], items.data(), bytes);
   SV_HIP_TRY(hipMemcpyAsync(b->dev[k], b->host[k], bytes, hipMemcpyHostToDevice, b->stream));
-  SV_HIP_TRY(launch_pass_batch(dt, (const BatchItemDev*)b->dev[k], count, tiles, max_m, b->stream));
+  SV_HIP_TRY(launch_pass_batch(dt, (const BatchItemDev*)b->dev[k], count, tiles, max_m, ladders, b->stream));
   SV_HIP_TRY(hipEventRecord(b->done[k], b->stream));
   b->used[k] = true;
   return SV_OK;

@@ -67,7 +67,14 @@ struct StageHost {
   uint32_t q[kPassRegBitsMax] = {0, 0, 0, 0, 0};  // local bit of each register bit
   std::vector<PassOpDev> ops;               // .mat indexes this stage's `mats`
   std::vector<cd> mats;
+  std::vector<uint8_t> raw;                 // per entry: 1 = two raw words (write_pool)
 };
+
+// Write `count` pool entries in the state precision (complex64: f32 = true).
+// An entry with raw[e] set holds two words in the bit patterns of its real
+// and imaginary parts (uint64 each); they are stored as two uint32 (complex64)
+// or two uint64 (complex128) instead of being converted.  raw may be null.
+void write_pool(unsigned char* dst, const cd* m, const uint8_t* raw, size_t count, bool f32);
 
 struct Pass {
   int kind = PASS_SWEEP;
@@ -80,6 +87,14 @@ struct Pass {
   uint32_t wpos[16] = {0};
   std::vector<StageHost> stages;
 };
+
+// The pass's stages hold phase-ladder ops (POP_LP).
+inline bool pass_has_ladders(const Pass& ps) {
+  for (const StageHost& sh : ps.stages)
+    for (const PassOpDev& od : sh.ops)
+      if (od.type == POP_LP) return true;
+  return false;
+}
 
 }  // namespace sv
 

@@ -183,6 +183,30 @@ __device__ __forceinline__ void op_p2(cplx<R>* v, cplx<R> p) {
     if (((r >> B0) & 1) && ((r >> B1) & 1)) v[r] = cmul(p, v[r]);
 }
 
+// Angle words of the phase ladder: fixed-point turns, summed modulo one turn.
+template <typename R>
+struct lp_word;
+template <>
+struct lp_word<float> {
+  typedef uint32_t W;
+  typedef int32_t S;
+  static __device__ __forceinline__ cplx<float> phase(W t) {
+    float s, c;
+    sincospif((float)(S)t * 0x1p-31f, &s, &c);  // angle 2 pi t / 2^32, as (-1, 1] half turns
+    return cplx<float>{c, s};
+  }
+};
+template <>
+struct lp_word<double> {
+  typedef uint64_t W;
+  typedef int64_t S;
+  static __device__ __forceinline__ cplx<double> phase(W t) {
+    double s, c;
+    sincospi((double)(S)t * 0x1p-63, &s, &c);
+    return cplx<double>{c, s};
+  }
+};
+
 template <int B, typename R>
 __device__ __forceinline__ void op_x(cplx<R>* v) {
   constexpr int NR = Regs<R>::NR;
@@ -243,11 +267,46 @@ __device__ __forceinline__ void op_d2(cplx<R>* v, cptr<cplx<R>> M) {
     default: break;                                                                          \
   }
 
+// POP_LP: the phase of the lane's amplitudes whose register bit b0 is 1:
+// the constant word plus the words of the set source bits, tile bits (the
+// same in every lane) and the lane's local group bits (xg has zeros at the
+// register positions).
+template <typename R>
+__device__ __forceinline__ cplx<R> lp_phase(const PassOpDev& op, cptr<cplx<R>> M, uint32_t xg, uint64_t base) {
+  typedef typename lp_word<R>::W W;
+  const cptr<W> words = (cptr<W>)M;
+  // words in chunks of 8 (one scalar load each; the loops stay rolled so
+  // that only one chunk is live in scalar registers)
+  constexpr int CH = 8;
+  static_assert(kPassLPLocalBits % CH == 0, "local words come in whole chunks");
+  uint64_t sel = base & op.tmask;
+  W t = words[kPassLPConst];
+#pragma unroll 1
+  for (int c = 0; c < (kPassLPTileBits + CH - 1) / CH && sel; ++c, sel >>= CH) {
+#pragma unroll
+    for (int b = 0; b < CH; ++b) {
+      const int i = CH * c + b;
+      const W w = i < kPassLPTileBits ? words[kPassLPLocalBits + i] : W(0);
+      t += ((sel >> b) & 1) ? w : W(0);
+    }
+  }
+  uint32_t lsel = xg & op.lmask;
+#pragma unroll 1
+  for (int c = 0; c < kPassLPLocalBits / CH; ++c, lsel >>= CH) {
+#pragma unroll
+    for (int b = 0; b < CH; ++b) {
+      const W w = words[CH * c + b];
+      t += ((lsel >> b) & 1) ? w : W(0);
+    }
+  }
+  return lp_word<R>::phase(t);
+}
+
 // M points at the op's first matrix entry (the same address in every lane, so
 // the entries come through scalar loads); `var` selects a variant per lane.
-template <typename R>
+template <typename R, bool LP>
 __device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, uint32_t var,
-                                         cplx<R>* v) {
+                                         cplx<R>* v, uint32_t xg, uint64_t base) {
   const uint32_t pair = op.b0 * 8 + op.b1;
   constexpr bool H5 = Regs<R>::RB > 4;
   switch (op.type) {
@@ -307,12 +366,18 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, u
 #undef F
       break;
     }
-    case POP_P1: {
-      cplx<R> p = cget(M, 0);
-      if (op.sa != kPassNoSel) {  // two variants, picked per lane
-        const cplx<R> p1 = cget(M, 1);
-        p.re = var ? p1.re : p.re;
-        p.im = var ? p1.im : p.im;
+    case POP_P1:
+    case POP_LP: {  // one phase per lane on the amplitudes whose bit b0 is 1
+      cplx<R> p;
+      if (LP && op.type == POP_LP) {
+        p = lp_phase<R>(op, M, xg, base);
+      } else {
+        p = cget(M, 0);
+        if (op.sa != kPassNoSel) {  // two variants, picked per lane
+          const cplx<R> p1 = cget(M, 1);
+          p.re = var ? p1.re : p.re;
+          p.im = var ? p1.im : p.im;
+        }
       }
 #define F(B) op_p1<B>(v, p)
       SV_BIT_SWITCH(op.b0, F, H5)
@@ -488,7 +553,7 @@ __device__ __forceinline__ void tile_fill(const TileRef<R>& T, const typename ge
 }
 
 // The pass's register stages on the tile in LDS (ends with a barrier).
-template <typename R, int WB>
+template <typename R, int WB, bool LP>
 __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_elem<R>::E* tile) {
   typedef typename dev_elem<R>::E E;
   const cptr<PassDescDev> P = T.P;
@@ -529,7 +594,7 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
       }
       for (uint32_t o = 0; o < S.op_count; ++o) {
         const PassOpDev op = cload(ops + (S.op_first + o));
-        if ((xg & op.lmask) != op.lmask || (base & op.tmask) != op.tmask) continue;
+        if (!(LP && op.type == POP_LP) && ((xg & op.lmask) != op.lmask || (base & op.tmask) != op.tmask)) continue;
         uint32_t var = 0;
         if (op.sa != kPassNoSel) {
           var = op.sa < kPassTileSel ? (xg >> op.sa) & 1u : (uint32_t)(base >> (op.sa - kPassTileSel)) & 1u;
@@ -537,7 +602,7 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
             var = (var << 1) |
                   (op.sb < kPassTileSel ? (xg >> op.sb) & 1u : (uint32_t)(base >> (op.sb - kPassTileSel)) & 1u);
         }
-        apply_op<R>(op, mats + op.mat, var, v);
+        apply_op<R, LP>(op, mats + op.mat, var, v, xg, base);
       }
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -607,7 +672,7 @@ __device__ __forceinline__ void tile_store(const TileRef<R>& T, const typename d
 // Persistent loop over tiles, software-pipelined: the next tile's loads are
 // in flight while the current tile runs its stages and is stored.  `next`
 // maps a global tile number to its TileRef.
-template <typename R, int WB, typename Src>
+template <typename R, int WB, bool LP, typename Src>
 __device__ __forceinline__ void tile_loop(uint64_t total, const Src& src, typename dev_elem<R>::E* tile) {
   typedef typename gelem<R>::G G;
   uint64_t g = xcd_block();
@@ -621,7 +686,7 @@ __device__ __forceinline__ void tile_loop(uint64_t total, const Src& src, typena
     tile_fill<R, WB>(cur, buf, tile);
     __syncthreads();
     if (ng < total) tile_load<R>(src(ng), buf);
-    tile_stages<R, WB>(cur, tile);
+    tile_stages<R, WB, LP>(cur, tile);
     tile_store<R, WB>(cur, tile);
     if (ng >= total) break;
     g = ng;
@@ -641,7 +706,7 @@ struct SingleSrc {
   }
 };
 
-template <typename R, int WB>
+template <typename R, int WB, bool LP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pass(typename dev_elem<R>::E* __restrict__ psi, int n,
                                                  const PassDescDev* __restrict__ passes, int pi,
                                                  const PassStageDev* __restrict__ stages,
@@ -652,7 +717,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   E* tile = reinterpret_cast<E*>(smem);
   const cptr<PassDescDev> P = as_const(passes + pi);
   const SingleSrc<R> src{psi, n, P, as_const(stages), as_const(ops), as_const(mats)};
-  tile_loop<R, WB>(1ull << (n - P->m), src, tile);
+  tile_loop<R, WB, LP>(1ull << (n - P->m), src, tile);
 }
 
 // Many states in one launch: work item i runs pass `pass` of its own program
@@ -678,14 +743,14 @@ struct BatchSrc {
   }
 };
 
-template <typename R, int WB>
+template <typename R, int WB, bool LP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pass_batch(const BatchItemDev* __restrict__ items, int count,
                                                        uint64_t total_tiles) {
   typedef typename dev_elem<R>::E E;
   extern __shared__ __align__(16) unsigned char smem[];
   E* tile = reinterpret_cast<E*>(smem);
   const BatchSrc<R> src{as_const(items), count};
-  tile_loop<R, WB>(total_tiles, src, tile);
+  tile_loop<R, WB, LP>(total_tiles, src, tile);
 }
 
 // Blocks that fit on the device at once for `kernel` with `lds` bytes of
@@ -701,7 +766,7 @@ uint64_t resident_blocks(F kernel, size_t lds, uint64_t* cache) {
   return *cache;
 }
 
-template <typename R, int WB>
+template <typename R, int WB, bool LP>
 hipError_t run(void* psi, int n, int m, const PassDescDev* passes, int pass, const PassStageDev* stages,
                const PassOpDev* ops, const void* mats, hipStream_t s) {
   typedef typename dev_elem<R>::E E;
@@ -709,50 +774,57 @@ hipError_t run(void* psi, int n, int m, const PassDescDev* passes, int pass, con
   static size_t attr = 0;            // largest dynamic LDS size requested so far
   static uint64_t resident[17] = {};  // per tile size
   if (lds > attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_pass<R, WB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)k_pass<R, WB, LP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
     attr = lds;
   }
-  if (!resident[m]) resident_blocks(k_pass<R, WB>, lds, &resident[m]);
+  if (!resident[m]) resident_blocks(k_pass<R, WB, LP>, lds, &resident[m]);
   const uint64_t tiles = 1ull << (n - m);
   const uint64_t blocks = tiles < resident[m] ? tiles : resident[m];
-  hipLaunchKernelGGL((k_pass<R, WB>), dim3((unsigned)blocks), dim3(kBlock), lds, s, (E*)psi, n, passes, pass, stages,
+  hipLaunchKernelGGL((k_pass<R, WB, LP>), dim3((unsigned)blocks), dim3(kBlock), lds, s, (E*)psi, n, passes, pass, stages,
                      ops, (const cplx<R>*)mats);
   return hipGetLastError();
 }
 
-template <typename R, int WB>
+template <typename R, int WB, bool LP>
 hipError_t run_batch(const BatchItemDev* items, int count, uint64_t total_tiles, int max_m, hipStream_t s) {
   typedef typename dev_elem<R>::E E;
   const size_t lds = ((size_t)1 << max_m) * sizeof(E);
   static size_t attr = 0;
   static uint64_t resident[17] = {};
   if (lds > attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_pass_batch<R, WB>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_pass_batch<R, WB, LP>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr = lds;
   }
   if (total_tiles == 0) return hipSuccess;
-  if (!resident[max_m]) resident_blocks(k_pass_batch<R, WB>, lds, &resident[max_m]);
+  if (!resident[max_m]) resident_blocks(k_pass_batch<R, WB, LP>, lds, &resident[max_m]);
   const uint64_t blocks = total_tiles < resident[max_m] ? total_tiles : resident[max_m];
-  hipLaunchKernelGGL((k_pass_batch<R, WB>), dim3((unsigned)blocks), dim3(kBlock), lds, s, items, count, total_tiles);
+  hipLaunchKernelGGL((k_pass_batch<R, WB, LP>), dim3((unsigned)blocks), dim3(kBlock), lds, s, items, count, total_tiles);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* passes, int pass,
-                       const PassStageDev* stages, const PassOpDev* ops, const void* mats, hipStream_t s) {
-  if (dt == SV_C128) return run<double, 3>(psi, n, m, passes, pass, stages, ops, mats, s);
-  return run<float, 4>(psi, n, m, passes, pass, stages, ops, mats, s);
+                       const PassStageDev* stages, const PassOpDev* ops, const void* mats, bool ladders,
+                       hipStream_t s) {
+  if (dt == SV_C128)
+    return ladders ? run<double, 3, true>(psi, n, m, passes, pass, stages, ops, mats, s)
+                   : run<double, 3, false>(psi, n, m, passes, pass, stages, ops, mats, s);
+  return ladders ? run<float, 4, true>(psi, n, m, passes, pass, stages, ops, mats, s)
+                 : run<float, 4, false>(psi, n, m, passes, pass, stages, ops, mats, s);
 }
 
 hipError_t launch_pass_batch(sv_dtype dt, const BatchItemDev* items, int count, uint64_t total_tiles, int max_m,
-                             hipStream_t s) {
-  if (dt == SV_C128) return run_batch<double, 3>(items, count, total_tiles, max_m, s);
-  return run_batch<float, 4>(items, count, total_tiles, max_m, s);
+                             bool ladders, hipStream_t s) {
+  if (dt == SV_C128)
+    return ladders ? run_batch<double, 3, true>(items, count, total_tiles, max_m, s)
+                   : run_batch<double, 3, false>(items, count, total_tiles, max_m, s);
+  return ladders ? run_batch<float, 4, true>(items, count, total_tiles, max_m, s)
+                 : run_batch<float, 4, false>(items, count, total_tiles, max_m, s);
 }
 
 }  // namespace sv

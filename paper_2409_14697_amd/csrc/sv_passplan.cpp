@@ -6,11 +6,35 @@
 // relabelings, and the map is brought back to the identity by permutations
 // fused into tile write-backs.  Host only.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "sv_host.h"
 
 namespace sv {
+
+void write_pool(unsigned char* dst, const cd* m, const uint8_t* raw, size_t count, bool f32) {
+  for (size_t e = 0; e < count; ++e) {
+    if (raw && raw[e]) {
+      uint64_t w[2];
+      const double re = m[e].real(), im = m[e].imag();
+      std::memcpy(&w[0], &re, sizeof re);
+      std::memcpy(&w[1], &im, sizeof im);
+      if (f32) {
+        const uint32_t v[2] = {(uint32_t)w[0], (uint32_t)w[1]};
+        std::memcpy(dst + 8 * e, v, 8);
+      } else {
+        std::memcpy(dst + 16 * e, w, 16);
+      }
+    } else if (f32) {
+      const float v[2] = {(float)m[e].real(), (float)m[e].imag()};
+      std::memcpy(dst + 8 * e, v, 8);
+    } else {
+      const double v[2] = {m[e].real(), m[e].imag()};
+      std::memcpy(dst + 16 * e, v, 16);
+    }
+  }
+}
 
 int default_lds_qubits(sv_dtype dt) { return dt == SV_C128 ? 12 : 13; }  // 64 KiB tiles
 int default_pinned_bits(sv_dtype dt) { return dt == SV_C128 ? 3 : 4; }   // 128-byte runs
@@ -49,6 +73,7 @@ double op_flops(const PassOpDev& od) {
     case POP_P1: return od.lmask ? 8.0 : 3.0;  // a per-lane predicate costs register copies
     case POP_P2: return 1.5;
     case POP_X: return od.lmask ? 6.0 : 1.0;
+    case POP_LP: return 14.0;
     default: return 1.0;
   }
 }
@@ -63,6 +88,12 @@ bool all_real(const cd* m, int count) {
 bool real_diag_imag_offdiag(const cd* m) {
   return m[0].imag() == 0.0 && m[3].imag() == 0.0 && m[1].real() == 0.0 && m[2].real() == 0.0;
 }
+
+static_assert(kPassLPTileBits >= SV_MAX_QUBITS, "every physical qubit has a ladder word");
+
+// Shortest run of phases worth one ladder op (its fixed cost is a few
+// single phases).
+constexpr int kLadderMin = 3;
 
 struct StageBuilder {
   const int* loc;  // physical bit -> local bit, or -1
@@ -88,12 +119,99 @@ struct StageBuilder {
     else od->tmask |= 1ull << physq;
   }
 
+  // Register bit j such that `op` multiplies the amplitudes whose qubit j is
+  // 1 by a unit phase that depends on at most one other qubit (a phase gate
+  // on j, or a controlled phase on (j, k)); candidates as a bit set over the
+  // register bits, 0 if none.
+  uint32_t ladder_targets(const Op& op) const {
+    if (!is_diag(op)) return 0;
+    const cd one(1.0, 0.0);
+    if (op.nq == 1) {
+      const int b = reg(op.q[0]);
+      return b >= 0 && op.m[0] == one && std::abs(std::abs(op.m[3]) - 1.0) < 1e-14 ? 1u << b : 0u;
+    }
+    if (op.nq != 2) return 0;
+    if (!(op.m[0] == one && op.m[5] == one && op.m[10] == one) || std::abs(std::abs(op.m[15]) - 1.0) >= 1e-14)
+      return 0;
+    uint32_t t = 0;
+    for (int i = 0; i < 2; ++i) {
+      const int b = reg(op.q[i]);
+      if (b >= 0) t |= 1u << b;
+    }
+    return t;
+  }
+
+  // One POP_LP op for ops[first, first + count) on register bit j: the
+  // partners outside the registers and the phase gates become angle words;
+  // partners in the registers become P2 ops (all of them commute).
+  void encode_ladder(StageHost* sh, size_t first, size_t count, int j) {
+    uint64_t words[kPassLPWords] = {};
+    const bool f32 = rb == pass_reg_bits(SV_C64);
+    auto add_angle = [&](int idx, const cd& e) {
+      // fixed-point turns modulo one turn, W = 32 (complex64) or 64 bits
+      double t = std::arg(e) / (2.0 * M_PI);
+      t -= std::floor(t);
+      const uint64_t w = f32 ? (uint64_t)(uint32_t)(uint64_t)std::llround(std::ldexp(t, 32))
+                             : (uint64_t)std::ldexp(t, 63) * 2u;
+      words[idx] = f32 ? (words[idx] + w) & 0xffffffffull : words[idx] + w;
+    };
+    PassOpDev od{};
+    od.type = POP_LP;
+    od.b0 = (uint32_t)j;
+    od.sa = od.sb = kPassNoSel;
+    od.mat = (uint32_t)sh->mats.size();
+    std::vector<Op> reg_pairs;
+    for (size_t i = first; i < first + count; ++i) {
+      const Op& op = ops[i];
+      if (op.nq == 1) {
+        add_angle(kPassLPConst, op.m[3]);
+        continue;
+      }
+      const int k = reg(op.q[0]) == j ? op.q[1] : op.q[0];  // the other qubit (physical)
+      const int l = loc[k];
+      if (reg(k) >= 0) {
+        reg_pairs.push_back(op);
+      } else if (l >= 0) {
+        add_angle(l, op.m[15]);
+        od.lmask |= 1u << l;
+      } else {
+        add_angle(kPassLPLocalBits + k, op.m[15]);
+        od.tmask |= 1ull << k;
+      }
+    }
+    for (int w = 0; w < kPassLPWords; w += 2) {
+      double re, im;
+      std::memcpy(&re, &words[w], sizeof re);
+      std::memcpy(&im, &words[w + 1], sizeof im);
+      sh->mats.push_back(cd(re, im));
+      sh->raw.push_back(1);
+    }
+    sh->ops.push_back(od);
+    for (const Op& op : reg_pairs) encode_op(sh, op);
+  }
+
   void encode(StageHost* sh) {
     // pad the register bits with the lowest unused local bits
     for (int l = 0; (int)qs.size() < rb && l < m; ++l)
       if (std::find(qs.begin(), qs.end(), l) == qs.end()) qs.push_back(l);
     for (int r = 0; r < rb; ++r) sh->q[r] = (uint32_t)qs[r];
-    for (const Op& op : ops) {
+    for (size_t i = 0; i < ops.size();) {
+      // a run of phases that share one register qubit becomes one ladder op
+      uint32_t t = ladder_targets(ops[i]);
+      size_t e = i;
+      while (t && e + 1 < ops.size() && (t & ladder_targets(ops[e + 1]))) t &= ladder_targets(ops[++e]);
+      if (t && e + 1 - i >= (size_t)kLadderMin) {
+        encode_ladder(sh, i, e + 1 - i, __builtin_ctz(t));
+        i = e + 1;
+        continue;
+      }
+      encode_op(sh, ops[i]);
+      ++i;
+    }
+  }
+
+  void encode_op(StageHost* sh, const Op& op) {
+    {
       PassOpDev od{};
       od.sa = od.sb = kPassNoSel;
       od.mat = (uint32_t)sh->mats.size();
@@ -196,6 +314,7 @@ struct StageBuilder {
         mv.assign(op.m.begin(), op.m.begin() + 16);
       }
       sh->mats.insert(sh->mats.end(), mv.begin(), mv.end());
+      sh->raw.insert(sh->raw.end(), mv.size(), 0);
       sh->ops.push_back(od);
     }
   }

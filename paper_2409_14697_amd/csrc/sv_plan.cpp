@@ -206,20 +206,10 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
   // One upload: dense matrices (state precision), then the tile-pass program.
   std::vector<unsigned char> host;
   auto align = [&](size_t a) { host.resize((host.size() + a - 1) / a * a); };
-  auto put_cd = [&](const cd* m, size_t count) {
+  auto put_cd = [&](const cd* m, size_t count, const uint8_t* raw = nullptr) {
     const size_t at = host.size();
     host.resize(at + count * 2 * scal);
-    for (size_t e = 0; e < count; ++e) {
-      if (f32) {
-        float* d = (float*)(host.data() + at);
-        d[2 * e] = (float)m[e].real();
-        d[2 * e + 1] = (float)m[e].imag();
-      } else {
-        double* d = (double*)(host.data() + at);
-        d[2 * e] = m[e].real();
-        d[2 * e + 1] = m[e].imag();
-      }
-    }
+    write_pool(host.data() + at, m, raw, count, f32);
     return at;
   };
   std::vector<size_t> dense_off(p->passes.size(), 0);
@@ -228,6 +218,7 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
   std::vector<PassStageDev> stages;
   std::vector<PassOpDev> pops;
   std::vector<cd> pool;
+  std::vector<uint8_t> pool_raw;
   for (size_t i = 0; i < p->passes.size(); ++i) {
     const Pass& ps = p->passes[i];
     if (ps.kind == PASS_DENSE) {
@@ -260,6 +251,7 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
           pops.push_back(od);
         }
         pool.insert(pool.end(), sh.mats.begin(), sh.mats.end());
+        pool_raw.insert(pool_raw.end(), sh.raw.begin(), sh.raw.end());
         stages.push_back(sd);
       }
       desc_index[i] = (int)descs.size();
@@ -280,7 +272,7 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
     off_ops = host.size();
     host.insert(host.end(), (const unsigned char*)pops.data(), (const unsigned char*)(pops.data() + pops.size()));
     align(256);
-    off_pool = pool.empty() ? host.size() : put_cd(pool.data(), pool.size());
+    off_pool = pool.empty() ? host.size() : put_cd(pool.data(), pool.size(), pool_raw.data());
   }
   void* dev = nullptr;
   if (!host.empty()) {
@@ -307,7 +299,7 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
     } else {
       SV_HIP_TRY(launch_pass(s->dt, s->ptr, s->n, ps.n_local, (const PassDescDev*)(db + off_desc), desc_index[i],
                              (const PassStageDev*)(db + off_stage), (const PassOpDev*)(db + off_ops),
-                             db + off_pool, s->stream));
+                             db + off_pool, pass_has_ladders(ps), s->stream));
     }
   }
   if (renorm > 0 && since > 0) return renormalize(s);

@@ -32,8 +32,21 @@ enum PassOpType : uint32_t {
   POP_UI = 8,  // 2x2 with real diagonal and imaginary off-diagonal
                // on register bit b0 (RX)                        (4 entries: re, im, im, re used)
   POP_P1 = 9,  // phase on the amplitudes whose bit b0 is 1     (1 entry)
-  POP_P2 = 10  // phase on the amplitudes whose bits b0, b1 are 1 (1 entry)
+  POP_P2 = 10, // phase on the amplitudes whose bits b0, b1 are 1 (1 entry)
+  POP_LP = 11  // phase ladder on register bit b0 (a run of controlled phases that
+               // share one qubit): the amplitudes whose bit b0 is 1 are
+               // multiplied by exp(2 pi i t / 2^W), t = the constant word plus
+               // the angle words of the set source bits (W-bit fixed-point
+               // turns, summed modulo one turn; W = 32 for complex64, 64 for
+               // complex128).  Entries: kPassLPWords words, two per entry:
+               // local bits 0..15, tile physical bits 0..kPassLPTileBits-1,
+               // the constant.  lmask / tmask name the source bits with a
+               // nonzero word (for this op they are not predicates).
 };
+constexpr int kPassLPLocalBits = 16;
+constexpr int kPassLPTileBits = 34;
+constexpr int kPassLPConst = kPassLPLocalBits + kPassLPTileBits;  // word of the constant angle
+constexpr int kPassLPWords = kPassLPConst + 2;                    // (even: whole entries)
 constexpr uint32_t kPassNoSel = 0xffffffffu;
 constexpr uint32_t kPassTileSel = 64;  // select codes >= 64 name tile (non-local) physical bits
 
@@ -76,12 +89,16 @@ struct alignas(16) BatchItemDev {
 };
 
 // Run pass items[i].pass of every item in one launch (all items share dt).
+// ladders: some item's pass holds POP_LP ops (selects the kernel variant that
+// decodes them; the other variant carries none of their code).
 hipError_t launch_pass_batch(sv_dtype dt, const BatchItemDev* items, int count, uint64_t total_tiles, int max_m,
-                             hipStream_t s);
+                             bool ladders, hipStream_t s);
 
-// Launch pass `pass` of a program already resident in device memory.
+// Launch pass `pass` of a program already resident in device memory
+// (ladders: the pass holds POP_LP ops).
 hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* passes, int pass,
-                       const PassStageDev* stages, const PassOpDev* ops, const void* mats, hipStream_t s);
+                       const PassStageDev* stages, const PassOpDev* ops, const void* mats, bool ladders,
+                       hipStream_t s);
 
 // --- dense k-qubit fused gate (3 <= k <= 6) ---------------------------------
 // m_dev: device copy of the 2^k x 2^k matrix, row-major interleaved, in the

@@ -59,6 +59,43 @@ def test_pass_mode_circuits(sv, dtype, lds, circuit):
     assert max_err(out, ref) <= TOL[dtype]
 
 
+def ladder_circuit(n, seed):
+    """Runs of phases that share one qubit (the QFT's controlled-phase
+    ladders, generalised): random angles, CPHASE / CZ with the shared qubit on
+    either side and the other qubit anywhere, phase gates on the shared qubit,
+    runs of 1-20 broken by H / RX gates."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(12):
+        j = int(rng.integers(n))
+        out.append(Gate("H", (j,)))
+        for _ in range(int(rng.integers(1, 21))):
+            r = rng.random()
+            if r < 0.15:
+                out.append(Gate("P", (j,), float(rng.uniform(-7, 7))))
+            elif r < 0.25:
+                k = int(rng.choice([q for q in range(n) if q != j]))
+                out.append(Gate("CZ", (j, k) if rng.random() < 0.5 else (k, j)))
+            else:
+                k = int(rng.choice([q for q in range(n) if q != j]))
+                out.append(Gate("CPHASE", (j, k) if rng.random() < 0.5 else (k, j), float(rng.uniform(-7, 7))))
+        out.append(Gate("RX", (int(rng.integers(n)),), float(rng.uniform(0, 6))))
+    return out
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("lds", [0, 7, 10])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_phase_ladders(sv, dtype, lds, seed):
+    """Phase ladders (one fixed-point angle sum per lane and tile) against the
+    oracle, with the shared qubit's partners in registers, in the tile and
+    outside it."""
+    n = 15
+    gates = ladder_circuit(n, seed)
+    out, ref = run_plan(sv, n, dtype, gaussian_state_np(n, 30 + seed), gates, {"mode": "pass", "lds_qubits": lds})
+    assert max_err(out, ref) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_pass_whole_state_tile(sv, dtype):
     """N at or below the tile size: one tile holds the whole state."""
