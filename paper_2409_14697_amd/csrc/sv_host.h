@@ -88,6 +88,11 @@ struct Pass {
   std::vector<StageHost> stages;
 };
 
+// Fill a pass descriptor's local-bit maps and store flags (lmask, lpos, wpos,
+// winv, flags); false if the write positions are not a permutation of the
+// load positions.
+bool fill_pass_maps(const Pass& ps, sv_dtype dt, PassDescDev* d);
+
 // The pass's stages hold phase-ladder ops (POP_LP).
 inline bool pass_has_ladders(const Pass& ps) {
   for (const StageHost& sh : ps.stages)

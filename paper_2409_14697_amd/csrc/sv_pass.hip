@@ -454,6 +454,11 @@ __device__ __forceinline__ uint64_t batch_bits(const uint64_t* h) {
   return ((U & 1) ? h[0] : 0ull) | ((U & 2) ? h[1] : 0ull) | ((U & 4) ? h[2] : 0ull) | ((U & 8) ? h[3] : 0ull);
 }
 
+template <int U>
+__device__ __forceinline__ uint32_t batch_bits32(const uint32_t* h) {
+  return ((U & 1) ? h[0] : 0u) | ((U & 2) ? h[1] : 0u) | ((U & 4) ? h[2] : 0u) | ((U & 8) ? h[3] : 0u);
+}
+
 // Everything a lane needs to move one tile: the pass, the state, the tile's
 // base index and the uniform offsets of its element counter.
 template <typename R>
@@ -617,56 +622,70 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
 
 }
 
-// Store the tile: local bit j goes to physical position wpos[j]; complex64
-// pairs stay 16-byte elements when local bit 0 is written back to bit 0.
+// Store the tile: local bit j goes to physical position wpos[j], a
+// permutation of the positions the tile was loaded from.  When the lowest
+// element bits keep their positions lanes walk the tile in load order;
+// otherwise they walk the destination addresses in the load's order (the
+// same coalesced runs and 16-byte elements whatever the permutation) and
+// gather each element from LDS: the element's k-th address bit holds local
+// bit winv[k].
 template <typename R, int WB>
 __device__ __forceinline__ void tile_store(const TileRef<R>& T, const typename dev_elem<R>::E* tile) {
   typedef typename dev_elem<R>::E E;
   typedef typename gelem<R>::G G;
   constexpr int LB = gelem<R>::LB;
   const cptr<PassDescDev> P = T.P;
-  const LaneGeo lg = lane_geo<LB>(P->m);
+  const uint32_t m = P->m;
+  const LaneGeo lg = lane_geo<LB>(m);
   const gptr<G> gpsi = as_global(reinterpret_cast<G*>(T.psi));
-  const gptr<E> epsi = as_global(T.psi);
-  const bool pair_store = LB == 0 || P->wpos[0] == 0;
-  const uint64_t lo = T.base | lane_bits<LB>(P->wpos, P->m);
+  const uint64_t a0 = T.base | lane_bits<LB>(P->lpos, m);
   PassOffsets po;
   pass_offsets<LB>(P, &po);
-  {
-    constexpr uint32_t j0 = 0;
-    const uint64_t a0 = lo;
-    G buf[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (j0 + u < lg.per && lg.on) {
-        const uint32_t x = (threadIdx.x + (j0 + u) * kBlock) << LB;
-        if constexpr (LB == 1) {
-          const E e0 = tile[swz<WB>(x)], e1 = tile[swz<WB>(x | 1u)];
-          buf[u] = G{e0.x, e0.y, e1.x, e1.y};
-        } else {
-          buf[u] = tile[swz<WB>(x)];
-        }
-      }
-    if (pair_store) {
-#define SV_ST(U) \
-      if (j0 + U < lg.per && lg.on) stg<G>(gpsi + ((a0 | batch_bits<U>(po.out)) >> LB), buf[U]);
-      SV_ST(0) SV_ST(1) SV_ST(2) SV_ST(3) SV_ST(4) SV_ST(5) SV_ST(6) SV_ST(7)
-      SV_ST(8) SV_ST(9) SV_ST(10) SV_ST(11) SV_ST(12) SV_ST(13) SV_ST(14) SV_ST(15)
-#undef SV_ST
-    } else if constexpr (LB == 1) {
-      // the pair splits: amplitude x | 1 goes to bit wpos[0]
-      const uint64_t b0 = 1ull << P->wpos[0];
-#define SV_ST2(U)                                                   \
-      if (j0 + U < lg.per && lg.on) {                               \
-        const uint64_t ad = a0 | batch_bits<U>(po.out);             \
-        stg<E>(epsi + ad, E{buf[U].x, buf[U].y});                   \
-        stg<E>(epsi + (ad | b0), E{buf[U].z, buf[U].w});            \
-      }
-      SV_ST2(0) SV_ST2(1) SV_ST2(2) SV_ST2(3) SV_ST2(4) SV_ST2(5) SV_ST2(6) SV_ST2(7)
-      SV_ST2(8) SV_ST2(9) SV_ST2(10) SV_ST2(11) SV_ST2(12) SV_ST2(13) SV_ST2(14) SV_ST2(15)
-#undef SV_ST2
+  if (P->flags & kPassStoreLaneOrder) {  // load order: the low element bits stay in place
+    const uint64_t w0 = T.base | lane_bits<LB>(P->wpos, m);
+#define SV_ST(U)                                                                       \
+    if (U < lg.per && lg.on) {                                                         \
+      const uint32_t x = (threadIdx.x + U * kBlock) << LB;                             \
+      G g;                                                                             \
+      if constexpr (LB == 1) {                                                         \
+        const E e0 = tile[swz<WB>(x)], e1 = tile[swz<WB>(x | 1u)];                     \
+        g = G{e0.x, e0.y, e1.x, e1.y};                                                 \
+      } else {                                                                         \
+        g = tile[swz<WB>(x)];                                                          \
+      }                                                                                \
+      stg<G>(gpsi + ((w0 | batch_bits<U>(po.out)) >> LB), g);                          \
     }
+    SV_ST(0) SV_ST(1) SV_ST(2) SV_ST(3) SV_ST(4) SV_ST(5) SV_ST(6) SV_ST(7)
+    SV_ST(8) SV_ST(9) SV_ST(10) SV_ST(11) SV_ST(12) SV_ST(13) SV_ST(14) SV_ST(15)
+#undef SV_ST
+    return;
   }
+  // LDS index of the lane's element: lane bit j is address bit LB + j
+  uint32_t xl = 0;
+  for (uint32_t jb = 0; jb < 8 && LB + jb < m; ++jb)
+    if ((threadIdx.x >> jb) & 1u) xl |= 1u << P->winv[LB + jb];
+  uint32_t xo[4];  // LDS offsets of the batch bits
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const uint32_t k = LB + 8 + b;
+    xo[b] = k < m ? 1u << P->winv[k] : 0u;
+  }
+  const uint32_t xp = LB ? 1u << P->winv[0] : 0u;  // the element's second amplitude (complex64)
+#define SV_ST(U)                                                                       \
+  if (U < lg.per && lg.on) {                                                           \
+    const uint32_t x = xl | batch_bits32<U>(xo);                                       \
+    G g;                                                                               \
+    if constexpr (LB == 1) {                                                           \
+      const E e0 = tile[swz<WB>(x)], e1 = tile[swz<WB>(x | xp)];                       \
+      g = G{e0.x, e0.y, e1.x, e1.y};                                                   \
+    } else {                                                                           \
+      g = tile[swz<WB>(x)];                                                            \
+    }                                                                                  \
+    stg<G>(gpsi + ((a0 | batch_bits<U>(po.in)) >> LB), g);                             \
+  }
+  SV_ST(0) SV_ST(1) SV_ST(2) SV_ST(3) SV_ST(4) SV_ST(5) SV_ST(6) SV_ST(7)
+  SV_ST(8) SV_ST(9) SV_ST(10) SV_ST(11) SV_ST(12) SV_ST(13) SV_ST(14) SV_ST(15)
+#undef SV_ST
 }
 
 // Persistent loop over tiles, software-pipelined: the next tile's loads are

@@ -36,6 +36,31 @@ void write_pool(unsigned char* dst, const cd* m, const uint8_t* raw, size_t coun
   }
 }
 
+bool fill_pass_maps(const Pass& ps, sv_dtype dt, PassDescDev* d) {
+  d->lmask = 0;
+  d->flags = kPassStoreLaneOrder;
+  // local bits inside the lowest three 16-byte element bits (complex64
+  // elements hold local bit 0 as well)
+  const int low = dt == SV_C64 ? 4 : 3;
+  for (int j = 0; j < ps.n_local; ++j) {
+    d->lpos[j] = ps.lpos[j];
+    d->wpos[j] = ps.wpos[j];
+    d->lmask |= 1ull << ps.lpos[j];
+    if (j < low && ps.wpos[j] != ps.lpos[j]) d->flags &= ~kPassStoreLaneOrder;
+  }
+  for (int k = 0; k < ps.n_local; ++k) {
+    int found = -1, count = 0;
+    for (int j = 0; j < ps.n_local; ++j)
+      if (ps.wpos[j] == ps.lpos[k]) {
+        found = j;
+        ++count;
+      }
+    if (count != 1) return false;
+    d->winv[k] = (uint32_t)found;
+  }
+  return true;
+}
+
 int default_lds_qubits(sv_dtype dt) { return dt == SV_C128 ? 12 : 13; }  // 64 KiB tiles
 int default_pinned_bits(sv_dtype dt) { return dt == SV_C128 ? 3 : 4; }   // 128-byte runs
 

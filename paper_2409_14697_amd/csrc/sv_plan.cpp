@@ -229,12 +229,7 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
       d.m = (uint32_t)ps.n_local;
       d.stage_first = (uint32_t)stages.size();
       d.stage_count = (uint32_t)ps.stages.size();
-      d.lmask = 0;
-      for (int j = 0; j < ps.n_local; ++j) {
-        d.lpos[j] = ps.lpos[j];
-        d.wpos[j] = ps.wpos[j];
-        d.lmask |= 1ull << ps.lpos[j];
-      }
+      if (!fill_pass_maps(ps, s->dt, &d)) return fail(SV_ERR_UNSUPPORTED, "internal: pass write map is not a permutation");
       for (const StageHost& sh : ps.stages) {
         PassStageDev sd{};
         const int rb = pass_reg_bits(s->dt);

@@ -67,13 +67,19 @@ struct PassStageDev {
   uint32_t op_first, op_count;
 };
 
+// PassDescDev flag: the store can walk the tile in load order (the lowest
+// three 16-byte element bits keep their positions, so every run of 8 lanes
+// still writes 128 contiguous bytes); otherwise it walks destination order.
+constexpr uint32_t kPassStoreLaneOrder = 1;
+
 struct alignas(16) PassDescDev {
   uint32_t m;                    // local bits per tile
   uint32_t stage_first, stage_count;
-  uint32_t pad;
+  uint32_t flags;                // kPassStoreLaneOrder
   uint64_t lmask;                // physical mask of the local bits
   uint32_t lpos[16];             // physical position of local bit j on load (ascending)
-  uint32_t wpos[16];             // physical position of local bit j on store
+  uint32_t wpos[16];             // physical position of local bit j on store (a permutation of lpos)
+  uint32_t winv[16];             // local bit stored to position lpos[k] (wpos[winv[k]] = lpos[k])
 };
 
 // One state in a batched pass launch (device-resident array).
