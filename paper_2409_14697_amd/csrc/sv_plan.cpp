@@ -135,7 +135,27 @@ std::vector<Op> fuse_ops(std::vector<Op> in, int n, sv_dtype dt, int kmax, bool 
     const int idx = (int)out.size() - 1;
     for (int j = 0; j < out.back().nq; ++j) last[out.back().q[j]] = idx;
   }
-  return out;
+  if (width < 2) return out;
+  // Forward pass: an op whose qubits all belong to the next op that touches
+  // any of them commutes with everything in between and joins that op (the
+  // greedy pass above only merges into the previous op).  Reverse order lets
+  // merges chain.
+  std::vector<char> gone(out.size(), 0);
+  for (int i = (int)out.size() - 2; i >= 0; --i) {
+    int j = i + 1;
+    while (j < (int)out.size() && (gone[j] || union_size(out[j], out[i]) == out[j].nq + out[i].nq)) ++j;
+    if (j == (int)out.size() || union_size(out[j], out[i]) != out[j].nq) continue;
+    Op m = merged(out[i], out[j]);
+    if (sweep_cost(m, dt, mfma) <= sweep_cost(out[i], dt, mfma) + sweep_cost(out[j], dt, mfma) + 1e-12) {
+      out[j] = std::move(m);
+      gone[i] = 1;
+    }
+  }
+  std::vector<Op> kept;
+  kept.reserve(out.size());
+  for (size_t i = 0; i < out.size(); ++i)
+    if (!gone[i]) kept.push_back(std::move(out[i]));
+  return kept;
 }
 
 double op_sweep_cost(const Op& op, sv_dtype dt, bool mfma) { return sweep_cost(op, dt, mfma); }

@@ -90,6 +90,22 @@ def test_fusion_plan_replays_circuit(kmax, dtype):
         assert 0 <= ps < n_passes
 
 
+@pytest.mark.parametrize("kmax", [2, 3, 5])
+def test_forward_merge_replays_brickwork(kmax):
+    """Ops that join a later op holding all their qubits (brickwork: the first
+    rotations before each CNOT pair) still reproduce the circuit, and no
+    single-qubit op is left once fusion may span a CNOT pair."""
+    n = 11
+    gates = brickwork_circuit(n, 8, seed=5)
+    plan = B.Plan(n, "c128", gates, {"max_fuse_qubits": kmax, "mode": "sweep"})
+    psi = gaussian_state_np(n, 6)
+    ref = oracle.run(gates, psi0=psi)
+    assert np.max(np.abs(_replay(plan, n, psi) - ref)) < 1e-13
+    sizes = [len(q) for q, _, _ in plan.export()]
+    assert all(k <= kmax for k in sizes)
+    assert 1 not in sizes
+
+
 def test_fusion_reduces_ops():
     gates = brickwork_circuit(12, 6, seed=3)
     n5 = B.Plan(12, "c128", gates, {"max_fuse_qubits": 5, "mode": "sweep"}).info()[0]
