@@ -391,6 +391,11 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, u
 #undef F
       break;
     }
+    case POP_DR: {
+#pragma unroll
+      for (int r = 0; r < Regs<R>::NR; ++r) v[r] = cmul(cget(M, r), v[r]);
+      break;
+    }
     case POP_DG: {
       cplx<R> p = cget(M, 0);
       if (op.sa != kPassNoSel) {

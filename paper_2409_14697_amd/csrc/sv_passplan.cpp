@@ -99,6 +99,7 @@ double op_flops(const PassOpDev& od) {
     case POP_P2: return 1.5;
     case POP_X: return od.lmask ? 6.0 : 1.0;
     case POP_LP: return 14.0;
+    case POP_DR: return 8.0;
     default: return 1.0;
   }
 }
@@ -166,6 +167,36 @@ struct StageBuilder {
     return t;
   }
 
+  // A diagonal op whose qubits are all register bits (a factor per register
+  // index).
+  bool reg_diag(const Op& op) const {
+    if (!is_diag(op)) return false;
+    for (int i = 0; i < op.nq; ++i)
+      if (reg(op.q[i]) < 0) return false;
+    return true;
+  }
+
+  // One POP_DR op: the product of the register-diagonal ops `run`.
+  void encode_reg_diag(StageHost* sh, const std::vector<const Op*>& run) {
+    const int nr = 1 << rb;
+    std::vector<cd> d(nr, cd(1.0, 0.0));
+    for (const Op* op : run) {
+      const int dim = 1 << op->nq;
+      for (int r = 0; r < nr; ++r) {
+        int idx = 0;  // the op's local index: q[0] is its most significant bit
+        for (int i = 0; i < op->nq; ++i) idx = (idx << 1) | ((r >> reg(op->q[i])) & 1);
+        d[r] *= op->m[(size_t)idx * dim + idx];
+      }
+    }
+    PassOpDev od{};
+    od.type = POP_DR;
+    od.sa = od.sb = kPassNoSel;
+    od.mat = (uint32_t)sh->mats.size();
+    sh->mats.insert(sh->mats.end(), d.begin(), d.end());
+    sh->raw.insert(sh->raw.end(), d.size(), 0);
+    sh->ops.push_back(od);
+  }
+
   // One POP_LP op for ops[first, first + count) on register bit j: the
   // partners outside the registers and the phase gates become angle words;
   // partners in the registers become P2 ops (all of them commute).
@@ -212,7 +243,13 @@ struct StageBuilder {
       sh->raw.push_back(1);
     }
     sh->ops.push_back(od);
-    for (const Op& op : reg_pairs) encode_op(sh, op);
+    if (reg_pairs.size() >= 2) {
+      std::vector<const Op*> run;
+      for (const Op& op : reg_pairs) run.push_back(&op);
+      encode_reg_diag(sh, run);
+    } else {
+      for (const Op& op : reg_pairs) encode_op(sh, op);
+    }
   }
 
   void encode(StageHost* sh) {
@@ -228,6 +265,17 @@ struct StageBuilder {
       if (t && e + 1 - i >= (size_t)kLadderMin) {
         encode_ladder(sh, i, e + 1 - i, __builtin_ctz(t));
         i = e + 1;
+        continue;
+      }
+      // a run of diagonal gates on register bits becomes one factor per
+      // register index
+      size_t f = i;
+      while (f < ops.size() && reg_diag(ops[f])) ++f;
+      if (f - i >= 2) {
+        std::vector<const Op*> run;
+        for (size_t x = i; x < f; ++x) run.push_back(&ops[x]);
+        encode_reg_diag(sh, run);
+        i = f;
         continue;
       }
       encode_op(sh, ops[i]);

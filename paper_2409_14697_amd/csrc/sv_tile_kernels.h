@@ -33,7 +33,7 @@ enum PassOpType : uint32_t {
                // on register bit b0 (RX)                        (4 entries: re, im, im, re used)
   POP_P1 = 9,  // phase on the amplitudes whose bit b0 is 1     (1 entry)
   POP_P2 = 10, // phase on the amplitudes whose bits b0, b1 are 1 (1 entry)
-  POP_LP = 11  // phase ladder on register bit b0 (a run of controlled phases that
+  POP_LP = 11, // phase ladder on register bit b0 (a run of controlled phases that
                // share one qubit): the amplitudes whose bit b0 is 1 are
                // multiplied by exp(2 pi i t / 2^W), t = the constant word plus
                // the angle words of the set source bits (W-bit fixed-point
@@ -42,6 +42,8 @@ enum PassOpType : uint32_t {
                // local bits 0..15, tile physical bits 0..kPassLPTileBits-1,
                // the constant.  lmask / tmask name the source bits with a
                // nonzero word (for this op they are not predicates).
+  POP_DR = 12  // diagonal over the register index: amplitude r times d[r]
+               // (NR entries; a run of diagonal gates on register bits)
 };
 constexpr int kPassLPLocalBits = 16;
 constexpr int kPassLPTileBits = 34;

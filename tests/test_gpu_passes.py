@@ -83,6 +83,35 @@ def ladder_circuit(n, seed):
     return out
 
 
+def diagonal_run_circuit(n, seed):
+    """Dense gates on a few qubits, then runs of diagonal gates among the same
+    qubits (register bits of the stage): CZ, CPHASE, RZZ, RZ, Z, S, T, P."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(10):
+        qs = [int(x) for x in rng.choice(n, 5, replace=False)]
+        out += [Gate("RY", (q,), float(rng.uniform(0, 6))) for q in qs]
+        for _ in range(int(rng.integers(2, 12))):
+            kind = ["CZ", "CPHASE", "RZZ", "RZ", "Z", "S", "T", "P"][int(rng.integers(8))]
+            if kind in ("CZ", "CPHASE", "RZZ"):
+                a, b = (int(x) for x in rng.choice(qs, 2, replace=False))
+                out.append(Gate(kind, (a, b), float(rng.uniform(-7, 7))))
+            else:
+                out.append(Gate(kind, (int(rng.choice(qs)),), float(rng.uniform(-7, 7))))
+    return out
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("lds", [0, 8])
+def test_register_diagonal_runs(sv, dtype, lds):
+    """Runs of diagonal gates on register bits (one factor per register index)
+    against the oracle."""
+    n = 14
+    gates = diagonal_run_circuit(n, 9)
+    out, ref = run_plan(sv, n, dtype, gaussian_state_np(n, 41), gates, {"mode": "pass", "lds_qubits": lds})
+    assert max_err(out, ref) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("lds", [0, 7, 10])
 @pytest.mark.parametrize("seed", [1, 2])
