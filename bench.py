@@ -428,7 +428,8 @@ def precision_bench(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 10 for gates, the gate benchmark's 10 repetitions; 3 for circuit)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=N_QUBITS)
     ap.add_argument("--dtypes", default="c128,c64")
@@ -453,6 +454,8 @@ def main():
         print("bench.py measures one GPU: the state-vector hot path here runs on a single MI355X "
               "(no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.steps is None:
+        args.steps = 10 if args.workload == "gates" else 3
     if args.workload == "circuit":
         circuit_bench(args)
         return
