@@ -10,8 +10,8 @@ import pytest
 
 import oracle
 from oracle import sv_oracle as so
-from svgen import (Gate, basis_state_np, fused_haar_circuit, gaussian_state_np, haar_unitary, layered_circuit,
-                   qft_circuit)
+from svgen import (Gate, basis_state_np, brickwork_circuit, fused_haar_circuit, gaussian_state_np, haar_unitary,
+                   layered_circuit, qft_circuit)
 from tests.gpu_util import TOL, max_err, to_device, to_host
 
 pytestmark = pytest.mark.gpu
@@ -131,6 +131,29 @@ def test_qft_against_inverse_fft(sv, dtype):
     st.sync()
     ref = math.sqrt(1 << n) * np.fft.ifft(host_in)
     assert max_err(to_host(t), ref) <= TOL[dtype]
+
+
+_BENCH_REF = {}
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("circuit", ["brickwork_d40", "qft"])
+def test_circuit_benchmark_generators_n20(sv, dtype, circuit):
+    """The circuit benchmark's generators (brickwork depth 40, seed 3; QFT) at
+    N=20 in plan mode auto (fused MFMA sweeps, tile passes with phase ladders
+    and register-diagonal runs), against the oracle on a Gaussian state."""
+    n = 20
+    gates = brickwork_circuit(n, 40, seed=3) if circuit == "brickwork_d40" else qft_circuit(n)
+    psi = gaussian_state_np(n, 13)
+    t, host_in = to_device(psi, dtype)
+    key = (circuit, dtype)
+    if key not in _BENCH_REF:
+        _BENCH_REF[key] = oracle.run(gates, psi0=host_in)
+    st = sv.StateVector(n, dtype, tensor=t, init=False)
+    st.apply_circuit(gates, {"mode": "auto"})
+    st.sync()
+    assert max_err(to_host(t), _BENCH_REF[key]) <= TOL[dtype]
+    st.close()
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
