@@ -65,6 +65,55 @@ def test_gate_benchmark_n30_sampled(sv, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_gate_benchmark_n30_repetitions(sv, dtype):
+    """The gate benchmark's repetition closed forms at N=30, on the whole
+    state: X, CNOT and SWAP applied twice return the input bitwise, CZ twice
+    returns it exactly (up to the sign of zero), H twice within the tolerance, and RZ / CPHASE applied 10 times
+    equal one application at 10 times the angle."""
+    import torch
+    n = 30
+    t = gaussian_state_torch(n, 2, torch_dtype(dtype))
+    ref = t.clone()
+    st = sv.StateVector(n, dtype, tensor=t, init=False)
+    tol = TOL[dtype]
+    by_kind = {}
+    for g in gate_bench_set(n, seed=2):
+        by_kind.setdefault(g.kind, []).append(g)
+    for kind in ("X", "CNOT", "CZ", "SWAP", "H"):
+        for g in (by_kind[kind][0], by_kind[kind][n // 2], by_kind[kind][-1]):
+            st.apply_gate(g)
+            st.apply_gate(g)
+            st.sync()
+            if kind == "H":
+                assert float((t - ref).abs().max()) <= tol, g.qubits
+                t.copy_(ref)
+            elif kind == "CZ":
+                # a sign flip through a complex product: exact values, but a
+                # zero component (the complex64 Gaussian state has a few) may
+                # come back as -0
+                assert torch.equal(t, ref), (kind, g.qubits)
+            else:
+                assert torch.equal(t.view(torch.uint8), ref.view(torch.uint8)), (kind, g.qubits)
+    for kind in ("RZ", "CPHASE"):
+        g = by_kind[kind][n // 3]
+        for _ in range(10):
+            st.apply_gate(g)
+        once = ref.clone()
+        so10 = sv.StateVector(n, dtype, tensor=once, init=False)
+        so10.apply_gate(Gate(kind, g.qubits, 10 * g.theta))
+        so10.sync()
+        st.sync()
+        # ten roundings of a phase against one: a few units of the tolerance
+        assert float((t - once).abs().max()) <= 10 * tol, (kind, g.qubits)
+        so10.close()
+        del once
+        t.copy_(ref)
+    st.close()
+    del t, ref
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_dense_k5_k6_n30_sampled(sv, dtype):
     """The precision form's fused gates (k = 5, 6; FP64 MFMA for complex128,
     FP32 MFMA for complex64) at N=30, on sampled groups, with low, high and
