@@ -199,7 +199,8 @@ struct StageBuilder {
 
   // One POP_LP op for ops[first, first + count) on register bit j: the
   // partners outside the registers and the phase gates become angle words;
-  // partners in the registers become P2 ops (all of them commute).
+  // the gates whose partner is a register bit follow as one POP_DR op (or
+  // their own op when there is only one); all of them commute.
   void encode_ladder(StageHost* sh, size_t first, size_t count, int j) {
     uint64_t words[kPassLPWords] = {};
     const bool f32 = rb == pass_reg_bits(SV_C64);
