@@ -5,6 +5,9 @@ Inputs are the CSV directories of three profiled runs of bench.py:
   --fetch : rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o bench -- python bench.py --steps 1 --warmup 0
             --no-cpu-baseline --copy-ceiling
   --write : the same with --pmc WRITE_SIZE
+Subcommands `trace` (kernel-trace summary of any profiled run) and `mfma`
+(matrix-core utilisation of the dense kernels from a counter run) write
+their own summaries.
 Outputs:
   profiles/gate_sweep_n30.md              per-kernel durations (kernel trace) and
                                           calibrated HBM traffic (counters)
@@ -88,9 +91,66 @@ def trace_summary(argv):
     print(f"wrote {args.out}")
 
 
+SIMDS = 256 * 4        # MI355X: 256 CUs, 4 SIMDs each
+CLOCK_HZ = 2.4e9       # peak engine clock
+MATRIX_PEAK = {"float": 157.3e12, "double": 78.6e12}  # dense MFMA FP32 / FP64
+
+
+def mfma_summary(argv):
+    """Matrix-core utilisation of the dense fused kernels from one counter run:
+    bench_profile.py mfma --dir D --n N --out profiles/NAME.md --title T --cmd "C"
+    where the run collected SQ_VALU_MFMA_BUSY_CYCLES (summed over all SIMDs).
+    Busy fraction = counter / (SIMDs x kernel duration x clock); the algorithmic
+    rate counts 8 * 2^(N+k) real flops per k-qubit gate (the real embedding of
+    the complex product) against the dense matrix peak of the kernel's type."""
+    ap = argparse.ArgumentParser(prog="bench_profile.py mfma")
+    ap.add_argument("--dir", required=True)
+    ap.add_argument("--n", type=int, required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--cmd", required=True)
+    args = ap.parse_args(argv)
+    rows = list(csv.DictReader(open(os.path.join(args.dir, "bench_counter_collection.csv"))))
+    per = defaultdict(lambda: {"busy": [], "dur": []})
+    seen = {}
+    for r in rows:
+        if r["Counter_Name"] != "SQ_VALU_MFMA_BUSY_CYCLES" or "k_dense_mfma" not in r["Kernel_Name"]:
+            continue
+        key = (r["Dispatch_Id"], short(r["Kernel_Name"]))
+        seen.setdefault(key, [0.0, (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9])
+        seen[key][0] += float(r["Counter_Value"])
+    for (_, name), (busy, dur) in seen.items():
+        per[name]["busy"].append(busy)
+        per[name]["dur"].append(dur)
+    lines = [f"# {args.title}: matrix-core utilisation (rocprofv3 counters)", "",
+             "Command (from the repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "```", args.cmd, "```", "",
+             f"Busy = SQ_VALU_MFMA_BUSY_CYCLES / ({SIMDS} SIMDs x duration x {CLOCK_HZ / 1e9:.1f} GHz). Algorithmic = "
+             f"8 * 2^(N+k) flops per gate at N={args.n} / duration, against the dense matrix peak "
+             "(FP32 157.3, FP64 78.6 TFLOP/s).", "",
+             "| kernel | dispatches | avg ms | MFMA busy | algorithmic TFLOP/s | of matrix peak |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for name in sorted(per):
+        d = per[name]
+        k = int(name.split(",")[1].strip(" >"))
+        rtype = name.split("<")[1].split(",")[0].strip()
+        dur = statistics.mean(d["dur"])
+        busy = statistics.mean(b / (SIMDS * t * CLOCK_HZ) for b, t in zip(d["busy"], d["dur"]))
+        tflops = 8.0 * 2.0 ** (args.n + k) / dur / 1e12
+        lines.append(f"| `{name}` | {len(d['dur'])} | {dur * 1e3:.3f} | {busy:.3f} | {tflops:.1f} | "
+                     f"{tflops * 1e12 / MATRIX_PEAK[rtype]:.3f} |")
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {args.out}")
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "trace":
         trace_summary(sys.argv[2:])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "mfma":
+        mfma_summary(sys.argv[2:])
         return
     import bench
     ap = argparse.ArgumentParser()
