@@ -23,15 +23,24 @@ constexpr int kBlock = 256;
 
 // Address map of a tile: tile-local index e has bit j at physical position
 // pos[j] (ascending; 64 = a column bit beyond the state, for states with
-// fewer groups than a tile has columns) and contributes lds[j] to the tile's
-// LDS index member * C + column.  The tile's base deposits the work-block
-// number into `rest`.
+// fewer groups than a tile has columns) and contributes lds[j] (XOR) to the
+// tile's LDS index member * C + column.  The tile's base deposits the
+// work-block number into `rest`.
+// The matrix-core kernels swizzle LDS: the column index is XORed with
+// fm(member) ^ fc[column >> es] (es = log2 of the LDS entries in 256 bytes;
+// fm(member) = XOR of fmb[b] over the set bits b of the member),
+// chosen per gate so that the 64 lanes of a wave, which walk the tile in
+// address order, spread over all banks; a run of 2^es aligned columns of one
+// member stays a permutation of itself, so the matrix-core operand reads and
+// result writes stay conflict-free.  lds[] already holds the swizzle.
 struct DenseGeo {
   uint64_t rest;
   uint32_t nbits;
   uint32_t inv;       // tile-local bits with no physical position
   uint32_t pos[16];
   uint32_t lds[16];
+  uint32_t fmb[6];    // swizzle of member bit b
+  uint32_t fc[16];    // swizzle of column block c (columns c * 2^es ..)
 };
 
 // Per-lane part of the map: tile-local bits LB .. LB+7 come from the lane.
@@ -44,20 +53,23 @@ struct LaneMap {
   bool on;
 };
 
-template <int LB, int TB = 8>
+// X: the LDS weights carry a swizzle and combine by XOR (plain maps have
+// disjoint weights and combine by OR).
+template <int LB, int TB = 8, bool X = false>
 __device__ __forceinline__ LaneMap lane_map(uint32_t t, const DenseGeo& g) {
   LaneMap m{0, 0, ((t << LB) & g.inv) == 0};
 #pragma unroll
   for (int j = 0; j < TB; ++j)
     if ((t >> j) & 1u) {
       if (g.pos[LB + j] < 64) m.addr |= 1ull << g.pos[LB + j];
-      m.lds |= g.lds[LB + j];
+      if constexpr (X) m.lds ^= g.lds[LB + j];
+      else m.lds |= g.lds[LB + j];
     }
   return m;
 }
 
 // Uniform part for element u of a lane (tile-local bits LB+TB ..; TB lane bits).
-template <int LB, int U, int TB = 8>
+template <int LB, int U, int TB = 8, bool X = false>
 __device__ __forceinline__ void elem_map(const DenseGeo& g, uint64_t* addr, uint32_t* lds, bool* on) {
   uint64_t a = 0;
   uint32_t l = 0;
@@ -65,7 +77,8 @@ __device__ __forceinline__ void elem_map(const DenseGeo& g, uint64_t* addr, uint
   for (int b = 0; b < 8; ++b)
     if ((U >> b) & 1) {
       if (g.pos[LB + TB + b] < 64) a |= 1ull << g.pos[LB + TB + b];
-      l |= g.lds[LB + TB + b];
+      if constexpr (X) l ^= g.lds[LB + TB + b];
+      else l |= g.lds[LB + TB + b];
     }
   *addr = a;
   *lds = l;
@@ -210,15 +223,28 @@ struct mfma_shape<float> {
   }
   // member (within the block) written by registers r, r + 1 of lane l (r even)
   static __device__ __forceinline__ int out_member(int l, int r) { return (8 * (r / 4) + 4 * (l / 32) + (r % 4)) >> 1; }
+  // the same for even r, as uniform and per-lane parts (disjoint bits)
+  static __device__ __forceinline__ int out_member_u(int r) { return 4 * (r / 4) + (r % 4) / 2; }
+  static __device__ __forceinline__ int out_member_l(int l) { return 2 * (l / 32); }
   static constexpr int MPB = 16;  // members per row block
-  // global 16-byte element: a complex64 pair (LDS entries li and li | l0)
+  static constexpr int ES = 5;    // log2 of the LDS entries (8 bytes) in 256 bytes
+  // global 16-byte element: a complex64 pair (LDS entries li and li | l0;
+  // li ^ l0 in a swizzled map)
   typedef flt4 G;
   static __device__ __forceinline__ void to_lds(E* xs, uint32_t li, uint32_t l0, G v) {
     xs[li] = E{v.x, v.y};
     xs[li | l0] = E{v.z, v.w};
   }
+  static __device__ __forceinline__ void to_lds_x(E* xs, uint32_t li, uint32_t l0, G v) {
+    xs[li] = E{v.x, v.y};
+    xs[li ^ l0] = E{v.z, v.w};
+  }
   static __device__ __forceinline__ G from_lds(const E* xs, uint32_t li, uint32_t l0) {
     const E a = xs[li], b = xs[li | l0];
+    return G{a.x, a.y, b.x, b.y};
+  }
+  static __device__ __forceinline__ G from_lds_x(const E* xs, uint32_t li, uint32_t l0) {
+    const E a = xs[li], b = xs[li ^ l0];
     return G{a.x, a.y, b.x, b.y};
   }
 };
@@ -235,10 +261,15 @@ struct mfma_shape<double> {
     *part = (rho / 4) % 2;
   }
   static __device__ __forceinline__ int out_member(int l, int r) { return 2 * (l / 16) + r / 2; }
+  static __device__ __forceinline__ int out_member_u(int r) { return r / 2; }
+  static __device__ __forceinline__ int out_member_l(int l) { return 2 * (l / 16); }
   static constexpr int MPB = 8;
+  static constexpr int ES = 4;  // log2 of the LDS entries (16 bytes) in 256 bytes
   typedef dbl2 G;  // one complex128 amplitude
   static __device__ __forceinline__ void to_lds(E* xs, uint32_t li, uint32_t, G v) { xs[li] = v; }
   static __device__ __forceinline__ G from_lds(const E* xs, uint32_t li, uint32_t) { return xs[li]; }
+  static __device__ __forceinline__ void to_lds_x(E* xs, uint32_t li, uint32_t, G v) { xs[li] = v; }
+  static __device__ __forceinline__ G from_lds_x(const E* xs, uint32_t li, uint32_t) { return xs[li]; }
 };
 
 // groups per column tile: the X tile holds 4096 complex64 / 2048 complex128
@@ -272,6 +303,7 @@ struct mfma_plan {
   static constexpr int NRB = RBLK >= W ? RBLK / W : 1;         // distinct row blocks per wave
   static constexpr int KSTEPS = 2 * D / MS::BK;
   static_assert(RBLK < W || RBLK % W == 0, "row blocks split evenly over the waves");
+  static_assert(NC / MS::BN <= 16, "column blocks fit the swizzle table");
 };
 
 template <typename R, int K>
@@ -393,47 +425,242 @@ __global__ __launch_bounds__((mfma_plan<R, K>::THREADS)) void k_dense_mfma(typen
 #undef SV_LD
 }
 
+// Swizzle of member mu from those of its single bits (the swizzle is linear).
+template <int K>
+__device__ __forceinline__ uint32_t member_swizzle(int mu, const uint32_t* fmb) {
+  uint32_t f = 0;
+#pragma unroll
+  for (int b = 0; b < K; ++b)
+    if ((mu >> b) & 1) f ^= fmb[b];
+  return f;
+}
+
+// The same contraction on a swizzled tile (see DenseGeo): operand and result
+// addresses take the member's and column block's swizzle.
 template <typename R, int K>
-hipError_t run_mfma(void* psi, int n, const DenseGeo& g, const void* m, hipStream_t s) {
-  constexpr int NC = mfma_cols<R, K>();
+__global__ __launch_bounds__((mfma_plan<R, K>::THREADS)) void k_dense_mfma_swz(typename mfma_shape<R>::E* __restrict__ psi, uint64_t nwork,
+                                                       DenseGeo g, const R* __restrict__ um) {
+  typedef mfma_shape<R> MS;
+  typedef mfma_plan<R, K> MP;
+  typedef typename MS::E E;
+  constexpr int D = MP::D, NC = MP::NC, RBLK = MP::RBLK, TILES = MP::TILES, TPW = MP::TPW, NRB = MP::NRB;
+  constexpr int KSTEPS = MP::KSTEPS, W = MP::W, TB = MP::TB;
+  // global memory moves in 16-byte elements: complex128 amplitudes, or
+  // complex64 pairs on tile-local bit 0 (LB = 1)
+  constexpr int LB = sizeof(R) == 4 ? 1 : 0;
+  typedef typename mfma_shape<R>::G G;
+  constexpr int PER = (D * NC / MP::THREADS) >> LB;  // 16-byte elements per lane
+  extern __shared__ __align__(16) unsigned char smem[];
+  E* xs = reinterpret_cast<E*>(smem);  // [member][NC]
+  const int t = threadIdx.x, l = t % 64;
+  const int w = __builtin_amdgcn_readfirstlane(t / 64);  // uniform per wave
+  // A fragments of this wave's row blocks: lane l supplies A[l % BM][BK ks + l / BM]
+  R afrag[NRB][KSTEPS];
+#pragma unroll
+  for (int i = 0; i < NRB; ++i) {
+    const int rb = (w + W * i) % RBLK;
+    int ai, aa;  // output member and re/im of the A row this lane supplies
+    MS::row_of(l % MS::BM, &ai, &aa);
+    ai += MS::MPB * rb;
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+      const int ak = MS::BK * ks + l / MS::BM;  // real column of A (= real row of B)
+      const R ur = um[2 * (ai * D + (ak >> 1))], ui = um[2 * (ai * D + (ak >> 1)) + 1];
+      afrag[i][ks] = aa == 0 ? ((ak & 1) == 0 ? ur : -ui) : ((ak & 1) == 0 ? ui : ur);
+    }
+  }
+  const LaneMap lm = lane_map<LB, TB, true>((uint32_t)t, g);
+  const uint32_t l0 = g.lds[0];  // LDS offset of the bit-0 partner (LB = 1)
+  G* gp = reinterpret_cast<G*>(psi);
+  const R* xr = reinterpret_cast<const R*>(smem);
+  // per-lane parts of the operand and result members (the swizzle is linear)
+  const int bml = (l / MS::BN) >> 1, bpart = (l / MS::BN) & 1, oml = MS::out_member_l(l);
+  uint32_t fmb0[K];
+#pragma unroll
+  for (int b = 0; b < K; ++b) fmb0[b] = g.fmb[b];
+  const uint32_t bfl = member_swizzle<K>(bml, fmb0), ofl = member_swizzle<K>(oml, fmb0);
+  // software-pipelined over column tiles: the next tile's loads are in flight
+  // while the current tile runs on the matrix cores and is stored
+  uint64_t wb = xcd_block();
+  if (wb >= nwork) return;
+  G buf[PER];
+#define SV_LD(U)                                                      \
+  {                                                                   \
+    uint64_t a;                                                       \
+    uint32_t li;                                                      \
+    bool on;                                                          \
+    elem_map<LB, U, TB, true>(g, &a, &li, &on);                                 \
+    buf[U] = ld(gp + (((on && lm.on) ? (ldbase | a) : ldbase) >> LB)); \
+  }
+  {
+    const uint64_t ldbase = deposit(wb, g.rest) | lm.addr;
+    SV_FOR_U(PER, SV_LD)
+  }
+  while (true) {
+    const uint64_t nb = wb + gridDim.x;
+    const uint64_t base = deposit(wb, g.rest) | lm.addr;
+    __syncthreads();  // the previous tile's store phase is done with LDS
+#define SV_LDS(U)                                                     \
+    {                                                                 \
+      uint64_t a;                                                     \
+      uint32_t li;                                                    \
+      bool on;                                                        \
+      elem_map<LB, U, TB, true>(g, &a, &li, &on);                               \
+      if (on && lm.on) mfma_shape<R>::to_lds_x(xs, lm.lds ^ li, l0, buf[U]); \
+    }
+    SV_FOR_U(PER, SV_LDS)
+#undef SV_LDS
+    __syncthreads();
+    if (nb < nwork) {
+      const uint64_t ldbase = deposit(nb, g.rest) | lm.addr;
+      SV_FOR_U(PER, SV_LD)
+    }
+    typename MS::acc_t acc[TPW];
+    uint32_t fmb[K];
+    {
+      // swizzles of the single member bits, opaque per tile: the compiler then
+      // derives each k-step's swizzle with a few scalar XORs instead of
+      // holding one value per k-step in registers
+#pragma unroll
+      for (int b = 0; b < K; ++b) {
+        fmb[b] = g.fmb[b];
+        asm volatile("" : "+s"(fmb[b]));
+      }
+      const uint32_t blane = 2 * ((uint32_t)(bml * NC + l % MS::BN) ^ bfl) + bpart;
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int tile = w + W * i;
+        acc[i] = typename MS::acc_t{};
+        if (tile >= TILES) continue;
+        const int cb = tile / RBLK;
+        const uint32_t bl = blane ^ (2u * (uint32_t)(MS::BN * cb ^ g.fc[cb]));
+#pragma unroll
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+          // B[bk][bcol], real row bk = 2 member + part: one float per lane at
+          // LDS entry ((mu + bml) NC + bcol) ^ fm(mu + bml) ^ fc[cb]
+          const int mu = (MS::BK * ks) >> 1;  // uniform part of the member (bits disjoint from bml)
+          const R b = xr[2 * mu * NC + (bl ^ (2u * member_swizzle<K>(mu, fmb)))];
+          acc[i] = MS::mma(afrag[i % NRB][ks], b, acc[i]);  // row block (w + W i) % RBLK
+        }
+      }
+    }
+    __syncthreads();  // every wave has read X: the outputs replace it in LDS
+    const uint32_t olane = (uint32_t)(oml * NC + l % MS::BN) ^ ofl;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int tile = w + W * i;
+      if (tile >= TILES) continue;
+      const int rb = tile % RBLK, cb = tile / RBLK;
+#pragma unroll
+      for (int r = 0; r < MS::NACC; r += 2) {
+        // result member mu + oml, column BN cb + l % BN
+        const int mu = MS::MPB * rb + MS::out_member_u(r);
+        E y;
+        y.x = acc[i][r];
+        y.y = acc[i][r + 1];
+        const uint32_t ol = olane ^ (uint32_t)(MS::BN * cb ^ g.fc[cb]);
+        xs[mu * NC + (ol ^ member_swizzle<K>(mu, fmb))] = y;
+      }
+    }
+    __syncthreads();
+    // store in address order
+#define SV_ST(U)                                                      \
+    {                                                                 \
+      uint64_t a;                                                     \
+      uint32_t li;                                                    \
+      bool on;                                                        \
+      elem_map<LB, U, TB, true>(g, &a, &li, &on);                               \
+      if (on && lm.on) st(gp + ((base | a) >> LB), mfma_shape<R>::from_lds_x(xs, lm.lds ^ li, l0)); \
+    }
+    SV_FOR_U(PER, SV_ST)
+#undef SV_ST
+    if (nb >= nwork) break;
+    wb = nb;
+  }
+#undef SV_LD
+}
+
+DenseGeo make_geo(int n, int k, const int* q, int nc, int es, int lb);
+
+template <typename R, int K, bool SWZ>
+hipError_t launch_mfma(void* psi, uint64_t nwork, const DenseGeo& g, const void* m, hipStream_t s) {
   constexpr size_t lds = mfma_lds<R, K>();
+  const void* fn = SWZ ? (const void*)k_dense_mfma_swz<R, K> : (const void*)k_dense_mfma<R, K>;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_dense_mfma<R, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  const uint64_t ngroups = 1ull << (n - K);
-  const uint64_t nwork = (ngroups + NC - 1) / NC;
   // persistent blocks: enough to fill the chip several times over, each
   // amortising its A fragments (loaded once) over many column tiles
   const uint64_t blocks = nwork < 4096 ? nwork : 4096;
-  hipLaunchKernelGGL((k_dense_mfma<R, K>), dim3((unsigned)blocks), dim3(mfma_plan<R, K>::THREADS), lds, s,
-                     (typename mfma_shape<R>::E*)psi, nwork, g, (const R*)m);
+  if constexpr (SWZ)
+    hipLaunchKernelGGL((k_dense_mfma_swz<R, K>), dim3((unsigned)blocks), dim3(mfma_plan<R, K>::THREADS), lds, s,
+                       (typename mfma_shape<R>::E*)psi, nwork, g, (const R*)m);
+  else
+    hipLaunchKernelGGL((k_dense_mfma<R, K>), dim3((unsigned)blocks), dim3(mfma_plan<R, K>::THREADS), lds, s,
+                       (typename mfma_shape<R>::E*)psi, nwork, g, (const R*)m);
   return hipGetLastError();
 }
 
+DenseGeo make_geo(int n, int k, const int* q, int nc, int es, int lb);
+
+// The swizzled kernel runs when the plain layout would put a wave's 64 lanes
+// on at most a quarter (complex64 k = 6: a sixteenth) of the LDS bank groups
+// they could use (member bits among the lanes: low qubit placements); the
+// plain kernel addresses its operands more cheaply and runs otherwise.
+template <typename R, int K>
+hipError_t run_mfma(void* psi, int n, const int* q, const void* m, hipStream_t s) {
+  constexpr int NC = mfma_cols<R, K>();
+  constexpr int LB = sizeof(R) == 4 ? 1 : 0;
+  const uint64_t ngroups = 1ull << (n - K);
+  const uint64_t nwork = (ngroups + NC - 1) / NC;
+  const DenseGeo plain = make_geo(n, K, q, NC, 0, LB);
+  // distinct bank groups (LDS index mod 2^ES) the 64 lanes of a wave touch
+  uint32_t seen[2] = {0, 0};
+  for (uint32_t t = 0; t < 64; ++t) {
+    uint32_t x = 0;
+    for (int j = 0; j < 6 && LB + j < (int)plain.nbits; ++j)
+      if ((t >> j) & 1u) x |= plain.lds[LB + j];
+    x &= (1u << mfma_shape<R>::ES) - 1u;
+    seen[x >> 5] |= 1u << (x & 31u);
+  }
+  const int distinct = __builtin_popcount(seen[0]) + __builtin_popcount(seen[1]);
+  // the complex64 k = 6 kernel is matrix-bound: the swizzle's extra address
+  // arithmetic pays only against the worst conflicts
+  const int factor = (sizeof(R) == 4 && K == 6) ? 16 : 4;
+  if (distinct * factor <= (1 << mfma_shape<R>::ES))
+    return launch_mfma<R, K, true>(psi, nwork, make_geo(n, K, q, NC, mfma_shape<R>::ES, LB), m, s);
+  return launch_mfma<R, K, false>(psi, nwork, plain, m, s);
+}
+
 // Tile map of a k-qubit gate q[0..k-1] (q[0] = MSB of the member index)
-// with nc columns per tile (a power of two), for an n-qubit state.
-DenseGeo make_geo(int n, int k, const int* q, int nc) {
+// with nc columns per tile (a power of two), for an n-qubit state.  es > 0
+// adds the LDS swizzle for a kernel whose lanes take tile-local bits lb ..
+// (es = log2 of the LDS entries in 256 bytes); es = 0 leaves LDS unswizzled.
+DenseGeo make_geo(int n, int k, const int* q, int nc, int es, int lb) {
   int cb = 0;
   while ((1 << cb) < nc) ++cb;
   struct Bit {
     uint32_t pos, lds;
+    int member, col;  // member bit or column bit (-1: not)
   } bits[16];
   int nb = 0;
   uint64_t gate = 0;
   for (int i = 0; i < k; ++i) {
-    bits[nb++] = {(uint32_t)q[i], (1u << (k - 1 - i)) << cb};
+    bits[nb++] = {(uint32_t)q[i], (1u << (k - 1 - i)) << cb, k - 1 - i, -1};
     gate |= 1ull << q[i];
   }
   int col = 0;
   for (int p = 0; p < n && col < cb; ++p)
-    if (!((gate >> p) & 1)) bits[nb++] = {(uint32_t)p, 1u << col++};
+    if (!((gate >> p) & 1)) {
+      bits[nb++] = {(uint32_t)p, 1u << col, -1, col};
+      ++col;
+    }
   uint64_t tilemask = gate;
   for (int i = k; i < nb; ++i) tilemask |= 1ull << bits[i].pos;
-  for (; col < cb; ++col) bits[nb++] = {64u, 1u << col};  // beyond the state
+  for (; col < cb; ++col) bits[nb++] = {64u, 1u << col, -1, col};  // beyond the state
   for (int i = 1; i < nb; ++i)
     for (int j = i; j > 0 && bits[j - 1].pos > bits[j].pos; --j) {
       const Bit tmp = bits[j];
@@ -442,10 +669,39 @@ DenseGeo make_geo(int n, int k, const int* q, int nc) {
     }
   DenseGeo g{};
   g.nbits = (uint32_t)nb;
+  uint32_t f[16] = {};
+  if (es > 0) {
+    // the wave's lanes take tile-local bits lb .. lb + 5: low column bits
+    // already select distinct banks; give each other bit (a member bit or a
+    // column bit >= es) a free bank bit until all es bank bits are used
+    const uint32_t low = (1u << es) - 1u;
+    uint32_t used = 0;
+    for (int j = lb; j < lb + 6 && j < nb; ++j)
+      if (bits[j].lds <= low) used |= bits[j].lds;
+    for (int j = lb; j < lb + 6 && j < nb; ++j) {
+      if (bits[j].lds <= low) continue;
+      for (int u = 0; u < es; ++u)
+        if (!((used >> u) & 1u)) {
+          f[j] = 1u << u;
+          used |= f[j];
+          break;
+        }
+    }
+  }
+  uint32_t fmem[8] = {}, fcol[16] = {};
   for (int j = 0; j < nb; ++j) {
     g.pos[j] = bits[j].pos;
-    g.lds[j] = bits[j].lds;
+    g.lds[j] = bits[j].lds ^ f[j];
     if (bits[j].pos == 64u) g.inv |= 1u << j;
+    if (bits[j].member >= 0) fmem[bits[j].member] = f[j];
+    if (bits[j].col >= 0) fcol[bits[j].col] = f[j];
+  }
+  for (int b = 0; b < k; ++b) g.fmb[b] = fmem[b];
+  for (int c = 0; es > 0 && c < 16 && (c << es) < nc; ++c) {
+    uint32_t v = 0;
+    for (int b = 0; es + b < cb; ++b)
+      if ((c >> b) & 1) v ^= fcol[es + b];
+    g.fc[c] = v;
   }
   const uint64_t all = n >= 64 ? ~0ull : (1ull << n) - 1ull;
   g.rest = all & ~tilemask;
@@ -458,25 +714,25 @@ hipError_t launch_dense_kq(sv_dtype dt, void* psi, int n, int k, const int* q, c
                            hipStream_t s) {
   if (dt == SV_C128) {
     switch (k) {
-      case 3: return run_mfma<double, 3>(psi, n, make_geo(n, k, q, mfma_cols<double, 3>()), m_dev, s);
-      case 4: return run_mfma<double, 4>(psi, n, make_geo(n, k, q, mfma_cols<double, 4>()), m_dev, s);
-      case 5: return run_mfma<double, 5>(psi, n, make_geo(n, k, q, mfma_cols<double, 5>()), m_dev, s);
-      case 6: return run_mfma<double, 6>(psi, n, make_geo(n, k, q, mfma_cols<double, 6>()), m_dev, s);
+      case 3: return run_mfma<double, 3>(psi, n, q, m_dev, s);
+      case 4: return run_mfma<double, 4>(psi, n, q, m_dev, s);
+      case 5: return run_mfma<double, 5>(psi, n, q, m_dev, s);
+      case 6: return run_mfma<double, 6>(psi, n, q, m_dev, s);
     }
     return hipErrorInvalidValue;
   }
   if (mfma && k >= 4) {
     switch (k) {
-      case 4: return run_mfma<float, 4>(psi, n, make_geo(n, k, q, mfma_cols<float, 4>()), m_dev, s);
-      case 5: return run_mfma<float, 5>(psi, n, make_geo(n, k, q, mfma_cols<float, 5>()), m_dev, s);
-      case 6: return run_mfma<float, 6>(psi, n, make_geo(n, k, q, mfma_cols<float, 6>()), m_dev, s);
+      case 4: return run_mfma<float, 4>(psi, n, q, m_dev, s);
+      case 5: return run_mfma<float, 5>(psi, n, q, m_dev, s);
+      case 6: return run_mfma<float, 6>(psi, n, q, m_dev, s);
     }
   }
   switch (k) {
-    case 3: return run<flt2, 3>(psi, n, make_geo(n, k, q, tile_cols<3>()), m_dev, s);
-    case 4: return run<flt2, 4>(psi, n, make_geo(n, k, q, tile_cols<4>()), m_dev, s);
-    case 5: return run<flt2, 5>(psi, n, make_geo(n, k, q, tile_cols<5>()), m_dev, s);
-    case 6: return run<flt2, 6>(psi, n, make_geo(n, k, q, tile_cols<6>()), m_dev, s);
+    case 3: return run<flt2, 3>(psi, n, make_geo(n, k, q, tile_cols<3>(), 0, 0), m_dev, s);
+    case 4: return run<flt2, 4>(psi, n, make_geo(n, k, q, tile_cols<4>(), 0, 0), m_dev, s);
+    case 5: return run<flt2, 5>(psi, n, make_geo(n, k, q, tile_cols<5>(), 0, 0), m_dev, s);
+    case 6: return run<flt2, 6>(psi, n, make_geo(n, k, q, tile_cols<6>(), 0, 0), m_dev, s);
   }
   return hipErrorInvalidValue;
 }
