@@ -285,10 +285,13 @@ class DeviceEngine:
         self.probs_qubits = probs_qubits
         self.inflight = max(1, inflight)
         self.keep_states = keep_states
-        # passes of at most max_pass_ops ops: a small state's whole circuit is
-        # split into passes of similar length to those of large states, so no
-        # single workgroup stretches a shared launch
+        # states larger than one LDS tile run passes of at most max_pass_ops
+        # ops (one pass per launch, like every other request); a state that
+        # fits one tile (n <= tile qubits) runs its whole circuit as one pass
+        # whose tile stays in LDS from the first gate to the last, so it
+        # completes in a single launch
         self.opts = {"mode": "pass", "lds_qubits": lds_qubits, "max_pass_ops": max_pass_ops}
+        self.tile_qubits = lds_qubits or (13 if dtype == "c64" else 12)
         self.stream = torch.cuda.current_stream()
         self.batcher = B.Batcher(self.stream)
         self.launch_events: collections.deque = collections.deque()
@@ -298,7 +301,8 @@ class DeviceEngine:
     # worker thread: host planning only
     def prepare(self, job: Job) -> Job:
         B = self.B
-        plan = B.Plan.from_array(job.n, self.dtype, job.gates, job.n_gates, self.opts)
+        opts = self.opts if job.n > self.tile_qubits else dict(self.opts, max_pass_ops=0)
+        plan = B.Plan.from_array(job.n, self.dtype, job.gates, job.n_gates, opts)
         job.handle = {"plan": plan, "flops": plan.pass_flops() if self.time_launches else None}
         job.n_passes = plan.info()[1]
         job.footprint = (1 << job.n) * self.elem_bytes + _round_up(plan.program_bytes(), 512) \

@@ -108,10 +108,13 @@ def test_serving_loop_results_match_oracle(sv, dtype, rate):
     s = res.summary()
     assert s["completed"] == len(reqs) and s["errors"] == 0 and s["rejected"] == 0
     assert s["p99_ms"] >= s["p50_ms"] > 0
+    tile = 13 if dtype == "c64" else 12  # qubits of one 64 KiB LDS tile
     for r, j in zip(reqs, jobs):
         ref = oracle.run(r.circuit(), n=r.n)
         assert max_err(to_host(j.handle["tensor"]), ref) <= TOL[dtype], (r.rid, r.n)
         assert max_err(j.probs, low_probs_ref(ref, r.n)) <= PROB_TOL[dtype], (r.rid, r.n)
+        if r.n <= tile:  # the whole circuit in one LDS-resident pass: one launch
+            assert j.n_passes == 1, (r.rid, r.n, j.n_passes)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
