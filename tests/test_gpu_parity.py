@@ -122,8 +122,8 @@ def test_layered_gate_by_gate_n16(sv, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_qft_against_inverse_fft(sv, dtype):
-    n = 14
+@pytest.mark.parametrize("n", [14, 24])
+def test_qft_against_inverse_fft(sv, dtype, n):
     psi = gaussian_state_np(n, 9)
     t, host_in = to_device(psi, dtype)
     st = sv.StateVector(n, dtype, tensor=t, init=False)
