@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from svgen import layered_circuit, serving_requests
+from svgen import layered_circuit, qft_circuit, serving_requests
 from tests.gpu_util import TOL, max_err, to_host
 
 pytestmark = pytest.mark.gpu
@@ -26,10 +26,17 @@ def low_probs_ref(psi, n, k=16):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_batched_pass_launch_matches_oracle_and_single_plans(sv, dtype):
+@pytest.mark.parametrize("family", ["layered", "qft"])
+def test_batched_pass_launch_matches_oracle_and_single_plans(sv, dtype, family):
+    """Batched passes (one launch per step for all states) against the oracle
+    and against the unbatched pass kernel; the QFT family runs the
+    phase-ladder and register-diagonal ops through the batched kernel."""
     import torch
     ns = [6, 9, 12, 13, 14, 16, 17]
-    circuits = {n: layered_circuit(n, n_layer_pairs=5, seed=n) for n in ns}
+    if family == "qft":
+        circuits = {n: qft_circuit(n) for n in ns}
+    else:
+        circuits = {n: layered_circuit(n, n_layer_pairs=5, seed=n) for n in ns}
     plans = {n: sv.Plan(n, dtype, circuits[n], {"mode": "pass", "max_pass_ops": 16}) for n in ns}
     progs = {n: sv.Program(plans[n]) for n in ns}
     states = {n: sv.StateVector(n, dtype) for n in ns}
@@ -42,6 +49,8 @@ def test_batched_pass_launch_matches_oracle_and_single_plans(sv, dtype):
         batcher.run([states[n] for n in live], [progs[n] for n in live], [step] * len(live))
         step += 1
     torch.cuda.synchronize()
+    if family == "qft":
+        assert any(lad for n in ns for _, lad in plans[n].kernel_ops())
     for n in ns:
         out = to_host(states[n].tensor)
         ref = oracle.run(circuits[n], n=n)
