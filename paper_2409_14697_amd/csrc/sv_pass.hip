@@ -5,12 +5,13 @@
 // tile base on every non-local bit.  The tile is gathered from HBM with the
 // PDEP-like deposit of its local index into the pass's local bit positions
 // (Sec. III-B), so the low pinned positions give contiguous runs.  The pass's
-// stages then run in LDS: a stage gives each lane groups of 16 amplitudes
-// (4 local bits held in registers) and applies a list of ops to them in
-// registers; ops whose controls or phase bits lie outside the register bits
-// read those bits from the group's local index or from the tile base.  The
-// tile is written back with local bit j at physical position wpos[j], which
-// fuses qubit reordering (Sec. II-B) into the store.
+// stages then run in LDS: a stage gives each lane a group of 32 (complex64)
+// or 16 (complex128) amplitudes (5 or 4 local bits held in registers) and
+// applies a list of ops to them in registers; ops whose controls or phase
+// bits lie outside the register bits read those bits from the group's local
+// index or from the tile base, and a phase ladder sums its angles from both.
+// The tile is written back with local bit j at physical position wpos[j],
+// which fuses qubit reordering (Sec. II-B) into the store.
 //
 // LDS rows are 128 bytes; the element index is XOR-swizzled (low bits folded
 // with every higher group of bits) so that power-of-two strides between the
