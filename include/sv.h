@@ -194,10 +194,13 @@ sv_status sv_plan_pass_info(const sv_plan *p, size_t pass, int32_t *kind, int32_
 sv_status sv_plan_pass_flops(const sv_plan *p, size_t pass, double *flops_per_amp);
 
 /* Kernel ops of tile pass `pass` after register staging: *n_ops ops in
- * total, *n_ladders of them phase ladders (a run of phase gates and
- * controlled phases that share one qubit, applied as one op with a
- * fixed-point angle sum; Sec. III-A's gate grouping inside a tile).  Both 0
- * for passes that are not tile passes.  Outputs may be NULL.
+ * total, *n_ladders of them fixed-point phase functions: a phase ladder (the
+ * phases of a run of diagonal gates that fall on the amplitudes whose
+ * register qubit is 1) or a quadratic phase over the bits outside the
+ * registers (the rest of such a run), each applied as one op with a
+ * fixed-point angle sum (Sec. III-A: gate grouping inside a tile and the
+ * fusion of diagonal gates).  Both 0 for passes that are not tile passes.
+ * Outputs may be NULL.
  * Errors: SV_ERR_ARG. */
 sv_status sv_plan_pass_ops(const sv_plan *p, size_t pass, int32_t *n_ops, int32_t *n_ladders);
 

@@ -342,7 +342,7 @@ sv_status sv_plan_pass_ops(const sv_plan* p, size_t pass, int32_t* n_ops, int32_
   for (const StageHost& sh : p->passes[pass].stages)
     for (const PassOpDev& od : sh.ops) {
       ++ops;
-      ladders += od.type == POP_LP;
+      ladders += od.type == POP_LP || od.type == POP_QG;
     }
   if (n_ops) *n_ops = ops;
   if (n_ladders) *n_ladders = ladders;

@@ -93,11 +93,11 @@ struct Pass {
 // load positions.
 bool fill_pass_maps(const Pass& ps, sv_dtype dt, PassDescDev* d);
 
-// The pass's stages hold phase-ladder ops (POP_LP).
+// The pass's stages hold fixed-point phase ops (POP_LP, POP_QG).
 inline bool pass_has_ladders(const Pass& ps) {
   for (const StageHost& sh : ps.stages)
     for (const PassOpDev& od : sh.ops)
-      if (od.type == POP_LP) return true;
+      if (od.type == POP_LP || od.type == POP_QG) return true;
   return false;
 }
 

@@ -268,20 +268,17 @@ __device__ __forceinline__ void op_d2(cplx<R>* v, cptr<cplx<R>> M) {
     default: break;                                                                          \
   }
 
-// POP_LP: the phase of the lane's amplitudes whose register bit b0 is 1:
-// the constant word plus the words of the set source bits, tile bits (the
-// same in every lane) and the lane's local group bits (xg has zeros at the
-// register positions).
+// Sum of the angle words (ladder layout) of the set bits: tile bits `sel`
+// (the same in every lane) and the lane's local bits `lsel`.
 template <typename R>
-__device__ __forceinline__ cplx<R> lp_phase(const PassOpDev& op, cptr<cplx<R>> M, uint32_t xg, uint64_t base) {
+__device__ __forceinline__ typename lp_word<R>::W lp_sum(cptr<typename lp_word<R>::W> words, uint32_t lsel,
+                                                         uint64_t sel) {
   typedef typename lp_word<R>::W W;
-  const cptr<W> words = (cptr<W>)M;
   // words in chunks of 8 (one scalar load each; the loops stay rolled so
   // that only one chunk is live in scalar registers)
   constexpr int CH = 8;
   static_assert(kPassLPLocalBits % CH == 0, "local words come in whole chunks");
-  uint64_t sel = base & op.tmask;
-  W t = words[kPassLPConst];
+  W t = 0;
 #pragma unroll 1
   for (int c = 0; c < (kPassLPTileBits + CH - 1) / CH && sel; ++c, sel >>= CH) {
 #pragma unroll
@@ -291,7 +288,6 @@ __device__ __forceinline__ cplx<R> lp_phase(const PassOpDev& op, cptr<cplx<R>> M
       t += ((sel >> b) & 1) ? w : W(0);
     }
   }
-  uint32_t lsel = xg & op.lmask;
 #pragma unroll 1
   for (int c = 0; c < kPassLPLocalBits / CH; ++c, lsel >>= CH) {
 #pragma unroll
@@ -299,6 +295,41 @@ __device__ __forceinline__ cplx<R> lp_phase(const PassOpDev& op, cptr<cplx<R>> M
       const W w = words[CH * c + b];
       t += ((lsel >> b) & 1) ? w : W(0);
     }
+  }
+  return t;
+}
+
+// POP_LP: the phase of the lane's amplitudes whose register bit b0 is 1:
+// the constant word plus the words of the set source bits, tile bits (the
+// same in every lane) and the lane's local group bits (xg has zeros at the
+// register positions).
+template <typename R>
+__device__ __forceinline__ cplx<R> lp_phase(const PassOpDev& op, cptr<cplx<R>> M, uint32_t xg, uint64_t base) {
+  typedef typename lp_word<R>::W W;
+  const cptr<W> words = (cptr<W>)M;
+  return lp_word<R>::phase(words[kPassLPConst] + lp_sum<R>(words, xg & op.lmask, base & op.tmask));
+}
+
+// POP_QG: row 0 and the constant, then the row of every set target bit.
+// The target loops run over uniform masks; a local target's row is summed
+// in every lane and kept where the lane's bit is set.
+template <typename R>
+__device__ __forceinline__ cplx<R> qg_phase(const PassOpDev& op, cptr<cplx<R>> M, uint32_t xg, uint64_t base) {
+  typedef typename lp_word<R>::W W;
+  cptr<W> words = (cptr<W>)M;
+  const uint32_t lsel = xg & op.lmask;
+  const uint64_t sel = base & op.tmask;
+  W t = words[kPassLPConst] + lp_sum<R>(words, lsel, sel);
+#pragma unroll 1
+  for (uint32_t lt = op.b0; lt; lt &= lt - 1u) {
+    words += kPassLPWords;
+    const W h = lp_sum<R>(words, lsel, sel);
+    t += ((xg >> __builtin_ctz(lt)) & 1u) ? h : W(0);
+  }
+#pragma unroll 1
+  for (uint64_t tt = ((uint64_t)op.pad << 32) | op.b1; tt; tt &= tt - 1u) {
+    words += kPassLPWords;
+    if ((base >> __builtin_ctzll(tt)) & 1u) t += lp_sum<R>(words, 0u, sel);
   }
   return lp_word<R>::phase(t);
 }
@@ -395,6 +426,14 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, u
     case POP_DR: {
 #pragma unroll
       for (int r = 0; r < Regs<R>::NR; ++r) v[r] = cmul(cget(M, r), v[r]);
+      break;
+    }
+    case POP_QG: {
+      if constexpr (LP) {
+        const cplx<R> p = qg_phase<R>(op, M, xg, base);
+#pragma unroll
+        for (int r = 0; r < Regs<R>::NR; ++r) v[r] = cmul(p, v[r]);
+      }
       break;
     }
     case POP_DG: {
@@ -605,7 +644,9 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
       }
       for (uint32_t o = 0; o < S.op_count; ++o) {
         const PassOpDev op = cload(ops + (S.op_first + o));
-        if (!(LP && op.type == POP_LP) && ((xg & op.lmask) != op.lmask || (base & op.tmask) != op.tmask)) continue;
+        if (!(LP && (op.type == POP_LP || op.type == POP_QG)) &&
+            ((xg & op.lmask) != op.lmask || (base & op.tmask) != op.tmask))
+          continue;
         uint32_t var = 0;
         if (op.sa != kPassNoSel) {
           var = op.sa < kPassTileSel ? (xg >> op.sa) & 1u : (uint32_t)(base >> (op.sa - kPassTileSel)) & 1u;

@@ -100,6 +100,7 @@ double op_flops(const PassOpDev& od) {
     case POP_X: return od.lmask ? 6.0 : 1.0;
     case POP_LP: return 14.0;
     case POP_DR: return 8.0;
+    case POP_QG: return 12.0;
     default: return 1.0;
   }
 }
@@ -117,9 +118,9 @@ bool real_diag_imag_offdiag(const cd* m) {
 
 static_assert(kPassLPTileBits >= SV_MAX_QUBITS, "every physical qubit has a ladder word");
 
-// Shortest run of phases worth one ladder op (its fixed cost is a few
-// single phases).
-constexpr int kLadderMin = 3;
+// Shortest run of phase gates worth fusing into one phase function (its
+// fixed cost is a few single phases).
+constexpr int kPhaseRunMin = 3;
 
 struct StageBuilder {
   const int* loc;  // physical bit -> local bit, or -1
@@ -145,26 +146,31 @@ struct StageBuilder {
     else od->tmask |= 1ull << physq;
   }
 
-  // Register bit j such that `op` multiplies the amplitudes whose qubit j is
-  // 1 by a unit phase that depends on at most one other qubit (a phase gate
-  // on j, or a controlled phase on (j, k)); candidates as a bit set over the
-  // register bits, 0 if none.
-  uint32_t ladder_targets(const Op& op) const {
-    if (!is_diag(op)) return 0;
-    const cd one(1.0, 0.0);
-    if (op.nq == 1) {
-      const int b = reg(op.q[0]);
-      return b >= 0 && op.m[0] == one && std::abs(std::abs(op.m[3]) - 1.0) < 1e-14 ? 1u << b : 0u;
-    }
-    if (op.nq != 2) return 0;
-    if (!(op.m[0] == one && op.m[5] == one && op.m[10] == one) || std::abs(std::abs(op.m[15]) - 1.0) >= 1e-14)
-      return 0;
-    uint32_t t = 0;
-    for (int i = 0; i < 2; ++i) {
-      const int b = reg(op.q[i]);
-      if (b >= 0) t |= 1u << b;
-    }
-    return t;
+  // A diagonal op on one or two qubits whose entries are unit phases: its
+  // phase is c + h_a x_a (+ h_b x_b + J_ab x_a x_b) over the bits x of its
+  // qubits, exact in fixed-point turns.
+  bool phase_op(const Op& op) const {
+    if (!is_diag(op) || op.nq > 2) return false;
+    const int d = 1 << op.nq;
+    for (int i = 0; i < d; ++i)
+      if (std::abs(std::abs(op.m[(size_t)i * d + i]) - 1.0) >= 1e-14) return false;
+    return true;
+  }
+
+  // Angle of a unit phase as a W-bit fixed-point turn (W = 32 for
+  // complex64, 64 for complex128), held in the low W bits.
+  uint64_t turns(const cd& e) const {
+    double t = std::arg(e) / (2.0 * M_PI);
+    t -= std::floor(t);
+    if (rb == pass_reg_bits(SV_C64)) return (uint64_t)(uint32_t)(uint64_t)std::llround(std::ldexp(t, 32));
+    return (uint64_t)std::ldexp(t, 63) * 2u;
+  }
+
+  // The unit phase of a W-bit fixed-point turn.
+  cd phase_of(uint64_t w) const {
+    const bool f32 = rb == pass_reg_bits(SV_C64);
+    const double t = f32 ? (double)(int32_t)(uint32_t)w * 0x1p-32 : (double)(int64_t)w * 0x1p-64;
+    return std::polar(1.0, 2.0 * M_PI * t);
   }
 
   // A diagonal op whose qubits are all register bits (a factor per register
@@ -197,59 +203,170 @@ struct StageBuilder {
     sh->ops.push_back(od);
   }
 
-  // One POP_LP op for ops[first, first + count) on register bit j: the
-  // partners outside the registers and the phase gates become angle words;
-  // the gates whose partner is a register bit follow as one POP_DR op (or
-  // their own op when there is only one); all of them commute.
-  void encode_ladder(StageHost* sh, size_t first, size_t count, int j) {
-    uint64_t words[kPassLPWords] = {};
-    const bool f32 = rb == pass_reg_bits(SV_C64);
-    auto add_angle = [&](int idx, const cd& e) {
-      // fixed-point turns modulo one turn, W = 32 (complex64) or 64 bits
-      double t = std::arg(e) / (2.0 * M_PI);
-      t -= std::floor(t);
-      const uint64_t w = f32 ? (uint64_t)(uint32_t)(uint64_t)std::llround(std::ldexp(t, 32))
-                             : (uint64_t)std::ldexp(t, 63) * 2u;
-      words[idx] = f32 ? (words[idx] + w) & 0xffffffffull : words[idx] + w;
-    };
-    PassOpDev od{};
-    od.type = POP_LP;
-    od.b0 = (uint32_t)j;
-    od.sa = od.sb = kPassNoSel;
-    od.mat = (uint32_t)sh->mats.size();
-    std::vector<Op> reg_pairs;
-    for (size_t i = first; i < first + count; ++i) {
-      const Op& op = ops[i];
-      if (op.nq == 1) {
-        add_angle(kPassLPConst, op.m[3]);
-        continue;
-      }
-      const int k = reg(op.q[0]) == j ? op.q[1] : op.q[0];  // the other qubit (physical)
-      const int l = loc[k];
-      if (reg(k) >= 0) {
-        reg_pairs.push_back(op);
-      } else if (l >= 0) {
-        add_angle(l, op.m[15]);
-        od.lmask |= 1u << l;
-      } else {
-        add_angle(kPassLPLocalBits + k, op.m[15]);
-        od.tmask |= 1ull << k;
-      }
-    }
-    for (int w = 0; w < kPassLPWords; w += 2) {
+  // Append `words` (kPassLPWords per row) to the pool, two per entry.
+  static void put_words(StageHost* sh, const std::vector<uint64_t>& words) {
+    for (size_t w = 0; w < words.size(); w += 2) {
       double re, im;
       std::memcpy(&re, &words[w], sizeof re);
       std::memcpy(&im, &words[w + 1], sizeof im);
       sh->mats.push_back(cd(re, im));
       sh->raw.push_back(1);
     }
-    sh->ops.push_back(od);
-    if (reg_pairs.size() >= 2) {
-      std::vector<const Op*> run;
-      for (const Op& op : reg_pairs) run.push_back(&op);
-      encode_reg_diag(sh, run);
-    } else {
-      for (const Op& op : reg_pairs) encode_op(sh, op);
+  }
+
+  // Ops [first, last): a run of phase ops (they commute), fused into one
+  // quadratic phase over the bits of their qubits,
+  //   theta(x) = c + sum_a h_a x_a + sum_{a<b} J_ab x_a x_b   (turns mod 1),
+  // summed exactly in W-bit fixed point (the words of every gate's entries
+  // are rounded once).  It is applied as at most three kinds of op:
+  //   * a POP_LP ladder per register bit a with pair terms to bits outside
+  //     the registers (its constant is h_a);
+  //   * one POP_DR factor per register index for the terms over register
+  //     bits only (and the constant when no POP_QG follows);
+  //   * one POP_QG for the terms over the other bits (the lane's group bits
+  //     and the tile bits).
+  void encode_phase_run(StageHost* sh, size_t first, size_t last) {
+    const bool f32 = rb == pass_reg_bits(SV_C64);
+    const uint64_t wmask = f32 ? 0xffffffffull : ~0ull;
+    constexpr int NQ = SV_MAX_QUBITS;
+    uint64_t c = 0;
+    std::vector<uint64_t> h(NQ, 0), J((size_t)NQ * NQ, 0);  // J[a * NQ + b], a < b
+    std::vector<char> used(NQ, 0);
+    for (size_t i = first; i < last; ++i) {
+      const Op& op = ops[i];
+      const int a = op.q[0];
+      used[a] = 1;
+      if (op.nq == 1) {
+        const uint64_t t0 = turns(op.m[0]), t1 = turns(op.m[3]);
+        c += t0;
+        h[a] += t1 - t0;
+        continue;
+      }
+      const int b = op.q[1];  // entry index (bit a) * 2 + (bit b)
+      used[b] = 1;
+      const uint64_t t00 = turns(op.m[0]), t01 = turns(op.m[5]), t10 = turns(op.m[10]), t11 = turns(op.m[15]);
+      c += t00;
+      h[a] += t10 - t00;
+      h[b] += t01 - t00;
+      J[(size_t)std::min(a, b) * NQ + std::max(a, b)] += t11 - t10 - t01 + t00;
+    }
+    c &= wmask;
+    for (auto& w : h) w &= wmask;
+    for (auto& w : J) w &= wmask;
+    auto pair = [&](int a, int b) { return J[(size_t)std::min(a, b) * NQ + std::max(a, b)]; };
+    // word index of a source bit outside the registers (ladder layout)
+    auto word_of = [&](int q) { return loc[q] >= 0 ? loc[q] : kPassLPLocalBits + q; };
+    std::vector<int> regq, other;  // qubits in / outside the registers
+    for (int q = 0; q < NQ; ++q)
+      if (used[q]) (reg(q) >= 0 ? regq : other).push_back(q);
+    // order of the bits outside the registers: local (ascending local bit),
+    // then tile (ascending physical bit); a pair term lives in the row of
+    // the earlier bit
+    std::sort(other.begin(), other.end(), [&](int x, int y) {
+      const bool lx = loc[x] >= 0, ly = loc[y] >= 0;
+      if (lx != ly) return lx;
+      return lx ? loc[x] < loc[y] : x < y;
+    });
+
+    // ladders
+    std::vector<char> in_ladder(NQ, 0);
+    for (int a : regq) {
+      std::vector<uint64_t> words(kPassLPWords, 0);
+      PassOpDev od{};
+      od.type = POP_LP;
+      od.b0 = (uint32_t)reg(a);
+      od.sa = od.sb = kPassNoSel;
+      for (int b : other) {
+        const uint64_t w = pair(a, b);
+        if (!w) continue;
+        words[word_of(b)] = w;
+        if (loc[b] >= 0) od.lmask |= 1u << loc[b];
+        else od.tmask |= 1ull << b;
+      }
+      if (!od.lmask && !od.tmask) continue;
+      words[kPassLPConst] = h[a];
+      in_ladder[a] = 1;
+      od.mat = (uint32_t)sh->mats.size();
+      put_words(sh, words);
+      sh->ops.push_back(od);
+    }
+
+    // quadratic phase outside the registers
+    std::vector<uint64_t> qw(kPassLPWords, 0);
+    PassOpDev qg{};
+    qg.type = POP_QG;
+    qg.sa = qg.sb = kPassNoSel;
+    bool any = false;
+    auto mark = [&](PassOpDev& od, int q) {
+      if (loc[q] >= 0) od.lmask |= 1u << loc[q];
+      else od.tmask |= 1ull << q;
+    };
+    for (int a : other)
+      if (h[a]) {
+        qw[word_of(a)] = h[a];
+        mark(qg, a);
+        any = true;
+      }
+    uint64_t tile_targets = 0;
+    for (size_t i = 0; i < other.size(); ++i) {
+      const int a = other[i];
+      std::vector<uint64_t> row(kPassLPWords, 0);
+      bool nz = false;
+      for (size_t k = i + 1; k < other.size(); ++k) {
+        const int b = other[k];
+        const uint64_t w = pair(a, b);
+        if (!w) continue;
+        row[word_of(b)] = w;
+        mark(qg, b);
+        nz = true;
+      }
+      if (!nz) continue;
+      mark(qg, a);
+      if (loc[a] >= 0) qg.b0 |= 1u << loc[a];
+      else tile_targets |= 1ull << a;
+      qw.insert(qw.end(), row.begin(), row.end());
+      any = true;
+    }
+    qg.b1 = (uint32_t)tile_targets;
+    qg.pad = (uint32_t)(tile_targets >> 32);
+    if (any) {
+      qw[kPassLPConst] = c;
+      c = 0;
+    }
+
+    // register factors (and the constant when there is no POP_QG)
+    const int nr = 1 << rb;
+    std::vector<uint64_t> dw(nr, c);
+    bool diag = c != 0;
+    for (size_t i = 0; i < regq.size(); ++i) {
+      const int a = regq[i], ra = reg(a);
+      if (!in_ladder[a] && h[a]) {
+        diag = true;
+        for (int r = 0; r < nr; ++r)
+          if ((r >> ra) & 1) dw[r] += h[a];
+      }
+      for (size_t k = i + 1; k < regq.size(); ++k) {
+        const int b = regq[k], rbit = reg(b);
+        const uint64_t w = pair(a, b);
+        if (!w) continue;
+        diag = true;
+        for (int r = 0; r < nr; ++r)
+          if (((r >> ra) & 1) && ((r >> rbit) & 1)) dw[r] += w;
+      }
+    }
+    if (diag) {
+      PassOpDev od{};
+      od.type = POP_DR;
+      od.sa = od.sb = kPassNoSel;
+      od.mat = (uint32_t)sh->mats.size();
+      for (int r = 0; r < nr; ++r) sh->mats.push_back(phase_of(dw[r] & wmask));
+      sh->raw.insert(sh->raw.end(), nr, 0);
+      sh->ops.push_back(od);
+    }
+    if (any) {
+      qg.mat = (uint32_t)sh->mats.size();
+      put_words(sh, qw);
+      sh->ops.push_back(qg);
     }
   }
 
@@ -259,13 +376,12 @@ struct StageBuilder {
       if (std::find(qs.begin(), qs.end(), l) == qs.end()) qs.push_back(l);
     for (int r = 0; r < rb; ++r) sh->q[r] = (uint32_t)qs[r];
     for (size_t i = 0; i < ops.size();) {
-      // a run of phases that share one register qubit becomes one ladder op
-      uint32_t t = ladder_targets(ops[i]);
+      // a run of phase gates becomes one fixed-point quadratic phase
       size_t e = i;
-      while (t && e + 1 < ops.size() && (t & ladder_targets(ops[e + 1]))) t &= ladder_targets(ops[++e]);
-      if (t && e + 1 - i >= (size_t)kLadderMin) {
-        encode_ladder(sh, i, e + 1 - i, __builtin_ctz(t));
-        i = e + 1;
+      while (e < ops.size() && phase_op(ops[e])) ++e;
+      if (e - i >= (size_t)kPhaseRunMin) {
+        encode_phase_run(sh, i, e);
+        i = e;
         continue;
       }
       // a run of diagonal gates on register bits becomes one factor per

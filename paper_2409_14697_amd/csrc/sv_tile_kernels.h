@@ -42,8 +42,18 @@ enum PassOpType : uint32_t {
                // local bits 0..15, tile physical bits 0..kPassLPTileBits-1,
                // the constant.  lmask / tmask name the source bits with a
                // nonzero word (for this op they are not predicates).
-  POP_DR = 12  // diagonal over the register index: amplitude r times d[r]
+  POP_DR = 12, // diagonal over the register index: amplitude r times d[r]
                // (NR entries; a run of diagonal gates on register bits)
+  POP_QG = 13  // quadratic phase over the bits outside the registers (one
+               // phase per lane, on all its amplitudes): exp(2 pi i t / 2^W),
+               // t = the sum of the row-0 words of the set bits plus the
+               // constant word, plus, for every target bit that is set, the
+               // sum of its row's words of the set bits (the pair terms).
+               // Rows of kPassLPWords words in the phase-ladder layout: row 0,
+               // then one row per local target (ascending local bit: b0 is
+               // their mask), then one per tile target (ascending physical
+               // bit: b1 | pad << 32 is their mask).  lmask / tmask cover every
+               // bit with a nonzero word or a row (not predicates).
 };
 constexpr int kPassLPLocalBits = 16;
 constexpr int kPassLPTileBits = 34;
@@ -97,13 +107,13 @@ struct alignas(16) BatchItemDev {
 };
 
 // Run pass items[i].pass of every item in one launch (all items share dt).
-// ladders: some item's pass holds POP_LP ops (selects the kernel variant that
-// decodes them; the other variant carries none of their code).
+// ladders: some item's pass holds POP_LP or POP_QG ops (selects the kernel
+// variant that decodes them; the other variant carries none of their code).
 hipError_t launch_pass_batch(sv_dtype dt, const BatchItemDev* items, int count, uint64_t total_tiles, int max_m,
                              bool ladders, hipStream_t s);
 
 // Launch pass `pass` of a program already resident in device memory
-// (ladders: the pass holds POP_LP ops).
+// (ladders: the pass holds POP_LP or POP_QG ops).
 hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* passes, int pass,
                        const PassStageDev* stages, const PassOpDev* ops, const void* mats, bool ladders,
                        hipStream_t s);

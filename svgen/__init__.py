@@ -7,10 +7,11 @@ to a state.  Both the oracle and the HIP library consume these lists and build
 their own matrices from (kind, qubits, theta).
 """
 from .circuits import (Gate, GATE_KINDS, layered_circuit, brickwork_circuit, qft_circuit,
+                       qaoa_circuit,
                        haar_unitary, fused_haar_circuit, gate_bench_set, random_matching,
                        serving_requests, Request)
 from .states import gaussian_state_np, basis_state_np
 
-__all__ = ["Gate", "GATE_KINDS", "layered_circuit", "brickwork_circuit", "qft_circuit",
+__all__ = ["Gate", "GATE_KINDS", "layered_circuit", "brickwork_circuit", "qft_circuit", "qaoa_circuit",
            "haar_unitary", "fused_haar_circuit", "gate_bench_set", "random_matching",
            "serving_requests", "Request", "gaussian_state_np", "basis_state_np"]

@@ -124,6 +124,24 @@ def qft_circuit(n: int):
     return gates
 
 
+def qaoa_circuit(n: int, levels: int = 5, seed: int = 7):
+    """QAOA on the complete graph K_n: H on every qubit, then per level a
+    cost layer RZZ(gamma) on every pair (a, b), a < b, in lexicographic order,
+    and a mixer layer RX(beta) on every qubit.  gamma ~ U[0, pi), beta ~
+    U[0, pi/2) per level, drawn from the seed."""
+    rng = np.random.default_rng(seed)
+    gates = [Gate("H", (q,)) for q in range(n)]
+    for _ in range(levels):
+        gamma = float(rng.uniform(0.0, math.pi))
+        beta = float(rng.uniform(0.0, 0.5 * math.pi))
+        for a in range(n):
+            for b in range(a + 1, n):
+                gates.append(Gate("RZZ", (a, b), gamma))
+        for q in range(n):
+            gates.append(Gate("RX", (q,), 2.0 * beta))
+    return gates
+
+
 def haar_unitary(d: int, rng: np.random.Generator) -> np.ndarray:
     """Haar-random d x d unitary: QR of a complex Gaussian matrix with the phases
     of R's diagonal moved into Q (Mezzadri's correction)."""

@@ -11,7 +11,8 @@ import pytest
 import oracle
 from oracle import sv_oracle as so
 from paper_2409_14697_amd import binding as B
-from svgen import Gate, fused_haar_circuit, layered_circuit, qft_circuit, brickwork_circuit, gaussian_state_np
+from svgen import (Gate, fused_haar_circuit, layered_circuit, qaoa_circuit, qft_circuit, brickwork_circuit,
+                   gaussian_state_np)
 
 
 def test_library_exports_every_header_symbol():
@@ -104,6 +105,20 @@ def test_forward_merge_replays_brickwork(kmax):
     sizes = [len(q) for q, _, _ in plan.export()]
     assert all(k <= kmax for k in sizes)
     assert 1 not in sizes
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_phase_runs_fuse_qaoa(dtype):
+    """Tile passes fold each QAOA cost layer (a run of n(n-1)/2 RZZ gates)
+    into a few fixed-point phase ops per stage: far fewer kernel ops than
+    gates, and phase functions in every pass that holds RZZ gates."""
+    n = 20
+    gates = qaoa_circuit(n, 5, seed=7)
+    plan = B.Plan(n, dtype, gates, {"mode": "pass"})
+    kops = plan.kernel_ops()
+    assert sum(k for k, _ in kops) < len(gates) / 4
+    rzz_pass = {ps for (q, m, ps) in plan.export() if len(q) == 2}
+    assert rzz_pass and all(kops[ps][1] > 0 for ps in rzz_pass)
 
 
 def test_fusion_reduces_ops():

@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 import oracle
-from svgen import Gate, basis_state_np, brickwork_circuit, gaussian_state_np, layered_circuit, qft_circuit
+from svgen import (Gate, basis_state_np, brickwork_circuit, gaussian_state_np, layered_circuit, qaoa_circuit,
+                   qft_circuit)
 from tests.gpu_util import TOL, max_err, to_device, to_host
 
 pytestmark = pytest.mark.gpu
@@ -99,6 +100,57 @@ def diagonal_run_circuit(n, seed):
             else:
                 out.append(Gate(kind, (int(rng.choice(qs)),), float(rng.uniform(-7, 7))))
     return out
+
+
+def phase_run_circuit(n, seed):
+    """Runs of 3-60 phase gates on any qubits (RZZ, CPHASE, CZ, RZ, P, S, T, Z
+    and random diagonal unitaries on one or two qubits), each run after H / RY
+    gates on four random qubits, so that the run's qubits fall in registers,
+    in the tile outside the registers and outside the tile."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(8):
+        for q in rng.choice(n, 4, replace=False):
+            out.append(Gate("H", (int(q),)) if rng.random() < 0.5 else Gate("RY", (int(q),), float(rng.uniform(0, 6))))
+        for _ in range(int(rng.integers(3, 61))):
+            kind = ["RZZ", "CPHASE", "CZ", "RZ", "P", "S", "T", "Z", "D1", "D2"][int(rng.integers(10))]
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            if kind == "D1":
+                out.append(Gate("MATRIX", (a,), matrix=np.diag(np.exp(1j * rng.uniform(-7, 7, 2)))))
+            elif kind == "D2":
+                out.append(Gate("MATRIX", (a, b), matrix=np.diag(np.exp(1j * rng.uniform(-7, 7, 4)))))
+            elif kind in ("RZZ", "CPHASE", "CZ"):
+                out.append(Gate(kind, (a, b), float(rng.uniform(-7, 7))))
+            else:
+                out.append(Gate(kind, (a,), float(rng.uniform(-7, 7))))
+    return out
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("lds", [0, 7, 10])
+@pytest.mark.parametrize("seed", [3, 4])
+def test_phase_runs(sv, dtype, lds, seed):
+    """Runs of phase gates fused into ladders, register factors and one
+    quadratic phase over the other bits, against the oracle; the plan holds
+    fused phase ops."""
+    n = 15
+    gates = phase_run_circuit(n, seed)
+    opts = {"mode": "pass", "lds_qubits": lds}
+    plan = sv.Plan(n, dtype, gates, opts)
+    assert sum(lad for _, lad in plan.kernel_ops()) > 0
+    out, ref = run_plan(sv, n, dtype, gaussian_state_np(n, 43 + seed), gates, opts)
+    assert max_err(out, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("lds", [0, 6, 9])
+def test_qaoa_complete_graph(sv, dtype, lds):
+    """Five QAOA levels on K_n from |0...0> (the H layer prepares |+>): every
+    ZZ layer is one run of phase gates."""
+    n = 16
+    gates = qaoa_circuit(n, 5, seed=11)
+    out, ref = run_plan(sv, n, dtype, basis_state_np(n, 0), gates, {"mode": "pass", "lds_qubits": lds})
+    assert max_err(out, ref) <= TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)

@@ -16,7 +16,7 @@ import oracle
 from oracle import brute
 from oracle import sv_oracle as so
 from svgen import (Gate, basis_state_np, brickwork_circuit, fused_haar_circuit, gate_bench_set,
-                   gaussian_state_np, haar_unitary, layered_circuit, qft_circuit, random_matching)
+                   gaussian_state_np, haar_unitary, layered_circuit, qaoa_circuit, qft_circuit, random_matching)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 PX = np.array([[0, 1], [1, 0]], dtype=complex)
@@ -149,6 +149,29 @@ def test_group_indices_and_apply_to_group():
             base = int(base) & ~mask
             idx = so.group_indices(base, qs)
             assert np.max(np.abs(out[idx] - so.apply_to_group(u, psi[idx]))) < 1e-15
+
+
+# ------------------------------------------------------------- QAOA
+@pytest.mark.parametrize("n", [4, 7])
+def test_qaoa_level_closed_form(n):
+    """One QAOA level on the complete graph as a closed form: the cost layer
+    multiplies basis state x by exp(-i gamma E / 2), E = sum_{a<b} s_a s_b =
+    (M^2 - n) / 2 with s = 1 - 2 x and M = sum s (the Ising energy of K_n);
+    the mixer is the n-fold tensor power of exp(-i beta X).  Checked against
+    the oracle's gate-by-gate run from |0...0>."""
+    gates = qaoa_circuit(n, 1, seed=3)
+    gamma, two_beta = gates[n].theta, gates[-1].theta
+    assert [g.kind for g in gates].count("RZZ") == n * (n - 1) // 2
+    x = np.arange(1 << n)
+    pop = np.array([bin(int(v)).count("1") for v in x])
+    mag = n - 2 * pop
+    psi = np.full(1 << n, 2.0 ** (-n / 2), dtype=complex) * np.exp(-0.25j * gamma * (mag * mag - n))
+    mix = scipy.linalg.expm(-0.5j * two_beta * PX)
+    u = np.ones((1, 1), dtype=complex)
+    for _ in range(n):
+        u = np.kron(u, mix)
+    ref = u @ psi
+    assert np.max(np.abs(oracle.run(gates, psi0=basis_state_np(n, 0)) - ref)) < 1e-13
 
 
 # ------------------------------------------------------------- named gates
