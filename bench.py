@@ -194,6 +194,104 @@ def circuit_bench(args):
                       "circuits": out}))
 
 
+def qaoa_cpu_baseline(gates, n: int):
+    """The oracle (numpy, complex128) on a bounded sample of the QAOA circuit:
+    one RZZ and one RX of it at N=30 on the host cores, extrapolated to the
+    whole gate list by gate kind (H costs what RX costs: one dense 2x2)."""
+    import numpy as np
+
+    import oracle
+    from svgen import gaussian_state_np
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = 1
+    psi = gaussian_state_np(n, 2)
+    per_kind = {}
+    for kind in ("RZZ", "RX"):
+        g = next(g for g in gates if g.kind == kind)
+        t0 = time.perf_counter()
+        psi = oracle.apply_gate(psi, g)
+        per_kind[kind] = time.perf_counter() - t0
+    del psi
+    per_kind["H"] = per_kind["RX"]
+    est = sum(per_kind[g.kind] for g in gates)
+    return {"value": round(est, 1), "unit": "s", "cores": blas_threads, "kind": "oracle",
+            "sample": f"one RZZ and one RX at N={n}, complex128 ({per_kind['RZZ'] + per_kind['RX']:.1f} s), "
+                      f"scaled to the {len(gates)} gates by kind"}
+
+
+def qaoa_bench(args):
+    """QAOA benchmark: five levels on the complete graph K_N (N=30: 2175 RZZ,
+    150 RX, 30 H) from |0..0>, complex128 (the paper's precision) and
+    complex64, planned once (mode auto) and applied `steps` times after
+    `warmup`.  Checks on 4096 sampled amplitudes: the state is symmetric under
+    qubit permutations (equal amplitudes for a bit rotation of the index), and
+    the two precisions agree."""
+    import numpy as np
+    import torch
+
+    import paper_2409_14697_amd as sv
+    from svgen import qaoa_circuit
+
+    torch.cuda.set_device(0)
+    n = args.n
+    gates = qaoa_circuit(n, 5, seed=7)
+    stream = torch.cuda.Stream()
+    rng = np.random.default_rng(9)
+    xs = rng.integers(0, 1 << n, size=4096, dtype=np.int64)
+    rot = ((xs << 7) | (xs >> (n - 7))) & ((1 << n) - 1)  # the same Hamming weight
+    out, samples = {}, {}
+    for dtype in ("c128", "c64"):
+        st = sv.StateVector(n, dtype, stream=stream)
+        t0 = time.perf_counter()
+        plan = sv.Plan(n, dtype, gates, {"mode": args.mode})
+        plan_s = time.perf_counter() - t0
+        for _ in range(args.warmup):
+            st.init_basis(0)
+            st.apply_plan(plan)
+        times = []
+        for _ in range(args.steps):
+            st.init_basis(0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            st.apply_plan(plan)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        sec = sum(times) / len(times)
+        got = st.tensor[torch.from_numpy(np.concatenate([xs, rot])).cuda()].cpu().numpy().astype(np.complex128)
+        samples[dtype] = got[:4096]
+        scale = float(np.max(np.abs(got)))
+        n_passes = plan.info()[1]
+        S = (1 << n) * (16 if dtype == "c128" else 8)
+        kops = plan.kernel_ops()
+        out[dtype] = {"seconds": round(sec, 5), "min_s": round(min(times), 5), "gates": len(gates),
+                      "passes": n_passes, "kernel_ops": sum(k for k, _ in kops),
+                      "phase_ops": sum(lad for _, lad in kops), "plan_s": round(plan_s, 4),
+                      "sweep_GBs": round(n_passes * 2 * S / sec / 1e9, 1),
+                      "symmetry_max_rel_err": float(np.max(np.abs(got[:4096] - got[4096:]))) / scale}
+        st.close()
+        torch.cuda.empty_cache()
+    out["c64_vs_c128_max_rel_err"] = float(np.max(np.abs(samples["c64"] - samples["c128"]))) / float(
+        np.max(np.abs(samples["c128"])))
+    achieved = out["c128"]["sweep_GBs"]
+    rec = {"metric": f"QAOA seconds at N={n} (5 levels, complete graph, complex128)",
+           "value": out["c128"]["seconds"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * out["c128"]["seconds"], 3),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"QAOA: N={n}, 5 levels on K_{n} (RZZ on all pairs + RX on all qubits, "
+                                  f"angles from seed 7), complex128 and complex64", "mode": args.mode},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None},
+           "qaoa": out}
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = qaoa_cpu_baseline(gates, n)
+    print(json.dumps(rec))
+
+
 def serve_cpu_baseline(requests, budget_s: float = 15.0):
     """The oracle on a bounded sample of the serving mix: for one request of
     each N in the mix, time its first few gates (at least 2, more while the
@@ -441,14 +539,14 @@ def main():
     ap.add_argument("--rate-fraction", type=float, default=0.8, help="serve workload: arrival rate / saturated rate")
     ap.add_argument("--contention-gib", type=float, default=0.0,
                     help="serve workload: also run with this HBM budget (GiB)")
-    ap.add_argument("--workload", default="gates", choices=["gates", "circuit", "precision", "serve"],
+    ap.add_argument("--workload", default="gates", choices=["gates", "circuit", "precision", "serve", "qaoa"],
                     help="gates: the per-gate sweep benchmark (default); circuit: N=32 circuits; "
                          "precision: FP32 MFMA vs FP64 fused Haar gates")
     ap.add_argument("--gates", type=int, default=2000, help="precision workload: number of fused gates")
     ap.add_argument("--checkpoint", type=int, default=250, help="precision workload: gates between error checks")
     ap.add_argument("--seeds", default="4,5,6", help="precision workload: circuit seeds")
     ap.add_argument("--renorm", type=int, default=250, help="precision workload: FP64 renorm interval (0: off)")
-    ap.add_argument("--mode", default="auto", choices=["auto", "pass", "sweep"], help="plan mode (circuit workload)")
+    ap.add_argument("--mode", default="auto", choices=["auto", "pass", "sweep"], help="plan mode (circuit and qaoa workloads)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the state-vector hot path here runs on a single MI355X "
@@ -464,6 +562,9 @@ def main():
         return
     if args.workload == "serve":
         serve_bench(args)
+        return
+    if args.workload == "qaoa":
+        qaoa_bench(args)
         return
 
     import torch

@@ -65,6 +65,9 @@ sv_status pack_program(const sv_plan* p, sv_program* prog) {
       sd.op_first = (uint32_t)pops.size();
       sd.op_count = (uint32_t)sh.ops.size();
       const uint32_t mbase = (uint32_t)pool.size();
+      sd.mat_base = mbase;
+      sd.rows = sh.rows;
+      sd.row_count = sh.row_count;
       for (PassOpDev od : sh.ops) {
         od.mat += mbase;
         pops.push_back(od);

@@ -68,6 +68,7 @@ struct StageHost {
   std::vector<PassOpDev> ops;               // .mat indexes this stage's `mats`
   std::vector<cd> mats;
   std::vector<uint8_t> raw;                 // per entry: 1 = two raw words (write_pool)
+  uint32_t rows = 0, row_count = 0;         // phase-op row table (PassStageDev)
 };
 
 // Write `count` pool entries in the state precision (complex64: f32 = true).

@@ -268,26 +268,15 @@ __device__ __forceinline__ void op_d2(cplx<R>* v, cptr<cplx<R>> M) {
     default: break;                                                                          \
   }
 
-// Sum of the angle words (ladder layout) of the set bits: tile bits `sel`
-// (the same in every lane) and the lane's local bits `lsel`.
+// Sum of the local words (ladder layout) of the lane's set local bits.
 template <typename R>
-__device__ __forceinline__ typename lp_word<R>::W lp_sum(cptr<typename lp_word<R>::W> words, uint32_t lsel,
-                                                         uint64_t sel) {
+__device__ __forceinline__ typename lp_word<R>::W lp_local(cptr<typename lp_word<R>::W> words, uint32_t lsel) {
   typedef typename lp_word<R>::W W;
-  // words in chunks of 8 (one scalar load each; the loops stay rolled so
+  // words in chunks of 8 (one scalar load each; the loop stays rolled so
   // that only one chunk is live in scalar registers)
   constexpr int CH = 8;
   static_assert(kPassLPLocalBits % CH == 0, "local words come in whole chunks");
   W t = 0;
-#pragma unroll 1
-  for (int c = 0; c < (kPassLPTileBits + CH - 1) / CH && sel; ++c, sel >>= CH) {
-#pragma unroll
-    for (int b = 0; b < CH; ++b) {
-      const int i = CH * c + b;
-      const W w = i < kPassLPTileBits ? words[kPassLPLocalBits + i] : W(0);
-      t += ((sel >> b) & 1) ? w : W(0);
-    }
-  }
 #pragma unroll 1
   for (int c = 0; c < kPassLPLocalBits / CH; ++c, lsel >>= CH) {
 #pragma unroll
@@ -299,46 +288,74 @@ __device__ __forceinline__ typename lp_word<R>::W lp_sum(cptr<typename lp_word<R
   return t;
 }
 
-// POP_LP: the phase of the lane's amplitudes whose register bit b0 is 1:
-// the constant word plus the words of the set source bits, tile bits (the
-// same in every lane) and the lane's local group bits (xg has zeros at the
-// register positions).
-template <typename R>
-__device__ __forceinline__ cplx<R> lp_phase(const PassOpDev& op, cptr<cplx<R>> M, uint32_t xg, uint64_t base) {
-  typedef typename lp_word<R>::W W;
-  const cptr<W> words = (cptr<W>)M;
-  return lp_word<R>::phase(words[kPassLPConst] + lp_sum<R>(words, xg & op.lmask, base & op.tmask));
+// Tile rows of a phase op (entries of the stage's row table).
+__device__ __forceinline__ uint32_t op_rows(const PassOpDev& op) {
+  if (op.type == POP_LP) return 1u;
+  if (op.type == POP_QG) return 1u + __builtin_popcount(op.b0) + __builtin_popcountll(((uint64_t)op.pad << 32) | op.b1);
+  return 0u;
 }
 
-// POP_QG: row 0 and the constant, then the row of every set target bit.
-// The target loops run over uniform masks; a local target's row is summed
-// in every lane and kept where the lane's bit is set.
+// POP_LP: the phase of the lane's amplitudes whose register bit b0 is 1:
+// the constant word, the row's tile sum (ts[0], the same in every lane) and
+// the words of the lane's set local group bits (xg has zeros at the
+// register positions).
 template <typename R>
-__device__ __forceinline__ cplx<R> qg_phase(const PassOpDev& op, cptr<cplx<R>> M, uint32_t xg, uint64_t base) {
+__device__ __forceinline__ cplx<R> lp_phase(const PassOpDev& op, cptr<cplx<R>> M, uint32_t xg,
+                                            const typename lp_word<R>::W* ts) {
+  typedef typename lp_word<R>::W W;
+  const cptr<W> words = (cptr<W>)M;
+  return lp_word<R>::phase(words[kPassLPConst] + ts[0] + lp_local<R>(words, xg & op.lmask));
+}
+
+// POP_QG: row 0 and the constant, then the rows of the local targets set in
+// the lane (tile sum ts[k] plus the row's local words), then the tile-target
+// rows (their tile sums are zero unless the target bit is set).
+template <typename R>
+__device__ __forceinline__ cplx<R> qg_phase(const PassOpDev& op, cptr<cplx<R>> M, uint32_t xg,
+                                            const typename lp_word<R>::W* ts) {
   typedef typename lp_word<R>::W W;
   cptr<W> words = (cptr<W>)M;
   const uint32_t lsel = xg & op.lmask;
-  const uint64_t sel = base & op.tmask;
-  W t = words[kPassLPConst] + lp_sum<R>(words, lsel, sel);
+  W t = words[kPassLPConst] + ts[0] + lp_local<R>(words, lsel);
+  uint32_t k = 1;
 #pragma unroll 1
-  for (uint32_t lt = op.b0; lt; lt &= lt - 1u) {
+  for (uint32_t lt = op.b0; lt; lt &= lt - 1u, ++k) {
     words += kPassLPWords;
-    const W h = lp_sum<R>(words, lsel, sel);
+    const W h = ts[k] + lp_local<R>(words, lsel);
     t += ((xg >> __builtin_ctz(lt)) & 1u) ? h : W(0);
   }
+  const uint32_t end = op_rows(op);
 #pragma unroll 1
-  for (uint64_t tt = ((uint64_t)op.pad << 32) | op.b1; tt; tt &= tt - 1u) {
-    words += kPassLPWords;
-    if ((base >> __builtin_ctzll(tt)) & 1u) t += lp_sum<R>(words, 0u, sel);
-  }
+  for (; k < end; ++k) t += ts[k];
   return lp_word<R>::phase(t);
+}
+
+// Tile sums of the stage's phase-op rows into ts[] (all threads; ends with a
+// barrier).  Each thread sums whole rows: its 34 tile words are independent
+// loads, so they are in flight together.
+template <typename R>
+__device__ __forceinline__ void stage_rows(const PassStageDev& S, cptr<cplx<R>> mats, uint64_t base,
+                                           typename lp_word<R>::W* ts) {
+  typedef typename lp_word<R>::W W;
+  const cptr<cplx<R>> sm = mats + S.mat_base;
+  const cptr<uint32_t> rt = (cptr<uint32_t>)(sm + S.rows);
+  for (uint32_t j = threadIdx.x; j < S.row_count; j += kBlock) {
+    const uint32_t word = rt[4 * j], pred = rt[4 * j + 1];
+    const uint64_t sel = base & (rt[4 * j + 2] | ((uint64_t)rt[4 * j + 3] << 32));
+    const cptr<W> w = (cptr<W>)sm + word;
+    W acc = 0;
+#pragma unroll
+    for (int i = 0; i < kPassLPTileBits; ++i) acc += ((sel >> i) & 1) ? w[i] : W(0);
+    ts[j] = (pred == kPassNoSel || ((base >> pred) & 1)) ? acc : W(0);
+  }
+  __syncthreads();
 }
 
 // M points at the op's first matrix entry (the same address in every lane, so
 // the entries come through scalar loads); `var` selects a variant per lane.
 template <typename R, bool LP>
 __device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, uint32_t var,
-                                         cplx<R>* v, uint32_t xg, uint64_t base) {
+                                         cplx<R>* v, uint32_t xg, const typename lp_word<R>::W* ts) {
   const uint32_t pair = op.b0 * 8 + op.b1;
   constexpr bool H5 = Regs<R>::RB > 4;
   switch (op.type) {
@@ -402,7 +419,7 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, u
     case POP_LP: {  // one phase per lane on the amplitudes whose bit b0 is 1
       cplx<R> p;
       if (LP && op.type == POP_LP) {
-        p = lp_phase<R>(op, M, xg, base);
+        p = lp_phase<R>(op, M, xg, ts);
       } else {
         p = cget(M, 0);
         if (op.sa != kPassNoSel) {  // two variants, picked per lane
@@ -430,7 +447,7 @@ __device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, u
     }
     case POP_QG: {
       if constexpr (LP) {
-        const cplx<R> p = qg_phase<R>(op, M, xg, base);
+        const cplx<R> p = qg_phase<R>(op, M, xg, ts);
 #pragma unroll
         for (int r = 0; r < Regs<R>::NR; ++r) v[r] = cmul(p, v[r]);
       }
@@ -614,8 +631,13 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
   const uint32_t size = 1u << P->m;
   const uint32_t t = threadIdx.x;
   constexpr int RB = Regs<R>::RB, NR = Regs<R>::NR;
+  typedef typename lp_word<R>::W W;
+  __shared__ W tsum[LP ? kPassStageRowsMax : 1];  // tile sums of the stage's phase-op rows
   for (uint32_t si = 0; si < P->stage_count; ++si) {
     const PassStageDev S = cload(stages + (P->stage_first + si));
+    if constexpr (LP) {
+      if (S.row_count) stage_rows<R>(S, mats, base, tsum);
+    }
     const uint32_t groups = size >> RB;
     // swz is linear over XOR and xg shares no bit with a register offset, so
     // swz(xg | off) = swz(xg) ^ swz(off): the 16 offsets are swizzled once
@@ -642,6 +664,7 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
         const E e = tile[sx ^ soff[r]];
         v[r] = cplx<R>{e.x, e.y};
       }
+      uint32_t row = 0;  // the op's first row in tsum
       for (uint32_t o = 0; o < S.op_count; ++o) {
         const PassOpDev op = cload(ops + (S.op_first + o));
         if (!(LP && (op.type == POP_LP || op.type == POP_QG)) &&
@@ -654,7 +677,8 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
             var = (var << 1) |
                   (op.sb < kPassTileSel ? (xg >> op.sb) & 1u : (uint32_t)(base >> (op.sb - kPassTileSel)) & 1u);
         }
-        apply_op<R, LP>(op, mats + op.mat, var, v, xg, base);
+        apply_op<R, LP>(op, mats + op.mat, var, v, xg, tsum + row);
+        if constexpr (LP) row += op_rows(op);
       }
 #pragma unroll
       for (int r = 0; r < NR; ++r) {

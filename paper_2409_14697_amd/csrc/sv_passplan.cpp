@@ -380,7 +380,14 @@ struct StageBuilder {
       size_t e = i;
       while (e < ops.size() && phase_op(ops[e])) ++e;
       if (e - i >= (size_t)kPhaseRunMin) {
+        const size_t n_ops = sh->ops.size(), n_mats = sh->mats.size();
         encode_phase_run(sh, i, e);
+        if (stage_rows(*sh) > (uint32_t)kPassStageRowsMax) {  // over the stage's row table: gate by gate
+          sh->ops.resize(n_ops);
+          sh->mats.resize(n_mats);
+          sh->raw.resize(n_mats);
+          for (size_t x = i; x < e; ++x) encode_op(sh, ops[x]);
+        }
         i = e;
         continue;
       }
@@ -398,6 +405,62 @@ struct StageBuilder {
       encode_op(sh, ops[i]);
       ++i;
     }
+    encode_rows(sh);
+  }
+
+  // Tile-summed rows of a phase op (the row table of PassStageDev).
+  static uint32_t op_rows(const PassOpDev& od) {
+    if (od.type == POP_LP) return 1;
+    if (od.type == POP_QG)
+      return 1u + (uint32_t)__builtin_popcount(od.b0) + (uint32_t)__builtin_popcountll(qg_tile_targets(od));
+    return 0;
+  }
+  static uint64_t qg_tile_targets(const PassOpDev& od) { return ((uint64_t)od.pad << 32) | od.b1; }
+  static uint32_t stage_rows(const StageHost& sh) {
+    uint32_t r = 0;
+    for (const PassOpDev& od : sh.ops) r += op_rows(od);
+    return r;
+  }
+
+  // Four uint32 in pool words (two entries for complex64, one for complex128).
+  void put_u32x4(StageHost* sh, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    auto entry = [&](uint64_t w0, uint64_t w1) {
+      double re, im;
+      std::memcpy(&re, &w0, sizeof re);
+      std::memcpy(&im, &w1, sizeof im);
+      sh->mats.push_back(cd(re, im));
+      sh->raw.push_back(1);
+    };
+    if (rb == pass_reg_bits(SV_C64)) {
+      entry(a, b);
+      entry(c, d);
+    } else {
+      entry(a | (uint64_t)b << 32, c | (uint64_t)d << 32);
+    }
+  }
+
+  // The stage's row table: per row, the word index of its tile words, the
+  // tile bit that gates it (tile-target rows) and the tile mask.
+  void encode_rows(StageHost* sh) {
+    sh->rows = (uint32_t)sh->mats.size();
+    sh->row_count = 0;
+    const std::vector<PassOpDev> ops_now = sh->ops;
+    for (const PassOpDev& od : ops_now) {
+      const uint32_t nr = op_rows(od);
+      const uint32_t nl = od.type == POP_QG ? (uint32_t)__builtin_popcount(od.b0) : 0u;
+      uint64_t tt = od.type == POP_QG ? qg_tile_targets(od) : 0;
+      for (uint32_t k = 0; k < nr; ++k) {
+        uint32_t pred = kPassNoSel;
+        if (k > nl) {
+          pred = (uint32_t)__builtin_ctzll(tt);
+          tt &= tt - 1;
+        }
+        put_u32x4(sh, 2u * od.mat + k * (uint32_t)kPassLPWords + (uint32_t)kPassLPLocalBits, pred,
+                  (uint32_t)od.tmask, (uint32_t)(od.tmask >> 32));
+        ++sh->row_count;
+      }
+    }
+    if (!sh->row_count) sh->rows = 0;
   }
 
   void encode_op(StageHost* sh, const Op& op) {

@@ -261,6 +261,9 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
         sd.op_first = (uint32_t)pops.size();
         sd.op_count = (uint32_t)sh.ops.size();
         const uint32_t mbase = (uint32_t)pool.size();
+        sd.mat_base = mbase;
+        sd.rows = sh.rows;
+        sd.row_count = sh.row_count;
         for (PassOpDev od : sh.ops) {
           od.mat += mbase;
           pops.push_back(od);

@@ -73,10 +73,23 @@ struct alignas(16) PassOpDev {
   uint64_t tmask;  // tile (non-local) physical bits that must all be 1
 };
 
+// Rows of the stage's phase ops whose tile part is summed once per tile
+// (before the stage's groups run): one per POP_LP, and per POP_QG row 0, its
+// local-target rows and its tile-target rows, in op order.  A row
+// descriptor is four uint32 pool words: the word index of the row's first
+// tile word (counted from the stage's first pool entry, two words per entry),
+// the tile bit that must be set for the row to count (kPassNoSel: always),
+// and the tile mask (low, high).
+constexpr int kPassStageRowsMax = 256;
+
 struct PassStageDev {
   uint32_t q[kPassRegBitsMax];      // local bit of register bit r (r < rb)
   uint32_t qsort[kPassRegBitsMax];  // the same bits, ascending (group enumeration)
   uint32_t op_first, op_count;
+  uint32_t mat_base;                // the stage's first pool entry
+  uint32_t rows;                    // row descriptors: pool entry, from mat_base
+  uint32_t row_count;               // <= kPassStageRowsMax
+  uint32_t pad;
 };
 
 // PassDescDev flag: the store can walk the tile in load order (the lowest

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from oracle import sv_oracle as so
-from svgen import Gate, brickwork_circuit, gate_bench_set, haar_unitary, qft_circuit, serving_requests
+from svgen import Gate, brickwork_circuit, gate_bench_set, haar_unitary, qaoa_circuit, qft_circuit, serving_requests
 from svgen.states import gaussian_state_torch
 from tests.gpu_util import TOL, max_err, torch_dtype
 
@@ -181,6 +181,31 @@ def test_circuit_benchmark_n32_properties(sv):
     ref = np.zeros(idx.shape, dtype=np.complex128)
     ref[0] = 1.0
     assert max_err(got, ref) <= 1e-4
+    st.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_qaoa_n30_closed_form(sv, dtype):
+    """Five complete-graph QAOA levels at N=30 with the QAOA benchmark's plan
+    (mode auto): 4096 sampled amplitudes (with |0..0> and |1..1>) against the
+    symmetric-subspace closed form, within the dtype's tolerance relative to
+    the largest amplitude; the FP64 norm stays 1."""
+    import torch
+    from oracle import qaoa
+    n = 30
+    gates = qaoa_circuit(n, 5, seed=7)
+    st = sv.StateVector(n, dtype)
+    st.init_basis(0)
+    st.apply_circuit(gates, {"mode": "auto"})
+    st.sync()
+    rng = np.random.default_rng(9)
+    idx = np.concatenate([[0, (1 << n) - 1], rng.integers(0, 1 << n, size=4094, dtype=np.int64)])
+    amp = qaoa.weight_amplitudes(n, qaoa.levels_of(gates))
+    ref = amp[[bin(int(i)).count("1") for i in idx]]
+    got = read(st.tensor, idx)
+    assert max_err(got, ref) <= TOL[dtype] * np.max(np.abs(amp))
+    assert abs(st.norm2() - 1.0) < (1e-12 if dtype == "c128" else 1e-5)
     st.close()
     torch.cuda.empty_cache()
 

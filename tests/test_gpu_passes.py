@@ -143,6 +143,27 @@ def test_phase_runs(sv, dtype, lds, seed):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+def test_phase_runs_many_per_stage(sv, dtype):
+    """Twenty large phase runs separated by RX on one qubit, so that they all
+    fall in one register stage: the first fill the stage's table of tile
+    rows, the rest are applied gate by gate; against the oracle."""
+    n = 18
+    rng = np.random.default_rng(12)
+    gates = [Gate("H", (q,)) for q in range(n)]
+    for _ in range(20):
+        for a in range(n):
+            for b in range(a + 1, n):
+                if rng.random() < 0.5:
+                    gates.append(Gate("RZZ", (a, b), float(rng.uniform(-3, 3))))
+        gates.append(Gate("RX", (0,), float(rng.uniform(0, 3))))
+    opts = {"mode": "pass"}
+    kops, ladders = sv.Plan(n, dtype, gates, opts).kernel_ops()[-1]
+    assert ladders > 0 and kops > 200  # fused runs, then gate-by-gate ones
+    out, ref = run_plan(sv, n, dtype, basis_state_np(n, 0), gates, opts)
+    assert max_err(out, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("lds", [0, 6, 9])
 def test_qaoa_complete_graph(sv, dtype, lds):
     """Five QAOA levels on K_n from |0...0> (the H layer prepares |+>): every

@@ -174,6 +174,22 @@ def test_qaoa_level_closed_form(n):
     assert np.max(np.abs(oracle.run(gates, psi0=basis_state_np(n, 0)) - ref)) < 1e-13
 
 
+@pytest.mark.parametrize("n,levels", [(3, 1), (6, 3), (9, 5)])
+def test_qaoa_symmetric_closed_form(n, levels):
+    """The symmetric-subspace closed form of the complete-graph QAOA state
+    (used at full size) against the gate-by-gate oracle on every amplitude,
+    for several levels; the H-only and the no-level cases are |+>^n."""
+    from oracle import qaoa
+    gates = qaoa_circuit(n, levels, seed=20 + n)
+    lv = qaoa.levels_of(gates)
+    assert len(lv) == levels
+    amp = qaoa.weight_amplitudes(n, lv)
+    pop = np.array([bin(i).count("1") for i in range(1 << n)])
+    ref = oracle.run(gates, psi0=basis_state_np(n, 0))
+    assert np.max(np.abs(amp[pop] - ref)) < 1e-13
+    assert np.max(np.abs(qaoa.weight_amplitudes(n, []) - 2.0 ** (-n / 2))) < 1e-15
+
+
 # ------------------------------------------------------------- named gates
 @pytest.mark.parametrize("theta", [0.0, 0.3, 1.7, math.pi, 5.9])
 def test_rotations_are_matrix_exponentials(theta):
