@@ -9,7 +9,9 @@
 // or 16 (complex128) amplitudes (5 or 4 local bits held in registers) and
 // applies a list of ops to them in registers; ops whose controls or phase
 // bits lie outside the register bits read those bits from the group's local
-// index or from the tile base, and a phase ladder sums its angles from both.
+// index or from the tile base.  A fused run of diagonal gates (Sec. III-A) is
+// a phase function of the index bits: its fixed-point angle words are summed
+// per lane from both, with the tile part summed once per tile and stage.
 // The tile is written back with local bit j at physical position wpos[j],
 // which fuses qubit reordering (Sec. II-B) into the store.
 //

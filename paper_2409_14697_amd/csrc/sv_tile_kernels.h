@@ -33,8 +33,8 @@ enum PassOpType : uint32_t {
                // on register bit b0 (RX)                        (4 entries: re, im, im, re used)
   POP_P1 = 9,  // phase on the amplitudes whose bit b0 is 1     (1 entry)
   POP_P2 = 10, // phase on the amplitudes whose bits b0, b1 are 1 (1 entry)
-  POP_LP = 11, // phase ladder on register bit b0 (a run of controlled phases that
-               // share one qubit): the amplitudes whose bit b0 is 1 are
+  POP_LP = 11, // phase ladder on register bit b0 (the terms of a fused run of
+               // phase gates that involve that bit): the amplitudes whose bit b0 is 1 are
                // multiplied by exp(2 pi i t / 2^W), t = the constant word plus
                // the angle words of the set source bits (W-bit fixed-point
                // turns, summed modulo one turn; W = 32 for complex64, 64 for
