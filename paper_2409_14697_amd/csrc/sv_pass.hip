@@ -642,16 +642,11 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
     }
     const uint32_t groups = size >> RB;
     // swz is linear over XOR and xg shares no bit with a register offset, so
-    // swz(xg | off) = swz(xg) ^ swz(off): the 16 offsets are swizzled once
-    uint32_t soff[NR];
+    // swz(xg | off) = swz(xg) ^ (XOR of swz(bit) over the offset's bits): only
+    // the swizzled register bits are kept, not one offset per register
+    uint32_t sbit[RB];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      uint32_t o = 0;
-#pragma unroll
-      for (int b = 0; b < RB; ++b)
-        if ((r >> b) & 1) o |= 1u << S.q[b];
-      soff[r] = swz<WB>(o);
-    }
+    for (int b = 0; b < RB; ++b) sbit[b] = swz<WB>(1u << S.q[b]);
     for (uint32_t gi = t; gi < groups; gi += kBlock) {
       uint32_t xg = gi;
 #pragma unroll
@@ -663,7 +658,11 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
       cplx<R> v[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const E e = tile[sx ^ soff[r]];
+        uint32_t o = sx;
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+          if ((r >> b) & 1) o ^= sbit[b];
+        const E e = tile[o];
         v[r] = cplx<R>{e.x, e.y};
       }
       uint32_t row = 0;  // the op's first row in tsum
@@ -682,12 +681,23 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
         apply_op<R, LP>(op, mats + op.mat, var, v, xg, tsum + row);
         if constexpr (LP) row += op_rows(op);
       }
+      // The store recomputes the offsets from opaque copies of the inputs, so
+      // the compiler cannot keep the load's NR offsets live across the ops
+      // (they would take NR scalar registers and push the kernel into spills).
+      uint32_t sxs = sx;
+      asm volatile("" : "+v"(sxs));
+#pragma unroll
+      for (int b = 0; b < RB; ++b) asm volatile("" : "+s"(sbit[b]));
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         E e;
         e.x = v[r].re;
         e.y = v[r].im;
-        tile[sx ^ soff[r]] = e;
+        uint32_t o = sxs;
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+          if ((r >> b) & 1) o ^= sbit[b];
+        tile[o] = e;
       }
     }
     __syncthreads();
