@@ -118,8 +118,8 @@ bool real_diag_imag_offdiag(const cd* m) {
 
 static_assert(kPassLPTileBits >= SV_MAX_QUBITS, "every physical qubit has a ladder word");
 
-// Shortest run of phase gates worth fusing into one phase function (its
-// fixed cost is a few single phases).
+// Fewest two-qubit phase gates in a run worth fusing it into one phase
+// function (its fixed cost is a few single phases).
 constexpr int kPhaseRunMin = 3;
 
 struct StageBuilder {
@@ -376,10 +376,12 @@ struct StageBuilder {
       if (std::find(qs.begin(), qs.end(), l) == qs.end()) qs.push_back(l);
     for (int r = 0; r < rb; ++r) sh->q[r] = (uint32_t)qs[r];
     for (size_t i = 0; i < ops.size();) {
-      // a run of phase gates becomes one fixed-point quadratic phase
-      size_t e = i;
-      while (e < ops.size() && phase_op(ops[e])) ++e;
-      if (e - i >= (size_t)kPhaseRunMin) {
+      // a run of phase gates with pair terms becomes one fixed-point
+      // quadratic phase (single-qubit phases alone stay per-op: their own
+      // ops are cheaper than a per-lane phase function)
+      size_t e = i, pairs = 0;
+      while (e < ops.size() && phase_op(ops[e])) pairs += ops[e++].nq == 2;
+      if (pairs >= (size_t)kPhaseRunMin) {
         const size_t n_ops = sh->ops.size(), n_mats = sh->mats.size();
         encode_phase_run(sh, i, e);
         if (stage_rows(*sh) > (uint32_t)kPassStageRowsMax) {  // over the stage's row table: gate by gate
