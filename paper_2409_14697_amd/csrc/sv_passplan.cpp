@@ -370,11 +370,46 @@ struct StageBuilder {
     }
   }
 
+  static uint64_t qubit_mask(const Op& op) {
+    uint64_t mk = 0;
+    for (int i = 0; i < op.nq; ++i) mk |= 1ull << op.q[i];
+    return mk;
+  }
+
+  // Gate reordering for diagonal visibility (Sec. III-A): every phase op
+  // joins the phase ops before it when it commutes with the ops it moves
+  // past, i.e. shares no qubit with any of them that is not a phase op
+  // (phase ops commute with each other).  Program order is kept otherwise.
+  void gather_phases() {
+    std::vector<Op> out;
+    out.reserve(ops.size());
+    std::vector<char> taken(ops.size(), 0);
+    for (size_t i = 0; i < ops.size(); ++i) {
+      if (taken[i]) continue;
+      out.push_back(ops[i]);
+      taken[i] = 1;
+      if (!phase_op(ops[i])) continue;
+      uint64_t blocked = 0;  // qubits of the non-phase ops left in place so far
+      for (size_t j = i + 1; j < ops.size(); ++j) {
+        if (taken[j]) continue;
+        const uint64_t mk = qubit_mask(ops[j]);
+        if (!phase_op(ops[j])) {
+          blocked |= mk;
+        } else if (!(mk & blocked)) {
+          out.push_back(ops[j]);
+          taken[j] = 1;
+        }
+      }
+    }
+    ops.swap(out);
+  }
+
   void encode(StageHost* sh) {
     // pad the register bits with the lowest unused local bits
     for (int l = 0; (int)qs.size() < rb && l < m; ++l)
       if (std::find(qs.begin(), qs.end(), l) == qs.end()) qs.push_back(l);
     for (int r = 0; r < rb; ++r) sh->q[r] = (uint32_t)qs[r];
+    gather_phases();
     for (size_t i = 0; i < ops.size();) {
       // a run of phase gates with pair terms becomes one fixed-point
       // quadratic phase (single-qubit phases alone stay per-op: their own

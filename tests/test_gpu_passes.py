@@ -126,6 +126,39 @@ def phase_run_circuit(n, seed):
     return out
 
 
+def interleaved_phase_circuit(n, count, seed):
+    """Two-qubit phase gates (RZZ, CPHASE, CZ) and RZ interleaved with H / RX
+    on random qubits, so that runs of phase gates form only after the phase
+    gates are moved past the gates on other qubits."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        r = rng.random()
+        a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+        if r < 0.6:
+            out.append(Gate(["RZZ", "CPHASE", "CZ"][int(rng.integers(3))], (a, b), float(rng.uniform(-7, 7))))
+        elif r < 0.7:
+            out.append(Gate("RZ", (a,), float(rng.uniform(-7, 7))))
+        elif r < 0.85:
+            out.append(Gate("H", (a,)))
+        else:
+            out.append(Gate("RX", (a,), float(rng.uniform(0, 6))))
+    return out
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("lds", [0, 8])
+def test_phase_gates_reordered(sv, dtype, lds):
+    """Phase gates gathered past the gates they commute with (other qubits)
+    and fused, against the oracle."""
+    n = 15
+    gates = interleaved_phase_circuit(n, 400, 8)
+    opts = {"mode": "pass", "lds_qubits": lds}
+    assert sum(lad for _, lad in sv.Plan(n, dtype, gates, opts).kernel_ops()) > 0
+    out, ref = run_plan(sv, n, dtype, gaussian_state_np(n, 47), gates, opts)
+    assert max_err(out, ref) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("lds", [0, 7, 10])
 @pytest.mark.parametrize("seed", [3, 4])
@@ -144,21 +177,24 @@ def test_phase_runs(sv, dtype, lds, seed):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_phase_runs_many_per_stage(sv, dtype):
-    """Twenty large phase runs separated by RX on one qubit, so that they all
-    fall in one register stage: the first fill the stage's table of tile
-    rows, the rest are applied gate by gate; against the oracle."""
-    n = 18
+    """Forty runs of RZZ on all pairs of qubits 2..15, each closed by CNOTs
+    from every one of those qubits onto qubit 1 (so no phase gate can move
+    into an earlier run, and the stage keeps one register bit busy): the
+    first runs fill the stage's table of tile rows, the rest are applied
+    gate by gate; against the oracle."""
+    n = 16
     rng = np.random.default_rng(12)
     gates = [Gate("H", (q,)) for q in range(n)]
-    for _ in range(20):
-        for a in range(n):
+    for _ in range(40):
+        for a in range(2, n):
             for b in range(a + 1, n):
-                if rng.random() < 0.5:
-                    gates.append(Gate("RZZ", (a, b), float(rng.uniform(-3, 3))))
-        gates.append(Gate("RX", (0,), float(rng.uniform(0, 3))))
+                gates.append(Gate("RZZ", (a, b), float(rng.uniform(-3, 3))))
+        gates += [Gate("CNOT", (c, 1)) for c in range(2, n)]
     opts = {"mode": "pass"}
     kops, ladders = sv.Plan(n, dtype, gates, opts).kernel_ops()[-1]
-    assert ladders > 0 and kops > 200  # fused runs, then gate-by-gate ones
+    # fused runs cost a few ops each, the 560 CNOTs one each; more than
+    # that means runs applied gate by gate
+    assert ladders > 0 and kops > 560 + 40 * 10
     out, ref = run_plan(sv, n, dtype, basis_state_np(n, 0), gates, opts)
     assert max_err(out, ref) <= TOL[dtype]
 
