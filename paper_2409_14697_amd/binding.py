@@ -230,7 +230,8 @@ class Plan:
         return out
 
     def kernel_ops(self) -> List[Tuple[int, int]]:
-        """(kernel ops, phase ladders among them) per pass (sv_plan_pass_ops)."""
+        """(kernel ops, fixed-point phase ops among them: ladders and quadratic
+        phases) per pass (sv_plan_pass_ops)."""
         lib = load_library()
         _, n_passes = self.info()
         out = []
