@@ -3,8 +3,9 @@
 The oracle cannot hold a 2^30 or 2^32 state, so these tests compare sampled
 outputs it computes one group at a time (Eq. 2/3 on the sampled group's
 amplitudes, read from the device right before the gate), or properties that
-hold at any size: the QFT's closed form on a basis state, a circuit followed
-by its inverse returning the start state, and the norm."""
+hold at any size: the QFT's closed form on a basis state, the complete-graph
+QAOA state's symmetric-subspace closed form (oracle/qaoa.py), a circuit
+followed by its inverse returning the start state, and the norm."""
 import math
 
 import numpy as np
@@ -242,6 +243,30 @@ def test_serving_large_requests(sv, dtype):
         b = mixed[r.rid].handle["tensor"].cpu().numpy()
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), r.rid
         assert np.array_equal(alone.probs, mixed[r.rid].probs)
+
+
+@pytest.mark.parametrize("dtype,n", [("c64", 34), ("c128", 33)])
+def test_qaoa_maximum_state_size(sv, dtype, n):
+    """Two complete-graph QAOA levels on the largest states (128 GiB): tile
+    bits at physical positions 32 and 33 feed the fused phase ops (their
+    high mask word); 4096 sampled amplitudes against the symmetric-subspace
+    closed form."""
+    import torch
+    from oracle import qaoa
+    gates = qaoa_circuit(n, 2, seed=5)
+    st = sv.StateVector(n, dtype)
+    st.init_basis(0)
+    st.apply_circuit(gates, {"mode": "auto"})
+    st.sync()
+    rng = np.random.default_rng(13)
+    idx = np.concatenate([[0, (1 << n) - 1, 1 << (n - 1), 3 << (n - 2)],
+                          rng.integers(0, 1 << n, size=4092, dtype=np.int64)])
+    amp = qaoa.weight_amplitudes(n, qaoa.levels_of(gates))
+    ref = amp[[bin(int(i)).count("1") for i in idx]]
+    got = read(st.tensor, idx)
+    assert max_err(got, ref) <= TOL[dtype] * np.max(np.abs(amp))
+    st.close()
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("dtype,n", [("c64", 34), ("c128", 33)])
