@@ -129,7 +129,9 @@ sv_status sv_default_opts(sv_opts *o);
 
 #define SV_NO_INIT 1u  /* sv_create flag: keep the buffer's current contents */
 
-/* Create a state of n_qubits (1..SV_MAX_QUBITS) amplitudes of type dt.
+/* Create a state vector |phi> = sum_i a_i |i> of 2^n_qubits amplitudes
+ * (Eq. 1 and the state of Sec. II-A: one complex amplitude per basis state,
+ * qubit q = index bit q), n_qubits in 1..SV_MAX_QUBITS, of type dt.
  *   dev_ptr    : NULL -> the library allocates 2^n elements on the current
  *                HIP device and frees them in sv_destroy; otherwise borrowed
  *                device memory of at least 2^n elements, 256-byte aligned,
@@ -169,10 +171,13 @@ sv_status sv_apply_gate(sv_state *s, const sv_gate *g);
 sv_status sv_fuse(int n_qubits, sv_dtype dt, const sv_gate *g, size_t n_gates,
                   const sv_opts *o, sv_plan **out);
 
-/* Plan introspection: number of fused ops and of state sweeps (passes). */
+/* Plan introspection: number of fused ops (Sec. II-B gate fusion) and of
+ * state sweeps (passes: in-cache tile passes of Sec. III-B count one each). */
 sv_status sv_plan_info(const sv_plan *p, size_t *n_ops, size_t *n_passes);
 
-/* Export fused op `op` (0-based, in execution order) in logical qubits:
+/* Export fused op `op` (0-based, in execution order) in logical qubits, as
+ * the generic gate that general gate fusion produces (Sec. II-B "Gate
+ * Fusion", Sec. III-A tier 5: the product of the fused gates' matrices):
  *   *nq, q[0..nq-1] (q[0] = MSB of the local index), the 2^nq x 2^nq matrix
  *   into m (row-major interleaved FP64; caller buffer of 2*64*64 doubles) and
  *   the pass it runs in (-1: a SWAP realised by relabeling qubits, no data
@@ -206,11 +211,18 @@ sv_status sv_plan_pass_ops(const sv_plan *p, size_t pass, int32_t *n_ops, int32_
 
 sv_status sv_plan_destroy(sv_plan *p);
 
-/* Execute a plan built for this state's n and dtype.  Async.  The state is
- * in logical qubit order again when the plan's last pass completes. */
+/* Execute a plan built for this state's n and dtype: the gate-by-gate
+ * result of Eq. 2 / Eq. 3 for every gate of the planned circuit, reached
+ * through fused ops, in-cache tile passes and qubit reordering (Sec. II-B,
+ * Sec. III-A/B).  Async.  The state is in logical qubit order again when the
+ * plan's last pass completes.  Errors: SV_ERR_ARG (null, or a plan built for
+ * another n or dtype), SV_ERR_NOMEM (upload buffer), SV_ERR_DEVICE. */
 sv_status sv_apply_plan(sv_state *s, const sv_plan *p);
 
-/* sv_fuse + sv_apply_plan + sv_plan_destroy. */
+/* Apply a gate list (a circuit, Sec. II-B / Sec. III: simulation applies its
+ * gates in order by Eq. 2 / Eq. 3) to the state: sv_fuse + sv_apply_plan +
+ * sv_plan_destroy with options o (NULL = defaults).  Async.  Errors: those of
+ * sv_fuse (nothing enqueued) and of sv_apply_plan. */
 sv_status sv_apply_circuit(sv_state *s, const sv_gate *g, size_t n_gates, const sv_opts *o);
 
 /* Physically reorder qubits (Sec. II-B qubit reordering / in-memory
@@ -222,7 +234,9 @@ sv_status sv_apply_circuit(sv_state *s, const sv_gate *g, size_t n_gates, const 
  * SV_ERR_DEVICE. */
 sv_status sv_permute_qubits(sv_state *s, const int32_t *dest);
 
-/* Marginal probabilities over m qubits (0 <= m <= n, distinct):
+/* Marginal probabilities over m qubits (0 <= m <= n, distinct), from the
+ * probability |a_i|^2 of basis state |i> (Eq. 1) and the normalisation
+ * sum_i |a_i|^2 = 1 of Sec. II-A:
  *   out_dev[b] = sum of |a_i|^2 over all i whose bit qubits[r] equals bit
  *   (m-1-r) of b, i.e. qubits[0] is the most significant bit of b.
  * m = 0 gives out_dev[0] = sum |a_i|^2 (the squared norm).  Accumulated in

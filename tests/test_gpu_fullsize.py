@@ -245,6 +245,50 @@ def test_serving_large_requests(sv, dtype):
         assert np.array_equal(alone.probs, mixed[r.rid].probs)
 
 
+_LARGE_REFS = {}
+
+
+def _large_ref(r):
+    """Oracle state of a served request (computed once, shared by both dtypes)."""
+    if r.rid not in _LARGE_REFS:
+        _LARGE_REFS[r.rid] = oracle.run(r.circuit(), n=r.n)
+    return _LARGE_REFS[r.rid]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_serving_large_requests_vs_oracle(sv, dtype):
+    """Requests of N = 21, 22, 23 and 24 (several tile passes each: the batched
+    kernel's multi-pass programs with permuted write-backs) served in a mix
+    with N = 12..16 requests: every amplitude and the marginal over the lowest
+    16 qubits of every request against the oracle, at the dtype's tolerance
+    (marginals: 1e-12 / 4e-5).  Short circuits (3 layer pairs) keep the host
+    oracle to well under a minute."""
+    from paper_2409_14697_amd import binding as B
+    from paper_2409_14697_amd.serve import DeviceEngine, Server, free_budget, make_jobs
+    from svgen.circuits import Request
+    seeds = np.random.SeedSequence(24).spawn(4)
+    big = [Request(200 + i, n, 3, int(seeds[i].generate_state(1)[0]), 0.0) for i, n in enumerate((21, 22, 23, 24))]
+    small = serving_requests(6, seed=25, n_range=(12, 16), depth_range=(3, 6))
+    for i, r in enumerate(small):
+        r.rid = 300 + i
+    reqs = big + small
+    print(f"serving vs oracle: dtype={dtype} n={[r.n for r in reqs]}", flush=True)
+    jobs = make_jobs(reqs, None, B.make_gates)
+    eng = DeviceEngine(dtype, keep_states=True)
+    Server(eng, free_budget(0.5), plan_workers=4).run(jobs)
+    eng.close()
+    done = {j.rid: j for j in jobs}
+    ptol = 1e-12 if dtype == "c128" else 4e-5
+    for r in reqs:
+        j = done[r.rid]
+        assert j.status == "done", r.rid
+        ref = _large_ref(r)
+        got = j.handle["tensor"].cpu().numpy().astype(np.complex128)
+        assert max_err(got, ref) <= TOL[dtype], (r.rid, r.n)
+        k = min(r.n, 16)
+        assert max_err(j.probs, oracle.probs(ref, list(range(k - 1, -1, -1)))) <= ptol, (r.rid, r.n)
+
+
 @pytest.mark.parametrize("dtype,n", [("c64", 34), ("c128", 33)])
 def test_qaoa_maximum_state_size(sv, dtype, n):
     """Two complete-graph QAOA levels on the largest states (128 GiB): tile
