@@ -244,6 +244,20 @@ sv_status sv_permute_qubits(sv_state *s, const int32_t *dest);
  * out_dev: device memory for 2^m doubles.  Async. */
 sv_status sv_measure_probs(sv_state *s, const int32_t *qubits, int m, double *out_dev);
 
+/* sv_measure_probs for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same marginal, bitwise, with its reduction partials in a
+ * static device array of the library (8 MiB per GPU, held until the process
+ * ends) instead of the state's lazily allocated scratch.  Calls no hipMalloc
+ * or hipFree; the first call on a GPU resolves the array's address there.
+ * Every call on one GPU shares that array: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and may return wrong
+ * values; order them.  Same arguments, ownership and errors as
+ * sv_measure_probs, plus SV_ERR_UNSUPPORTED if a reduction ever needed more
+ * than the array holds (the reduction's geometry keeps every marginal
+ * within it). */
+sv_status sv_measure_probs_noalloc(sv_state *s, const int32_t *qubits, int m, double *out_dev);
+
 /* Multiply every amplitude by the real factor `scale` (e.g. 1/||psi|| in
  * FP64).  Async. */
 sv_status sv_scale(sv_state *s, double scale);

@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sv_apply_circuit": (S, [c_void_p, POINTER(SvGate), c_size_t, POINTER(SvOpts)]),
         "sv_permute_qubits": (S, [c_void_p, POINTER(c_int32)]),
         "sv_measure_probs": (S, [c_void_p, POINTER(c_int32), c_int, c_void_p]),
+        "sv_measure_probs_noalloc": (S, [c_void_p, POINTER(c_int32), c_int, c_void_p]),
         "sv_scale": (S, [c_void_p, c_double]),
         "sv_sync": (S, [c_void_p]),
         "sv_last_error": (c_char_p, []),
@@ -322,14 +323,18 @@ class StateVector:
         d = (c_int32 * self.n)(*[int(x) for x in dest])
         check(load_library().sv_permute_qubits(self._h, d))
 
-    def measure_probs(self, qubits: Optional[Sequence[int]] = None, out=None):
+    def measure_probs(self, qubits: Optional[Sequence[int]] = None, out=None, noalloc: bool = False):
+        """Marginal probabilities (sv_measure_probs; noalloc=True calls
+        sv_measure_probs_noalloc, whose partials live in the library's static
+        device array; `out` must then be given by a caller that cannot allocate)."""
         import torch
         qubits = list(range(self.n - 1, -1, -1)) if qubits is None else [int(q) for q in qubits]
         m = len(qubits)
         if out is None:
             out = torch.empty(1 << m, dtype=torch.float64, device=self.tensor.device)
         qa = (c_int32 * max(1, m))(*qubits)
-        check(load_library().sv_measure_probs(self._h, qa, m, c_void_p(out.data_ptr())))
+        fn = load_library().sv_measure_probs_noalloc if noalloc else load_library().sv_measure_probs
+        check(fn(self._h, qa, m, c_void_p(out.data_ptr())))
         return out
 
     def norm2(self) -> float:

@@ -426,6 +426,21 @@ sv_status sv_measure_probs(sv_state* s, const int32_t* qubits, int m, double* ou
   return SV_OK;
 }
 
+sv_status sv_measure_probs_noalloc(sv_state* s, const int32_t* qubits, int m, double* out_dev) {
+  clear_error();
+  if (sv_status st = check_state(s)) return st;
+  int qs[SV_MAX_QUBITS];
+  if (sv_status st = probs_args(s->n, qubits, m, out_dev, qs)) return st;
+  const size_t need = probs_scratch_bytes(s->n, m, qs);
+  if (need > static_scratch_bytes())
+    return fail(SV_ERR_UNSUPPORTED, "reduction needs %zu bytes of scratch, the static array holds %zu", need,
+                static_scratch_bytes());
+  void* scratch = nullptr;
+  SV_HIP_TRY(static_scratch(s->device, &scratch));
+  SV_HIP_TRY(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, scratch, s->stream));
+  return SV_OK;
+}
+
 sv_status sv_scale(sv_state* s, double scale) {
   clear_error();
   if (sv_status st = check_state(s)) return st;

@@ -76,6 +76,10 @@ hipError_t launch_sweep(sv_dtype dt, void* psi, int n, const SweepArgs& a, hipSt
 size_t probs_scratch_bytes(int n, int m, const int* qubits);
 hipError_t launch_probs(sv_dtype dt, const void* psi, int n, const int* qubits, int m, double* out,
                         void* scratch, hipStream_t s);
+// The library's static reduction scratch on `device` (a file-scope device
+// array; no allocation): its bytes, and its device address.
+size_t static_scratch_bytes();
+hipError_t static_scratch(int device, void** out);
 
 // --- utilities --------------------------------------------------------------
 hipError_t launch_init_basis(sv_dtype dt, void* psi, int n, uint64_t index, hipStream_t s);

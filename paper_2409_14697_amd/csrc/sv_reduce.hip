@@ -14,6 +14,8 @@
 // accumulates exactly one output bin.  Lanes that share a bin (they differ
 // only in unmeasured low bits) are combined in a fixed order through LDS, and
 // the per-chunk partial sums are added in chunk order by a second kernel.
+#include <mutex>
+
 #include "sv_device.h"
 #include "sv_kernels.h"
 
@@ -121,7 +123,44 @@ ProbGeo make_geo(int n, int m, const int* qubits, unsigned* chunks_out, uint64_t
   return g;
 }
 
+// Reduction partials of sv_measure_probs_noalloc: one array per GPU, held
+// until the process ends.  The block and chunk geometry above never needs
+// more than 4096 blocks' worth of 256 bins (2^20 doubles), so every marginal
+// fits; calls that overlap on one GPU share it (and race).
+constexpr size_t kStaticScratchDoubles = 1ull << 20;  // 8 MiB
+__device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+size_t static_scratch_bytes() { return kStaticScratchDoubles * sizeof(double); }
+
+// The device address of `scratch` on `device`, resolved once per device with
+// that device current (in host code the array's name is only a stand-in).
+hipError_t static_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t r = hipSetDevice(cur);
+      if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 size_t probs_scratch_bytes(int n, int m, const int* qubits) {
   unsigned chunks;
