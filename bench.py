@@ -1,22 +1,29 @@
-"""Gate-sweep benchmark: HBM GB/s per gate at N=30 on one MI355X.
+"""Benchmarks of the state-vector hot path on one MI355X.  Prints ONE JSON line.
 
-Workload (the per-gate benchmark of QueenV2 Sec. IV-B, made concrete): a
-normalised complex Gaussian state of N=30 qubits in complex128 (16 GiB) and in
-complex64 (8 GiB), seeded; each of H, X, RZ, CNOT, CZ, SWAP, CPHASE applied on
-every target qubit 0..29 (two-qubit partners drawn at random), one gate per
-sv_apply_gate call.  One step = all 210 gates on the complex128 state and all
-210 on the complex64 state.
+Default run (the headline first, then the other two parts of the metric
+"HBM GB/s per gate at N=30; circuit sec; served circuits/s + p99 latency"):
 
-value = algorithmic bytes / time over the timed steps, where a gate's
-algorithmic bytes are the bytes it must read and write: 2 * S * f, S the state
-size and f the fraction of 128-byte lines that hold an amplitude the gate
-changes (1 for H/X/RZ; 1/2 or 1 for CNOT and SWAP; 1/4, 1/2 or 1 for CZ and
-CPHASE, depending on whether the gate's qubits lie above the line).  128 bytes
-is the read granularity FETCH_SIZE shows on MI355X.
+  * gate benchmark (the per-gate benchmark of QueenV2 Sec. IV-B, made
+    concrete): a normalised complex Gaussian state of N=30 qubits in
+    complex128 (16 GiB, the paper's FP64) and complex64 (8 GiB), seeded; each
+    of H, X, RZ, CNOT, CZ, SWAP, CPHASE on every target qubit 0..29 (two-qubit
+    partners drawn at random), one gate per sv_apply_gate call.  One step =
+    the 210 gates on each state.  value = complex128 algorithmic bytes /
+    kernel time (GB/s); complex64 is reported beside it.  A gate's algorithmic
+    bytes are 2 * S * f, S the state size and f the fraction of 128-byte lines
+    holding an amplitude the gate changes (1 for H/X/RZ; 1/2 or 1 for CNOT
+    and SWAP; 1/4, 1/2 or 1 for CZ and CPHASE).
+  * "circuit": N=32 complex64 (32 GiB) brickwork depth 40 + QFT with the
+    planner's plans (Sec. IV-C circuit families), seconds and passes;
+  * "precision": N=30, 2000 fused Haar 5/6-qubit gates (one seed), FP32 MFMA
+    against FP64 on the same GPU, with errors;
+  * "serving": continuous batching of random circuit requests (N 12..26),
+    closed-loop throughput, Poisson arrivals at 0.8 x, p50 / p99 latency.
 
-Every launch is bracketed by HIP events on the stream the library launches on
-(torch's current stream, handed to sv_create), so per-kernel average durations
-come from the same timed region.  Prints ONE JSON line.
+Every launch of the gate benchmark is bracketed by HIP events on the stream
+the library launches on (torch's current stream, handed to sv_create), so
+per-kernel average durations come from the same timed region.  Inputs are
+resident in HBM before every timed region; no host transfer is timed.
 """
 from __future__ import annotations
 
@@ -34,8 +41,14 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 # vector (VALU) peaks: 256 CUs x 2.4 GHz; FP32 counts packed math, FP64 does not
 PEAK_VALU_TFLOPS = {"c64": 157.3, "c128": 78.6}
+# dense matrix-core peaks (no sparsity): FP32 and FP64 MFMA
+PEAK_MFMA_TFLOPS = {"c64": 157.3, "c128": 78.6}
 N_QUBITS = 30
 LINE = 128  # bytes per memory read granule (FETCH_SIZE of sub-line subsets)
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def line_qubits(dtype: str) -> int:
@@ -105,38 +118,181 @@ def load_traffic(kernel_key: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(gates, n: int):
-    """The oracle (numpy, complex128) on a bounded sample of the same workload:
-    three gates of the set at N=30 on the host cores."""
+# ---------------------------------------------------------------- CPU baseline
+def _host_info():
+    """The host the oracle runs on: core counts, BLAS build, thread settings."""
     import numpy as np
-
-    import oracle
-    from svgen import gaussian_state_np
+    info = {"cpu_count": os.cpu_count()}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        info["affinity"] = None
+    try:
+        cfg = np.show_config(mode="dicts")
+        blas = cfg.get("Build Dependencies", {}).get("blas", {})
+        info["blas"] = f"{blas.get('name', '?')} {blas.get('version', '')}".strip()
+    except Exception:
+        info["blas"] = "?"
     try:
         from threadpoolctl import threadpool_info
-        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        pools = threadpool_info()
+        info["blas_threads"] = max([p.get("num_threads", 1) for p in pools] or [1])
+        info["blas_runtime"] = ", ".join(sorted({f"{p.get('internal_api')} {p.get('version')}" for p in pools}))
     except Exception:
-        blas_threads = 1
-    sample = [g for g in gates if (g.kind, g.qubits[-1]) in (("H", n - 1), ("CNOT", 0), ("CPHASE", n // 2))]
+        info["blas_threads"] = 1
+    info["thread_env"] = {k: os.environ[k] for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+                          if k in os.environ}
+    return info
+
+
+def _oracle_gate_rate(gates, n: int):
+    """Oracle seconds and algorithmic GB/s over `gates` at N=n (complex128)."""
+    import oracle
+    from svgen import gaussian_state_np
     psi = gaussian_state_np(n, 2)
     total_bytes, total_t = 0.0, 0.0
-    for g in sample:
+    for g in gates:
         t0 = time.perf_counter()
         psi = oracle.apply_gate(psi, g)
         total_t += time.perf_counter() - t0
         total_bytes += 2.0 * (1 << n) * 16 * touched_fraction(g, "c128")
-    del psi
+    return total_bytes / total_t / 1e9, total_t
+
+
+def cpu_baseline(gates, n: int):
+    """The oracle (numpy, complex128) on a bounded sample of the gate
+    benchmark -- three of its gates at N=30 -- on the host cores, with all
+    BLAS threads and with one; plus the seconds the oracle takes for the
+    N=16, 200-gate parity circuit."""
+    import oracle
+    from svgen import layered_circuit
+    host = _host_info()
+    sample = [g for g in gates if (g.kind, g.qubits[-1]) in (("H", n - 1), ("CNOT", 0), ("CPHASE", n // 2))]
+    gbs, secs = _oracle_gate_rate(sample, n)
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            gbs1, secs1 = _oracle_gate_rate(sample[:1], n)
+        single = {"value": round(gbs1, 3), "unit": "GB/s", "cores": 1, "sample": f"{sample[0].kind}{sample[0].qubits} at N={n}",
+                  "seconds": round(secs1, 2)}
+    except Exception as e:  # threadpoolctl missing: say so
+        single = {"error": str(e)}
+    c1 = layered_circuit(16, n_gates=200, seed=1)
+    t0 = time.perf_counter()
+    oracle.run(c1, n=16)
+    c1_s = time.perf_counter() - t0
     desc = ", ".join(f"{g.kind}{g.qubits}" for g in sample)
-    return {"value": total_bytes / total_t / 1e9, "unit": "GB/s", "cores": blas_threads, "kind": "oracle",
-            "sample": f"{len(sample)} gates of the set ({desc}) at N={n}, complex128, {total_t:.1f} s"}
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": host["blas_threads"], "kind": "oracle",
+            "sample": f"{len(sample)} gates of the set ({desc}) at N={n}, complex128, {secs:.1f} s",
+            "single_thread": single, "c1_parity_circuit_s": round(c1_s, 4),
+            "c1_workload": "N=16 complex128, 200-gate layered circuit (seed 1), all host threads",
+            "host": host}
 
 
-def circuit_bench(args):
+# ---------------------------------------------------------------- gate benchmark
+def gates_bench(args):
+    import torch
+
+    import paper_2409_14697_amd as sv
+    from svgen import gate_bench_set
+    from svgen.states import gaussian_state_torch
+
+    torch.cuda.set_device(0)
+    n = args.n
+    gates = gate_bench_set(n, seed=2)
+    dtypes = [d for d in args.dtypes.split(",") if d]
+    stream = torch.cuda.current_stream()
+    per_kernel = {}   # (dtype, key) -> [bytes, seconds, launches]
+    per_dtype = {}
+    launch_min = {}   # dtype -> (GB/s, gate) of the slowest (gate, target) launch
+    for dtype in dtypes:
+        tdt = torch.complex128 if dtype == "c128" else torch.complex64
+        psi = gaussian_state_torch(n, 2, tdt)
+        st = sv.StateVector(n, dtype, tensor=psi, init=False, stream=stream)
+        S = psi.numel() * psi.element_size()
+        kernels = [sv.gate_kernel(n, dtype, g) for g in gates]
+        for _ in range(args.warmup):
+            for g in gates:
+                st.apply_gate(g)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in gates]
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        durations = [0.0] * len(gates)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(args.steps):
+            for i, g in enumerate(gates):
+                evs[i][0].record(stream)
+                st.apply_gate(g)
+                evs[i][1].record(stream)
+            stream.synchronize()
+            for i in range(len(gates)):
+                durations[i] += evs[i][0].elapsed_time(evs[i][1]) * 1e-3
+        stop.record(stream)
+        torch.cuda.synchronize()
+        wall = start.elapsed_time(stop) * 1e-3
+        dbytes = 0.0
+        worst = None
+        for i, g in enumerate(gates):
+            b = 2.0 * S * touched_fraction(g, dtype) * args.steps
+            dbytes += b
+            rate = b / durations[i] / 1e9
+            if worst is None or rate < worst[0]:
+                worst = (rate, f"{g.kind}{tuple(g.qubits)}")
+            acc = per_kernel.setdefault((dtype, kernels[i]), [0.0, 0.0, 0])
+            acc[0] += b
+            acc[1] += durations[i]
+            acc[2] += args.steps
+        kern_s = sum(durations)
+        per_dtype[dtype] = {"GB/s": round(dbytes / kern_s / 1e9, 1), "ms_per_step": round(1e3 * wall / args.steps, 3),
+                            "gates_per_step": len(gates), "kernel_s": kern_s, "bytes": dbytes}
+        launch_min[dtype] = {"GB/s": round(worst[0], 1), "gate": worst[1], "frac": round(worst[0] / PEAK_HBM_GBS, 4)}
+        st.close()
+        del psi
+        torch.cuda.empty_cache()
+
+    copy_gbs = None
+    if args.copy_ceiling:
+        src = torch.empty(1 << (n - 1), dtype=torch.complex128, device="cuda")
+        dst = torch.empty_like(src)
+        sv.util_copy(dst, src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            sv.util_copy(dst, src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        copy_gbs = 2.0 * src.numel() * 16 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del src, dst
+    head = "c128" if "c128" in per_dtype else dtypes[0]
+    # dominant kernel of the headline dtype = the one with the most time in the timed region
+    (_, dom_key), (dbytes, dsec, dl) = max(((k, v) for k, v in per_kernel.items() if k[0] == head),
+                                           key=lambda kv: kv[1][1])
+    achieved = dbytes / dsec / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": load_traffic(dom_key),
+                "traffic_calibration": "FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000: the factors that turn the "
+                                       "counters of the 16-byte copy kernel into its known bytes",
+                "kernel": dom_key, "symbol": kernel_symbol(dom_key),
+                "launches": dl, "avg_ms": round(1e3 * dsec / dl, 4),
+                "algorithmic_bytes_per_launch": round(dbytes / dl)}
+    out = {"value": per_dtype[head]["GB/s"], "head": head, "per_dtype": per_dtype, "launch_min": launch_min,
+           "per_kernel": {f"{d}:{k}": {"GB/s": round(v[0] / v[1] / 1e9, 1), "launches": v[2], "ms": round(1e3 * v[1], 2)}
+                          for (d, k), v in sorted(per_kernel.items())},
+           "roofline": roofline, "copy_kernel_GBs": None if copy_gbs is None else round(copy_gbs, 1),
+           "gates": gates}
+    return out
+
+
+# ---------------------------------------------------------------- circuits
+def circuit_bench(args, n: int = 32):
     """Circuit benchmark: N=32 complex64 (32 GiB) random brickwork circuit of
     depth 40 (1900 gates) and the N=32 QFT (544 gates), planned once (gate
-    fusion + in-cache tile passes) and applied `steps` times after `warmup`.
-    The QFT runs on a seeded basis state and is checked against its closed form
-    on 4096 sampled amplitudes."""
+    fusion + in-cache tile passes, mode `args.mode`) and applied `steps`
+    times after `warmup`.  The QFT runs on a seeded basis state and is
+    checked against its closed form on 4096 sampled amplitudes."""
     import numpy as np
     import torch
 
@@ -144,7 +300,6 @@ def circuit_bench(args):
     from svgen import brickwork_circuit, qft_circuit
 
     torch.cuda.set_device(0)
-    n = args.n if args.n != N_QUBITS else 32
     dtype = "c64"
     stream = torch.cuda.current_stream()
     st = sv.StateVector(n, dtype, stream=stream)
@@ -152,6 +307,7 @@ def circuit_bench(args):
     out = {}
     rng = np.random.default_rng(7)
     x0 = int(rng.integers(0, 1 << n))
+    steps, warmup = args.circuit_steps, args.circuit_warmup
     for name, gates in (("brickwork_d40", brickwork_circuit(n, 40, seed=3)), ("qft", qft_circuit(n))):
         t0 = time.perf_counter()
         plan = sv.Plan(n, dtype, gates, {"mode": args.mode})
@@ -159,11 +315,11 @@ def circuit_bench(args):
         kinds = [k for k, _, _ in plan.passes()]
         sweeps = len(kinds)
         init = x0 if name == "qft" else 0
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             st.init_basis(init)
             st.apply_plan(plan)
         times = []
-        for _ in range(args.steps):
+        for _ in range(steps):
             st.init_basis(init)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
@@ -172,10 +328,16 @@ def circuit_bench(args):
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1) * 1e-3)
         sec = sum(times) / len(times)
+        # matrix-core work of the dense passes: 8 * 2^(N+k) real flops per k-qubit op
+        dense_flops = sum(8.0 * 2.0 ** (n + len(q)) for q, _, ps in plan.export() if ps >= 0 and len(q) >= 3)
         rec = {"seconds": round(sec, 5), "min_s": round(min(times), 5), "gates": len(gates),
                "ops": plan.info()[0], "passes": sweeps,
                "pass_kinds": {str(k): kinds.count(k) for k in sorted(set(kinds))},
-               "plan_s": round(plan_s, 4), "sweep_GBs": round(sweeps * 2 * S / sec / 1e9, 1)}
+               "plan_s": round(plan_s, 4),
+               "roofline": {"bound": "hbm", "achieved": round(sweeps * 2 * S / sec / 1e9, 1), "peak": PEAK_HBM_GBS,
+                            "unit": "GB/s", "frac": round(sweeps * 2 * S / sec / 1e9 / PEAK_HBM_GBS, 4),
+                            "traffic": None, "bytes": "passes x read + write of the 32 GiB state"},
+               "mfma_algorithmic_frac": round(dense_flops / sec / (PEAK_MFMA_TFLOPS["c64"] * 1e12), 4)}
         if name == "qft":
             ys = torch.from_numpy(rng.integers(0, 1 << n, size=4096)).cuda()
             got = st.tensor[ys].cpu().numpy().astype(np.complex128)
@@ -183,30 +345,23 @@ def circuit_bench(args):
             ref = np.exp(2j * np.pi * ((x0 * y) % (1 << n)) / (1 << n)) / math.sqrt(1 << n)
             rec["closed_form_max_err"] = float(np.max(np.abs(got - ref)))
         out[name] = rec
+        plan.close()
     st.close()
+    torch.cuda.empty_cache()
     total = sum(v["seconds"] for v in out.values())
-    print(json.dumps({"metric": f"circuit seconds at N={n} (complex64)", "value": round(total, 5), "unit": "s",
-                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * total, 3),
-                      "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-                      "data": "synthetic",
-                      "config": {"workload": f"circuit benchmark: N={n} complex64, brickwork depth 40 (seed 3) + QFT",
-                                 "mode": args.mode},
-                      "circuits": out}))
+    out["seconds"] = round(total, 5)
+    out["config"] = {"workload": f"N={n} complex64, brickwork depth 40 (seed 3) + QFT", "mode": args.mode,
+                     "steps": steps, "warmup": warmup}
+    return out
 
 
 def qaoa_cpu_baseline(gates, n: int):
     """The oracle (numpy, complex128) on a bounded sample of the QAOA circuit:
     one RZZ and one RX of it at N=30 on the host cores, extrapolated to the
     whole gate list by gate kind (H costs what RX costs: one dense 2x2)."""
-    import numpy as np
-
     import oracle
     from svgen import gaussian_state_np
-    try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        blas_threads = 1
+    host = _host_info()
     psi = gaussian_state_np(n, 2)
     per_kind = {}
     for kind in ("RZZ", "RX"):
@@ -217,9 +372,9 @@ def qaoa_cpu_baseline(gates, n: int):
     del psi
     per_kind["H"] = per_kind["RX"]
     est = sum(per_kind[g.kind] for g in gates)
-    return {"value": round(est, 1), "unit": "s", "cores": blas_threads, "kind": "oracle",
+    return {"value": round(est, 1), "unit": "s", "cores": host["blas_threads"], "kind": "oracle",
             "sample": f"one RZZ and one RX at N={n}, complex128 ({per_kind['RZZ'] + per_kind['RX']:.1f} s), "
-                      f"scaled to the {len(gates)} gates by kind"}
+                      f"scaled to the {len(gates)} gates by kind", "host": host}
 
 
 def qaoa_bench(args):
@@ -273,6 +428,7 @@ def qaoa_bench(args):
                       "sweep_GBs": round(n_passes * 2 * S / sec / 1e9, 1),
                       "symmetry_max_rel_err": float(np.max(np.abs(got[:4096] - got[4096:]))) / scale}
         st.close()
+        plan.close()
         torch.cuda.empty_cache()
     out["c64_vs_c128_max_rel_err"] = float(np.max(np.abs(samples["c64"] - samples["c128"]))) / float(
         np.max(np.abs(samples["c128"])))
@@ -289,10 +445,11 @@ def qaoa_bench(args):
            "qaoa": out}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = qaoa_cpu_baseline(gates, n)
-    print(json.dumps(rec))
+    return rec
 
 
-def serve_cpu_baseline(requests, budget_s: float = 15.0):
+# ---------------------------------------------------------------- serving
+def serve_cpu_baseline(requests, budget_s: float = 8.0):
     """The oracle on a bounded sample of the serving mix: for one request of
     each N in the mix, time its first few gates (at least 2, more while the
     per-N share of `budget_s` allows), extrapolate linearly to the request's
@@ -300,9 +457,9 @@ def serve_cpu_baseline(requests, budget_s: float = 15.0):
     oracle circuits/s over the whole mix."""
     import numpy as np
 
-    import oracle
     from oracle import sv_oracle as so
 
+    host = _host_info()
     by_n = {}
     for r in requests:
         by_n.setdefault(r.n, []).append(r)
@@ -323,19 +480,11 @@ def serve_cpu_baseline(requests, budget_s: float = 15.0):
         timed += k
         mean_gates = sum(r.depth * (r.n + r.n // 2) for r in rs) / len(rs)  # N rotations + N/2 CNOTs per pair
         total_s += per_gate * mean_gates * len(rs)
-    return {"value": round(len(requests) / total_s, 4), "unit": "circuits/s", "cores": _blas_threads(),
+    return {"value": round(len(requests) / total_s, 4), "unit": "circuits/s", "cores": host["blas_threads"],
             "kind": "oracle",
             "sample": f"oracle (numpy complex128) timed on the first gates of one request per N "
                       f"({timed} gates over N={min(by_n)}..{max(by_n)}), extrapolated linearly in gate count "
-                      f"to the {len(requests)}-request mix"}
-
-
-def _blas_threads():
-    try:
-        from threadpoolctl import threadpool_info
-        return max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        return 1
+                      f"to the {len(requests)}-request mix", "host": host}
 
 
 def _cpu_threads():
@@ -343,75 +492,6 @@ def _cpu_threads():
         return len(os.sched_getaffinity(0))
     except AttributeError:
         return os.cpu_count()
-
-
-def serve_bench(args):
-    """Serving form: a stream of circuit requests (N ~ U{12..nmax}, depth ~
-    U{20..200} layer pairs of N rotations + N/2 CNOTs, Poisson arrivals) served
-    by the continuous-batching loop, in complex64 and complex128.  For each
-    dtype: a closed-loop run (all requests at t=0) measures the saturated
-    throughput X; the timed run replays the arrivals at rate 0.8 X.  The
-    reported value is the complex64 timed run's served circuits/s."""
-    from svgen import serving_requests
-    from paper_2409_14697_amd.serve import marshal_requests, jobs_from_marshalled
-
-    reqs = serving_requests(args.requests, seed=5, n_range=(12, args.nmax), depth_range=(20, 200))
-    t0 = time.perf_counter()
-    marshalled = marshal_requests(reqs, workers=min(16, _cpu_threads()))
-    prep_s = time.perf_counter() - t0
-
-    import torch
-
-    from paper_2409_14697_amd.serve import DeviceEngine, Server, free_budget
-
-    torch.cuda.set_device(0)
-    out = {}
-    dtypes = [d for d in args.dtypes.split(",") if d]
-    launch = {}
-    for dt in dtypes:
-        def run(rate, budget=None, timed=False):
-            eng = DeviceEngine(dt, time_launches=timed)
-            srv = Server(eng, budget or free_budget(0.8), max_active=args.max_active,
-                         plan_workers=min(16, _cpu_threads()))
-            res = srv.run(jobs_from_marshalled(reqs, marshalled, rate))
-            stats = eng.launch_stats() if timed else None
-            eng.close()
-            torch.cuda.synchronize()
-            return res, stats
-        # warm-up: allocator, kernels, planner threads
-        warm = max(1, min(32, len(reqs) // 8))
-        eng = DeviceEngine(dt)
-        Server(eng, free_budget(0.8), plan_workers=4).run(jobs_from_marshalled(reqs[:warm], marshalled[:warm], None))
-        eng.close()
-        closed, _ = run(None)
-        sat = closed.summary()["circuits_per_s"]
-        lam = args.rate_fraction * sat
-        timed, stats = run(lam, timed=True)
-        rec = {"closed_loop": _round(closed.summary()), "rate_per_s": round(lam, 3),
-               "poisson": _round(timed.summary()), "launch": _round(stats)}
-        if args.contention_gib > 0:
-            cont, _ = run(lam, budget=int(args.contention_gib * (1 << 30)))
-            rec["contention"] = dict(_round(cont.summary()), budget_gib=args.contention_gib)
-        out[dt] = rec
-        launch[dt] = stats
-        print(f"[serve] {dt}: closed {sat:.1f}/s, poisson {timed.summary()['circuits_per_s']:.1f}/s "
-              f"p99 {timed.summary()['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
-    main_dt = "c64" if "c64" in out else dtypes[0]
-    summ = out[main_dt]["poisson"]
-    st = launch[main_dt]
-    line = {"metric": "served circuits/s", "value": summ["circuits_per_s"], "unit": "circuits/s", "n_gpus": 1,
-            "steps": summ["completed"], "warmup": 1, "ms_per_step": round(1e3 / max(summ["circuits_per_s"], 1e-9), 3),
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32" if main_dt == "c64" else "f64", "data": "synthetic",
-            "config": {"workload": f"serving: {len(reqs)} requests, N~U{{12..{args.nmax}}}, depth~U{{20..200}} layer "
-                                   f"pairs, Poisson arrivals at {args.rate_fraction} x closed-loop throughput, "
-                                   f"budget 0.8 x free HBM, {main_dt} timed run",
-                       "p99_ms": summ["p99_ms"], "p50_ms": summ["p50_ms"]},
-            "roofline": serve_roofline(st, main_dt),
-            "serving": out, "prep_s": round(prep_s, 2)}
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = serve_cpu_baseline(reqs)
-    print(json.dumps(line))
 
 
 def serve_roofline(st, dt):
@@ -435,6 +515,63 @@ def _round(d):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
 
 
+def serve_bench(args, requests_by_dtype):
+    """Serving form: a stream of circuit requests (N ~ U{12..nmax}, depth ~
+    U{20..200} layer pairs of N rotations + N/2 CNOTs, Poisson arrivals)
+    served by the continuous-batching loop, per dtype.  For each dtype: a
+    closed-loop run (all requests at t=0) measures the saturated throughput X;
+    the timed run replays the arrivals at rate 0.8 X."""
+    from svgen import serving_requests
+    from paper_2409_14697_amd.serve import marshal_requests, jobs_from_marshalled
+
+    import torch
+
+    from paper_2409_14697_amd.serve import DeviceEngine, Server, free_budget
+
+    torch.cuda.set_device(0)
+    out = {}
+    for dt, count in requests_by_dtype:
+        reqs = serving_requests(count, seed=5, n_range=(12, args.nmax), depth_range=(20, 200))
+        t0 = time.perf_counter()
+        marshalled = marshal_requests(reqs, workers=min(16, _cpu_threads()))
+        prep_s = time.perf_counter() - t0
+
+        def run(rate, budget=None, timed=False):
+            eng = DeviceEngine(dt, time_launches=timed)
+            srv = Server(eng, budget or free_budget(0.8), max_active=args.max_active,
+                         plan_workers=min(16, _cpu_threads()))
+            res = srv.run(jobs_from_marshalled(reqs, marshalled, rate))
+            stats = eng.launch_stats() if timed else None
+            eng.close()
+            torch.cuda.synchronize()
+            return res, stats
+        # warm-up: allocator, kernels, planner threads
+        warm = max(1, min(32, len(reqs) // 8))
+        eng = DeviceEngine(dt)
+        Server(eng, free_budget(0.8), plan_workers=4).run(jobs_from_marshalled(reqs[:warm], marshalled[:warm], None))
+        eng.close()
+        closed, _ = run(None)
+        sat = closed.summary()["circuits_per_s"]
+        lam = args.rate_fraction * sat
+        timed, stats = run(lam, timed=True)
+        rec = {"requests": count, "closed_loop": _round(closed.summary()), "rate_per_s": round(lam, 3),
+               "poisson": _round(timed.summary()), "launch": _round(stats), "roofline": serve_roofline(stats, dt),
+               "prep_s": round(prep_s, 2)}
+        if args.contention_gib > 0:
+            cont, _ = run(lam, budget=int(args.contention_gib * (1 << 30)))
+            rec["contention"] = dict(_round(cont.summary()), budget_gib=args.contention_gib)
+        out[dt] = rec
+        log(f"serve {dt}: {count} requests, closed {sat:.1f}/s, poisson {timed.summary()['circuits_per_s']:.1f}/s "
+            f"p99 {timed.summary()['p99_ms']:.1f} ms")
+        if not args.no_cpu_baseline and "cpu_baseline" not in out:
+            out["cpu_baseline"] = serve_cpu_baseline(reqs)
+    out["config"] = {"workload": f"serving: requests N~U{{12..{args.nmax}}}, depth~U{{20..200}} layer pairs "
+                                 f"(seed 5), Poisson arrivals at {args.rate_fraction} x closed-loop throughput, "
+                                 f"budget 0.8 x free HBM"}
+    return out
+
+
+# ---------------------------------------------------------------- precision form
 def _compare(a64, b128):
     """FP64 error metrics of a complex64 state against a complex128 one
     (chunked, on the device): max-abs, relative L2, infidelity, norm drift."""
@@ -456,12 +593,12 @@ def _compare(a64, b128):
             "norm_drift_fp32": own2 - 1.0, "norm_drift_fp64": ref2 - 1.0}
 
 
-def precision_bench(args):
-    """Precision form: N=30, 2000 Haar-random 5- and 6-qubit unitaries on
+def precision_bench(args, seeds, n_gates, checkpoint):
+    """Precision form: N=30, `n_gates` Haar-random 5- and 6-qubit unitaries on
     random ordered qubit sets; complex64 state with FP32 MFMA contractions
     (FP32 accumulation, FP64 renormalisation every `renorm` ops) against a
-    complex128 state with the FP64 kernel, same GPU, same seeded input.
-    Errors are taken at checkpoints; one record per seed."""
+    complex128 state with the FP64 matrix-core kernel, same GPU, same seeded
+    input.  Errors are taken at checkpoints; one record per seed."""
     import torch
 
     import paper_2409_14697_amd as sv
@@ -473,17 +610,18 @@ def precision_bench(args):
     stream = torch.cuda.current_stream()
     records = []
     t32_total = t64_total = 0.0
-    for seed in [int(x) for x in args.seeds.split(",")]:
-        gates = fused_haar_circuit(n, args.gates, seed=seed)
+    flops = {"c64": 0.0, "c128": 0.0}
+    for seed in seeds:
+        gates = fused_haar_circuit(n, n_gates, seed=seed)
+        gflops = sum(8.0 * 2.0 ** (n + len(g.qubits)) for g in gates)
         s128 = gaussian_state_torch(n, seed, torch.complex128)
         s64 = s128.to(torch.complex64)
         st64 = sv.StateVector(n, "c128", tensor=s128, init=False, stream=stream)
         st32 = sv.StateVector(n, "c64", tensor=s64, init=False, stream=stream)
-        chk = args.checkpoint
         rec = {"seed": seed, "gates": len(gates), "checkpoints": []}
         t32 = t64 = 0.0
-        for g0 in range(0, len(gates), chk):
-            part = gates[g0:g0 + chk]
+        for g0 in range(0, len(gates), checkpoint):
+            part = gates[g0:g0 + checkpoint]
             for st, dtype in ((st32, "c64"), (st64, "c128")):
                 opts = {"mode": "sweep", "max_fuse_qubits": 0}
                 if dtype == "c64":
@@ -494,6 +632,7 @@ def precision_bench(args):
                 st.apply_plan(plan)
                 e1.record(stream)
                 torch.cuda.synchronize()
+                plan.close()
                 dt = e0.elapsed_time(e1) * 1e-3
                 if dtype == "c64":
                     t32 += dt
@@ -507,41 +646,54 @@ def precision_bench(args):
         records.append(rec)
         t32_total += t32
         t64_total += t64
+        flops["c64"] += gflops
+        flops["c128"] += gflops
         st32.close()
         st64.close()
         del s64, s128
         torch.cuda.empty_cache()
     final_err = max(r["checkpoints"][-1]["max_abs"] for r in records)
-    print(json.dumps({"metric": f"precision form: seconds for {args.gates} fused 5/6-qubit gates at N={n}, "
-                                "FP32 MFMA vs FP64", "value": round(t32_total / len(records), 4), "unit": "s",
-                      "n_gpus": 1, "steps": len(records), "warmup": 0,
-                      "ms_per_step": round(1e3 * t32_total / len(records), 3), "higher_is_better": False,
-                      "scaling": "weak", "vs_baseline": None, "dtype": "f32 (vs f64)", "data": "synthetic",
-                      "config": {"workload": f"precision form: N={n}, {args.gates} Haar unitaries alternating "
-                                             f"k=5/6 (seeds {args.seeds}), renorm every {args.renorm}"},
-                      "fp64_seconds": round(t64_total / len(records), 4),
-                      "fp32_max_abs_error": final_err, "bar_max_abs": 1e-5, "records": records}))
+    mfma32 = flops["c64"] / t32_total / 1e12
+    mfma64 = flops["c128"] / t64_total / 1e12
+    return {"fp32_mfma_s": round(t32_total / len(records), 4), "fp64_s": round(t64_total / len(records), 4),
+            "fp32_max_abs_error": final_err, "bar_max_abs": 1e-5,
+            "roofline_fp32": {"bound": "mfma", "achieved": round(mfma32, 2), "peak": PEAK_MFMA_TFLOPS["c64"],
+                              "unit": "TFLOP/s", "frac": round(mfma32 / PEAK_MFMA_TFLOPS["c64"], 4),
+                              "traffic": None, "flops": "8 * 2^(N+k) per k-qubit gate (real embedding)"},
+            "roofline_fp64": {"bound": "mfma", "achieved": round(mfma64, 2), "peak": PEAK_MFMA_TFLOPS["c128"],
+                              "unit": "TFLOP/s", "frac": round(mfma64 / PEAK_MFMA_TFLOPS["c128"], 4),
+                              "traffic": None},
+            "config": {"workload": f"precision form: N={n}, {n_gates} Haar unitaries alternating k=5/6 "
+                                   f"(seeds {seeds}), renorm every {args.renorm}"},
+            "records": records}
 
 
+# ---------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: 10 for gates, the gate benchmark's 10 repetitions; 3 for circuit)")
+                    help="timed steps (default: 10 for gates, the gate benchmark's 10 repetitions; 3 otherwise)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=N_QUBITS)
     ap.add_argument("--dtypes", default="c128,c64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ceiling", action="store_true", help="also time the 16-byte copy kernel")
-    ap.add_argument("--requests", type=int, default=512, help="serve workload: number of requests")
+    ap.add_argument("--extras", default="circuit,precision,serve",
+                    help="default workload: parts of the metric run after the gate benchmark ('none' for none)")
+    ap.add_argument("--circuit-steps", type=int, default=2)
+    ap.add_argument("--circuit-warmup", type=int, default=1)
+    ap.add_argument("--requests", type=int, default=None, help="serve workload: number of requests")
+    ap.add_argument("--serve-default", default="c64:4096,c128:1024",
+                    help="default workload's serving part: dtype:requests list")
     ap.add_argument("--nmax", type=int, default=26, help="serve workload: largest request N")
     ap.add_argument("--max-active", type=int, default=512, help="serve workload: slot cap")
     ap.add_argument("--rate-fraction", type=float, default=0.8, help="serve workload: arrival rate / saturated rate")
     ap.add_argument("--contention-gib", type=float, default=0.0,
                     help="serve workload: also run with this HBM budget (GiB)")
     ap.add_argument("--workload", default="gates", choices=["gates", "circuit", "precision", "serve", "qaoa"],
-                    help="gates: the per-gate sweep benchmark (default); circuit: N=32 circuits; "
-                         "precision: FP32 MFMA vs FP64 fused Haar gates")
+                    help="gates: the default line (gate benchmark + extras); circuit: N=32 circuits; "
+                         "precision: FP32 MFMA vs FP64 fused Haar gates; serve: the serving form; qaoa")
     ap.add_argument("--gates", type=int, default=2000, help="precision workload: number of fused gates")
     ap.add_argument("--checkpoint", type=int, default=250, help="precision workload: gates between error checks")
     ap.add_argument("--seeds", default="4,5,6", help="precision workload: circuit seeds")
@@ -554,126 +706,91 @@ def main():
         sys.exit(2)
     if args.steps is None:
         args.steps = 10 if args.workload == "gates" else 3
+    common = {"n_gpus": 1, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
     if args.workload == "circuit":
-        circuit_bench(args)
+        args.circuit_steps, args.circuit_warmup = args.steps, args.warmup
+        c = circuit_bench(args, n=32 if args.n == N_QUBITS else args.n)
+        print(json.dumps(dict({"metric": "circuit seconds at N=32 (complex64)", "value": c["seconds"], "unit": "s",
+                               "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * c["seconds"], 3),
+                               "higher_is_better": False, "dtype": "f32", "config": c.pop("config"),
+                               "roofline": c["brickwork_d40"]["roofline"], "circuits": c}, **common)))
         return
     if args.workload == "precision":
-        precision_bench(args)
+        p = precision_bench(args, [int(x) for x in args.seeds.split(",")], args.gates, args.checkpoint)
+        print(json.dumps(dict({"metric": f"precision form: seconds for {args.gates} fused 5/6-qubit gates at N={args.n}, "
+                                         "FP32 MFMA vs FP64", "value": p["fp32_mfma_s"], "unit": "s",
+                               "steps": len(p["records"]), "warmup": 0, "ms_per_step": round(1e3 * p["fp32_mfma_s"], 3),
+                               "higher_is_better": False, "dtype": "f32 (vs f64)", "config": p.pop("config"),
+                               "roofline": p["roofline_fp32"], "precision": p}, **common)))
         return
     if args.workload == "serve":
-        serve_bench(args)
+        count = args.requests or 512
+        s = serve_bench(args, [(d, count) for d in args.dtypes.split(",") if d])
+        main_dt = "c64" if "c64" in s else args.dtypes.split(",")[0]
+        summ = s[main_dt]["poisson"]
+        line = dict({"metric": "served circuits/s", "value": summ["circuits_per_s"], "unit": "circuits/s",
+                     "steps": summ["completed"], "warmup": 1,
+                     "ms_per_step": round(1e3 / max(summ["circuits_per_s"], 1e-9), 3), "higher_is_better": True,
+                     "dtype": "f32" if main_dt == "c64" else "f64",
+                     "config": dict(s.pop("config"), requests=count, p99_ms=summ["p99_ms"], p50_ms=summ["p50_ms"]),
+                     "roofline": s[main_dt]["roofline"], "serving": s}, **common)
+        if "cpu_baseline" in s:
+            line["cpu_baseline"] = s.pop("cpu_baseline")
+        print(json.dumps(line))
         return
     if args.workload == "qaoa":
-        qaoa_bench(args)
+        print(json.dumps(qaoa_bench(args)))
         return
 
-    import torch
-
-    import paper_2409_14697_amd as sv
-    from svgen import gate_bench_set
-    from svgen.states import gaussian_state_torch
-
-    torch.cuda.set_device(0)
-    n = args.n
-    gates = gate_bench_set(n, seed=2)
-    dtypes = [d for d in args.dtypes.split(",") if d]
-    stream = torch.cuda.current_stream()
-    per_kernel = {}   # key -> [bytes, seconds, launches]
-    per_dtype = {}
-    total_bytes, total_s = 0.0, 0.0
-    for dtype in dtypes:
-        tdt = torch.complex128 if dtype == "c128" else torch.complex64
-        psi = gaussian_state_torch(n, 2, tdt)
-        st = sv.StateVector(n, dtype, tensor=psi, init=False, stream=stream)
-        S = psi.numel() * psi.element_size()
-        kernels = [sv.gate_kernel(n, dtype, g) for g in gates]
-        for _ in range(args.warmup):
-            for g in gates:
-                st.apply_gate(g)
-        torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in gates]
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        durations = [0.0] * len(gates)
-        torch.cuda.synchronize()
-        start.record(stream)
-        for _ in range(args.steps):
-            for i, g in enumerate(gates):
-                evs[i][0].record(stream)
-                st.apply_gate(g)
-                evs[i][1].record(stream)
-            stream.synchronize()
-            for i in range(len(gates)):
-                durations[i] += evs[i][0].elapsed_time(evs[i][1]) * 1e-3
-        stop.record(stream)
-        torch.cuda.synchronize()
-        wall = start.elapsed_time(stop) * 1e-3
-        dbytes = 0.0
-        for i, g in enumerate(gates):
-            b = 2.0 * S * touched_fraction(g, dtype) * args.steps
-            dbytes += b
-            key = kernels[i]
-            acc = per_kernel.setdefault(key, [0.0, 0.0, 0])
-            acc[0] += b
-            acc[1] += durations[i]
-            acc[2] += args.steps
-        kern_s = sum(durations)
-        per_dtype[dtype] = {"GB/s": round(dbytes / kern_s / 1e9, 1), "ms_per_step": round(1e3 * wall / args.steps, 3),
-                            "gates_per_step": len(gates)}
-        total_bytes += dbytes
-        total_s += kern_s
-        st.close()
-        del psi
-        torch.cuda.empty_cache()
-
-    copy_gbs = None
-    if args.copy_ceiling:
-        src = torch.empty(1 << (n - 1), dtype=torch.complex128, device="cuda")
-        dst = torch.empty_like(src)
-        sv.util_copy(dst, src)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(5):
-            sv.util_copy(dst, src)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        copy_gbs = 2.0 * src.numel() * 16 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        del src, dst
-
-    # dominant kernel = the one with the most time in the timed region
-    dom_key, (dbytes, dsec, dl) = max(per_kernel.items(), key=lambda kv: kv[1][1])
-    achieved = dbytes / dsec / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": load_traffic(dom_key),
-                "kernel": dom_key, "symbol": kernel_symbol(dom_key),
-                "launches": dl, "avg_ms": round(1e3 * dsec / dl, 4),
-                "algorithmic_bytes_per_launch": round(dbytes / dl)}
-    value = total_bytes / total_s / 1e9
-    out = {
+    # ---- default line: the gate benchmark (headline), then the other parts
+    t_start = time.perf_counter()
+    g = gates_bench(args)
+    log(f"gates: c128 {g['per_dtype'].get('c128', {}).get('GB/s')} GB/s, c64 {g['per_dtype'].get('c64', {}).get('GB/s')} "
+        f"GB/s ({time.perf_counter() - t_start:.0f} s)")
+    gates = g.pop("gates")
+    head = g["head"]
+    out = dict({
         "metric": "HBM GB/s per gate at N=30 (gate sweep benchmark)",
-        "value": round(value, 1),
+        "value": g["value"],
         "unit": "GB/s",
-        "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(sum(v["ms_per_step"] for v in per_dtype.values()), 3),
+        "ms_per_step": g["per_dtype"][head]["ms_per_step"],
         "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "+".join({"c128": "f64", "c64": "f32"}[d] for d in dtypes),
-        "data": "synthetic",
-        "config": {"workload": f"gate sweep benchmark: N={n}, {'+'.join(dtypes)} Gaussian state (seed 2), "
-                               f"H/X/RZ/CNOT/CZ/SWAP/CPHASE on every target (partners random, seed 2)",
-                   "n_qubits": n, "gates_per_step": len(gates) * len(dtypes)},
-        "by_dtype": per_dtype,
-        "per_kernel": {k: {"GB/s": round(v[0] / v[1] / 1e9, 1), "launches": v[2], "ms": round(1e3 * v[1], 2)}
-                       for k, v in sorted(per_kernel.items())},
-        "roofline": roofline,
-    }
-    if copy_gbs is not None:
-        out["copy_kernel_GBs"] = round(copy_gbs, 1)
+        "dtype": {"c128": "f64", "c64": "f32"}[head],
+        "config": {"workload": f"gate sweep benchmark: N={args.n}, Gaussian state (seed 2), H/X/RZ/CNOT/CZ/SWAP/CPHASE "
+                               f"on every target (partners random, seed 2); value: {head}",
+                   "n_qubits": args.n, "gates_per_step": len(gates), "dtypes": args.dtypes},
+        "by_dtype": {d: {k: v for k, v in r.items() if k not in ("kernel_s", "bytes")} for d, r in g["per_dtype"].items()},
+        "launch_min": g["launch_min"],
+        "per_kernel": g["per_kernel"],
+        "roofline": g["roofline"],
+    }, **common)
+    if g["copy_kernel_GBs"] is not None:
+        out["copy_kernel_GBs"] = g["copy_kernel_GBs"]
+    extras = [] if args.extras == "none" else [x for x in args.extras.split(",") if x]
+    if "circuit" in extras:
+        t0 = time.perf_counter()
+        out["circuit"] = circuit_bench(args, n=32)
+        log(f"circuit: {out['circuit']['seconds']} s ({time.perf_counter() - t0:.0f} s)")
+    if "precision" in extras:
+        t0 = time.perf_counter()
+        out["precision"] = precision_bench(args, [4], args.gates, 500)
+        log(f"precision: fp32 {out['precision']['fp32_mfma_s']} s, fp64 {out['precision']['fp64_s']} s "
+            f"({time.perf_counter() - t0:.0f} s)")
+    if "serve" in extras:
+        t0 = time.perf_counter()
+        plan = []
+        for item in args.serve_default.split(","):
+            d, c = item.split(":")
+            plan.append((d, int(c)))
+        out["serving"] = serve_bench(args, plan)
+        log(f"serving ({time.perf_counter() - t0:.0f} s)")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(gates, n)
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(gates, args.n)
+        log(f"cpu baseline ({time.perf_counter() - t0:.0f} s)")
+    out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out))
 
 

@@ -199,7 +199,10 @@ sv_status sv_plan_pass_info(const sv_plan *p, size_t pass, int32_t *kind, int32_
 sv_status sv_plan_pass_flops(const sv_plan *p, size_t pass, double *flops_per_amp);
 
 /* Kernel ops of tile pass `pass` after register staging: *n_ops ops in
- * total, *n_ladders of them fixed-point phase functions: a phase ladder (the
+ * total (per register stage: one per single-qubit gate of its tensor-product
+ * layer, one for a dense two-qubit gate, one for its register-index factor
+ * table, one per lane item and one per permutation gate), *n_ladders of them
+ * fixed-point phase functions: a phase ladder (the
  * phases of a run of diagonal gates that fall on the amplitudes whose
  * register qubit is 1) or a quadratic phase over the bits outside the
  * registers (the rest of such a run), each applied as one op with a

@@ -339,11 +339,10 @@ sv_status sv_plan_pass_ops(const sv_plan* p, size_t pass, int32_t* n_ops, int32_
   if (!p) return fail(SV_ERR_ARG, "null plan");
   if (pass >= p->passes.size()) return fail(SV_ERR_ARG, "pass %zu out of range", pass);
   int32_t ops = 0, ladders = 0;
-  for (const StageHost& sh : p->passes[pass].stages)
-    for (const PassOpDev& od : sh.ops) {
-      ++ops;
-      ladders += od.type == POP_LP || od.type == POP_QG;
-    }
+  for (const StageHost& sh : p->passes[pass].stages) {
+    ops += sh.n_ops;
+    ladders += sh.n_fixed;
+  }
   if (n_ops) *n_ops = ops;
   if (n_ladders) *n_ladders = ladders;
   return SV_OK;

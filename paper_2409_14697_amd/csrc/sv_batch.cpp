@@ -11,13 +11,11 @@ struct sv_program {
   sv_dtype dt = SV_C128;
   int n_passes = 0;
   int max_m = 0;
-  std::vector<int> pass_m;  // local qubits of each pass
-  std::vector<char> pass_lp;  // the pass holds phase-ladder ops
-  std::vector<unsigned char> host;  // [descs][stages][ops][pool], kept for the async upload
+  std::vector<int> pass_m;    // local qubits of each pass
+  sv::PackedPlan packed;      // device image, kept for the async upload
   void* dev = nullptr;
   bool owned = false;
   hipEvent_t uploaded = nullptr;  // after the upload: the host copy may be freed
-  size_t off_desc = 0, off_stage = 0, off_ops = 0, off_pool = 0;
   hipStream_t stream = nullptr;
 };
 
@@ -37,71 +35,15 @@ struct sv_batcher {
 namespace sv {
 namespace {
 
-// Pack the plan's tile passes into prog->host (offsets 256-byte aligned).
+// Pack the plan's tile passes into the program's device image.
 sv_status pack_program(const sv_plan* p, sv_program* prog) {
-  if (!p || (p->dt != SV_C64 && p->dt != SV_C128)) return fail(SV_ERR_ARG, "bad plan");
-  const bool f32 = p->dt == SV_C64;
-  const size_t scal = f32 ? sizeof(float) : sizeof(double);
-  std::vector<PassDescDev> descs;
-  std::vector<PassStageDev> stages;
-  std::vector<PassOpDev> pops;
-  std::vector<cd> pool;
-  std::vector<uint8_t> pool_raw;
-  for (const Pass& ps : p->passes) {
-    if (ps.kind != PASS_TILE && ps.kind != PASS_PERMUTE)
-      return fail(SV_ERR_UNSUPPORTED, "program needs a plan of in-cache tile passes only (build it with mode PASS)");
-    PassDescDev d{};
-    d.m = (uint32_t)ps.n_local;
-    d.stage_first = (uint32_t)stages.size();
-    d.stage_count = (uint32_t)ps.stages.size();
-    if (!fill_pass_maps(ps, p->dt, &d)) return fail(SV_ERR_UNSUPPORTED, "internal: pass write map is not a permutation");
-    for (const StageHost& sh : ps.stages) {
-      PassStageDev sd{};
-      const int rb = pass_reg_bits(p->dt);
-      uint32_t srt[kPassRegBitsMax];
-      for (int r = 0; r < rb; ++r) sd.q[r] = srt[r] = sh.q[r];
-      std::sort(srt, srt + rb);
-      for (int r = 0; r < rb; ++r) sd.qsort[r] = srt[r];
-      sd.op_first = (uint32_t)pops.size();
-      sd.op_count = (uint32_t)sh.ops.size();
-      const uint32_t mbase = (uint32_t)pool.size();
-      sd.mat_base = mbase;
-      sd.rows = sh.rows;
-      sd.row_count = sh.row_count;
-      for (PassOpDev od : sh.ops) {
-        od.mat += mbase;
-        pops.push_back(od);
-      }
-      pool.insert(pool.end(), sh.mats.begin(), sh.mats.end());
-      pool_raw.insert(pool_raw.end(), sh.raw.begin(), sh.raw.end());
-      stages.push_back(sd);
-    }
-    descs.push_back(d);
-    prog->pass_m.push_back(ps.n_local);
-    prog->pass_lp.push_back(pass_has_ladders(ps) ? 1 : 0);
-    prog->max_m = std::max(prog->max_m, ps.n_local);
-  }
-  std::vector<unsigned char>& host = prog->host;
-  host.clear();
-  auto align = [&]() { host.resize((host.size() + 255) / 256 * 256); };
-  auto put = [&](const void* src, size_t bytes) {
-    align();
-    const size_t at = host.size();
-    host.resize(at + bytes);
-    if (bytes) std::memcpy(host.data() + at, src, bytes);
-    return at;
-  };
-  prog->off_desc = put(descs.data(), descs.size() * sizeof(PassDescDev));
-  prog->off_stage = put(stages.data(), stages.size() * sizeof(PassStageDev));
-  prog->off_ops = put(pops.data(), pops.size() * sizeof(PassOpDev));
-  align();
-  prog->off_pool = host.size();
-  host.resize(host.size() + pool.size() * 2 * scal);
-  write_pool(host.data() + prog->off_pool, pool.data(), pool_raw.data(), pool.size(), f32);
-  align();
+  if (sv_status st = pack_plan(p, true, &prog->packed)) return st;
   prog->n = p->n;
   prog->dt = p->dt;
-  prog->n_passes = (int)descs.size();
+  prog->n_passes = prog->packed.n_desc;
+  prog->max_m = prog->packed.max_m;
+  prog->pass_m.clear();
+  for (const Pass& ps : p->passes) prog->pass_m.push_back(ps.n_local);
   return SV_OK;
 }
 
@@ -117,7 +59,7 @@ sv_status sv_program_bytes(const sv_plan* p, size_t* bytes) {
   if (!p || !bytes) return fail(SV_ERR_ARG, "null argument");
   sv_program tmp;
   if (sv_status st = pack_program(p, &tmp)) return st;
-  *bytes = tmp.host.size();
+  *bytes = tmp.packed.host.size();
   return SV_OK;
 }
 
@@ -131,7 +73,7 @@ sv_status sv_program_create(const sv_plan* p, void* dev_buf, size_t buf_bytes, v
   prog->stream = (hipStream_t)stream;
   sv_status st = pack_program(p, prog);
   if (st == SV_OK) {
-    const size_t bytes = prog->host.size();
+    const size_t bytes = prog->packed.host.size();
     if (dev_buf) {
       if (buf_bytes < bytes) st = fail(SV_ERR_ARG, "program buffer of %zu bytes, %zu needed", buf_bytes, bytes);
       prog->dev = dev_buf;
@@ -146,7 +88,7 @@ sv_status sv_program_create(const sv_plan* p, void* dev_buf, size_t buf_bytes, v
     prog->uploaded = nullptr;
     st = fail(SV_ERR_DEVICE, "hipEventCreate failed");
   }
-  if (st == SV_OK && (hipMemcpyAsync(prog->dev, prog->host.data(), prog->host.size(), hipMemcpyHostToDevice,
+  if (st == SV_OK && (hipMemcpyAsync(prog->dev, prog->packed.host.data(), prog->packed.host.size(), hipMemcpyHostToDevice,
                                      prog->stream) != hipSuccess ||
                       hipEventRecord(prog->uploaded, prog->stream) != hipSuccess))
     st = fail(SV_ERR_DEVICE, "program upload failed");
@@ -226,16 +168,16 @@ sv_status sv_batcher_run(sv_batcher* b, int count, sv_state* const* states, cons
     BatchItemDev& it = items[i];
     unsigned char* pd = (unsigned char*)p->dev;
     it.psi = s->ptr;
-    it.passes = (const PassDescDev*)(pd + p->off_desc);
-    it.stages = (const PassStageDev*)(pd + p->off_stage);
-    it.ops = (const PassOpDev*)(pd + p->off_ops);
-    it.mats = pd + p->off_pool;
+    it.passes = (const PassDescDev*)(pd + p->packed.off_desc);
+    it.stages = (const PassStageDev*)(pd + p->packed.off_stage);
+    it.items = (const PassItemDev*)(pd + p->packed.off_items);
+    it.mats = pd + p->packed.off_pool;
     it.tile_begin = tiles;
     it.n = s->n;
     it.pass = pass_index[i];
     tiles += 1ull << (s->n - m);
     max_m = std::max(max_m, m);
-    ladders = ladders || p->pass_lp[pass_index[i]];
+    ladders = ladders || p->packed.pass_lp[pass_index[i]];
   }
   const size_t bytes = items.size() * sizeof(BatchItemDev);
   const int k = b->next;

@@ -170,13 +170,9 @@ hipError_t run(void* psi, int n, const DenseGeo& g, const void* m, hipStream_t s
   constexpr int D = 1 << K;
   constexpr int C = tile_cols<K>();
   const size_t lds = (size_t)(D * D + D * C) * sizeof(cplx<R>);
-  static bool attr_set = false;  // per process; the attribute is per function
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_dense<E, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  static KernelLaunchCache cache;
+  hipError_t e = prepare_launch(cache, (const void*)k_dense<E, K>, kBlock, lds, nullptr);
+  if (e != hipSuccess) return e;
   const uint64_t ngroups = 1ull << (n - K);
   const uint64_t nwork = (ngroups + C - 1) / C;
   hipLaunchKernelGGL((k_dense<E, K>), dim3((unsigned)capped_grid(nwork)), dim3(kBlock), lds, s, (E*)psi, nwork, g,
@@ -580,18 +576,222 @@ __global__ __launch_bounds__((mfma_plan<R, K>::THREADS)) void k_dense_mfma_swz(t
 #undef SV_LD
 }
 
+// ---------------------------------------------------------------- direct
+// The same contraction without LDS.  A column block is BN consecutive
+// groups; when the gate's qubits leave the lowest physical bits to the
+// column index (or to the lowest member bits a lane group owns), every load
+// and store instruction of a wave covers whole 128-byte lines, so the
+// matrix-core operands come straight from HBM into registers and the
+// results go straight back: no staging, no barrier between a wave's column
+// blocks, and the next block's loads are in flight during the current
+// block's matrix work.
+//
+// Lanes form G = 64 / BN groups of BN lanes (complex64: 2 groups of 32,
+// complex128: 4 of 16); lane (col = l % BN, grp = l / BN) loads members
+// G j + grp of its column (j < D / G, whole amplitudes).  Real row bk of the
+// operand at k-step ks, bk = BK ks + grp, is part (ks & 1) of member
+// G (ks >> 1) + grp; the A fragments are built with the same order.  The
+// result rows are assigned so that a lane also stores the members whose low
+// bits are its group (and re / im of one member sit in registers r, r + 1):
+// complex64 row 8 q + 4 h + t of a block is member 4 q + 2 (t >> 1) + h,
+// part t & 1; complex128 row g + 4 r is member 4 (r >> 1) + g, part r & 1.
+// When the gate needs more row blocks than one wave holds (k = 6), WPC waves
+// of a block share a column block, each computing its own row blocks; they
+// read every input before any of them writes.
+template <typename R, int K>
+struct direct_plan {
+  typedef mfma_shape<R> MS;
+  static constexpr int D = 1 << K;
+  static constexpr int G = 64 / MS::BN;                // lane groups
+  static constexpr int NB = D / G;                     // members a lane loads per column block
+  static constexpr int RBLK = 2 * D / MS::BM;          // row blocks
+  static constexpr int KSTEPS = 2 * D / MS::BK;
+  static constexpr int RW = (sizeof(R) == 4 ? (K == 6 ? 1 : RBLK) : (K == 6 ? 2 : RBLK));  // row blocks per wave
+  static constexpr int WPC = RBLK / RW;                // waves per column block
+  static constexpr int CB = sizeof(R) == 4 ? 5 : 4;    // column bits
+  static constexpr bool PREFETCH = !(sizeof(R) == 8 && K == 6);  // registers for the next block's operands
+  static_assert(MS::BK == G, "one k-step takes one real row per lane group");
+
+  // block row -> (member within the block, re/im)
+  static __device__ __forceinline__ void row_of(int rho, int* mem, int* part) {
+    if constexpr (sizeof(R) == 4) {
+      *mem = 4 * (rho >> 3) + 2 * ((rho & 3) >> 1) + ((rho >> 2) & 1);
+      *part = rho & 1;
+    } else {
+      *mem = 4 * ((rho >> 2) >> 1) + (rho & 3);
+      *part = (rho >> 2) & 1;
+    }
+  }
+  // member (within the block) of registers r, r + 1 (r even): uniform part;
+  // the lane part is its group
+  static __device__ __forceinline__ int out_member_u(int r) {
+    if constexpr (sizeof(R) == 4) return 4 * (r >> 2) + 2 * ((r & 3) >> 1);
+    else return 4 * (r >> 1);
+  }
+  static_assert(RBLK % RW == 0 && 4 % WPC == 0, "row blocks split over the block's waves");
+};
+
+// Tile map of the direct kernel: member bit b of the gate (bit b of the
+// member index; q[k-1-b]) at physical offset mbit[b]; column bits at
+// colpos[]; the column-block index deposited into `rest`.
+struct DirectGeo {
+  uint64_t rest;
+  uint64_t mbit[6];
+  uint32_t colpos[5];
+  uint32_t pad;
+};
+
+// Physical offset of member index mu (a compile-time or uniform value).
+template <int K>
+__device__ __forceinline__ uint64_t member_off(uint32_t mu, const uint64_t* mbit) {
+  uint64_t o = 0;
+#pragma unroll
+  for (int b = 0; b < K; ++b)
+    if ((mu >> b) & 1u) o |= mbit[b];
+  return o;
+}
+
+template <typename R, int K>
+__global__ __launch_bounds__(256) void k_dense_direct(typename mfma_shape<R>::E* __restrict__ psi, uint64_t nwork,
+                                                     DirectGeo g, const R* __restrict__ um) {
+  typedef mfma_shape<R> MS;
+  typedef direct_plan<R, K> DP;
+  typedef typename MS::E E;
+  constexpr int D = DP::D, G = DP::G, NB = DP::NB, KSTEPS = DP::KSTEPS, RW = DP::RW, WPC = DP::WPC;
+  const int l = threadIdx.x % 64;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int col = l % MS::BN, grp = l / MS::BN;
+  // row blocks of this wave: (w % WPC) * RW + i
+  const int rb0 = (w % WPC) * RW;
+  R afrag[RW][KSTEPS];
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    int ai, aa;  // output member and re/im of the A row this lane supplies
+    DP::row_of(l % MS::BM, &ai, &aa);
+    ai += MS::MPB * (rb0 + i);
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+      const int mu = G * (ks >> 1) + l / MS::BM;  // input member of real column BK ks + l / BM
+      const int part = ks & 1;
+      const R ur = um[2 * (ai * D + mu)], ui = um[2 * (ai * D + mu) + 1];
+      // A[2i + aa][2 mu + part] of the real embedding (Ur, -Ui; Ui, Ur)
+      afrag[i][ks] = aa == 0 ? (part == 0 ? ur : -ui) : (part == 0 ? ui : ur);
+    }
+  }
+  uint64_t mbit[K];
+#pragma unroll
+  for (int b = 0; b < K; ++b) mbit[b] = g.mbit[b];
+  uint64_t lane_col = 0;
+#pragma unroll
+  for (int b = 0; b < DP::CB; ++b)
+    if ((col >> b) & 1) lane_col |= 1ull << g.colpos[b];
+  // lane parts of the loaded and of the stored members
+  const uint64_t lane = lane_col | member_off<K>((uint32_t)grp, mbit);  // loads and stores alike
+  E* const p = psi;
+  // column blocks: block-major over the grid, XCD-aware; WPC waves of a block
+  // share one column block, the others take their own
+  const uint64_t waves_per_block = 4 / WPC;
+  const uint64_t slot = xcd_block() * waves_per_block + (uint64_t)(w / WPC);
+  const uint64_t stride = (uint64_t)gridDim.x * waves_per_block;
+  E x[NB], xn[DP::PREFETCH ? NB : 1];
+  auto load = [&](uint64_t c, E* dst) {
+    const uint64_t base = deposit(c, g.rest) | lane;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) dst[j] = ld(p + (base | member_off<K>((uint32_t)(G * j), mbit)));
+  };
+  // the waves of a block that share column blocks (WPC > 1) share `slot`
+  // and so run the same iterations: all reach the barrier
+  if constexpr (DP::PREFETCH) {
+    if (slot < nwork) load(slot, x);
+  }
+  for (uint64_t cb = slot; cb < nwork; cb += stride) {
+    if constexpr (DP::PREFETCH) {
+      if (cb + stride < nwork) load(cb + stride, xn);
+    } else {
+      load(cb, x);
+    }
+    typename MS::acc_t acc[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+      acc[i] = typename MS::acc_t{};
+#pragma unroll
+      for (int ks = 0; ks < KSTEPS; ++ks) {
+        const E xv = x[ks >> 1];
+        const R b = (ks & 1) ? xv.y : xv.x;
+        acc[i] = MS::mma(afrag[i][ks], b, acc[i]);
+      }
+    }
+    if constexpr (WPC > 1) __syncthreads();  // every wave of the block has read the column block
+    const uint64_t base = deposit(cb, g.rest) | lane;
+#pragma unroll
+    for (int i = 0; i < RW; ++i)
+#pragma unroll
+      for (int r = 0; r < MS::NACC; r += 2) {
+        const uint32_t mu = (uint32_t)(MS::MPB * (rb0 + i) + DP::out_member_u(r));
+        E y;
+        y.x = acc[i][r];
+        y.y = acc[i][r + 1];
+        st(p + (base | member_off<K>(mu, mbit)), y);
+      }
+    if constexpr (DP::PREFETCH) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) x[j] = xn[j];
+    }
+  }
+}
+
+// The direct kernel's map, or false when the placement does not suit it:
+// the lowest 128-byte line must be covered by the column bits and the member
+// bits a lane group owns.
+template <typename R, int K>
+bool direct_geo(int n, const int* q, DirectGeo* g) {
+  typedef direct_plan<R, K> DP;
+  if (n < K + DP::CB) return false;
+  uint64_t gate = 0;
+  for (int i = 0; i < K; ++i) gate |= 1ull << q[i];
+  *g = DirectGeo{};
+  for (int b = 0; b < K; ++b) g->mbit[b] = 1ull << q[K - 1 - b];
+  int c = 0;
+  uint64_t cols = 0;
+  for (int p = 0; p < n && c < DP::CB; ++p)
+    if (!((gate >> p) & 1)) {
+      g->colpos[c++] = (uint32_t)p;
+      cols |= 1ull << p;
+    }
+  uint64_t lanebits = cols;
+  for (int b = 0; (1 << b) < DP::G; ++b) lanebits |= g->mbit[b];
+  const int line_bits = sizeof(R) == 4 ? 4 : 3;  // amplitudes in 128 bytes
+  if ((lanebits & ((1ull << line_bits) - 1)) != ((1ull << line_bits) - 1)) return false;
+  const uint64_t all = (1ull << n) - 1ull;
+  g->rest = all & ~gate & ~cols;
+  return true;
+}
+
+template <typename R, int K>
+hipError_t launch_direct(void* psi, int n, const DirectGeo& g, const void* m, hipStream_t s) {
+  typedef direct_plan<R, K> DP;
+  const uint64_t nwork = 1ull << (n - K - DP::CB);  // column blocks
+  static KernelLaunchCache cache;
+  uint64_t resident = 0;
+  hipError_t e = prepare_launch(cache, (const void*)k_dense_direct<R, K>, 256, 0, &resident);
+  if (e != hipSuccess) return e;
+  const uint64_t per_block = 4 / DP::WPC;
+  uint64_t blocks = (nwork + per_block - 1) / per_block;
+  if (blocks > resident) blocks = resident;
+  hipLaunchKernelGGL((k_dense_direct<R, K>), dim3((unsigned)blocks), dim3(256), 0, s,
+                     (typename mfma_shape<R>::E*)psi, nwork, g, (const R*)m);
+  return hipGetLastError();
+}
+
 DenseGeo make_geo(int n, int k, const int* q, int nc, int es, int lb);
 
 template <typename R, int K, bool SWZ>
 hipError_t launch_mfma(void* psi, uint64_t nwork, const DenseGeo& g, const void* m, hipStream_t s) {
   constexpr size_t lds = mfma_lds<R, K>();
   const void* fn = SWZ ? (const void*)k_dense_mfma_swz<R, K> : (const void*)k_dense_mfma<R, K>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  static KernelLaunchCache cache;
+  hipError_t e = prepare_launch(cache, fn, mfma_plan<R, K>::THREADS, lds, nullptr);
+  if (e != hipSuccess) return e;
   // persistent blocks: enough to fill the chip several times over, each
   // amortising its A fragments (loaded once) over many column tiles
   const uint64_t blocks = nwork < 4096 ? nwork : 4096;
@@ -606,12 +806,15 @@ hipError_t launch_mfma(void* psi, uint64_t nwork, const DenseGeo& g, const void*
 
 DenseGeo make_geo(int n, int k, const int* q, int nc, int es, int lb);
 
-// The swizzled kernel runs when the plain layout would put a wave's 64 lanes
+// Placements whose lowest 128-byte line the direct kernel's lanes cover run
+// without LDS.  Otherwise the swizzled kernel runs when the plain layout would put a wave's 64 lanes
 // on at most a quarter (complex64 k = 6: a sixteenth) of the LDS bank groups
 // they could use (member bits among the lanes: low qubit placements); the
 // plain kernel addresses its operands more cheaply and runs otherwise.
 template <typename R, int K>
 hipError_t run_mfma(void* psi, int n, const int* q, const void* m, hipStream_t s) {
+  DirectGeo dg;
+  if (direct_geo<R, K>(n, q, &dg)) return launch_direct<R, K>(psi, n, dg, m, s);
   constexpr int NC = mfma_cols<R, K>();
   constexpr int LB = sizeof(R) == 4 ? 1 : 0;
   const uint64_t ngroups = 1ull << (n - K);

@@ -65,10 +65,18 @@ enum PassKind { PASS_SWEEP = 0, PASS_TILE = 1, PASS_DENSE = 2, PASS_PERMUTE = 3 
 
 struct StageHost {
   uint32_t q[kPassRegBitsMax] = {0, 0, 0, 0, 0};  // local bit of each register bit
-  std::vector<PassOpDev> ops;               // .mat indexes this stage's `mats`
+  uint32_t form = PFORM_NONE;               // PassForm of the 2x2 part
+  uint32_t flags = 0;                       // PassStageFlags
+  uint32_t slots = 0, u2 = 0, dr = 0;       // entries of `mats`
+  std::vector<PassItemDev> items;           // lane items (.mat indexes `mats`)
+  std::vector<PassItemDev> px;              // permutation terms (PIT_PX)
+  uint32_t pcol[kPassRegBitsMax] = {1, 2, 4, 8, 16};  // register permutation, columns
+  uint32_t pconst = 0;
   std::vector<cd> mats;
   std::vector<uint8_t> raw;                 // per entry: 1 = two raw words (write_pool)
-  uint32_t rows = 0, row_count = 0;         // phase-op row table (PassStageDev)
+  uint32_t rows = 0, row_count = 0;         // fixed-point row table (PassStageDev)
+  int n_ops = 0;                            // kernel ops (sv_plan_pass_ops)
+  int n_fixed = 0;                          // fixed-point phase items among them
 };
 
 // Write `count` pool entries in the state precision (complex64: f32 = true).
@@ -94,11 +102,10 @@ struct Pass {
 // load positions.
 bool fill_pass_maps(const Pass& ps, sv_dtype dt, PassDescDev* d);
 
-// The pass's stages hold fixed-point phase ops (POP_LP, POP_QG).
+// The pass's stages hold fixed-point phase items (PIT_LP, PIT_QG).
 inline bool pass_has_ladders(const Pass& ps) {
   for (const StageHost& sh : ps.stages)
-    for (const PassOpDev& od : sh.ops)
-      if (od.type == POP_LP || od.type == POP_QG) return true;
+    if (sh.n_fixed) return true;
   return false;
 }
 
@@ -162,4 +169,18 @@ double op_sweep_cost(const Op& op, sv_dtype dt, bool mfma);
 int default_lds_qubits(sv_dtype dt);
 int default_pinned_bits(sv_dtype dt);
 sv_status execute_plan(sv_state* s, const sv_plan* p);
+
+// Device image of a plan: dense matrices (state precision) and the tile-pass
+// program [descriptors][stages][items][pool], every part 256-byte aligned.
+// The single packer of both sv_apply_plan and sv_program_create.
+struct PackedPlan {
+  std::vector<unsigned char> host;
+  std::vector<size_t> dense_off;   // per pass: offset of its dense matrix (PASS_DENSE)
+  std::vector<int> desc_index;     // per pass: descriptor index (PASS_TILE / PASS_PERMUTE) or -1
+  std::vector<char> pass_lp;       // per pass: holds fixed-point phase items
+  size_t off_desc = 0, off_stage = 0, off_items = 0, off_pool = 0;
+  int n_desc = 0, max_m = 0;
+};
+// tile_only: fail with SV_ERR_UNSUPPORTED on sweep and dense passes.
+sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out);
 }  // namespace sv

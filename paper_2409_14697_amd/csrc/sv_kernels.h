@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <complex>
+#include <mutex>
 
 #include "sv.h"
 
@@ -80,6 +81,47 @@ hipError_t launch_probs(sv_dtype dt, const void* psi, int n, const int* qubits, 
 // array; no allocation): its bytes, and its device address.
 size_t static_scratch_bytes();
 hipError_t static_scratch(int device, void** out);
+
+// --- launch state -----------------------------------------------------------
+// Per-device launch state of one kernel: the dynamic LDS limit raised with
+// hipFuncSetAttribute and the number of blocks resident on the device per
+// dynamic LDS size.  Launches may come from several host threads and several
+// devices; the cache is guarded and kept per device.
+struct KernelLaunchCache {
+  static constexpr int kMaxDevices = 64;
+  static constexpr int kSizes = 18;  // dynamic LDS sizes 2^0 .. 2^17 bytes
+  std::mutex mu;
+  size_t lds_attr[kMaxDevices] = {};
+  uint64_t resident[kMaxDevices][kSizes] = {};
+};
+
+// Make `fn` launchable with `lds` bytes of dynamic LDS on the current device;
+// *resident (if non-null) receives the blocks of `block` threads that fit on
+// the device at once with that LDS (the persistent grid of a tile loop).
+inline hipError_t prepare_launch(KernelLaunchCache& c, const void* fn, int block, size_t lds, uint64_t* resident) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= KernelLaunchCache::kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(c.mu);
+  if (lds > c.lds_attr[dev]) {
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    c.lds_attr[dev] = lds;
+  }
+  if (!resident) return hipSuccess;
+  int lg = 0;
+  while (lg + 1 < KernelLaunchCache::kSizes && ((size_t)1 << lg) < lds) ++lg;
+  uint64_t& r = c.resident[dev][lg];
+  if (!r) {
+    int nb = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, block, lds) != hipSuccess || nb < 1) nb = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    r = (uint64_t)nb * (uint64_t)cus;
+  }
+  *resident = r;
+  return hipSuccess;
+}
 
 // --- utilities --------------------------------------------------------------
 hipError_t launch_init_basis(sv_dtype dt, void* psi, int n, uint64_t index, hipStream_t s);

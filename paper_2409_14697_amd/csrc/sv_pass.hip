@@ -5,13 +5,19 @@
 // tile base on every non-local bit.  The tile is gathered from HBM with the
 // PDEP-like deposit of its local index into the pass's local bit positions
 // (Sec. III-B), so the low pinned positions give contiguous runs.  The pass's
-// stages then run in LDS: a stage gives each lane a group of 32 (complex64)
-// or 16 (complex128) amplitudes (5 or 4 local bits held in registers) and
-// applies a list of ops to them in registers; ops whose controls or phase
-// bits lie outside the register bits read those bits from the group's local
-// index or from the tile base.  A fused run of diagonal gates (Sec. III-A) is
-// a phase function of the index bits: its fixed-point angle words are summed
-// per lane from both, with the tile part summed once per tile and stage.
+// register stages then run in LDS: a stage gives each lane a group of 32
+// (complex64) or 16 (complex128) amplitudes (5 or 4 local bits held in
+// registers) and applies, as straight-line code with the bit positions
+// fixed at compile time,
+//   - the tensor product of one 2x2 per register bit (a layer of
+//     single-qubit gates: the tensor product booster of Sec. III-A), in the
+//     cheapest of four forms that holds all of them;
+//   - a diagonal: one factor per register index, times per-lane factors for
+//     the gates that involve bits outside the registers (a fused run of
+//     phase gates, Sec. III-A, is a fixed-point phase function of the index
+//     bits; its tile part is summed once per tile and stage);
+//   - a permutation of the register index (X, CNOT, SWAP) at no cost: the
+//     stage's LDS store writes each amplitude to its permuted address.
 // The tile is written back with local bit j at physical position wpos[j],
 // which fuses qubit reordering (Sec. II-B) into the store.
 //
@@ -53,7 +59,7 @@ struct dev_elem<float> {
   typedef flt2 E;
 };
 
-// Program memory (pass descriptors, stages, ops, matrices, batch items) is
+// Program memory (pass descriptors, stages, items, matrices, batch items) is
 // read-only while a pass kernel runs.  Reading it through the constant
 // address space lets uniform reads go through scalar loads even where the
 // compiler cannot prove that the state's stores do not alias it (the batched
@@ -109,6 +115,11 @@ __device__ __forceinline__ T cload(cptr<T> p) {
   return out;
 }
 
+// ---- the 2x2 part: one gate per register bit, in the stage's form ----------
+// Each applies the 2x2 at M[0..3] to every pair of register amplitudes that
+// differ in bit B (Eq. 2 on the register bits).
+
+// General complex 2x2: 8 multiply-adds per amplitude.
 template <int B, typename R>
 __device__ __forceinline__ void op_u1(cplx<R>* v, cptr<cplx<R>> M) {
   constexpr int NR = Regs<R>::NR;
@@ -122,26 +133,7 @@ __device__ __forceinline__ void op_u1(cplx<R>* v, cptr<cplx<R>> M) {
     }
 }
 
-template <int B0, int B1, typename R>
-__device__ __forceinline__ void op_u2(cplx<R>* v, cptr<cplx<R>> M) {
-  constexpr int NR = Regs<R>::NR;
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-    if (!((r >> B0) & 1) && !((r >> B1) & 1)) {
-      const int i[4] = {r, r | (1 << B1), r | (1 << B0), r | (1 << B0) | (1 << B1)};
-      const cplx<R> x0 = v[i[0]], x1 = v[i[1]], x2 = v[i[2]], x3 = v[i[3]];
-#pragma unroll
-      for (int o = 0; o < 4; ++o) {
-        cplx<R> y = cmul(cget(M, 4 * o), x0);
-        y = cfma(y, cget(M, 4 * o + 1), x1);
-        y = cfma(y, cget(M, 4 * o + 2), x2);
-        y = cfma(y, cget(M, 4 * o + 3), x3);
-        v[i[o]] = y;
-      }
-    }
-}
-
-// Real 2x2 (H, RY): two real scalars per output, 4 multiply-adds per amplitude.
+// Real 2x2 (H, RY): 4 per amplitude.
 template <int B, typename R>
 __device__ __forceinline__ void op_ur(cplx<R>* v, cptr<cplx<R>> M) {
   constexpr int NR = Regs<R>::NR;
@@ -155,7 +147,7 @@ __device__ __forceinline__ void op_ur(cplx<R>* v, cptr<cplx<R>> M) {
     }
 }
 
-// Real diagonal, imaginary off-diagonal (RX): (x + i y) * (i s) = -s y + i s x.
+// Real diagonal, imaginary off-diagonal (RX, Y): (x + i y) * (i s) = -s y + i s x.
 template <int B, typename R>
 __device__ __forceinline__ void op_ui(cplx<R>* v, cptr<cplx<R>> M) {
   constexpr int NR = Regs<R>::NR;
@@ -169,21 +161,60 @@ __device__ __forceinline__ void op_ui(cplx<R>* v, cptr<cplx<R>> M) {
     }
 }
 
-// Phase on the amplitudes whose register bit B is 1 (controlled phases).
+// Real diagonal, complex off-diagonal (a layer mixing the two kinds above): 6.
 template <int B, typename R>
-__device__ __forceinline__ void op_p1(cplx<R>* v, cplx<R> p) {
+__device__ __forceinline__ void op_rc(cplx<R>* v, cptr<cplx<R>> M) {
   constexpr int NR = Regs<R>::NR;
+  const R m0 = cget(M, 0).re, m3 = cget(M, 3).re;
+  const cplx<R> m1 = cget(M, 1), m2 = cget(M, 2);
 #pragma unroll
   for (int r = 0; r < NR; ++r)
-    if ((r >> B) & 1) v[r] = cmul(p, v[r]);
+    if (!((r >> B) & 1)) {
+      const cplx<R> a0 = v[r], a1 = v[r | (1 << B)];
+      cplx<R> o0 = cmul(m1, a1), o1 = cmul(m2, a0);
+      o0.re = fma(m0, a0.re, o0.re);
+      o0.im = fma(m0, a0.im, o0.im);
+      o1.re = fma(m3, a1.re, o1.re);
+      o1.im = fma(m3, a1.im, o1.im);
+      v[r] = o0;
+      v[r | (1 << B)] = o1;
+    }
 }
 
-template <int B0, int B1, typename R>
-__device__ __forceinline__ void op_p2(cplx<R>* v, cplx<R> p) {
+// Dense 4x4 on register bits (1 = most significant bit of its index, 0).
+template <typename R>
+__device__ __forceinline__ void op_u2(cplx<R>* v, cptr<cplx<R>> M) {
   constexpr int NR = Regs<R>::NR;
 #pragma unroll
-  for (int r = 0; r < NR; ++r)
-    if (((r >> B0) & 1) && ((r >> B1) & 1)) v[r] = cmul(p, v[r]);
+  for (int r = 0; r < NR; r += 4) {
+    const cplx<R> x0 = v[r], x1 = v[r | 1], x2 = v[r | 2], x3 = v[r | 3];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      cplx<R> y = cmul(cget(M, 4 * o), x0);
+      y = cfma(y, cget(M, 4 * o + 1), x1);
+      y = cfma(y, cget(M, 4 * o + 2), x2);
+      y = cfma(y, cget(M, 4 * o + 3), x3);
+      v[r | o] = y;
+    }
+  }
+}
+
+// The tensor product of one 2x2 per register bit (4 entries per bit, bit 0
+// first), every bit in form F.
+template <int F, int B, typename R>
+__device__ __forceinline__ void slot(cplx<R>* v, cptr<cplx<R>> M) {
+  if constexpr (F == PFORM_UR) op_ur<B>(v, M + 4 * B);
+  else if constexpr (F == PFORM_UI) op_ui<B>(v, M + 4 * B);
+  else if constexpr (F == PFORM_RC) op_rc<B>(v, M + 4 * B);
+  else op_u1<B>(v, M + 4 * B);
+}
+template <int F, typename R>
+__device__ __forceinline__ void layer(cplx<R>* v, cptr<cplx<R>> M) {
+  slot<F, 0>(v, M);
+  slot<F, 1>(v, M);
+  slot<F, 2>(v, M);
+  slot<F, 3>(v, M);
+  if constexpr (Regs<R>::RB > 4) slot<F, 4>(v, M);
 }
 
 // Angle words of the phase ladder: fixed-point turns, summed modulo one turn.
@@ -210,66 +241,6 @@ struct lp_word<double> {
   }
 };
 
-template <int B, typename R>
-__device__ __forceinline__ void op_x(cplx<R>* v) {
-  constexpr int NR = Regs<R>::NR;
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-    if (!((r >> B) & 1)) {
-      const cplx<R> t = v[r];
-      v[r] = v[r | (1 << B)];
-      v[r | (1 << B)] = t;
-    }
-}
-
-template <int BC, int BT, typename R>
-__device__ __forceinline__ void op_cx(cplx<R>* v) {
-  constexpr int NR = Regs<R>::NR;
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-    if (((r >> BC) & 1) && !((r >> BT) & 1)) {
-      const cplx<R> t = v[r];
-      v[r] = v[r | (1 << BT)];
-      v[r | (1 << BT)] = t;
-    }
-}
-
-template <int B, typename R>
-__device__ __forceinline__ void op_d1(cplx<R>* v, const cplx<R>* M) {
-  constexpr int NR = Regs<R>::NR;
-  const cplx<R> d0 = M[0], d1 = M[1];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) v[r] = cmul(((r >> B) & 1) ? d1 : d0, v[r]);
-}
-
-template <int B0, int B1, typename R>
-__device__ __forceinline__ void op_d2(cplx<R>* v, cptr<cplx<R>> M) {
-  constexpr int NR = Regs<R>::NR;
-  const cplx<R> d[4] = {cget(M, 0), cget(M, 1), cget(M, 2), cget(M, 3)};
-#pragma unroll
-  for (int r = 0; r < NR; ++r) v[r] = cmul(d[(((r >> B0) & 1) << 1) | ((r >> B1) & 1)], v[r]);
-}
-
-// Dispatch on register bits; bit 4 exists only with 5 register bits (H5).
-#define SV_PAIR_SWITCH(code, F, H5)                                                          \
-  switch (code) {                                                                            \
-    case 1: F(0, 1); break;   case 2: F(0, 2); break;   case 3: F(0, 3); break;             \
-    case 8: F(1, 0); break;   case 10: F(1, 2); break;  case 11: F(1, 3); break;            \
-    case 16: F(2, 0); break;  case 17: F(2, 1); break;  case 19: F(2, 3); break;            \
-    case 24: F(3, 0); break;  case 25: F(3, 1); break;  case 26: F(3, 2); break;            \
-    case 4: if constexpr (H5) F(0, 4); break;   case 12: if constexpr (H5) F(1, 4); break;  \
-    case 20: if constexpr (H5) F(2, 4); break;  case 28: if constexpr (H5) F(3, 4); break;  \
-    case 32: if constexpr (H5) F(4, 0); break;  case 33: if constexpr (H5) F(4, 1); break;  \
-    case 34: if constexpr (H5) F(4, 2); break;  case 35: if constexpr (H5) F(4, 3); break;  \
-    default: break;                                                                          \
-  }
-#define SV_BIT_SWITCH(b, F, H5)                                                              \
-  switch (b) {                                                                               \
-    case 0: F(0); break; case 1: F(1); break; case 2: F(2); break; case 3: F(3); break;     \
-    case 4: if constexpr (H5) F(4); break;                                                   \
-    default: break;                                                                          \
-  }
-
 // Sum of the local words (ladder layout) of the lane's set local bits.
 template <typename R>
 __device__ __forceinline__ typename lp_word<R>::W lp_local(cptr<typename lp_word<R>::W> words, uint32_t lsel) {
@@ -290,51 +261,51 @@ __device__ __forceinline__ typename lp_word<R>::W lp_local(cptr<typename lp_word
   return t;
 }
 
-// Tile rows of a phase op (entries of the stage's row table).
-__device__ __forceinline__ uint32_t op_rows(const PassOpDev& op) {
-  if (op.type == POP_LP) return 1u;
-  if (op.type == POP_QG) return 1u + __builtin_popcount(op.b0) + __builtin_popcountll(((uint64_t)op.pad << 32) | op.b1);
+// Tile rows of a fixed-point item (entries of the stage's row table).
+__device__ __forceinline__ uint32_t item_rows(const PassItemDev& it) {
+  if (it.type == PIT_LP) return 1u;
+  if (it.type == PIT_QG) return 1u + __builtin_popcount(it.a) + __builtin_popcountll(it.tt);
   return 0u;
 }
 
-// POP_LP: the phase of the lane's amplitudes whose register bit b0 is 1:
+// PIT_LP: the phase of the lane's amplitudes whose register bit `a` is 1:
 // the constant word, the row's tile sum (ts[0], the same in every lane) and
 // the words of the lane's set local group bits (xg has zeros at the
 // register positions).
 template <typename R>
-__device__ __forceinline__ cplx<R> lp_phase(const PassOpDev& op, cptr<cplx<R>> M, uint32_t xg,
+__device__ __forceinline__ cplx<R> lp_phase(const PassItemDev& it, cptr<cplx<R>> M, uint32_t xg,
                                             const typename lp_word<R>::W* ts) {
   typedef typename lp_word<R>::W W;
   const cptr<W> words = (cptr<W>)M;
-  return lp_word<R>::phase(words[kPassLPConst] + ts[0] + lp_local<R>(words, xg & op.lmask));
+  return lp_word<R>::phase(words[kPassLPConst] + ts[0] + lp_local<R>(words, xg & it.lmask));
 }
 
-// POP_QG: row 0 and the constant, then the rows of the local targets set in
+// PIT_QG: row 0 and the constant, then the rows of the local targets set in
 // the lane (tile sum ts[k] plus the row's local words), then the tile-target
 // rows (their tile sums are zero unless the target bit is set).
 template <typename R>
-__device__ __forceinline__ cplx<R> qg_phase(const PassOpDev& op, cptr<cplx<R>> M, uint32_t xg,
+__device__ __forceinline__ cplx<R> qg_phase(const PassItemDev& it, cptr<cplx<R>> M, uint32_t xg,
                                             const typename lp_word<R>::W* ts) {
   typedef typename lp_word<R>::W W;
   cptr<W> words = (cptr<W>)M;
-  const uint32_t lsel = xg & op.lmask;
+  const uint32_t lsel = xg & it.lmask;
   W t = words[kPassLPConst] + ts[0] + lp_local<R>(words, lsel);
   uint32_t k = 1;
 #pragma unroll 1
-  for (uint32_t lt = op.b0; lt; lt &= lt - 1u, ++k) {
+  for (uint32_t lt = it.a; lt; lt &= lt - 1u, ++k) {
     words += kPassLPWords;
     const W h = ts[k] + lp_local<R>(words, lsel);
     t += ((xg >> __builtin_ctz(lt)) & 1u) ? h : W(0);
   }
-  const uint32_t end = op_rows(op);
+  const uint32_t end = item_rows(it);
 #pragma unroll 1
   for (; k < end; ++k) t += ts[k];
   return lp_word<R>::phase(t);
 }
 
-// Tile sums of the stage's phase-op rows into ts[] (all threads; ends with a
-// barrier).  Each thread sums whole rows: its 34 tile words are independent
-// loads, so they are in flight together.
+// Tile sums of the stage's fixed-point rows into ts[] (all threads; ends
+// with a barrier).  Each thread sums whole rows: its 34 tile words are
+// independent loads, so they are in flight together.
 template <typename R>
 __device__ __forceinline__ void stage_rows(const PassStageDev& S, cptr<cplx<R>> mats, uint64_t base,
                                            typename lp_word<R>::W* ts) {
@@ -348,135 +319,105 @@ __device__ __forceinline__ void stage_rows(const PassStageDev& S, cptr<cplx<R>> 
     W acc = 0;
 #pragma unroll
     for (int i = 0; i < kPassLPTileBits; ++i) acc += ((sel >> i) & 1) ? w[i] : W(0);
-    ts[j] = (pred == kPassNoSel || ((base >> pred) & 1)) ? acc : W(0);
+    ts[j] = (pred == kPassRowAlways || ((base >> pred) & 1)) ? acc : W(0);
   }
   __syncthreads();
 }
 
-// M points at the op's first matrix entry (the same address in every lane, so
-// the entries come through scalar loads); `var` selects a variant per lane.
+// Value of selector code c for the lane: local bit c of its group index, or
+// tile physical bit c - 64 of the tile base.
+__device__ __forceinline__ uint32_t sel_bit(uint32_t c, uint32_t xg, uint64_t base) {
+  return c < kPassTileSel ? (xg >> c) & 1u : (uint32_t)(base >> (c - kPassTileSel)) & 1u;
+}
+__device__ __forceinline__ uint32_t item_var(uint32_t sel, uint32_t xg, uint64_t base) {
+  const uint32_t a = sel & 0xffu, b = (sel >> 8) & 0xffu;
+  uint32_t var = a == kPassNoSel ? 0u : sel_bit(a, xg, base);
+  if (b != kPassNoSel) var = (var << 1) | sel_bit(b, xg, base);
+  return var;
+}
+
+// Entry `var` of a table of n <= 4 entries, loaded uniformly (scalar loads)
+// and selected per lane.
+template <typename R>
+__device__ __forceinline__ cplx<R> pick(cptr<cplx<R>> T, uint32_t var, int n) {
+  cplx<R> x = cget(T, 0);
+  if (n > 1) {
+    const cplx<R> y = cget(T, 1);
+    x.re = (var & 1u) ? y.re : x.re;
+    x.im = (var & 1u) ? y.im : x.im;
+  }
+  if (n > 2) {
+    const cplx<R> z = cget(T, 2), w = cget(T, 3);
+    const R zr = (var & 1u) ? w.re : z.re, zi = (var & 1u) ? w.im : z.im;
+    x.re = (var & 2u) ? zr : x.re;
+    x.im = (var & 2u) ? zi : x.im;
+  }
+  return x;
+}
+
+// The diagonal part with lane items: per lane a factor G on all amplitudes
+// and, per register bit a, factors f0[a] / f1[a] on the amplitudes whose bit
+// a is 0 / 1; amplitude r is multiplied by G * prod_a f_{r_a}[a] * dr[r].
 template <typename R, bool LP>
-__device__ __forceinline__ void apply_op(const PassOpDev& op, cptr<cplx<R>> M, uint32_t var,
-                                         cplx<R>* v, uint32_t xg, const typename lp_word<R>::W* ts) {
-  const uint32_t pair = op.b0 * 8 + op.b1;
-  constexpr bool H5 = Regs<R>::RB > 4;
-  switch (op.type) {
-    case POP_U1: {
-#define F(B) op_u1<B>(v, M)
-      SV_BIT_SWITCH(op.b0, F, H5)
-#undef F
-      break;
-    }
-    case POP_U2: {
-#define F(A, B) op_u2<A, B>(v, M)
-      SV_PAIR_SWITCH(pair, F, H5)
-#undef F
-      break;
-    }
-    case POP_X: {
-#define F(B) op_x<B>(v)
-      SV_BIT_SWITCH(op.b0, F, H5)
-#undef F
-      break;
-    }
-    case POP_CX: {
-#define F(A, B) op_cx<A, B>(v)
-      SV_PAIR_SWITCH(pair, F, H5)
-#undef F
-      break;
-    }
-    case POP_D1: {
-      cplx<R> d[2] = {cget(M, 0), cget(M, 1)};
-      if (op.sa != kPassNoSel) {  // two variants, picked per lane (value selects: the loads stay uniform)
-        const cplx<R> e0 = cget(M, 2), e1 = cget(M, 3);
-        d[0].re = var ? e0.re : d[0].re;
-        d[0].im = var ? e0.im : d[0].im;
-        d[1].re = var ? e1.re : d[1].re;
-        d[1].im = var ? e1.im : d[1].im;
-      }
-#define F(B) op_d1<B>(v, d)
-      SV_BIT_SWITCH(op.b0, F, H5)
-#undef F
-      break;
-    }
-    case POP_D2: {
-#define F(A, B) op_d2<A, B>(v, M)
-      SV_PAIR_SWITCH(pair, F, H5)
-#undef F
-      break;
-    }
-    case POP_UR: {
-#define F(B) op_ur<B>(v, M)
-      SV_BIT_SWITCH(op.b0, F, H5)
-#undef F
-      break;
-    }
-    case POP_UI: {
-#define F(B) op_ui<B>(v, M)
-      SV_BIT_SWITCH(op.b0, F, H5)
-#undef F
-      break;
-    }
-    case POP_P1:
-    case POP_LP: {  // one phase per lane on the amplitudes whose bit b0 is 1
-      cplx<R> p;
-      if (LP && op.type == POP_LP) {
-        p = lp_phase<R>(op, M, xg, ts);
-      } else {
-        p = cget(M, 0);
-        if (op.sa != kPassNoSel) {  // two variants, picked per lane
-          const cplx<R> p1 = cget(M, 1);
-          p.re = var ? p1.re : p.re;
-          p.im = var ? p1.im : p.im;
+__device__ __forceinline__ void lane_diag(const PassStageDev& S, cptr<PassItemDev> items, cptr<cplx<R>> mats,
+                                          uint32_t xg, uint64_t base, const typename lp_word<R>::W* ts,
+                                          cplx<R>* v) {
+  constexpr int RB = Regs<R>::RB, NR = Regs<R>::NR, HALF = NR / 2;
+  const cplx<R> one = {R(1), R(0)};
+  cplx<R> G = one, f0[RB], f1[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) f0[b] = f1[b] = one;
+  uint32_t row = 0;  // the item's first row in ts
+  for (uint32_t i = 0; i < S.item_count; ++i) {
+    const PassItemDev it = cload(items + (S.item_first + i));
+    const cptr<cplx<R>> T = mats + it.mat;
+    if (it.type == PIT_DG) {
+      const uint32_t sb = (it.sel >> 8) & 0xffu;
+      G = cmul(G, pick<R>(T, item_var(it.sel, xg, base), sb == kPassNoSel ? 2 : 4));
+    } else if (it.type == PIT_D1) {
+      const uint32_t var = item_var(it.sel, xg, base);
+      const cplx<R> e0 = pick<R>(T, var << 1, 4), e1 = pick<R>(T, (var << 1) | 1u, 4);
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+        if (it.a == (uint32_t)b) {
+          f0[b] = cmul(f0[b], e0);
+          f1[b] = cmul(f1[b], e1);
         }
-      }
-#define F(B) op_p1<B>(v, p)
-      SV_BIT_SWITCH(op.b0, F, H5)
-#undef F
-      break;
-    }
-    case POP_P2: {
-      const cplx<R> p = cget(M, 0);
-#define F(A, B) op_p2<A, B>(v, p)
-      SV_PAIR_SWITCH(pair, F, H5)
-#undef F
-      break;
-    }
-    case POP_DR: {
+    } else if (LP && it.type == PIT_LP) {
+      const cplx<R> p = lp_phase<R>(it, T, xg, ts + row);
 #pragma unroll
-      for (int r = 0; r < Regs<R>::NR; ++r) v[r] = cmul(cget(M, r), v[r]);
-      break;
+      for (int b = 0; b < RB; ++b)
+        if (it.a == (uint32_t)b) f1[b] = cmul(f1[b], p);
+      row += 1;
+    } else if (LP && it.type == PIT_QG) {
+      G = cmul(G, qg_phase<R>(it, T, xg, ts + row));
+      row += item_rows(it);
     }
-    case POP_QG: {
-      if constexpr (LP) {
-        const cplx<R> p = qg_phase<R>(op, M, xg, ts);
+  }
+  // factors of the register index over the bits below the top one, by doubling
+  cplx<R> H[HALF];
+  H[0] = G;
+  if (S.flags & PSF_F0) {
 #pragma unroll
-        for (int r = 0; r < Regs<R>::NR; ++r) v[r] = cmul(p, v[r]);
-      }
-      break;
-    }
-    case POP_DG: {
-      cplx<R> p = cget(M, 0);
-      if (op.sa != kPassNoSel) {
-        const cplx<R> p1 = cget(M, 1);
-        if (op.sb != kPassNoSel) {
-          const cplx<R> p2 = cget(M, 2), p3 = cget(M, 3);
-          // two-level select on the variant bits (kept as selects, not a table)
-          const bool hi = (var >> 1) & 1u, lo = var & 1u;
-          const R re0 = lo ? p1.re : p.re, im0 = lo ? p1.im : p.im;
-          const R re1 = lo ? p3.re : p2.re, im1 = lo ? p3.im : p2.im;
-          p.re = hi ? re1 : re0;
-          p.im = hi ? im1 : im0;
-        } else if (var) {
-          p = p1;
-        }
-      }
+    for (int a = 0; a < RB - 1; ++a)
 #pragma unroll
-      for (int r = 0; r < Regs<R>::NR; ++r) v[r] = cmul(p, v[r]);
-      break;
-    }
-    default:
-      break;
+      for (int k = 0; k < (1 << a); ++k) {
+        H[k | (1 << a)] = cmul(H[k], f1[a]);
+        H[k] = cmul(H[k], f0[a]);
+      }
+  } else {
+#pragma unroll
+    for (int a = 0; a < RB - 1; ++a)
+#pragma unroll
+      for (int k = 0; k < (1 << a); ++k) H[k | (1 << a)] = cmul(H[k], f1[a]);
+  }
+  const cptr<cplx<R>> D = mats + S.dr;
+#pragma unroll
+  for (int r = 0; r < HALF; ++r) {
+    const cplx<R> lo = cmul(cmul(H[r], f0[RB - 1]), cget(D, r));
+    const cplx<R> hi = cmul(cmul(H[r], f1[RB - 1]), cget(D, r + HALF));
+    v[r] = cmul(lo, v[r]);
+    v[r + HALF] = cmul(hi, v[r + HALF]);
   }
 }
 
@@ -530,20 +471,20 @@ struct TileRef {
   typename dev_elem<R>::E* psi;
   cptr<PassDescDev> P;
   cptr<PassStageDev> stages;
-  cptr<PassOpDev> ops;
+  cptr<PassItemDev> items;
   cptr<cplx<R>> mats;
   uint64_t base;
 };
 
 template <typename R>
 __device__ __forceinline__ TileRef<R> tile_ref(typename dev_elem<R>::E* psi, int n, cptr<PassDescDev> P,
-                                               cptr<PassStageDev> stages, cptr<PassOpDev> ops,
+                                               cptr<PassStageDev> stages, cptr<PassItemDev> items,
                                                cptr<cplx<R>> mats, uint64_t tile_id) {
   TileRef<R> r;
   r.psi = uniform_ptr(psi);
   r.P = uniform_ptr(P);
   r.stages = uniform_ptr(stages);
-  r.ops = uniform_ptr(ops);
+  r.items = uniform_ptr(items);
   r.mats = uniform_ptr(mats);
   r.base = uniform64(deposit(tile_id, ((1ull << n) - 1ull) & ~r.P->lmask));
   return r;
@@ -627,14 +568,14 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
   typedef typename dev_elem<R>::E E;
   const cptr<PassDescDev> P = T.P;
   const cptr<PassStageDev> stages = T.stages;
-  const cptr<PassOpDev> ops = T.ops;
+  const cptr<PassItemDev> items = T.items;
   const cptr<cplx<R>> mats = T.mats;
   const uint64_t base = T.base;
   const uint32_t size = 1u << P->m;
   const uint32_t t = threadIdx.x;
   constexpr int RB = Regs<R>::RB, NR = Regs<R>::NR;
   typedef typename lp_word<R>::W W;
-  __shared__ W tsum[LP ? kPassStageRowsMax : 1];  // tile sums of the stage's phase-op rows
+  __shared__ W tsum[LP ? kPassStageRowsMax : 1];  // tile sums of the stage's fixed-point rows
   for (uint32_t si = 0; si < P->stage_count; ++si) {
     const PassStageDev S = cload(stages + (P->stage_first + si));
     if constexpr (LP) {
@@ -644,9 +585,19 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
     // swz is linear over XOR and xg shares no bit with a register offset, so
     // swz(xg | off) = swz(xg) ^ (XOR of swz(bit) over the offset's bits): only
     // the swizzled register bits are kept, not one offset per register
-    uint32_t sbit[RB];
+    uint32_t sbit[RB], cbit[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) sbit[b] = swz<WB>(1u << S.q[b]);
+    // the store writes amplitude r to register index A r ^ c: bit j of r
+    // moves the address by the swizzled image of column j
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      uint32_t o = 0;
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+        if ((S.pcol[j] >> b) & 1u) o ^= sbit[b];
+      cbit[j] = o;
+    }
     for (uint32_t gi = t; gi < groups; gi += kBlock) {
       uint32_t xg = gi;
 #pragma unroll
@@ -665,44 +616,50 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
         const E e = tile[o];
         v[r] = cplx<R>{e.x, e.y};
       }
-      uint32_t row = 0;  // the op's first row in tsum
-      for (uint32_t o = 0; o < S.op_count; ++o) {
-        const PassOpDev op = cload(ops + (S.op_first + o));
-        if (!(LP && (op.type == POP_LP || op.type == POP_QG)) &&
-            ((xg & op.lmask) != op.lmask || (base & op.tmask) != op.tmask))
-          continue;
-        uint32_t var = 0;
-        if (op.sa != kPassNoSel) {
-          var = op.sa < kPassTileSel ? (xg >> op.sa) & 1u : (uint32_t)(base >> (op.sa - kPassTileSel)) & 1u;
-          if (op.sb != kPassNoSel)
-            var = (var << 1) |
-                  (op.sb < kPassTileSel ? (xg >> op.sb) & 1u : (uint32_t)(base >> (op.sb - kPassTileSel)) & 1u);
-        }
-        apply_op<R, LP>(op, mats + op.mat, var, v, xg, tsum + row);
-        if constexpr (LP) row += op_rows(op);
+      if (S.flags & PSF_U2) op_u2<R>(v, mats + S.u2);
+      switch (S.form) {
+        case PFORM_UR: layer<PFORM_UR>(v, mats + S.slots); break;
+        case PFORM_UI: layer<PFORM_UI>(v, mats + S.slots); break;
+        case PFORM_RC: layer<PFORM_RC>(v, mats + S.slots); break;
+        case PFORM_U: layer<PFORM_U>(v, mats + S.slots); break;
+        default: break;
       }
-      // The store recomputes the offsets from opaque copies of the inputs, so
-      // the compiler cannot keep the load's NR offsets live across the ops
-      // (they would take NR scalar registers and push the kernel into spills).
-      uint32_t sxs = sx;
-      asm volatile("" : "+v"(sxs));
+      if (S.flags & PSF_LANE) {
+        lane_diag<R, LP>(S, items, mats, xg, base, tsum, v);
+      } else if (S.flags & PSF_DR) {
+        const cptr<cplx<R>> D = mats + S.dr;
 #pragma unroll
-      for (int b = 0; b < RB; ++b) asm volatile("" : "+s"(sbit[b]));
+        for (int r = 0; r < NR; ++r) v[r] = cmul(cget(D, r), v[r]);
+      }
+      // register index of amplitude 0 after the permutation
+      uint32_t c = S.pconst;
+      for (uint32_t k = 0; k < S.px_count; ++k) {
+        const PassItemDev it = cload(items + (S.px_first + k));
+        if (sel_bit(it.sel & 0xffu, xg, base)) c ^= it.a;
+      }
+      uint32_t so = sx;
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+        if ((c >> b) & 1u) so ^= sbit[b];
+      // The store recomputes the offsets from opaque copies of the inputs, so
+      // the compiler cannot keep NR offsets live across the stage's work.
+      asm volatile("" : "+v"(so));
+#pragma unroll
+      for (int b = 0; b < RB; ++b) asm volatile("" : "+s"(cbit[b]));
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         E e;
         e.x = v[r].re;
         e.y = v[r].im;
-        uint32_t o = sxs;
+        uint32_t o = so;
 #pragma unroll
         for (int b = 0; b < RB; ++b)
-          if ((r >> b) & 1) o ^= sbit[b];
+          if ((r >> b) & 1) o ^= cbit[b];
         tile[o] = e;
       }
     }
     __syncthreads();
   }
-
 }
 
 // Store the tile: local bit j goes to physical position wpos[j], a
@@ -801,10 +758,10 @@ struct SingleSrc {
   int n;
   cptr<PassDescDev> P;
   cptr<PassStageDev> stages;
-  cptr<PassOpDev> ops;
+  cptr<PassItemDev> items;
   cptr<cplx<R>> mats;
   __device__ __forceinline__ TileRef<R> operator()(uint64_t g) const {
-    return tile_ref<R>(psi, n, P, stages, ops, mats, g);
+    return tile_ref<R>(psi, n, P, stages, items, mats, g);
   }
 };
 
@@ -812,13 +769,13 @@ template <typename R, int WB, bool LP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pass(typename dev_elem<R>::E* __restrict__ psi, int n,
                                                  const PassDescDev* __restrict__ passes, int pi,
                                                  const PassStageDev* __restrict__ stages,
-                                                 const PassOpDev* __restrict__ ops,
+                                                 const PassItemDev* __restrict__ items,
                                                  const cplx<R>* __restrict__ mats) {
   typedef typename dev_elem<R>::E E;
   extern __shared__ __align__(16) unsigned char smem[];
   E* tile = reinterpret_cast<E*>(smem);
   const cptr<PassDescDev> P = as_const(passes + pi);
-  const SingleSrc<R> src{psi, n, P, as_const(stages), as_const(ops), as_const(mats)};
+  const SingleSrc<R> src{psi, n, P, as_const(stages), as_const(items), as_const(mats)};
   tile_loop<R, WB, LP>(1ull << (n - P->m), src, tile);
 }
 
@@ -840,7 +797,7 @@ struct BatchSrc {
     lo = __builtin_amdgcn_readfirstlane(lo);  // the same in every lane
     const cptr<BatchItemDev> it = items + lo;  // fields read one by one: scalar loads
     return tile_ref<R>((typename dev_elem<R>::E*)it->psi, it->n, as_const(it->passes + it->pass),
-                       as_const(it->stages), as_const(it->ops), as_const((const cplx<R>*)it->mats),
+                       as_const(it->stages), as_const(it->items), as_const((const cplx<R>*)it->mats),
                        g - it->tile_begin);
   }
 };
@@ -855,37 +812,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   tile_loop<R, WB, LP>(total_tiles, src, tile);
 }
 
-// Blocks that fit on the device at once for `kernel` with `lds` bytes of
-// dynamic LDS (the persistent grid of the pipelined tile loop).
-template <typename F>
-uint64_t resident_blocks(F kernel, size_t lds, uint64_t* cache) {
-  int nb = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, lds) != hipSuccess || nb < 1) nb = 1;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-    cus = 256;
-  *cache = (uint64_t)nb * (uint64_t)cus;
-  return *cache;
-}
-
 template <typename R, int WB, bool LP>
 hipError_t run(void* psi, int n, int m, const PassDescDev* passes, int pass, const PassStageDev* stages,
-               const PassOpDev* ops, const void* mats, hipStream_t s) {
+               const PassItemDev* items, const void* mats, hipStream_t s) {
   typedef typename dev_elem<R>::E E;
   const size_t lds = ((size_t)1 << m) * sizeof(E);
-  static size_t attr = 0;            // largest dynamic LDS size requested so far
-  static uint64_t resident[17] = {};  // per tile size
-  if (lds > attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_pass<R, WB, LP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    attr = lds;
-  }
-  if (!resident[m]) resident_blocks(k_pass<R, WB, LP>, lds, &resident[m]);
+  static KernelLaunchCache cache;
+  uint64_t resident = 0;
+  hipError_t e = prepare_launch(cache, (const void*)k_pass<R, WB, LP>, kBlock, lds, &resident);
+  if (e != hipSuccess) return e;
   const uint64_t tiles = 1ull << (n - m);
-  const uint64_t blocks = tiles < resident[m] ? tiles : resident[m];
+  const uint64_t blocks = tiles < resident ? tiles : resident;
   hipLaunchKernelGGL((k_pass<R, WB, LP>), dim3((unsigned)blocks), dim3(kBlock), lds, s, (E*)psi, n, passes, pass, stages,
-                     ops, (const cplx<R>*)mats);
+                     items, (const cplx<R>*)mats);
   return hipGetLastError();
 }
 
@@ -893,17 +832,12 @@ template <typename R, int WB, bool LP>
 hipError_t run_batch(const BatchItemDev* items, int count, uint64_t total_tiles, int max_m, hipStream_t s) {
   typedef typename dev_elem<R>::E E;
   const size_t lds = ((size_t)1 << max_m) * sizeof(E);
-  static size_t attr = 0;
-  static uint64_t resident[17] = {};
-  if (lds > attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_pass_batch<R, WB, LP>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = lds;
-  }
+  static KernelLaunchCache cache;
+  uint64_t resident = 0;
+  hipError_t e = prepare_launch(cache, (const void*)k_pass_batch<R, WB, LP>, kBlock, lds, &resident);
+  if (e != hipSuccess) return e;
   if (total_tiles == 0) return hipSuccess;
-  if (!resident[max_m]) resident_blocks(k_pass_batch<R, WB, LP>, lds, &resident[max_m]);
-  const uint64_t blocks = total_tiles < resident[max_m] ? total_tiles : resident[max_m];
+  const uint64_t blocks = total_tiles < resident ? total_tiles : resident;
   hipLaunchKernelGGL((k_pass_batch<R, WB, LP>), dim3((unsigned)blocks), dim3(kBlock), lds, s, items, count, total_tiles);
   return hipGetLastError();
 }
@@ -911,13 +845,13 @@ hipError_t run_batch(const BatchItemDev* items, int count, uint64_t total_tiles,
 }  // namespace
 
 hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* passes, int pass,
-                       const PassStageDev* stages, const PassOpDev* ops, const void* mats, bool ladders,
+                       const PassStageDev* stages, const PassItemDev* items, const void* mats, bool ladders,
                        hipStream_t s) {
   if (dt == SV_C128)
-    return ladders ? run<double, 3, true>(psi, n, m, passes, pass, stages, ops, mats, s)
-                   : run<double, 3, false>(psi, n, m, passes, pass, stages, ops, mats, s);
-  return ladders ? run<float, 4, true>(psi, n, m, passes, pass, stages, ops, mats, s)
-                 : run<float, 4, false>(psi, n, m, passes, pass, stages, ops, mats, s);
+    return ladders ? run<double, 3, true>(psi, n, m, passes, pass, stages, items, mats, s)
+                   : run<double, 3, false>(psi, n, m, passes, pass, stages, items, mats, s);
+  return ladders ? run<float, 4, true>(psi, n, m, passes, pass, stages, items, mats, s)
+                 : run<float, 4, false>(psi, n, m, passes, pass, stages, items, mats, s);
 }
 
 hipError_t launch_pass_batch(sv_dtype dt, const BatchItemDev* items, int count, uint64_t total_tiles, int max_m,

@@ -6,6 +6,7 @@
 // relabelings, and the map is brought back to the identity by permutations
 // fused into tile write-backs.  Host only.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 
@@ -88,46 +89,108 @@ Op to_physical(const Op& op, const std::vector<int>& phys) {
   return r;
 }
 
-// Arithmetic per amplitude of one op inside a pass (real flops).
-double op_flops(const PassOpDev& od) {
-  switch (od.type) {
-    case POP_U1: return 16.0;
-    case POP_U2: return 32.0;
-    case POP_UR: case POP_UI: return 8.0;
-    case POP_D1: case POP_D2: case POP_DG: return 6.0;
-    case POP_P1: return od.lmask ? 8.0 : 3.0;  // a per-lane predicate costs register copies
-    case POP_P2: return 1.5;
-    case POP_X: return od.lmask ? 6.0 : 1.0;
-    case POP_LP: return 14.0;
-    case POP_DR: return 8.0;
-    case POP_QG: return 12.0;
-    default: return 1.0;
+typedef std::array<cd, 4> M2;
+
+const M2 kIdentity2 = {cd(1.0, 0.0), cd(0.0, 0.0), cd(0.0, 0.0), cd(1.0, 0.0)};
+
+// a * b (2x2, row-major)
+M2 mul2(const M2& a, const M2& b) {
+  return {a[0] * b[0] + a[1] * b[2], a[0] * b[1] + a[1] * b[3], a[2] * b[0] + a[3] * b[2],
+          a[2] * b[1] + a[3] * b[3]};
+}
+
+// The cheapest 2x2 form that holds m exactly.
+uint32_t form_of(const M2& m) {
+  const bool real_diag = m[0].imag() == 0.0 && m[3].imag() == 0.0;
+  if (real_diag && m[1].imag() == 0.0 && m[2].imag() == 0.0) return PFORM_UR;
+  if (real_diag && m[1].real() == 0.0 && m[2].real() == 0.0) return PFORM_UI;
+  if (real_diag) return PFORM_RC;
+  return PFORM_U;
+}
+
+// The form that holds every one of a stage's 2x2s (PFORM_UR and PFORM_UI
+// only when all of them are of that kind).
+uint32_t join_form(uint32_t a, uint32_t b) {
+  if (a == PFORM_NONE) return b;
+  if (a == b) return a;
+  if (a == PFORM_U || b == PFORM_U) return PFORM_U;
+  return PFORM_RC;
+}
+
+// VALU instructions per amplitude of a 2x2 in each form (the kernel applies
+// one 2x2 per register bit).
+double form_ops(uint32_t f) {
+  switch (f) {
+    case PFORM_UR: case PFORM_UI: return 4.0;
+    case PFORM_RC: return 6.0;
+    case PFORM_U: return 8.0;
+    default: return 0.0;
   }
-}
-
-bool all_real(const cd* m, int count) {
-  for (int i = 0; i < count; ++i)
-    if (m[i].imag() != 0.0) return false;
-  return true;
-}
-
-// Real diagonal and imaginary off-diagonal (RX, Y).
-bool real_diag_imag_offdiag(const cd* m) {
-  return m[0].imag() == 0.0 && m[3].imag() == 0.0 && m[1].real() == 0.0 && m[2].real() == 0.0;
 }
 
 static_assert(kPassLPTileBits >= SV_MAX_QUBITS, "every physical qubit has a ladder word");
 
-// Fewest two-qubit phase gates in a run worth fusing it into one phase
-// function (its fixed cost is a few single phases).
+// Fewest two-qubit phase gates among a stage's diagonal gates worth fusing
+// them into one fixed-point phase function (its fixed cost is a few
+// per-lane factors).
 constexpr int kPhaseRunMin = 3;
 
-struct StageBuilder {
+uint64_t qubit_mask(const Op& op) {
+  uint64_t mk = 0;
+  for (int i = 0; i < op.nq; ++i) mk |= 1ull << op.q[i];
+  return mk;
+}
+
+// Builds the register stages of one tile pass from its ops (program order,
+// physical qubits).  A stage applies, in this order, an optional 4x4 on
+// register bits (1, 0), one 2x2 per register bit, a diagonal and a register
+// permutation (see PassStageDev).  Each gate joins the current stage when it
+// may move to its part of that order: a single-qubit gate when no diagonal
+// or permutation gate of the stage involves its qubit, a diagonal gate when
+// the permutation leaves its register bits unchanged, a permutation gate
+// always (it is the latest); otherwise the stage is closed and a new one
+// starts.  A stage is also closed when its register bits are all taken.
+struct LayerBuilder {
   const int* loc;  // physical bit -> local bit, or -1
   int m;
   int rb;          // register bits per stage
-  std::vector<int> qs;   // register bits (local indices), in register order
-  std::vector<Op> ops;   // physical qubits
+  sv_dtype dt;
+  std::vector<StageHost>* out;
+
+  // the stage being built
+  std::vector<int> qs;  // local bit of each register bit, in register order
+  bool has_u2 = false;
+  std::vector<cd> u2m;
+  M2 slot[kPassRegBitsMax];
+  bool slot_on[kPassRegBitsMax] = {};
+  std::vector<Op> diag;  // diagonal gates (physical qubits), program order
+  uint64_t diag_q = 0;   // physical qubits of the diagonal gates
+  uint32_t A[kPassRegBitsMax];  // permutation r -> A r ^ c0 ^ (px terms): columns
+  uint32_t c0 = 0;
+  std::vector<std::pair<uint32_t, uint32_t>> px;  // (selector code, register mask)
+  uint32_t sel_local = 0;  // local bits that are permutation selectors
+  int n_perm = 0;          // permutation gates composed
+  int n_members = 0;
+
+  bool f32() const { return dt == SV_C64; }
+
+  void reset() {
+    qs.clear();
+    has_u2 = false;
+    u2m.clear();
+    for (int r = 0; r < kPassRegBitsMax; ++r) {
+      slot[r] = kIdentity2;
+      slot_on[r] = false;
+      A[r] = 1u << r;
+    }
+    diag.clear();
+    diag_q = 0;
+    c0 = 0;
+    px.clear();
+    sel_local = 0;
+    n_perm = 0;
+    n_members = 0;
+  }
 
   int reg(int physq) const {
     const int l = loc[physq];
@@ -136,21 +199,162 @@ struct StageBuilder {
       if (qs[r] == l) return (int)r;
     return -1;
   }
+  // selector code of a bit outside the registers
   uint32_t src(int physq) const {
     const int l = loc[physq];
     return l >= 0 ? (uint32_t)l : kPassTileSel + (uint32_t)physq;
   }
-  void predicate(PassOpDev* od, int physq) const {
-    const int l = loc[physq];
-    if (l >= 0) od->lmask |= 1u << l;
-    else od->tmask |= 1ull << physq;
+
+  // register bits the permutation involves (as a source or a destination)
+  uint32_t moved() const {
+    uint32_t mv = c0;
+    for (const auto& t : px) mv |= t.second;
+    for (int j = 0; j < rb; ++j)
+      if (A[j] != (1u << j)) mv |= (1u << j) | A[j];
+    return mv;
+  }
+  // register bits whose value the permutation may change
+  uint32_t unstable() const {
+    uint32_t un = c0;
+    for (const auto& t : px) un |= t.second;
+    for (int j = 0; j < rb; ++j) {
+      un |= A[j] & ~(1u << j);
+      if (!((A[j] >> j) & 1u)) un |= 1u << j;
+    }
+    return un;
   }
 
-  // A diagonal op on one or two qubits whose entries are unit phases: its
-  // phase is c + h_a x_a (+ h_b x_b + J_ab x_a x_b) over the bits x of its
-  // qubits, exact in fixed-point turns.
+  // The register bit of local qubit `physq`, taking a free one if needed;
+  // -1 if none is free or the qubit selects a permutation term.
+  int want_reg(int physq) {
+    const int j = reg(physq);
+    if (j >= 0) return j;
+    const int l = loc[physq];
+    if (l < 0 || (int)qs.size() >= rb || ((sel_local >> l) & 1u)) return -1;
+    qs.push_back(l);
+    return (int)qs.size() - 1;
+  }
+
+  // Compose the permutation with a linear map of the register index that
+  // flips bit t when bit c is set (a CNOT on register bits).
+  void compose_cx(int c, int t) {
+    auto f = [&](uint32_t x) { return ((x >> c) & 1u) ? x ^ (1u << t) : x; };
+    for (int j = 0; j < rb; ++j) A[j] = f(A[j]);
+    c0 = f(c0);
+    for (auto& p : px) p.second = f(p.second);
+  }
+  void compose_swap(int a, int b) {
+    auto f = [&](uint32_t x) {
+      const uint32_t xa = (x >> a) & 1u, xb = (x >> b) & 1u;
+      return (x & ~((1u << a) | (1u << b))) | (xa << b) | (xb << a);
+    };
+    for (int j = 0; j < rb; ++j) A[j] = f(A[j]);
+    c0 = f(c0);
+    for (auto& p : px) p.second = f(p.second);
+  }
+
+  bool is_perm_gate(const Op& op) const {
+    return op.kind == SV_G_X || op.kind == SV_G_CNOT || op.kind == SV_G_SWAP;
+  }
+
+  // Try to add a permutation gate to the current stage; false: close first
+  // (a fresh stage always takes it).
+  bool add_perm(const Op& op) {
+    const int free = rb - (int)qs.size();
+    if (op.kind == SV_G_X) {
+      const int j = want_reg(op.q[0]);
+      if (j < 0) return false;
+      c0 ^= 1u << j;
+      return true;
+    }
+    if (op.kind == SV_G_SWAP) {
+      if ((reg(op.q[0]) < 0) + (reg(op.q[1]) < 0) > free) return false;
+      const int a = want_reg(op.q[0]);
+      if (a < 0) return false;
+      const int b = want_reg(op.q[1]);
+      if (b < 0) return false;
+      compose_swap(a, b);
+      return true;
+    }
+    // CNOT: control q[0], target q[1].  A control outside the registers
+    // becomes a permutation term selected by its bit; a local one is then a
+    // selector, and the register padding needs rb local bits that are not.
+    const int c = op.q[0], lc = loc[c];
+    int jc = reg(c);
+    bool new_sel = jc < 0 && lc >= 0 && !((sel_local >> lc) & 1u);
+    const bool ctrl_reg = new_sel && m - (__builtin_popcount(sel_local) + 1) < rb;
+    if (ctrl_reg) new_sel = false;
+    if ((reg(op.q[1]) < 0) + (ctrl_reg ? 1 : 0) > free) return false;
+    if (ctrl_reg) {
+      jc = want_reg(c);
+      if (jc < 0) return false;
+    }
+    const int jt = want_reg(op.q[1]);
+    if (jt < 0) return false;
+    if (jc >= 0) {
+      compose_cx(jc, jt);
+    } else {
+      px.push_back({src(c), 1u << jt});
+      if (new_sel) sel_local |= 1u << lc;
+    }
+    return true;
+  }
+
+  void add(const Op& op) {
+    const OpClass cls = classify(op);
+    if (cls == CLS_DIAG) {
+      uint32_t regs = 0;
+      for (int i = 0; i < op.nq; ++i) {
+        const int j = reg(op.q[i]);
+        if (j >= 0) regs |= 1u << j;
+      }
+      if (regs & unstable()) close();
+      diag.push_back(op);
+      diag_q |= qubit_mask(op);
+      ++n_members;
+      return;
+    }
+    if (is_perm_gate(op)) {
+      if (!add_perm(op)) {
+        close();
+        const bool ok = add_perm(op);
+        (void)ok;  // a fresh stage always has room for one gate
+      }
+      ++n_perm;
+      ++n_members;
+      return;
+    }
+    if (op.nq == 2) {  // dense 4x4: first in a fresh stage, on register bits (1, 0)
+      close();
+      qs = {loc[op.q[1]], loc[op.q[0]]};
+      has_u2 = true;
+      u2m = op.m;
+      ++n_members;
+      return;
+    }
+    // single-qubit, not diagonal: the 2x2 of its register bit
+    const int q = op.q[0];
+    int j = reg(q);
+    bool conflict = ((diag_q >> q) & 1ull) || (j >= 0 && ((moved() >> j) & 1u));
+    if (!conflict && j < 0) {
+      j = want_reg(q);
+      conflict = j < 0;
+    }
+    if (conflict) {
+      close();
+      j = want_reg(q);
+    }
+    slot[j] = mul2({op.m[0], op.m[1], op.m[2], op.m[3]}, slot[j]);
+    slot_on[j] = true;
+    ++n_members;
+  }
+
+  // ---- encoding of the stage ----------------------------------------------
+  // A unit-phase diagonal gate on one or two qubits: its phase is
+  // c + h_a x_a (+ h_b x_b + J_ab x_a x_b) over the bits x of its qubits,
+  // exact in fixed-point turns.
   bool phase_op(const Op& op) const {
-    if (!is_diag(op) || op.nq > 2) return false;
+    if (op.nq > 2) return false;
     const int d = 1 << op.nq;
     for (int i = 0; i < d; ++i)
       if (std::abs(std::abs(op.m[(size_t)i * d + i]) - 1.0) >= 1e-14) return false;
@@ -162,49 +366,26 @@ struct StageBuilder {
   uint64_t turns(const cd& e) const {
     double t = std::arg(e) / (2.0 * M_PI);
     t -= std::floor(t);
-    if (rb == pass_reg_bits(SV_C64)) return (uint64_t)(uint32_t)(uint64_t)std::llround(std::ldexp(t, 32));
+    if (f32()) return (uint64_t)(uint32_t)(uint64_t)std::llround(std::ldexp(t, 32));
     return (uint64_t)std::ldexp(t, 63) * 2u;
   }
 
   // The unit phase of a W-bit fixed-point turn.
   cd phase_of(uint64_t w) const {
-    const bool f32 = rb == pass_reg_bits(SV_C64);
-    const double t = f32 ? (double)(int32_t)(uint32_t)w * 0x1p-32 : (double)(int64_t)w * 0x1p-64;
+    const double t = f32() ? (double)(int32_t)(uint32_t)w * 0x1p-32 : (double)(int64_t)w * 0x1p-64;
     return std::polar(1.0, 2.0 * M_PI * t);
   }
 
-  // A diagonal op whose qubits are all register bits (a factor per register
-  // index).
-  bool reg_diag(const Op& op) const {
-    if (!is_diag(op)) return false;
-    for (int i = 0; i < op.nq; ++i)
-      if (reg(op.q[i]) < 0) return false;
-    return true;
-  }
-
-  // One POP_DR op: the product of the register-diagonal ops `run`.
-  void encode_reg_diag(StageHost* sh, const std::vector<const Op*>& run) {
-    const int nr = 1 << rb;
-    std::vector<cd> d(nr, cd(1.0, 0.0));
-    for (const Op* op : run) {
-      const int dim = 1 << op->nq;
-      for (int r = 0; r < nr; ++r) {
-        int idx = 0;  // the op's local index: q[0] is its most significant bit
-        for (int i = 0; i < op->nq; ++i) idx = (idx << 1) | ((r >> reg(op->q[i])) & 1);
-        d[r] *= op->m[(size_t)idx * dim + idx];
-      }
-    }
-    PassOpDev od{};
-    od.type = POP_DR;
-    od.sa = od.sb = kPassNoSel;
-    od.mat = (uint32_t)sh->mats.size();
-    sh->mats.insert(sh->mats.end(), d.begin(), d.end());
-    sh->raw.insert(sh->raw.end(), d.size(), 0);
-    sh->ops.push_back(od);
+  static uint32_t push_entries(StageHost* sh, const cd* e, size_t count) {
+    const uint32_t at = (uint32_t)sh->mats.size();
+    sh->mats.insert(sh->mats.end(), e, e + count);
+    sh->raw.insert(sh->raw.end(), count, 0);
+    return at;
   }
 
   // Append `words` (kPassLPWords per row) to the pool, two per entry.
-  static void put_words(StageHost* sh, const std::vector<uint64_t>& words) {
+  static uint32_t put_words(StageHost* sh, const std::vector<uint64_t>& words) {
+    const uint32_t at = (uint32_t)sh->mats.size();
     for (size_t w = 0; w < words.size(); w += 2) {
       double re, im;
       std::memcpy(&re, &words[w], sizeof re);
@@ -212,39 +393,43 @@ struct StageBuilder {
       sh->mats.push_back(cd(re, im));
       sh->raw.push_back(1);
     }
+    return at;
   }
 
-  // Ops [first, last): a run of phase ops (they commute), fused into one
-  // quadratic phase over the bits of their qubits,
+  static PassItemDev item(uint32_t type) {
+    PassItemDev it{};
+    it.type = type;
+    it.sel = kPassNoSel | (kPassNoSel << 8);
+    return it;
+  }
+
+  // The phase gates `run` (they commute) as one quadratic phase over the bits
+  // of their qubits,
   //   theta(x) = c + sum_a h_a x_a + sum_{a<b} J_ab x_a x_b   (turns mod 1),
   // summed exactly in W-bit fixed point (the words of every gate's entries
-  // are rounded once).  It is applied as at most three kinds of op:
-  //   * a POP_LP ladder per register bit a with pair terms to bits outside
-  //     the registers (its constant is h_a);
-  //   * one POP_DR factor per register index for the terms over register
-  //     bits only (and the constant when no POP_QG follows);
-  //   * one POP_QG for the terms over the other bits (the lane's group bits
-  //     and the tile bits).
-  void encode_phase_run(StageHost* sh, size_t first, size_t last) {
-    const bool f32 = rb == pass_reg_bits(SV_C64);
-    const uint64_t wmask = f32 ? 0xffffffffull : ~0ull;
+  // are rounded once).  Terms over register bits only (and the constant when
+  // no quadratic item follows) multiply the register factors `dr`; every
+  // register bit with pair terms to bits outside the registers gets a phase
+  // ladder; the terms over the other bits (the lane's group bits and the tile
+  // bits) form one quadratic-phase item.
+  void encode_phase_run(StageHost* sh, const std::vector<const Op*>& run, std::vector<cd>* dr) {
+    const uint64_t wmask = f32() ? 0xffffffffull : ~0ull;
     constexpr int NQ = SV_MAX_QUBITS;
     uint64_t c = 0;
     std::vector<uint64_t> h(NQ, 0), J((size_t)NQ * NQ, 0);  // J[a * NQ + b], a < b
     std::vector<char> used(NQ, 0);
-    for (size_t i = first; i < last; ++i) {
-      const Op& op = ops[i];
-      const int a = op.q[0];
+    for (const Op* op : run) {
+      const int a = op->q[0];
       used[a] = 1;
-      if (op.nq == 1) {
-        const uint64_t t0 = turns(op.m[0]), t1 = turns(op.m[3]);
+      if (op->nq == 1) {
+        const uint64_t t0 = turns(op->m[0]), t1 = turns(op->m[3]);
         c += t0;
         h[a] += t1 - t0;
         continue;
       }
-      const int b = op.q[1];  // entry index (bit a) * 2 + (bit b)
+      const int b = op->q[1];  // entry index (bit a) * 2 + (bit b)
       used[b] = 1;
-      const uint64_t t00 = turns(op.m[0]), t01 = turns(op.m[5]), t10 = turns(op.m[10]), t11 = turns(op.m[15]);
+      const uint64_t t00 = turns(op->m[0]), t01 = turns(op->m[5]), t10 = turns(op->m[10]), t11 = turns(op->m[15]);
       c += t00;
       h[a] += t10 - t00;
       h[b] += t01 - t00;
@@ -272,34 +457,30 @@ struct StageBuilder {
     std::vector<char> in_ladder(NQ, 0);
     for (int a : regq) {
       std::vector<uint64_t> words(kPassLPWords, 0);
-      PassOpDev od{};
-      od.type = POP_LP;
-      od.b0 = (uint32_t)reg(a);
-      od.sa = od.sb = kPassNoSel;
+      PassItemDev it = item(PIT_LP);
+      it.a = (uint32_t)reg(a);
       for (int b : other) {
         const uint64_t w = pair(a, b);
         if (!w) continue;
         words[word_of(b)] = w;
-        if (loc[b] >= 0) od.lmask |= 1u << loc[b];
-        else od.tmask |= 1ull << b;
+        if (loc[b] >= 0) it.lmask |= 1u << loc[b];
+        else it.tmask |= 1ull << b;
       }
-      if (!od.lmask && !od.tmask) continue;
+      if (!it.lmask && !it.tmask) continue;
       words[kPassLPConst] = h[a];
       in_ladder[a] = 1;
-      od.mat = (uint32_t)sh->mats.size();
-      put_words(sh, words);
-      sh->ops.push_back(od);
+      it.mat = put_words(sh, words);
+      sh->items.push_back(it);
+      ++sh->n_fixed;
     }
 
     // quadratic phase outside the registers
     std::vector<uint64_t> qw(kPassLPWords, 0);
-    PassOpDev qg{};
-    qg.type = POP_QG;
-    qg.sa = qg.sb = kPassNoSel;
+    PassItemDev qg = item(PIT_QG);
     bool any = false;
-    auto mark = [&](PassOpDev& od, int q) {
-      if (loc[q] >= 0) od.lmask |= 1u << loc[q];
-      else od.tmask |= 1ull << q;
+    auto mark = [&](PassItemDev& it, int q) {
+      if (loc[q] >= 0) it.lmask |= 1u << loc[q];
+      else it.tmask |= 1ull << q;
     };
     for (int a : other)
       if (h[a]) {
@@ -307,7 +488,6 @@ struct StageBuilder {
         mark(qg, a);
         any = true;
       }
-    uint64_t tile_targets = 0;
     for (size_t i = 0; i < other.size(); ++i) {
       const int a = other[i];
       std::vector<uint64_t> row(kPassLPWords, 0);
@@ -322,140 +502,137 @@ struct StageBuilder {
       }
       if (!nz) continue;
       mark(qg, a);
-      if (loc[a] >= 0) qg.b0 |= 1u << loc[a];
-      else tile_targets |= 1ull << a;
+      if (loc[a] >= 0) qg.a |= 1u << loc[a];
+      else qg.tt |= 1ull << a;
       qw.insert(qw.end(), row.begin(), row.end());
       any = true;
     }
-    qg.b1 = (uint32_t)tile_targets;
-    qg.pad = (uint32_t)(tile_targets >> 32);
     if (any) {
       qw[kPassLPConst] = c;
       c = 0;
     }
 
-    // register factors (and the constant when there is no POP_QG)
+    // register factors (and the constant when there is no quadratic item)
     const int nr = 1 << rb;
     std::vector<uint64_t> dw(nr, c);
-    bool diag = c != 0;
     for (size_t i = 0; i < regq.size(); ++i) {
       const int a = regq[i], ra = reg(a);
-      if (!in_ladder[a] && h[a]) {
-        diag = true;
+      if (!in_ladder[a] && h[a])
         for (int r = 0; r < nr; ++r)
           if ((r >> ra) & 1) dw[r] += h[a];
-      }
       for (size_t k = i + 1; k < regq.size(); ++k) {
         const int b = regq[k], rbit = reg(b);
         const uint64_t w = pair(a, b);
         if (!w) continue;
-        diag = true;
         for (int r = 0; r < nr; ++r)
           if (((r >> ra) & 1) && ((r >> rbit) & 1)) dw[r] += w;
       }
     }
-    if (diag) {
-      PassOpDev od{};
-      od.type = POP_DR;
-      od.sa = od.sb = kPassNoSel;
-      od.mat = (uint32_t)sh->mats.size();
-      for (int r = 0; r < nr; ++r) sh->mats.push_back(phase_of(dw[r] & wmask));
-      sh->raw.insert(sh->raw.end(), nr, 0);
-      sh->ops.push_back(od);
-    }
+    for (int r = 0; r < nr; ++r) (*dr)[r] *= phase_of(dw[r] & wmask);
     if (any) {
-      qg.mat = (uint32_t)sh->mats.size();
-      put_words(sh, qw);
-      sh->ops.push_back(qg);
+      qg.mat = put_words(sh, qw);
+      sh->items.push_back(qg);
+      ++sh->n_fixed;
     }
   }
 
-  static uint64_t qubit_mask(const Op& op) {
-    uint64_t mk = 0;
-    for (int i = 0; i < op.nq; ++i) mk |= 1ull << op.q[i];
-    return mk;
-  }
-
-  // Gate reordering for diagonal visibility (Sec. III-A): every phase op
-  // joins the phase ops before it when it commutes with the ops it moves
-  // past, i.e. shares no qubit with any of them that is not a phase op
-  // (phase ops commute with each other).  Program order is kept otherwise.
-  void gather_phases() {
-    std::vector<Op> out;
-    out.reserve(ops.size());
-    std::vector<char> taken(ops.size(), 0);
-    for (size_t i = 0; i < ops.size(); ++i) {
-      if (taken[i]) continue;
-      out.push_back(ops[i]);
-      taken[i] = 1;
-      if (!phase_op(ops[i])) continue;
-      uint64_t blocked = 0;  // qubits of the non-phase ops left in place so far
-      for (size_t j = i + 1; j < ops.size(); ++j) {
-        if (taken[j]) continue;
-        const uint64_t mk = qubit_mask(ops[j]);
-        if (!phase_op(ops[j])) {
-          blocked |= mk;
-        } else if (!(mk & blocked)) {
-          out.push_back(ops[j]);
-          taken[j] = 1;
-        }
-      }
+  // A diagonal gate applied exactly: a factor per register index when all
+  // its qubits are register bits, else a lane item.
+  void encode_exact(StageHost* sh, const Op& op, std::vector<cd>* dr, bool* any_dr) {
+    const int dim = 1 << op.nq;
+    int regs[2] = {-1, -1};
+    int nreg = 0;
+    for (int i = 0; i < op.nq; ++i) {
+      regs[i] = reg(op.q[i]);
+      nreg += regs[i] >= 0;
     }
-    ops.swap(out);
-  }
-
-  void encode(StageHost* sh) {
-    // pad the register bits with the lowest unused local bits
-    for (int l = 0; (int)qs.size() < rb && l < m; ++l)
-      if (std::find(qs.begin(), qs.end(), l) == qs.end()) qs.push_back(l);
-    for (int r = 0; r < rb; ++r) sh->q[r] = (uint32_t)qs[r];
-    gather_phases();
-    for (size_t i = 0; i < ops.size();) {
-      // a run of phase gates with pair terms becomes one fixed-point
-      // quadratic phase (single-qubit phases alone stay per-op: their own
-      // ops are cheaper than a per-lane phase function)
-      size_t e = i, pairs = 0;
-      while (e < ops.size() && phase_op(ops[e])) pairs += ops[e++].nq == 2;
-      if (pairs >= (size_t)kPhaseRunMin) {
-        const size_t n_ops = sh->ops.size(), n_mats = sh->mats.size();
-        encode_phase_run(sh, i, e);
-        if (stage_rows(*sh) > (uint32_t)kPassStageRowsMax) {  // over the stage's row table: gate by gate
-          sh->ops.resize(n_ops);
-          sh->mats.resize(n_mats);
-          sh->raw.resize(n_mats);
-          for (size_t x = i; x < e; ++x) encode_op(sh, ops[x]);
-        }
-        i = e;
-        continue;
+    if (nreg == op.nq) {
+      const int nr = 1 << rb;
+      for (int r = 0; r < nr; ++r) {
+        int idx = 0;  // the gate's local index: q[0] is its most significant bit
+        for (int i = 0; i < op.nq; ++i) idx = (idx << 1) | ((r >> regs[i]) & 1);
+        (*dr)[r] *= op.m[(size_t)idx * dim + idx];
       }
-      // a run of diagonal gates on register bits becomes one factor per
-      // register index
-      size_t f = i;
-      while (f < ops.size() && reg_diag(ops[f])) ++f;
-      if (f - i >= 2) {
-        std::vector<const Op*> run;
-        for (size_t x = i; x < f; ++x) run.push_back(&ops[x]);
-        encode_reg_diag(sh, run);
-        i = f;
-        continue;
-      }
-      encode_op(sh, ops[i]);
-      ++i;
+      *any_dr = true;
+      return;
     }
-    encode_rows(sh);
+    auto d = [&](int idx) { return op.m[(size_t)idx * dim + idx]; };
+    if (nreg == 0) {  // every qubit outside the registers: one factor per lane
+      PassItemDev it = item(PIT_DG);
+      cd tab[4];
+      if (op.nq == 1) {
+        it.sel = src(op.q[0]) | (kPassNoSel << 8);
+        tab[0] = d(0);
+        tab[1] = d(1);
+      } else {
+        it.sel = src(op.q[0]) | (src(op.q[1]) << 8);
+        for (int i = 0; i < 4; ++i) tab[i] = d(i);
+      }
+      it.mat = push_entries(sh, tab, (size_t)dim);
+      sh->items.push_back(it);
+      return;
+    }
+    // two qubits, one in the registers (bit a), the other (o) selects
+    const bool first = regs[0] >= 0;
+    const int a = first ? regs[0] : regs[1], o = first ? op.q[1] : op.q[0];
+    PassItemDev it = item(PIT_D1);
+    it.a = (uint32_t)a;
+    it.sel = src(o) | (kPassNoSel << 8);
+    cd tab[4];
+    for (int var = 0; var < 2; ++var)
+      for (int bit = 0; bit < 2; ++bit) tab[2 * var + bit] = d(first ? 2 * bit + var : 2 * var + bit);
+    it.mat = push_entries(sh, tab, 4);
+    if (tab[0] != cd(1.0, 0.0) || tab[2] != cd(1.0, 0.0)) sh->flags |= PSF_F0;
+    sh->items.push_back(it);
   }
 
-  // Tile-summed rows of a phase op (the row table of PassStageDev).
-  static uint32_t op_rows(const PassOpDev& od) {
-    if (od.type == POP_LP) return 1;
-    if (od.type == POP_QG)
-      return 1u + (uint32_t)__builtin_popcount(od.b0) + (uint32_t)__builtin_popcountll(qg_tile_targets(od));
+  void encode_diag(StageHost* sh) {
+    if (diag.empty()) return;
+    const int nr = 1 << rb;
+    std::vector<cd> dr(nr, cd(1.0, 0.0));
+    bool any_dr = false;
+    size_t pairs = 0;
+    for (const Op& op : diag) pairs += op.nq == 2 && phase_op(op);
+    std::vector<const Op*> exact;
+    if (pairs >= (size_t)kPhaseRunMin) {
+      std::vector<const Op*> run;
+      for (const Op& op : diag) (phase_op(op) ? run : exact).push_back(&op);
+      const size_t n_items = sh->items.size(), n_mats = sh->mats.size();
+      encode_phase_run(sh, run, &dr);
+      any_dr = true;
+      if (stage_rows(*sh) > (uint32_t)kPassStageRowsMax) {  // over the row table: gate by gate
+        sh->items.resize(n_items);
+        sh->mats.resize(n_mats);
+        sh->raw.resize(n_mats);
+        sh->n_fixed = 0;
+        std::fill(dr.begin(), dr.end(), cd(1.0, 0.0));
+        any_dr = false;
+        exact.clear();
+        for (const Op& op : diag) exact.push_back(&op);
+      }
+    } else {
+      for (const Op& op : diag) exact.push_back(&op);
+    }
+    for (const Op* op : exact) encode_exact(sh, *op, &dr, &any_dr);
+    if (!sh->items.empty()) {
+      sh->flags |= PSF_LANE;
+      any_dr = true;  // the lane path multiplies by the register factors too
+    }
+    if (any_dr) {
+      sh->flags |= PSF_DR;
+      sh->dr = push_entries(sh, dr.data(), dr.size());
+    }
+  }
+
+  // Tile-summed rows of a fixed-point item (the row table of PassStageDev).
+  static uint32_t item_rows(const PassItemDev& it) {
+    if (it.type == PIT_LP) return 1;
+    if (it.type == PIT_QG) return 1u + (uint32_t)__builtin_popcount(it.a) + (uint32_t)__builtin_popcountll(it.tt);
     return 0;
   }
-  static uint64_t qg_tile_targets(const PassOpDev& od) { return ((uint64_t)od.pad << 32) | od.b1; }
   static uint32_t stage_rows(const StageHost& sh) {
     uint32_t r = 0;
-    for (const PassOpDev& od : sh.ops) r += op_rows(od);
+    for (const PassItemDev& it : sh.items) r += item_rows(it);
     return r;
   }
 
@@ -468,7 +645,7 @@ struct StageBuilder {
       sh->mats.push_back(cd(re, im));
       sh->raw.push_back(1);
     };
-    if (rb == pass_reg_bits(SV_C64)) {
+    if (f32()) {
       entry(a, b);
       entry(c, d);
     } else {
@@ -481,169 +658,105 @@ struct StageBuilder {
   void encode_rows(StageHost* sh) {
     sh->rows = (uint32_t)sh->mats.size();
     sh->row_count = 0;
-    const std::vector<PassOpDev> ops_now = sh->ops;
-    for (const PassOpDev& od : ops_now) {
-      const uint32_t nr = op_rows(od);
-      const uint32_t nl = od.type == POP_QG ? (uint32_t)__builtin_popcount(od.b0) : 0u;
-      uint64_t tt = od.type == POP_QG ? qg_tile_targets(od) : 0;
+    const std::vector<PassItemDev> items_now = sh->items;
+    for (const PassItemDev& it : items_now) {
+      const uint32_t nr = item_rows(it);
+      const uint32_t nl = it.type == PIT_QG ? (uint32_t)__builtin_popcount(it.a) : 0u;
+      uint64_t tt = it.type == PIT_QG ? it.tt : 0;
       for (uint32_t k = 0; k < nr; ++k) {
-        uint32_t pred = kPassNoSel;
+        uint32_t pred = kPassRowAlways;
         if (k > nl) {
           pred = (uint32_t)__builtin_ctzll(tt);
           tt &= tt - 1;
         }
-        put_u32x4(sh, 2u * od.mat + k * (uint32_t)kPassLPWords + (uint32_t)kPassLPLocalBits, pred,
-                  (uint32_t)od.tmask, (uint32_t)(od.tmask >> 32));
+        put_u32x4(sh, 2u * it.mat + k * (uint32_t)kPassLPWords + (uint32_t)kPassLPLocalBits, pred,
+                  (uint32_t)it.tmask, (uint32_t)(it.tmask >> 32));
         ++sh->row_count;
       }
     }
     if (!sh->row_count) sh->rows = 0;
   }
 
-  void encode_op(StageHost* sh, const Op& op) {
-    {
-      PassOpDev od{};
-      od.sa = od.sb = kPassNoSel;
-      od.mat = (uint32_t)sh->mats.size();
-      std::vector<cd> mv;
-      const bool diag = is_diag(op);
-      if (op.nq == 1) {
-        const int q = op.q[0], b = reg(q);
-        if (diag) {
-          const cd d0 = op.m[0], d1 = op.m[3];
-          if (b >= 0 && d0 == cd(1.0, 0.0)) {
-            od.type = POP_P1;
-            od.b0 = (uint32_t)b;
-            mv = {d1};
-          } else if (b >= 0) {
-            od.type = POP_D1;
-            od.b0 = (uint32_t)b;
-            mv = {d0, d1};
-          } else if (d0 == cd(1.0, 0.0)) {
-            od.type = POP_DG;
-            predicate(&od, q);
-            mv = {d1};
-          } else {
-            od.type = POP_DG;
-            od.sa = src(q);
-            mv = {d0, d1};
-          }
-        } else if (op.kind == SV_G_X) {
-          od.type = POP_X;
-          od.b0 = (uint32_t)b;
-        } else {
-          od.type = all_real(op.m.data(), 4) ? POP_UR : real_diag_imag_offdiag(op.m.data()) ? POP_UI : POP_U1;
-          od.b0 = (uint32_t)b;
-          mv.assign(op.m.begin(), op.m.begin() + 4);
-        }
-      } else if (op.kind == SV_G_CNOT) {
-        const int c = op.q[0], t = op.q[1];
-        const int bt = reg(t), bc = reg(c);
-        if (bc >= 0) {
-          od.type = POP_CX;
-          od.b0 = (uint32_t)bc;
-          od.b1 = (uint32_t)bt;
-        } else {
-          od.type = POP_X;
-          od.b0 = (uint32_t)bt;
-          predicate(&od, c);
-        }
-      } else if (diag) {
-        const cd d[4] = {op.m[0], op.m[5], op.m[10], op.m[15]};
-        const int q0 = op.q[0], q1 = op.q[1];
-        const int r0 = reg(q0), r1 = reg(q1);
-        const cd one(1.0, 0.0);
-        const bool cz_like = d[0] == one && d[1] == one && d[2] == one;
-        if (r0 >= 0 && r1 >= 0 && cz_like) {
-          od.type = POP_P2;
-          od.b0 = (uint32_t)r0;
-          od.b1 = (uint32_t)r1;
-          mv = {d[3]};
-        } else if (r0 >= 0 && r1 >= 0) {
-          od.type = POP_D2;
-          od.b0 = (uint32_t)r0;
-          od.b1 = (uint32_t)r1;
-          mv = {d[0], d[1], d[2], d[3]};
-        } else if (r0 >= 0 || r1 >= 0) {
-          // one qubit in registers (bit b of the register index), the other
-          // (o) selects: entries by (bit of o, bit b)
-          const bool first = r0 >= 0;
-          const int b = first ? r0 : r1, o = first ? q1 : q0;
-          const cd e00 = first ? d[0] : d[0], e01 = first ? d[2] : d[1];  // o = 0: b = 0, 1
-          const cd e10 = first ? d[1] : d[2], e11 = first ? d[3] : d[3];  // o = 1: b = 0, 1
-          od.b0 = (uint32_t)b;
-          if (cz_like) {
-            od.type = POP_P1;
-            predicate(&od, o);
-            mv = {d[3]};
-          } else if (e00 == one && e10 == one) {
-            od.type = POP_P1;  // only the b = 1 half changes
-            od.sa = src(o);
-            mv = {e01, e11};
-          } else {
-            od.type = POP_D1;
-            od.sa = src(o);
-            mv = {e00, e01, e10, e11};
-          }
-        } else {
-          od.type = POP_DG;
-          if (cz_like) {
-            predicate(&od, q0);
-            predicate(&od, q1);
-            mv = {d[3]};
-          } else {
-            od.sa = src(q0);
-            od.sb = src(q1);
-            mv = {d[0], d[1], d[2], d[3]};
-          }
-        }
-      } else {
-        od.type = POP_U2;
-        od.b0 = (uint32_t)reg(op.q[0]);
-        od.b1 = (uint32_t)reg(op.q[1]);
-        mv.assign(op.m.begin(), op.m.begin() + 16);
+  void encode(StageHost* sh) {
+    // pad the register bits with the lowest local bits that are neither
+    // register bits nor permutation selectors
+    for (int l = 0; (int)qs.size() < rb && l < m; ++l)
+      if (std::find(qs.begin(), qs.end(), l) == qs.end() && !((sel_local >> l) & 1u)) qs.push_back(l);
+    for (int r = 0; r < rb; ++r) sh->q[r] = (uint32_t)qs[r];
+    int n_slots = 0;
+    uint32_t form = PFORM_NONE;
+    for (int r = 0; r < rb; ++r)
+      if (slot_on[r]) {
+        form = join_form(form, form_of(slot[r]));
+        ++n_slots;
       }
-      sh->mats.insert(sh->mats.end(), mv.begin(), mv.end());
-      sh->raw.insert(sh->raw.end(), mv.size(), 0);
-      sh->ops.push_back(od);
+    if (n_slots) {
+      // absent 2x2s are identities, which every form holds
+      sh->form = form;
+      std::vector<cd> e;
+      for (int r = 0; r < rb; ++r) e.insert(e.end(), slot[r].begin(), slot[r].end());
+      sh->slots = push_entries(sh, e.data(), e.size());
     }
+    if (has_u2) {
+      sh->flags |= PSF_U2;
+      sh->u2 = push_entries(sh, u2m.data(), 16);
+    }
+    encode_diag(sh);
+    bool perm = c0 != 0 || !px.empty();
+    for (int j = 0; j < rb; ++j) {
+      sh->pcol[j] = A[j];
+      perm = perm || A[j] != (1u << j);
+    }
+    sh->pconst = c0;
+    for (const auto& t : px) {
+      PassItemDev it = item(PIT_PX);
+      it.sel = t.first | (kPassNoSel << 8);
+      it.a = t.second;
+      sh->px.push_back(it);
+    }
+    if (perm) sh->flags |= PSF_PERM;
+    encode_rows(sh);
+    sh->n_ops = n_slots + (has_u2 ? 1 : 0) + ((sh->flags & PSF_DR) ? 1 : 0) + (int)sh->items.size() + n_perm;
+  }
+
+  void close() {
+    if (n_members == 0) {
+      reset();
+      return;
+    }
+    StageHost sh;
+    encode(&sh);
+    out->push_back(std::move(sh));
+    reset();
   }
 };
 
-// Split the ops of one pass (physical qubits, program order) into stages of at
-// most rb register bits.
-std::vector<StageHost> build_stages(const std::vector<Op>& ops, const int* loc, int m, int rb) {
+// Split the ops of one pass (physical qubits, program order) into register
+// stages of rb register bits.
+std::vector<StageHost> build_stages(const std::vector<Op>& ops, const int* loc, int m, sv_dtype dt) {
   std::vector<StageHost> out;
-  StageBuilder sb{loc, m, rb, {}, {}};
-  for (const Op& op : ops) {
-    int q[SV_MAX_GATE_QUBITS];
-    const int k = locality(op, q);
-    std::vector<int> need;
-    for (int i = 0; i < k; ++i) {
-      const int l = loc[q[i]];
-      if (std::find(sb.qs.begin(), sb.qs.end(), l) == sb.qs.end() &&
-          std::find(need.begin(), need.end(), l) == need.end())
-        need.push_back(l);
-    }
-    if (sb.qs.size() + need.size() > (size_t)rb) {
-      StageHost sh;
-      sb.encode(&sh);
-      out.push_back(std::move(sh));
-      sb.qs.clear();
-      sb.ops.clear();
-      need.clear();
-      for (int i = 0; i < k; ++i)
-        if (std::find(need.begin(), need.end(), loc[q[i]]) == need.end()) need.push_back(loc[q[i]]);
-    }
-    sb.qs.insert(sb.qs.end(), need.begin(), need.end());
-    sb.ops.push_back(op);
-  }
-  if (!sb.ops.empty()) {
-    StageHost sh;
-    sb.encode(&sh);
-    out.push_back(std::move(sh));
-  }
+  LayerBuilder lb;
+  lb.loc = loc;
+  lb.m = m;
+  lb.rb = pass_reg_bits(dt);
+  lb.dt = dt;
+  lb.out = &out;
+  lb.reset();
+  for (const Op& op : ops) lb.add(op);
+  lb.close();
   return out;
+}
+
+// Cost of a stage in VALU instructions per amplitude (the 2x2 part, the
+// diagonal part) plus its LDS round trip.
+double stage_ops(const StageHost& sh, sv_dtype dt) {
+  const int rb = pass_reg_bits(dt);
+  double ops = (dt == SV_C64 ? 8.0 : 16.0);  // LDS read + write of every amplitude, barrier
+  ops += form_ops(sh.form) * rb;
+  if (sh.flags & PSF_U2) ops += 32.0;
+  if (sh.flags & PSF_LANE) ops += 12.0 + 4.0 * (double)sh.items.size();
+  else if (sh.flags & PSF_DR) ops += 4.0;
+  return ops;
 }
 
 struct QubitMap {
@@ -708,13 +821,13 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
   int pin = o.pinned_low_bits ? o.pinned_low_bits : default_pinned_bits(dt);
   pin = std::min(pin, m - 2);
   const bool reorder = o.reorder != 0;
-  // Cost of a tile pass in full-state sweeps (measured on MI355X at N=30):
-  // the data movement alone takes ~1.2 sweeps and hides ~0.3 sweeps of
-  // arithmetic; beyond that the stages and ops add up.  flop_scale: op flops
-  // per amplitude that take one sweep's time; stage_cost: one LDS round trip.
-  const double flop_scale = dt == SV_C128 ? 180.0 : 100.0;
-  const double stage_cost = 0.08;
-  const double pass_base = 1.2, hidden = 0.3;
+  // Cost of a tile pass in full-state sweeps: the data movement alone takes
+  // pass_base sweeps and hides `hidden` sweeps of arithmetic; beyond that the
+  // stages add up.  ops_per_sweep: VALU instructions per amplitude that take
+  // one sweep's time (MI355X: 2.4 GHz x 64 lanes per CU against 8 TB/s, at
+  // about 70 % of the issue rate).
+  const double ops_per_sweep = dt == SV_C128 ? 110.0 : 55.0;
+  const double pass_base = 1.15, hidden = 0.5;
 
   p->ops.clear();
   p->op_pass.clear();
@@ -825,7 +938,7 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
         ps.lpos[j] = ps.wpos[j] = (uint32_t)b;
         loc[b] = j++;
       }
-    ps.stages = build_stages(members, loc, m, rb);
+    ps.stages = build_stages(members, loc, m, dt);
     // write-back: complete cycles of the map that lie inside the tile go home
     if (last && !mp.identity()) {
       for (const auto& c : cycles_of(mp)) {
@@ -842,9 +955,8 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
       }
       mp = nm;
     }
-    double alu = stage_cost * (double)ps.stages.size();
-    for (const StageHost& sh : ps.stages)
-      for (const PassOpDev& od : sh.ops) alu += op_flops(od) / flop_scale;
+    double alu = 0.0;
+    for (const StageHost& sh : ps.stages) alu += stage_ops(sh, dt) / ops_per_sweep;
     p->est_cost += pass_base + std::max(0.0, alu - hidden);
     p->passes.push_back(std::move(ps));
   }

@@ -220,82 +220,102 @@ sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const
   return SV_OK;
 }
 
-sv_status execute_plan(sv_state* s, const sv_plan* p) {
-  const bool f32 = s->dt == SV_C64;
+sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out) {
+  if (!p || (p->dt != SV_C64 && p->dt != SV_C128)) return fail(SV_ERR_ARG, "bad plan");
+  const bool f32 = p->dt == SV_C64;
   const size_t scal = f32 ? sizeof(float) : sizeof(double);
-  // One upload: dense matrices (state precision), then the tile-pass program.
-  std::vector<unsigned char> host;
-  auto align = [&](size_t a) { host.resize((host.size() + a - 1) / a * a); };
-  auto put_cd = [&](const cd* m, size_t count, const uint8_t* raw = nullptr) {
+  const int rb = pass_reg_bits(p->dt);
+  std::vector<unsigned char>& host = out->host;
+  host.clear();
+  auto align = [&]() { host.resize((host.size() + 255) / 256 * 256); };
+  auto put_cd = [&](const cd* m, size_t count, const uint8_t* raw) {
+    align();
     const size_t at = host.size();
     host.resize(at + count * 2 * scal);
     write_pool(host.data() + at, m, raw, count, f32);
     return at;
   };
-  std::vector<size_t> dense_off(p->passes.size(), 0);
-  std::vector<int> desc_index(p->passes.size(), -1);
+  auto put = [&](const void* src, size_t bytes) {
+    align();
+    const size_t at = host.size();
+    host.resize(at + bytes);
+    if (bytes) std::memcpy(host.data() + at, src, bytes);
+    return at;
+  };
+  out->dense_off.assign(p->passes.size(), 0);
+  out->desc_index.assign(p->passes.size(), -1);
+  out->pass_lp.assign(p->passes.size(), 0);
+  out->max_m = 0;
   std::vector<PassDescDev> descs;
   std::vector<PassStageDev> stages;
-  std::vector<PassOpDev> pops;
+  std::vector<PassItemDev> items;
   std::vector<cd> pool;
   std::vector<uint8_t> pool_raw;
   for (size_t i = 0; i < p->passes.size(); ++i) {
     const Pass& ps = p->passes[i];
-    if (ps.kind == PASS_DENSE) {
-      align(256);
-      dense_off[i] = put_cd(ps.phys.m.data(), ps.phys.m.size());
-    } else if (ps.kind == PASS_TILE || ps.kind == PASS_PERMUTE) {
-      PassDescDev d{};
-      d.m = (uint32_t)ps.n_local;
-      d.stage_first = (uint32_t)stages.size();
-      d.stage_count = (uint32_t)ps.stages.size();
-      if (!fill_pass_maps(ps, s->dt, &d)) return fail(SV_ERR_UNSUPPORTED, "internal: pass write map is not a permutation");
-      for (const StageHost& sh : ps.stages) {
-        PassStageDev sd{};
-        const int rb = pass_reg_bits(s->dt);
-        for (int r = 0; r < rb; ++r) sd.q[r] = sh.q[r];
-        uint32_t srt[kPassRegBitsMax];
-        for (int r = 0; r < rb; ++r) srt[r] = sh.q[r];
-        std::sort(srt, srt + rb);
-        for (int r = 0; r < rb; ++r) sd.qsort[r] = srt[r];
-        sd.op_first = (uint32_t)pops.size();
-        sd.op_count = (uint32_t)sh.ops.size();
-        const uint32_t mbase = (uint32_t)pool.size();
-        sd.mat_base = mbase;
-        sd.rows = sh.rows;
-        sd.row_count = sh.row_count;
-        for (PassOpDev od : sh.ops) {
-          od.mat += mbase;
-          pops.push_back(od);
-        }
-        pool.insert(pool.end(), sh.mats.begin(), sh.mats.end());
-        pool_raw.insert(pool_raw.end(), sh.raw.begin(), sh.raw.end());
-        stages.push_back(sd);
-      }
-      desc_index[i] = (int)descs.size();
-      descs.push_back(d);
+    if (ps.kind == PASS_DENSE || ps.kind == PASS_SWEEP) {
+      if (tile_only)
+        return fail(SV_ERR_UNSUPPORTED, "program needs a plan of in-cache tile passes only (build it with mode PASS)");
+      if (ps.kind == PASS_DENSE) out->dense_off[i] = put_cd(ps.phys.m.data(), ps.phys.m.size(), nullptr);
+      continue;
     }
+    PassDescDev d{};
+    d.m = (uint32_t)ps.n_local;
+    d.stage_first = (uint32_t)stages.size();
+    d.stage_count = (uint32_t)ps.stages.size();
+    if (!fill_pass_maps(ps, p->dt, &d)) return fail(SV_ERR_UNSUPPORTED, "internal: pass write map is not a permutation");
+    for (const StageHost& sh : ps.stages) {
+      PassStageDev sd{};
+      uint32_t srt[kPassRegBitsMax];
+      for (int r = 0; r < rb; ++r) sd.q[r] = srt[r] = sh.q[r];
+      std::sort(srt, srt + rb);
+      for (int r = 0; r < rb; ++r) sd.qsort[r] = srt[r];
+      const uint32_t mbase = (uint32_t)pool.size();
+      sd.form = sh.form;
+      sd.flags = sh.flags;
+      sd.slots = mbase + sh.slots;
+      sd.u2 = mbase + sh.u2;
+      sd.dr = mbase + sh.dr;
+      sd.mat_base = mbase;
+      sd.rows = sh.rows;
+      sd.row_count = sh.row_count;
+      for (int r = 0; r < kPassRegBitsMax; ++r) sd.pcol[r] = sh.pcol[r];
+      sd.pconst = sh.pconst;
+      sd.item_first = (uint32_t)items.size();
+      sd.item_count = (uint32_t)sh.items.size();
+      for (PassItemDev it : sh.items) {
+        it.mat += mbase;
+        items.push_back(it);
+      }
+      sd.px_first = (uint32_t)items.size();
+      sd.px_count = (uint32_t)sh.px.size();
+      items.insert(items.end(), sh.px.begin(), sh.px.end());
+      pool.insert(pool.end(), sh.mats.begin(), sh.mats.end());
+      pool_raw.insert(pool_raw.end(), sh.raw.begin(), sh.raw.end());
+      stages.push_back(sd);
+    }
+    out->desc_index[i] = (int)descs.size();
+    out->pass_lp[i] = pass_has_ladders(ps) ? 1 : 0;
+    out->max_m = std::max(out->max_m, ps.n_local);
+    descs.push_back(d);
   }
-  size_t off_desc = 0, off_stage = 0, off_ops = 0, off_pool = 0;
+  out->n_desc = (int)descs.size();
   if (!descs.empty()) {
-    align(256);
-    off_desc = host.size();
-    host.insert(host.end(), (const unsigned char*)descs.data(),
-                (const unsigned char*)(descs.data() + descs.size()));
-    align(256);
-    off_stage = host.size();
-    host.insert(host.end(), (const unsigned char*)stages.data(),
-                (const unsigned char*)(stages.data() + stages.size()));
-    align(256);
-    off_ops = host.size();
-    host.insert(host.end(), (const unsigned char*)pops.data(), (const unsigned char*)(pops.data() + pops.size()));
-    align(256);
-    off_pool = pool.empty() ? host.size() : put_cd(pool.data(), pool.size(), pool_raw.data());
+    out->off_desc = put(descs.data(), descs.size() * sizeof(PassDescDev));
+    out->off_stage = put(stages.data(), stages.size() * sizeof(PassStageDev));
+    out->off_items = put(items.data(), items.size() * sizeof(PassItemDev));
+    out->off_pool = put_cd(pool.data(), pool.size(), pool_raw.data());
   }
+  align();
+  return SV_OK;
+}
+
+sv_status execute_plan(sv_state* s, const sv_plan* p) {
+  PackedPlan pk;
+  if (sv_status st = pack_plan(p, false, &pk)) return st;
   void* dev = nullptr;
-  if (!host.empty()) {
-    align(256);
-    sv_status st = upload(s, host.data(), host.size(), &dev);
+  if (!pk.host.empty()) {
+    sv_status st = upload(s, pk.host.data(), pk.host.size(), &dev);
     if (st != SV_OK) return st;
   }
   unsigned char* db = (unsigned char*)dev;
@@ -308,16 +328,17 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
       sv_status st = run_op_sweep(s, ps.phys, nullptr);
       if (st != SV_OK) return st;
     } else if (ps.kind == PASS_DENSE) {
-      sv_status st = run_op_sweep(s, ps.phys, db + dense_off[i], p->opts.fp32_mfma != 0);
+      sv_status st = run_op_sweep(s, ps.phys, db + pk.dense_off[i], p->opts.fp32_mfma != 0);
       if (st != SV_OK) return st;
       if (renorm > 0 && ++since >= renorm) {
         if (sv_status r = renormalize(s)) return r;
         since = 0;
       }
     } else {
-      SV_HIP_TRY(launch_pass(s->dt, s->ptr, s->n, ps.n_local, (const PassDescDev*)(db + off_desc), desc_index[i],
-                             (const PassStageDev*)(db + off_stage), (const PassOpDev*)(db + off_ops),
-                             db + off_pool, pass_has_ladders(ps), s->stream));
+      SV_HIP_TRY(launch_pass(s->dt, s->ptr, s->n, ps.n_local, (const PassDescDev*)(db + pk.off_desc),
+                             pk.desc_index[i], (const PassStageDev*)(db + pk.off_stage),
+                             (const PassItemDev*)(db + pk.off_items), db + pk.off_pool, pk.pass_lp[i] != 0,
+                             s->stream));
     }
   }
   if (renorm > 0 && since > 0) return renormalize(s);

@@ -20,76 +20,108 @@ namespace sv {
 constexpr int kPassRegBitsMax = 5;
 inline constexpr int pass_reg_bits(sv_dtype dt) { return dt == SV_C64 ? 5 : 4; }
 
-enum PassOpType : uint32_t {
-  POP_U1 = 0,  // 2x2 on register bit b0                        (4 entries)
-  POP_U2 = 1,  // 4x4 on register bits (b0 = MSB, b1)           (16 entries)
-  POP_X = 2,   // exchange register pairs on bit b0              (0 entries)
-  POP_CX = 3,  // exchange pairs on bit b1 where bit b0 is 1     (0 entries)
-  POP_D1 = 4,  // diag(d0, d1) on register bit b0                (2 entries)
-  POP_D2 = 5,  // diag(d0..d3) on register bits (b0 = MSB, b1)   (4 entries)
-  POP_DG = 6,  // one phase for the whole group                  (1 entry)
-  POP_UR = 7,  // real 2x2 on register bit b0 (H, RY)            (4 entries, real parts used)
-  POP_UI = 8,  // 2x2 with real diagonal and imaginary off-diagonal
-               // on register bit b0 (RX)                        (4 entries: re, im, im, re used)
-  POP_P1 = 9,  // phase on the amplitudes whose bit b0 is 1     (1 entry)
-  POP_P2 = 10, // phase on the amplitudes whose bits b0, b1 are 1 (1 entry)
-  POP_LP = 11, // phase ladder on register bit b0 (the terms of a fused run of
-               // phase gates that involve that bit): the amplitudes whose bit b0 is 1 are
-               // multiplied by exp(2 pi i t / 2^W), t = the constant word plus
-               // the angle words of the set source bits (W-bit fixed-point
-               // turns, summed modulo one turn; W = 32 for complex64, 64 for
-               // complex128).  Entries: kPassLPWords words, two per entry:
+// A register stage of a tile pass applies, in this order (each part a block
+// of gates in program order that the planner proved may run in that order):
+//   1. optionally a dense 4x4 on register bits (1, 0)          (PSF_U2)
+//   2. one 2x2 on every register bit: the tensor product of a layer of
+//      single-qubit gates (identity on bits without a gate); `form` says
+//      which entries are nonzero or real, so the kernel runs the cheapest
+//      code that applies all of them
+//   3. a diagonal: a factor per register index (PSF_DR) times per-lane
+//      factors of the lane items (PSF_LANE): phases and diagonal gates that
+//      involve bits outside the registers
+//   4. a permutation of the register index, r -> A r ^ c(lane) over GF(2)
+//      (X, CNOT, SWAP: PSF_PERM), which costs nothing: the stage's LDS store
+//      writes amplitude r to the address of register index A r ^ c(lane).
+enum PassForm : uint32_t {
+  PFORM_NONE = 0,  // no 2x2 part
+  PFORM_UR = 1,    // every 2x2 real (H, RY)
+  PFORM_UI = 2,    // real diagonal, imaginary off-diagonal (RX, Y)
+  PFORM_RC = 3,    // real diagonal, complex off-diagonal (mixtures of the two)
+  PFORM_U = 4      // general complex 2x2
+};
+enum PassStageFlags : uint32_t {
+  PSF_U2 = 1,    // dense 4x4 on register bits (1 = MSB, 0) first
+  PSF_DR = 2,    // factor table over the register index
+  PSF_LANE = 4,  // lane items
+  PSF_F0 = 8,    // some lane item multiplies the amplitudes whose register bit is 0
+  PSF_PERM = 16  // register permutation at the store
+};
+enum PassItemType : uint32_t {
+  PIT_DG = 0,  // factor on all the lane's amplitudes: table[var] (var from sel)
+  PIT_D1 = 1,  // register bit a: amplitudes with bit a = 0 times table[2 var],
+               // bit a = 1 times table[2 var + 1]
+  PIT_LP = 2,  // phase ladder on register bit a (the terms of a fused run of
+               // phase gates that pair that bit with bits outside the
+               // registers): the amplitudes whose bit a is 1 are multiplied by
+               // exp(2 pi i t / 2^W), t = the constant word plus the angle
+               // words of the set source bits (W-bit fixed-point turns,
+               // summed modulo one turn; W = 32 for complex64, 64 for
+               // complex128).  Words at mat: kPassLPWords, two per entry:
                // local bits 0..15, tile physical bits 0..kPassLPTileBits-1,
                // the constant.  lmask / tmask name the source bits with a
-               // nonzero word (for this op they are not predicates).
-  POP_DR = 12, // diagonal over the register index: amplitude r times d[r]
-               // (NR entries; a run of diagonal gates on register bits)
-  POP_QG = 13  // quadratic phase over the bits outside the registers (one
+               // nonzero word.
+  PIT_QG = 3,  // quadratic phase over the bits outside the registers (one
                // phase per lane, on all its amplitudes): exp(2 pi i t / 2^W),
                // t = the sum of the row-0 words of the set bits plus the
                // constant word, plus, for every target bit that is set, the
                // sum of its row's words of the set bits (the pair terms).
-               // Rows of kPassLPWords words in the phase-ladder layout: row 0,
-               // then one row per local target (ascending local bit: b0 is
-               // their mask), then one per tile target (ascending physical
-               // bit: b1 | pad << 32 is their mask).  lmask / tmask cover every
-               // bit with a nonzero word or a row (not predicates).
+               // Rows of kPassLPWords words in the ladder layout: row 0, then
+               // one row per local target (ascending local bit; `a` is their
+               // mask), then one per tile target (ascending physical bit; `tt`
+               // is their mask).  lmask / tmask cover every bit with a nonzero
+               // word or a row.
+  PIT_PX = 4   // permutation term: when the selector bit is 1, the register
+               // index is XORed with the mask `a` (a CNOT whose control lies
+               // outside the registers)
 };
 constexpr int kPassLPLocalBits = 16;
 constexpr int kPassLPTileBits = 34;
 constexpr int kPassLPConst = kPassLPLocalBits + kPassLPTileBits;  // word of the constant angle
 constexpr int kPassLPWords = kPassLPConst + 2;                    // (even: whole entries)
-constexpr uint32_t kPassNoSel = 0xffffffffu;
-constexpr uint32_t kPassTileSel = 64;  // select codes >= 64 name tile (non-local) physical bits
+constexpr uint32_t kPassNoSel = 0xffu;
+constexpr uint32_t kPassTileSel = 64;  // selector codes >= 64 name tile (non-local) physical bits
 
-struct alignas(16) PassOpDev {
-  uint32_t type;   // PassOpType
-  uint32_t b0, b1; // register bits
-  uint32_t mat;    // first complex entry in the matrix pool
-  uint32_t lmask;  // local bits (outside the stage's register bits) that must all be 1
-  uint32_t sa, sb; // matrix-variant selectors: local bit (< 64) or 64 + tile physical bit;
-                   // variant = bit(sa) [*2 + bit(sb)]; entries of variant v at mat + v * size
+// Selector codes of an item: sel & 0xff (first) and (sel >> 8) & 0xff
+// (second); a code < 64 is a local bit outside the registers, 64 + p the tile
+// physical bit p; kPassNoSel = none.  var = bit(first) [* 2 + bit(second)].
+struct alignas(16) PassItemDev {
+  uint32_t type;    // PassItemType
+  uint32_t a;       // register bit (D1, LP), register-index mask (PX), local targets (QG)
+  uint32_t mat;     // first pool entry of the item's table or words
+  uint32_t sel;     // variant selectors (DG, D1, PX)
+  uint32_t lmask;   // LP / QG: local source bits
   uint32_t pad;
-  uint64_t tmask;  // tile (non-local) physical bits that must all be 1
+  uint64_t tmask;   // LP / QG: tile source bits
+  uint64_t tt;      // QG: tile targets
 };
 
-// Rows of the stage's phase ops whose tile part is summed once per tile
-// (before the stage's groups run): one per POP_LP, and per POP_QG row 0, its
-// local-target rows and its tile-target rows, in op order.  A row
-// descriptor is four uint32 pool words: the word index of the row's first
-// tile word (counted from the stage's first pool entry, two words per entry),
-// the tile bit that must be set for the row to count (kPassNoSel: always),
-// and the tile mask (low, high).
+// Rows of the stage's fixed-point phase items whose tile part is summed once
+// per tile (before the stage's groups run): one per PIT_LP, and per PIT_QG
+// row 0, its local-target rows and its tile-target rows, in item order.  A
+// row descriptor is four uint32 pool words: the word index of the row's
+// first tile word (counted from the stage's first pool entry, two words per
+// entry), the tile bit that must be set for the row to count (kPassNoSel:
+// always), and the tile mask (low, high).
 constexpr int kPassStageRowsMax = 256;
+constexpr uint32_t kPassRowAlways = 0xffffffffu;  // row descriptor: no gating tile bit
 
-struct PassStageDev {
+struct alignas(16) PassStageDev {
   uint32_t q[kPassRegBitsMax];      // local bit of register bit r (r < rb)
   uint32_t qsort[kPassRegBitsMax];  // the same bits, ascending (group enumeration)
-  uint32_t op_first, op_count;
+  uint32_t form;                    // PassForm
+  uint32_t flags;                   // PassStageFlags
+  uint32_t slots;                   // pool entry of the 2x2s: 4 per register bit, bit 0 first
+  uint32_t u2;                      // pool entry of the 4x4 (16 entries, row-major)
+  uint32_t dr;                      // pool entry of the register factors (2^rb entries)
+  uint32_t item_first, item_count;  // lane items
+  uint32_t px_first, px_count;      // permutation terms (PIT_PX items)
   uint32_t mat_base;                // the stage's first pool entry
   uint32_t rows;                    // row descriptors: pool entry, from mat_base
   uint32_t row_count;               // <= kPassStageRowsMax
-  uint32_t pad;
+  uint32_t pcol[kPassRegBitsMax];   // permutation: image of register bit j (A e_j)
+  uint32_t pconst;                  // permutation: constant XOR
+  uint32_t pad[2];
 };
 
 // PassDescDev flag: the store can walk the tile in load order (the lowest
@@ -112,7 +144,7 @@ struct alignas(16) BatchItemDev {
   void* psi;                      // state amplitudes
   const PassDescDev* passes;      // the state's program
   const PassStageDev* stages;
-  const PassOpDev* ops;
+  const PassItemDev* items;
   const void* mats;
   uint64_t tile_begin;            // first global tile of this item (ascending)
   int32_t n;                      // qubits
@@ -120,15 +152,15 @@ struct alignas(16) BatchItemDev {
 };
 
 // Run pass items[i].pass of every item in one launch (all items share dt).
-// ladders: some item's pass holds POP_LP or POP_QG ops (selects the kernel
+// ladders: some item's pass holds PIT_LP or PIT_QG items (selects the kernel
 // variant that decodes them; the other variant carries none of their code).
 hipError_t launch_pass_batch(sv_dtype dt, const BatchItemDev* items, int count, uint64_t total_tiles, int max_m,
                              bool ladders, hipStream_t s);
 
 // Launch pass `pass` of a program already resident in device memory
-// (ladders: the pass holds POP_LP or POP_QG ops).
+// (ladders: the pass holds PIT_LP or PIT_QG items).
 hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* passes, int pass,
-                       const PassStageDev* stages, const PassOpDev* ops, const void* mats, bool ladders,
+                       const PassStageDev* stages, const PassItemDev* items, const void* mats, bool ladders,
                        hipStream_t s);
 
 // --- dense k-qubit fused gate (3 <= k <= 6) ---------------------------------

@@ -1,4 +1,4 @@
-"""GPU parity of the dense k-qubit kernels: FP64 VALU (complex128), FP32 VALU
+"""GPU parity of the dense k-qubit kernels: FP64 MFMA (complex128), FP32 VALU
 and FP32 MFMA (complex64), and the FP64 renormalisation of complex64 plans."""
 import numpy as np
 import pytest
@@ -75,3 +75,22 @@ def test_mfma_and_valu_agree_to_fp32(sv):
     a, ref, _ = run(sv, n, "c64", gaussian_state_np(n, 1), [g], {"mode": "sweep", "fp32_mfma": 1})
     b, _, _ = run(sv, n, "c64", gaussian_state_np(n, 1), [g], {"mode": "sweep", "fp32_mfma": 0})
     assert max_err(a, b) <= 2 * TOL["c64"] and max_err(a, ref) <= TOL["c64"]
+
+
+@pytest.mark.parametrize("dtype,k", [("c128", 3), ("c128", 4), ("c128", 5), ("c128", 6),
+                                     ("c64", 4), ("c64", 5), ("c64", 6)])
+def test_dense_register_direct_placements(sv, dtype, k):
+    """Placements whose lowest 128-byte line is covered by the column bits or
+    by the member bits a lane group owns: the matrix-core kernel that loads
+    its operands from HBM straight into registers (no LDS).  N=22, so that
+    waves loop over many column blocks (with the next block's loads in
+    flight) and k = 6 blocks share column blocks; against the oracle."""
+    n = 22
+    rng = np.random.default_rng(70 + k)
+    low = [0] if dtype == "c64" else [1, 0]  # member bits the lane groups own, at physical 0 (and 1)
+    placements = [tuple(range(n - 1, n - 1 - k, -1)),                          # the highest bits, MSB first
+                  tuple(int(x) for x in rng.choice(np.arange(6, n), k - len(low), replace=False)) + tuple(low)]
+    for qs in placements:
+        g = Gate("MATRIX", qs, matrix=haar_unitary(1 << k, rng))
+        out, ref, _ = run(sv, n, dtype, gaussian_state_np(n, 5), [g], {"mode": "sweep", "max_fuse_qubits": 0})
+        assert max_err(out, ref) <= TOL[dtype], (dtype, k, qs, max_err(out, ref))
