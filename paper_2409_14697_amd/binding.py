@@ -16,7 +16,9 @@ from typing import Iterable, List, Optional, Sequence, Tuple
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libsv.so")
+# SV_LIBRARY names another build of the same library (the sanitizer build of
+# build.py); the default is the in-tree libsv.so
+LIB_PATH = os.environ.get("SV_LIBRARY") or os.path.join(PKG, "libsv.so")
 ROOT = os.path.dirname(PKG)
 HEADERS = [os.path.join(ROOT, "include", "sv.h"), os.path.join(ROOT, "include", "sv_util.h")]
 

@@ -5,6 +5,17 @@
 Every source under csrc/ is compiled with hipcc for gfx950 and linked into
 paper_2409_14697_amd/libsv.so.  Packed FP32 instructions are disabled for the
 device code (-packed-fp32-ops).
+
+SV_SANITIZE=1 builds a debug variant instead, _build/sanitize/libsv.so: the
+host-only sources (the C ABI, planners, packer, batcher: compiled with g++)
+carry UndefinedBehaviorSanitizer, aborting on the first report; device code
+is unchanged.  Load it with SV_LIBRARY=<path> to run the CPU tests under it:
+
+    SV_SANITIZE=1 python paper_2409_14697_amd/build.py
+    SV_SANITIZE=1 SV_LIBRARY=_build/sanitize/libsv.so python -m pytest tests -m "not gpu"
+
+(the host model of the tile-pass kernel, tests/emu, is then built with
+AddressSanitizer as well).
 """
 from __future__ import annotations
 
@@ -18,8 +29,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
-BUILD = os.path.join(ROOT, "_build")
-LIB = os.path.join(PKG, "libsv.so")
+SANITIZE = os.environ.get("SV_SANITIZE", "") not in ("", "0")
+BUILD = os.path.join(ROOT, "_build", "sanitize") if SANITIZE else os.path.join(ROOT, "_build")
+LIB = os.path.join(BUILD, "libsv.so") if SANITIZE else os.path.join(PKG, "libsv.so")
+HOST_SANITIZE = ["-g", "-fsanitize=undefined", "-fno-sanitize-recover=undefined"] if SANITIZE else []
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.environ.get("HIPCC", f"{ROCM}/bin/hipcc")
@@ -43,7 +56,7 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC] + COMMON + ["-x", "hip"] + DEVICE
     else:  # host-only C++: plain g++ against the HIP runtime headers
-        cmd = [CXX] + COMMON + ["-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include"]
+        cmd = [CXX] + COMMON + HOST_SANITIZE + ["-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include"]
     cmd += ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -64,6 +77,8 @@ def build(verbose: bool = True) -> str:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp] + objs + [f"-L{ROCM}/lib", "-lamdhip64"]
+    if SANITIZE:
+        cmd.append("-lubsan")  # the runtime of the host objects' checks
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -1,5 +1,6 @@
 // C ABI of the state-vector core (declared in include/sv.h).
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -21,6 +22,14 @@ sv_status fail(sv_status st, const char* fmt, ...) {
 }
 
 void clear_error() { g_error.clear(); }
+
+bool debug_sync_enabled() {
+  static const bool on = [] {
+    const char* v = std::getenv("SV_DEBUG_SYNC");
+    return v && v[0] && v[0] != '0';
+  }();
+  return on;
+}
 
 size_t elem_bytes(sv_dtype dt) { return dt == SV_C128 ? 16 : 8; }
 
@@ -76,11 +85,11 @@ sv_status run_op_sweep(sv_state* s, const Op& op, const void* m_dev, bool mfma) 
   if (op.nq <= 2) {
     SweepArgs a;
     if (!low_args_for(op, s->dt, &a)) sweep_args_for(op, &a);
-    SV_HIP_TRY(launch_sweep(s->dt, s->ptr, s->n, a, s->stream));
+    SV_LAUNCH(launch_sweep(s->dt, s->ptr, s->n, a, s->stream), s->stream);
     return SV_OK;
   }
   if (op.nq > s->n) return fail(SV_ERR_QUBIT, "op on %d qubits exceeds the state's %d", op.nq, s->n);
-  SV_HIP_TRY(launch_dense_kq(s->dt, s->ptr, s->n, op.nq, op.q, m_dev, mfma, s->stream));
+  SV_LAUNCH(launch_dense_kq(s->dt, s->ptr, s->n, op.nq, op.q, m_dev, mfma, s->stream), s->stream);
   return SV_OK;
 }
 
@@ -89,13 +98,13 @@ sv_status renormalize(sv_state* s) {
   const size_t part = probs_scratch_bytes(s->n, 0, nullptr);
   if (sv_status st = ensure_scratch(s, 256 + part)) return st;
   double* norm2 = (double*)s->scratch;
-  SV_HIP_TRY(launch_probs(s->dt, s->ptr, s->n, nullptr, 0, norm2, (unsigned char*)s->scratch + 256, s->stream));
+  SV_LAUNCH(launch_probs(s->dt, s->ptr, s->n, nullptr, 0, norm2, (unsigned char*)s->scratch + 256, s->stream), s->stream);
   SweepArgs a{};
   a.op = SWEEP_SCALE_NORM;
   a.g.nz = 0;
   a.g.nv = 1;
   a.norm2_dev = norm2;
-  SV_HIP_TRY(launch_sweep(s->dt, s->ptr, s->n, a, s->stream));
+  SV_LAUNCH(launch_sweep(s->dt, s->ptr, s->n, a, s->stream), s->stream);
   return SV_OK;
 }
 
@@ -226,7 +235,7 @@ sv_status sv_init_basis(sv_state* s, uint64_t index) {
   clear_error();
   if (sv_status st = check_state(s)) return st;
   if (index >= (1ull << s->n)) return fail(SV_ERR_ARG, "basis index out of range");
-  SV_HIP_TRY(launch_init_basis(s->dt, s->ptr, s->n, index, s->stream));
+  SV_LAUNCH(launch_init_basis(s->dt, s->ptr, s->n, index, s->stream), s->stream);
   return SV_OK;
 }
 
@@ -421,7 +430,7 @@ sv_status sv_measure_probs(sv_state* s, const int32_t* qubits, int m, double* ou
   if (sv_status st = probs_args(s->n, qubits, m, out_dev, qs)) return st;
   const size_t need = probs_scratch_bytes(s->n, m, qs);
   if (sv_status st = ensure_scratch(s, 256 + need)) return st;
-  SV_HIP_TRY(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, (unsigned char*)s->scratch + 256, s->stream));
+  SV_LAUNCH(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, (unsigned char*)s->scratch + 256, s->stream), s->stream);
   return SV_OK;
 }
 
@@ -436,7 +445,7 @@ sv_status sv_measure_probs_noalloc(sv_state* s, const int32_t* qubits, int m, do
                 static_scratch_bytes());
   void* scratch = nullptr;
   SV_HIP_TRY(static_scratch(s->device, &scratch));
-  SV_HIP_TRY(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, scratch, s->stream));
+  SV_LAUNCH(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, scratch, s->stream), s->stream);
   return SV_OK;
 }
 
@@ -448,7 +457,7 @@ sv_status sv_scale(sv_state* s, double scale) {
   a.g.nz = 0;
   a.g.nv = 1;
   a.m[0] = scale;
-  SV_HIP_TRY(launch_sweep(s->dt, s->ptr, s->n, a, s->stream));
+  SV_LAUNCH(launch_sweep(s->dt, s->ptr, s->n, a, s->stream), s->stream);
   return SV_OK;
 }
 
@@ -503,6 +512,6 @@ extern "C" sv_status sv_util_copy(void* dst, const void* src, size_t bytes, void
   clear_error();
   if (!dst || !src) return fail(SV_ERR_ARG, "null buffer");
   if (bytes % 16) return fail(SV_ERR_ARG, "size %zu is not a multiple of 16", bytes);
-  SV_HIP_TRY(launch_copy_bytes(dst, src, bytes, (hipStream_t)stream));
+  SV_LAUNCH(launch_copy_bytes(dst, src, bytes, (hipStream_t)stream), (hipStream_t)stream);
   return SV_OK;
 }

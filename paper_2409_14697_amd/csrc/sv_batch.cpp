@@ -205,7 +205,7 @@ sv_status sv_batcher_run(sv_batcher* b, int count, sv_state* const* states, cons
   }
   std::memcpy(b->host[k], items.data(), bytes);
   SV_HIP_TRY(hipMemcpyAsync(b->dev[k], b->host[k], bytes, hipMemcpyHostToDevice, b->stream));
-  SV_HIP_TRY(launch_pass_batch(dt, (const BatchItemDev*)b->dev[k], count, tiles, max_m, ladders, b->stream));
+  SV_LAUNCH(launch_pass_batch(dt, (const BatchItemDev*)b->dev[k], count, tiles, max_m, ladders, b->stream), b->stream);
   SV_HIP_TRY(hipEventRecord(b->done[k], b->stream));
   b->used[k] = true;
   return SV_OK;
@@ -230,7 +230,7 @@ sv_status sv_batcher_probs(sv_batcher* b, const sv_state* s, const int32_t* qubi
     }
     b->scratch_bytes = need;
   }
-  SV_HIP_TRY(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, b->scratch, b->stream));
+  SV_LAUNCH(launch_probs(s->dt, s->ptr, s->n, qs, m, out_dev, b->scratch, b->stream), b->stream);
   return SV_OK;
 }
 

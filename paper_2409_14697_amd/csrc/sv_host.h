@@ -25,6 +25,22 @@ void clear_error();
     if (_e != hipSuccess) return ::sv::fail(SV_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
   } while (0)
 
+// Debug mode (environment SV_DEBUG_SYNC=1, read once): every kernel launch is
+// followed by a synchronisation of its stream, so that a device fault is
+// reported by the call that enqueued the faulting kernel, with the launch
+// named in the message, instead of by a later call.
+bool debug_sync_enabled();
+#define SV_LAUNCH(expr, stream)                                                        \
+  do {                                                                                 \
+    SV_HIP_TRY(expr);                                                                  \
+    if (::sv::debug_sync_enabled()) {                                                  \
+      hipError_t _d = hipStreamSynchronize(stream);                                    \
+      if (_d == hipSuccess) _d = hipGetLastError();                                    \
+      if (_d != hipSuccess)                                                            \
+        return ::sv::fail(SV_ERR_DEVICE, "%s (debug sync): %s", #expr, hipGetErrorString(_d)); \
+    }                                                                                  \
+  } while (0)
+
 // ------------------------------------------------------------------ ops
 // One operation in logical qubits: a 2^nq x 2^nq matrix on q[0..nq-1]
 // (q[0] = most significant bit of the local index, as in Eq. 3).  `kind`

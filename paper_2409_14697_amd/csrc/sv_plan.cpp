@@ -335,10 +335,11 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
         since = 0;
       }
     } else {
-      SV_HIP_TRY(launch_pass(s->dt, s->ptr, s->n, ps.n_local, (const PassDescDev*)(db + pk.off_desc),
-                             pk.desc_index[i], (const PassStageDev*)(db + pk.off_stage),
-                             (const PassItemDev*)(db + pk.off_items), db + pk.off_pool, pk.pass_lp[i] != 0,
-                             s->stream));
+      SV_LAUNCH(launch_pass(s->dt, s->ptr, s->n, ps.n_local, (const PassDescDev*)(db + pk.off_desc),
+                            pk.desc_index[i], (const PassStageDev*)(db + pk.off_stage),
+                            (const PassItemDev*)(db + pk.off_items), db + pk.off_pool, pk.pass_lp[i] != 0,
+                            s->stream),
+                s->stream);
     }
   }
   if (renorm > 0 && since > 0) return renormalize(s);

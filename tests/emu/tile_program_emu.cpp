@@ -47,9 +47,12 @@ sv_status fail(sv_status st, const char* fmt, ...) {
 }
 void clear_error() { g_err.clear(); }
 size_t elem_bytes(sv_dtype dt) { return dt == SV_C128 ? 16 : 8; }
+bool debug_sync_enabled() { return false; }
 }  // namespace sv
 
 extern "C" const char* hipGetErrorString(hipError_t) { return "stub"; }
+extern "C" hipError_t hipStreamSynchronize(hipStream_t) { return hipErrorInvalidValue; }
+extern "C" hipError_t hipGetLastError(void) { return hipErrorInvalidValue; }
 
 static void die(const char* msg) {
   fprintf(stderr, "EMU ERROR: %s\n", msg);

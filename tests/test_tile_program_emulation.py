@@ -24,18 +24,30 @@ KIND = {"MATRIX": 0, "H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "T": 6, "RX": 7, "R
 TOL = {"c128": 1e-12, "c64": 1e-5}
 
 
-@pytest.fixture(scope="module")
-def emu():
+# SV_SANITIZE=1: the model (and with it the library's planner and packer
+# sources) is built with AddressSanitizer and UndefinedBehaviorSanitizer,
+# aborting on the first report.
+SANITIZE = os.environ.get("SV_SANITIZE", "") not in ("", "0")
+
+
+def build_model(binary, sanitize):
     srcs = [SRC] + [os.path.join(CSRC, f) for f in ("sv_plan.cpp", "sv_passplan.cpp", "sv_gates.cpp")]
     newest = max(os.path.getmtime(f) for f in srcs + [os.path.join(CSRC, "sv_tile_kernels.h"),
                                                       os.path.join(CSRC, "sv_host.h")])
-    if not os.path.exists(BIN) or os.path.getmtime(BIN) < newest:
-        os.makedirs(os.path.dirname(BIN), exist_ok=True)
-        cmd = ["g++", "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
-               f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"] + srcs + ["-o", BIN]
+    if not os.path.exists(binary) or os.path.getmtime(binary) < newest:
+        os.makedirs(os.path.dirname(binary), exist_ok=True)
+        flags = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                 "-fno-omit-frame-pointer"] if sanitize else ["-O2"]
+        cmd = ["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+               f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"] + flags + srcs + ["-o", binary]
         r = subprocess.run(cmd, capture_output=True, text=True)
         assert r.returncode == 0, r.stderr
-    return BIN
+    return binary
+
+
+@pytest.fixture(scope="module")
+def emu():
+    return build_model(BIN + ("_asan" if SANITIZE else ""), SANITIZE)
 
 
 def run_emu(binary, n, dtype, mode, lds, gates, psi0):
@@ -142,3 +154,15 @@ def test_tile_program_model_permutations_exact(emu, dtype):
     for lds in (0, 5, 8):
         out = run_emu(emu, n, dtype, "pass", lds, gates, psi)
         assert np.array_equal(out, oracle.run(gates, psi0=psi)), lds
+
+
+def test_tile_program_model_under_sanitizers():
+    """The planner and packer sources, built with AddressSanitizer and
+    UndefinedBehaviorSanitizer into the host model, plan and run a mixed
+    circuit, a QAOA level and the QFT without a report."""
+    binary = build_model(BIN + "_asan", True)
+    n = 10
+    for gates in (mixed(n, 200, 3), qaoa_circuit(n, 1, seed=2), qft_circuit(n)):
+        psi = gaussian_state_np(n, 2)
+        out = run_emu(binary, n, "c64", "pass", 0, gates, psi)
+        assert np.max(np.abs(out - oracle.run(gates, psi0=psi))) <= TOL["c64"]
