@@ -178,7 +178,11 @@ sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const
 // merges only one-qubit ops on the same qubit).
 std::vector<Op> fuse_ops(std::vector<Op> in, int n, sv_dtype dt, int kmax, bool mfma);
 // In-cache pass planning of an op list (logical qubits) into p->passes/ops.
-sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const sv_opts& o, sv_plan* p);
+// progress: every pass's write-back also moves data toward the position the
+// remaining relabelings give it (fewer permutation passes at the end, at
+// times more locality to pay in later passes; build_plan tries both).
+sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const sv_opts& o, sv_plan* p,
+                           bool progress);
 // Cost of one op run as its own sweep, in full read+write sweeps of the state.
 double op_sweep_cost(const Op& op, sv_dtype dt, bool mfma);
 // Tile size defaults.

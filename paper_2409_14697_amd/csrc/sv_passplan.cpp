@@ -808,9 +808,47 @@ std::vector<std::vector<int>> cycles_of(const QubitMap& mp) {
   return cyc;
 }
 
+// Final position of the data at every physical position.  SWAP gates still
+// ahead in the op list will be relabelings (they rename data, no data
+// moves), and the plan must leave label l at position l: the data now
+// labelled l ends labelled f(l), so it belongs at position f(l).
+std::vector<int> destinations(const QubitMap& mp, const std::vector<Op>& ops, const std::vector<char>& done,
+                              size_t first, bool reorder) {
+  const int n = (int)mp.logi.size();
+  std::vector<int> f(n);
+  for (int l = 0; l < n; ++l) f[l] = l;
+  if (reorder)
+    for (size_t j = first; j < ops.size(); ++j) {
+      if (done[j] || ops[j].kind != SV_G_SWAP) continue;
+      const int a = ops[j].q[0], b = ops[j].q[1];
+      for (int l = 0; l < n; ++l) f[l] = f[l] == a ? b : f[l] == b ? a : f[l];
+    }
+  std::vector<int> d(n);
+  for (int x = 0; x < n; ++x) d[x] = f[mp.logi[x]];
+  return d;
+}
+
+// Cycles of the position permutation x -> d[x] (fixed points left out).
+std::vector<std::vector<int>> dest_cycles(const std::vector<int>& d) {
+  const int n = (int)d.size();
+  std::vector<char> seen(n, 0);
+  std::vector<std::vector<int>> cyc;
+  for (int x = 0; x < n; ++x) {
+    if (seen[x] || d[x] == x) continue;
+    std::vector<int> c;
+    for (int y = x; !seen[y]; y = d[y]) {
+      seen[y] = 1;
+      c.push_back(y);
+    }
+    cyc.push_back(c);
+  }
+  return cyc;
+}
+
 }  // namespace
 
-sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const sv_opts& o, sv_plan* p) {
+sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const sv_opts& o, sv_plan* p,
+                           bool progress) {
   int m = o.lds_qubits ? o.lds_qubits : default_lds_qubits(dt);
   // 64 KiB tiles: two blocks per CU, and 16 elements of 16 bytes per lane
   const int m_max = dt == SV_C128 ? 12 : 13;
@@ -912,16 +950,28 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
     }
     bool last = true;
     for (size_t j = first; j < ops.size(); ++j) last = last && done[j];
-    // the last pass also takes the bits whose data must move back home
+    // Data moves of the write-back: the last pass brings data home; with
+    // `progress`, every pass moves the data whose final position (after the
+    // relabelings still ahead) lies in its tile, and fills its free tile
+    // bits with whole cycles of those moves, fewest new bits first.
+    const bool moves = last || progress;
+    std::vector<int> dest;
     std::vector<int> prefer;
-    if (last && !mp.identity()) {
-      int room = m - count;
-      for (const auto& c : cycles_of(mp)) {
+    if (moves) {
+      dest = destinations(mp, ops, done, first, reorder);
+      std::vector<std::vector<int>> cyc = dest_cycles(dest);
+      std::vector<std::pair<int, size_t>> order;  // (new bits, cycle)
+      for (size_t c = 0; c < cyc.size(); ++c) {
         int extra = 0;
-        for (int x : c) extra += in_l[x] ? 0 : 1;
-        if (extra > room) continue;
-        room -= extra;
-        prefer.insert(prefer.end(), c.begin(), c.end());
+        for (int x : cyc[c]) extra += in_l[x] ? 0 : 1;
+        order.push_back({extra, c});
+      }
+      std::stable_sort(order.begin(), order.end());
+      int room = m - count;
+      for (const auto& oc : order) {
+        if (oc.first > room) continue;
+        room -= oc.first;
+        prefer.insert(prefer.end(), cyc[oc.second].begin(), cyc[oc.second].end());
       }
     }
     fill_local(in_l, count, m, n, prefer);
@@ -939,13 +989,30 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
         loc[b] = j++;
       }
     ps.stages = build_stages(members, loc, m, dt);
-    // write-back: complete cycles of the map that lie inside the tile go home
-    if (last && !mp.identity()) {
-      for (const auto& c : cycles_of(mp)) {
-        bool inside = true;
-        for (int x : c) inside = inside && in_l[x];
-        if (!inside) continue;
-        for (int x : c) ps.wpos[loc[x]] = (uint32_t)mp.logi[x];
+    if (moves) {
+      // data whose destination is local goes there; the rest take the local
+      // positions nobody moves into (their own when free)
+      std::vector<char> taken(n, 0), placed(m, 0);
+      for (int jj = 0; jj < m; ++jj) {
+        const int x = (int)ps.lpos[jj], dx = dest[x];
+        if (in_l[dx]) {
+          ps.wpos[jj] = (uint32_t)dx;
+          taken[dx] = 1;
+          placed[jj] = 1;
+        }
+      }
+      for (int jj = 0; jj < m; ++jj)
+        if (!placed[jj] && !taken[ps.lpos[jj]]) {
+          ps.wpos[jj] = ps.lpos[jj];
+          taken[ps.lpos[jj]] = 1;
+          placed[jj] = 1;
+        }
+      int free_at = 0;
+      for (int jj = 0; jj < m; ++jj) {
+        if (placed[jj]) continue;
+        while (taken[ps.lpos[free_at]]) ++free_at;
+        ps.wpos[jj] = ps.lpos[free_at];
+        taken[ps.lpos[free_at]] = 1;
       }
       QubitMap nm = mp;
       for (int jj = 0; jj < m; ++jj) {

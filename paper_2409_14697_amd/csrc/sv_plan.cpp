@@ -181,8 +181,15 @@ sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const
     tp.dt = dt;
     tp.opts = o;
     std::vector<Op> light = fuse_ops(raw, n, dt, std::min(o.max_fuse_qubits, 1), mfma);
-    sv_status st = plan_tile_passes(light, n, dt, o, &tp);
+    sv_status st = plan_tile_passes(light, n, dt, o, &tp, false);
     if (st != SV_OK) return st;
+    // the same with data moved toward its final position in every pass's
+    // write-back; the cheaper of the two is kept
+    sv_plan tq;
+    tq.n = n;
+    tq.dt = dt;
+    tq.opts = o;
+    if (plan_tile_passes(light, n, dt, o, &tq, true) == SV_OK && tq.est_cost < tp.est_cost) tp = std::move(tq);
     if (o.mode == SV_MODE_PASS) {
       p->ops = std::move(tp.ops);
       p->op_pass = std::move(tp.op_pass);
