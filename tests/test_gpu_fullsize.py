@@ -189,6 +189,54 @@ def test_circuit_benchmark_n32_properties(sv):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_tensor_product_layers_n30_pairs(sv, dtype):
+    """Three layers of Haar single-qubit gates on all 30 qubits, with the same
+    CNOT matching after the first two, in tile passes (register stages apply
+    each layer as a tensor product of 2x2s): the result is a product of
+    two-qubit states, one per matched pair, each computed by the oracle on
+    two qubits; 4096 sampled amplitudes against their products."""
+    import torch
+    n = 30
+    rng = np.random.default_rng(41)
+    perm = rng.permutation(n)
+    pairs = [(int(perm[2 * i]), int(perm[2 * i + 1])) for i in range(n // 2)]
+    layers = [[haar_unitary(2, rng) for _ in range(n)] for _ in range(3)]
+    gates = []
+    for li, layer in enumerate(layers):
+        gates += [Gate("MATRIX", (q,), matrix=layer[q]) for q in range(n)]
+        if li < 2:
+            gates += [Gate("CNOT", pr) for pr in pairs]
+    plan = sv.Plan(n, dtype, gates, {"mode": "pass"})
+    assert all(k == 1 for k, _, _ in plan.passes())  # tile passes only
+    st = sv.StateVector(n, dtype)
+    st.init_basis(0)
+    st.apply_plan(plan)
+    st.sync()
+    plan.close()
+    psi00 = np.zeros(4, dtype=np.complex128)
+    psi00[0] = 1.0
+    pair_states = []
+    for c, t in pairs:  # local qubit 1 = c, 0 = t
+        g2 = []
+        for li, layer in enumerate(layers):
+            g2 += [Gate("MATRIX", (1,), matrix=layer[c]), Gate("MATRIX", (0,), matrix=layer[t])]
+            if li < 2:
+                g2.append(Gate("CNOT", (1, 0)))
+        pair_states.append(oracle.run(g2, psi0=psi00))
+    idx = np.concatenate([[0, (1 << n) - 1], rng.integers(0, 1 << n, size=4094, dtype=np.int64)])
+    ref = np.ones(idx.shape, dtype=np.complex128)
+    for (c, t), ps in zip(pairs, pair_states):
+        ref *= ps[2 * ((idx >> c) & 1) + ((idx >> t) & 1)]
+    got = read(st.tensor, idx)
+    # amplitudes are products of 15 factors below 1: the bar is relative to
+    # the largest sampled one
+    assert max_err(got, ref) <= TOL[dtype] * max(np.max(np.abs(ref)), 1e-300)
+    assert abs(st.norm2() - 1.0) < (1e-12 if dtype == "c128" else 1e-5)
+    st.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_qaoa_n30_closed_form(sv, dtype):
     """Five complete-graph QAOA levels at N=30 with the QAOA benchmark's plan
     (mode auto): 4096 sampled amplitudes (with |0..0> and |1..1>) against the

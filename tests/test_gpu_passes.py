@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 
 import oracle
-from svgen import (Gate, basis_state_np, brickwork_circuit, gaussian_state_np, layered_circuit, qaoa_circuit,
-                   qft_circuit)
+from svgen import (Gate, basis_state_np, brickwork_circuit, gaussian_state_np, haar_unitary, layered_circuit,
+                   qaoa_circuit, qft_circuit)
 from tests.gpu_util import TOL, max_err, to_device, to_host
 
 pytestmark = pytest.mark.gpu
@@ -175,13 +175,61 @@ def test_phase_runs(sv, dtype, lds, seed):
     assert max_err(out, ref) <= TOL[dtype]
 
 
+def single_qubit_layers(n, depth, family, seed):
+    """Layers of single-qubit gates on every qubit (the family fixes which
+    2x2 form a register stage needs: real, real-diagonal/imaginary
+    off-diagonal, both mixed, or general complex), each followed by CNOTs
+    on a random disjoint matching."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(depth):
+        for q in range(n):
+            th = float(rng.uniform(0, 2 * math.pi))
+            if family == "real":
+                kind = ("H", "RY")[int(rng.integers(2))]
+            elif family == "imag":
+                kind = ("RX", "Y")[int(rng.integers(2))]
+            elif family == "mixed":
+                kind = ("H", "RY", "RX", "Y")[int(rng.integers(4))]
+            else:
+                out.append(Gate("MATRIX", (q,), matrix=haar_unitary(2, rng)))
+                continue
+            out.append(Gate(kind, (q,), th))
+        p = rng.permutation(n)
+        out += [Gate("CNOT", (int(p[2 * i]), int(p[2 * i + 1]))) for i in range(n // 2)]
+    return out
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_phase_runs_many_per_stage(sv, dtype):
+@pytest.mark.parametrize("family", ["real", "imag", "mixed", "haar"])
+@pytest.mark.parametrize("lds", list(range(4, 14)))
+def test_tensor_product_layers(sv, dtype, family, lds):
+    """A layer of single-qubit gates is applied by a register stage as the
+    tensor product of one 2x2 per register bit (Sec. III-A's tensor product
+    booster, own design); random layers of each form mixed with CNOTs at
+    N=14, every tile size, against the oracle."""
+    rb = 4 if dtype == "c128" else 5
+    m_max = 12 if dtype == "c128" else 13
+    if lds < rb or lds > m_max:
+        pytest.skip("tile size outside this dtype's range")
+    n = 14
+    gates = single_qubit_layers(n, 6, family, seed=31 + lds)
+    plan = sv.Plan(n, dtype, gates, {"mode": "pass", "lds_qubits": lds})
+    # several single-qubit gates per stage: fewer stages than such gates
+    stages = sum(p[3] for p in plan.passes(stages=True))
+    plan.close()
+    assert stages < 6 * n
+    out, ref = run_plan(sv, n, dtype, gaussian_state_np(n, 5), gates, {"mode": "pass", "lds_qubits": lds})
+    assert max_err(out, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_phase_runs_across_permutations(sv, dtype):
     """Forty runs of RZZ on all pairs of qubits 2..15, each closed by CNOTs
-    from every one of those qubits onto qubit 1 (so no phase gate can move
-    into an earlier run, and the stage keeps one register bit busy): the
-    first runs fill the stage's table of tile rows, the rest are applied
-    gate by gate; against the oracle."""
+    from every one of those qubits onto qubit 1.  A phase gate on a CNOT's
+    control commutes with it, so a stage applies all forty runs as one fused
+    phase before its register permutation: a few fixed-point items, not one
+    item per gate; against the oracle."""
     n = 16
     rng = np.random.default_rng(12)
     gates = [Gate("H", (q,)) for q in range(n)]
@@ -192,9 +240,8 @@ def test_phase_runs_many_per_stage(sv, dtype):
         gates += [Gate("CNOT", (c, 1)) for c in range(2, n)]
     opts = {"mode": "pass"}
     kops, ladders = sv.Plan(n, dtype, gates, opts).kernel_ops()[-1]
-    # fused runs cost a few ops each, the 560 CNOTs one each; more than
-    # that means runs applied gate by gate
-    assert ladders > 0 and kops > 560 + 40 * 10
+    # the 560 CNOTs count one each; the 3640 phase gates a handful
+    assert ladders > 0 and kops <= 560 + 20
     out, ref = run_plan(sv, n, dtype, basis_state_np(n, 0), gates, opts)
     assert max_err(out, ref) <= TOL[dtype]
 
