@@ -576,209 +576,180 @@ __global__ __launch_bounds__((mfma_plan<R, K>::THREADS)) void k_dense_mfma_swz(t
 #undef SV_LD
 }
 
-// ---------------------------------------------------------------- direct
-// The same contraction without LDS.  A column block is BN consecutive
-// groups; when the gate's qubits leave the lowest physical bits to the
-// column index (or to the lowest member bits a lane group owns), every load
-// and store instruction of a wave covers whole 128-byte lines, so the
-// matrix-core operands come straight from HBM into registers and the
-// results go straight back: no staging, no barrier between a wave's column
-// blocks, and the next block's loads are in flight during the current
-// block's matrix work.
-//
-// Lanes form G = 64 / BN groups of BN lanes (complex64: 2 groups of 32,
-// complex128: 4 of 16); lane (col = l % BN, grp = l / BN) loads members
-// G j + grp of its column (j < D / G, whole amplitudes).  Real row bk of the
-// operand at k-step ks, bk = BK ks + grp, is part (ks & 1) of member
-// G (ks >> 1) + grp; the A fragments are built with the same order.  The
-// result rows are assigned so that a lane also stores the members whose low
-// bits are its group (and re / im of one member sit in registers r, r + 1):
-// complex64 row 8 q + 4 h + t of a block is member 4 q + 2 (t >> 1) + h,
-// part t & 1; complex128 row g + 4 r is member 4 (r >> 1) + g, part r & 1.
-// When the gate needs more row blocks than one wave holds (k = 6), WPC waves
-// of a block share a column block, each computing its own row blocks; they
-// read every input before any of them writes.
+// ---------------------------------------------------------------- 3M
+// The same product with three real matrix products instead of the four of
+// the real embedding (Gauss's complex multiplication): with U = Ur + i Ui and
+// X = Xr + i Xi,
+//   P1 = Ur Xr,  P2 = Ui Xi,  P3 = (Ur + Ui)(Xr + Xi),
+//   Yr = P1 - P2,  Yi = P3 - P1 - P2,
+// so the matrix cores do 6 D^2 real multiply-adds per column instead of 8.
+// Real rows of each product are members, so a gate needs D >= BM (complex64
+// k >= 5, complex128 k >= 4).  The tile, its gather and its store are those
+// of the embedding kernels; a lane reads one complex operand per k-step and
+// feeds its real part, imaginary part and their sum to the three products.
+// SWZ: the tile is swizzled (member and column-block masks, see DenseGeo).
 template <typename R, int K>
-struct direct_plan {
+struct m3_plan {
   typedef mfma_shape<R> MS;
   static constexpr int D = 1 << K;
-  static constexpr int G = 64 / MS::BN;                // lane groups
-  static constexpr int NB = D / G;                     // members a lane loads per column block
-  static constexpr int RBLK = 2 * D / MS::BM;          // row blocks
-  static constexpr int KSTEPS = 2 * D / MS::BK;
-  static constexpr int RW = (sizeof(R) == 4 ? (K == 6 ? 1 : RBLK) : (K == 6 ? 2 : RBLK));  // row blocks per wave
-  static constexpr int WPC = RBLK / RW;                // waves per column block
-  static constexpr int CB = sizeof(R) == 4 ? 5 : 4;    // column bits
-  static constexpr bool PREFETCH = !(sizeof(R) == 8 && K == 6);  // registers for the next block's operands
-  static_assert(MS::BK == G, "one k-step takes one real row per lane group");
-
-  // block row -> (member within the block, re/im)
-  static __device__ __forceinline__ void row_of(int rho, int* mem, int* part) {
-    if constexpr (sizeof(R) == 4) {
-      *mem = 4 * (rho >> 3) + 2 * ((rho & 3) >> 1) + ((rho >> 2) & 1);
-      *part = rho & 1;
-    } else {
-      *mem = 4 * ((rho >> 2) >> 1) + (rho & 3);
-      *part = (rho >> 2) & 1;
-    }
-  }
-  // member (within the block) of registers r, r + 1 (r even): uniform part;
-  // the lane part is its group
-  static __device__ __forceinline__ int out_member_u(int r) {
-    if constexpr (sizeof(R) == 4) return 4 * (r >> 2) + 2 * ((r & 3) >> 1);
-    else return 4 * (r >> 1);
-  }
-  static_assert(RBLK % RW == 0 && 4 % WPC == 0, "row blocks split over the block's waves");
+  static constexpr int NC = mfma_cols<R, K>();
+  static constexpr int W = (sizeof(R) == 8 && K == 6) ? 8 : 4;
+  static constexpr int THREADS = 64 * W, TB = W == 8 ? 9 : 8;
+  static constexpr int RB = D / MS::BM;             // row blocks (members)
+  static constexpr int CBLK = NC / MS::BN, TILES = RB * CBLK;
+  static constexpr int TPW = TILES / W;             // output tiles per wave
+  static constexpr int KS = D / MS::BK;             // k-steps (members)
+  static_assert(D >= MS::BM, "3M products need a full row block of members");
+  static_assert(TILES % W == 0 && W % RB == 0, "each wave keeps one row block");
 };
 
-// Tile map of the direct kernel: member bit b of the gate (bit b of the
-// member index; q[k-1-b]) at physical offset mbit[b]; column bits at
-// colpos[]; the column-block index deposited into `rest`.
-struct DirectGeo {
-  uint64_t rest;
-  uint64_t mbit[6];
-  uint32_t colpos[5];
-  uint32_t pad;
-};
-
-// Physical offset of member index mu (a compile-time or uniform value).
-template <int K>
-__device__ __forceinline__ uint64_t member_off(uint32_t mu, const uint64_t* mbit) {
-  uint64_t o = 0;
-#pragma unroll
-  for (int b = 0; b < K; ++b)
-    if ((mu >> b) & 1u) o |= mbit[b];
-  return o;
+// Output member (within a row block) of accumulator register r of lane l.
+template <typename R>
+__device__ __forceinline__ int m3_out_member(int l, int r) {
+  if constexpr (sizeof(R) == 4) return 8 * (r / 4) + 4 * (l / 32) + r % 4;
+  else return l / 16 + 4 * r;
 }
 
-template <typename R, int K>
-__global__ __launch_bounds__(256) void k_dense_direct(typename mfma_shape<R>::E* __restrict__ psi, uint64_t nwork,
-                                                     DirectGeo g, const R* __restrict__ um) {
+template <typename R, int K, bool SWZ>
+__global__ __launch_bounds__((m3_plan<R, K>::THREADS)) void k_dense_3m(typename mfma_shape<R>::E* __restrict__ psi,
+                                                                      uint64_t nwork, DenseGeo g,
+                                                                      const R* __restrict__ um) {
   typedef mfma_shape<R> MS;
-  typedef direct_plan<R, K> DP;
+  typedef m3_plan<R, K> MP;
   typedef typename MS::E E;
-  constexpr int D = DP::D, G = DP::G, NB = DP::NB, KSTEPS = DP::KSTEPS, RW = DP::RW, WPC = DP::WPC;
-  const int l = threadIdx.x % 64;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-  const int col = l % MS::BN, grp = l / MS::BN;
-  // row blocks of this wave: (w % WPC) * RW + i
-  const int rb0 = (w % WPC) * RW;
-  R afrag[RW][KSTEPS];
+  constexpr int D = MP::D, NC = MP::NC, RB = MP::RB, TPW = MP::TPW, KS = MP::KS, W = MP::W, TB = MP::TB;
+  constexpr int LB = sizeof(R) == 4 ? 1 : 0;
+  typedef typename mfma_shape<R>::G G;
+  constexpr int PER = (D * NC / MP::THREADS) >> LB;  // 16-byte elements per lane
+  extern __shared__ __align__(16) unsigned char smem[];
+  E* xs = reinterpret_cast<E*>(smem);  // [member][NC]
+  const int t = threadIdx.x, l = t % 64;
+  const int w = __builtin_amdgcn_readfirstlane(t / 64);
+  const int rb = w % RB;  // this wave's row block (tiles w, w + W, ... share it)
+  // A fragments: lane l supplies row l % BM, column BK ks + l / BM of Ur, Ui
+  // and Ur + Ui (rows and columns are members)
+  R a1[KS], a2[KS], a3[KS];
+  {
+    const int row = MS::BM * rb + l % MS::BM;
 #pragma unroll
-  for (int i = 0; i < RW; ++i) {
-    int ai, aa;  // output member and re/im of the A row this lane supplies
-    DP::row_of(l % MS::BM, &ai, &aa);
-    ai += MS::MPB * (rb0 + i);
-#pragma unroll
-    for (int ks = 0; ks < KSTEPS; ++ks) {
-      const int mu = G * (ks >> 1) + l / MS::BM;  // input member of real column BK ks + l / BM
-      const int part = ks & 1;
-      const R ur = um[2 * (ai * D + mu)], ui = um[2 * (ai * D + mu) + 1];
-      // A[2i + aa][2 mu + part] of the real embedding (Ur, -Ui; Ui, Ur)
-      afrag[i][ks] = aa == 0 ? (part == 0 ? ur : -ui) : (part == 0 ? ui : ur);
+    for (int ks = 0; ks < KS; ++ks) {
+      const int col = MS::BK * ks + l / MS::BM;
+      const R ur = um[2 * (row * D + col)], ui = um[2 * (row * D + col) + 1];
+      a1[ks] = ur;
+      a2[ks] = ui;
+      a3[ks] = ur + ui;
     }
   }
-  uint64_t mbit[K];
+  const LaneMap lm = lane_map<LB, TB, SWZ>((uint32_t)t, g);
+  const uint32_t l0 = g.lds[0];
+  G* gp = reinterpret_cast<G*>(psi);
+  // lane parts of the operand member (l / BN) and of the result members
+  const int bml = l / MS::BN;
+  uint32_t fmb0[K];
 #pragma unroll
-  for (int b = 0; b < K; ++b) mbit[b] = g.mbit[b];
-  uint64_t lane_col = 0;
-#pragma unroll
-  for (int b = 0; b < DP::CB; ++b)
-    if ((col >> b) & 1) lane_col |= 1ull << g.colpos[b];
-  // lane parts of the loaded and of the stored members
-  const uint64_t lane = lane_col | member_off<K>((uint32_t)grp, mbit);  // loads and stores alike
-  E* const p = psi;
-  // column blocks: block-major over the grid, XCD-aware; WPC waves of a block
-  // share one column block, the others take their own
-  const uint64_t waves_per_block = 4 / WPC;
-  const uint64_t slot = xcd_block() * waves_per_block + (uint64_t)(w / WPC);
-  const uint64_t stride = (uint64_t)gridDim.x * waves_per_block;
-  E x[NB], xn[DP::PREFETCH ? NB : 1];
-  auto load = [&](uint64_t c, E* dst) {
-    const uint64_t base = deposit(c, g.rest) | lane;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) dst[j] = ld(p + (base | member_off<K>((uint32_t)(G * j), mbit)));
-  };
-  // the waves of a block that share column blocks (WPC > 1) share `slot`
-  // and so run the same iterations: all reach the barrier
-  if constexpr (DP::PREFETCH) {
-    if (slot < nwork) load(slot, x);
+  for (int b = 0; b < K; ++b) fmb0[b] = SWZ ? g.fmb[b] : 0u;
+  const uint32_t bfl = member_swizzle<K>(bml, fmb0);
+  uint64_t wb = xcd_block();
+  if (wb >= nwork) return;
+  G buf[PER];
+#define SV_LD(U)                                                        \
+  {                                                                     \
+    uint64_t a;                                                         \
+    uint32_t li;                                                        \
+    bool on;                                                            \
+    elem_map<LB, U, TB, SWZ>(g, &a, &li, &on);                          \
+    buf[U] = ld(gp + (((on && lm.on) ? (ldbase | a) : ldbase) >> LB));  \
   }
-  for (uint64_t cb = slot; cb < nwork; cb += stride) {
-    if constexpr (DP::PREFETCH) {
-      if (cb + stride < nwork) load(cb + stride, xn);
-    } else {
-      load(cb, x);
+  {
+    const uint64_t ldbase = deposit(wb, g.rest) | lm.addr;
+    SV_FOR_U(PER, SV_LD)
+  }
+  while (true) {
+    const uint64_t nb = wb + gridDim.x;
+    const uint64_t base = deposit(wb, g.rest) | lm.addr;
+    __syncthreads();  // the previous tile's store phase is done with LDS
+#define SV_LDS(U)                                                       \
+    {                                                                   \
+      uint64_t a;                                                       \
+      uint32_t li;                                                      \
+      bool on;                                                          \
+      elem_map<LB, U, TB, SWZ>(g, &a, &li, &on);                        \
+      if (on && lm.on) {                                                \
+        if constexpr (SWZ) mfma_shape<R>::to_lds_x(xs, lm.lds ^ li, l0, buf[U]); \
+        else mfma_shape<R>::to_lds(xs, lm.lds | li, l0, buf[U]);        \
+      }                                                                 \
     }
-    typename MS::acc_t acc[RW];
+    SV_FOR_U(PER, SV_LDS)
+#undef SV_LDS
+    __syncthreads();
+    if (nb < nwork) {
+      const uint64_t ldbase = deposit(nb, g.rest) | lm.addr;
+      SV_FOR_U(PER, SV_LD)
+    }
+    typename MS::acc_t p1[TPW], p2[TPW], p3[TPW];
+    uint32_t fmb[K];
 #pragma unroll
-    for (int i = 0; i < RW; ++i) {
-      acc[i] = typename MS::acc_t{};
+    for (int b = 0; b < K; ++b) {
+      fmb[b] = SWZ ? g.fmb[b] : 0u;
+      asm volatile("" : "+s"(fmb[b]));
+    }
 #pragma unroll
-      for (int ks = 0; ks < KSTEPS; ++ks) {
-        const E xv = x[ks >> 1];
-        const R b = (ks & 1) ? xv.y : xv.x;
-        acc[i] = MS::mma(afrag[i][ks], b, acc[i]);
+    for (int i = 0; i < TPW; ++i) {
+      const int cb = (w + W * i) / RB;
+      const uint32_t bl = (uint32_t)(bml * NC) + ((uint32_t)(MS::BN * cb + l % MS::BN) ^ bfl ^ (SWZ ? g.fc[cb] : 0u));
+      p1[i] = p2[i] = p3[i] = typename MS::acc_t{};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        // operand member BK ks + bml, column BN cb + l % BN
+        const int mu = MS::BK * ks;  // uniform part (bits disjoint from bml)
+        const E xv = xs[mu * NC + (bl ^ member_swizzle<K>(mu, fmb))];
+        p1[i] = MS::mma(a1[ks], xv.x, p1[i]);
+        p2[i] = MS::mma(a2[ks], xv.y, p2[i]);
+        p3[i] = MS::mma(a3[ks], xv.x + xv.y, p3[i]);
       }
     }
-    if constexpr (WPC > 1) __syncthreads();  // every wave of the block has read the column block
-    const uint64_t base = deposit(cb, g.rest) | lane;
+    __syncthreads();  // every wave has read X: the outputs replace it in LDS
 #pragma unroll
-    for (int i = 0; i < RW; ++i)
+    for (int i = 0; i < TPW; ++i) {
+      const int cb = (w + W * i) / RB;
+      const uint32_t col = (uint32_t)(MS::BN * cb + l % MS::BN) ^ (SWZ ? g.fc[cb] : 0u);
 #pragma unroll
-      for (int r = 0; r < MS::NACC; r += 2) {
-        const uint32_t mu = (uint32_t)(MS::MPB * (rb0 + i) + DP::out_member_u(r));
+      for (int r = 0; r < MS::NACC; ++r) {
+        const int mu = MS::BM * rb + m3_out_member<R>(l, r);
         E y;
-        y.x = acc[i][r];
-        y.y = acc[i][r + 1];
-        st(p + (base | member_off<K>(mu, mbit)), y);
+        y.x = p1[i][r] - p2[i][r];
+        y.y = p3[i][r] - p1[i][r] - p2[i][r];
+        xs[mu * NC + (col ^ member_swizzle<K>(mu, fmb))] = y;
       }
-    if constexpr (DP::PREFETCH) {
-#pragma unroll
-      for (int j = 0; j < NB; ++j) x[j] = xn[j];
     }
+    __syncthreads();
+#define SV_ST(U)                                                        \
+    {                                                                   \
+      uint64_t a;                                                       \
+      uint32_t li;                                                      \
+      bool on;                                                          \
+      elem_map<LB, U, TB, SWZ>(g, &a, &li, &on);                        \
+      if (on && lm.on) {                                                \
+        if constexpr (SWZ) st(gp + ((base | a) >> LB), mfma_shape<R>::from_lds_x(xs, lm.lds ^ li, l0)); \
+        else st(gp + ((base | a) >> LB), mfma_shape<R>::from_lds(xs, lm.lds | li, l0)); \
+      }                                                                 \
+    }
+    SV_FOR_U(PER, SV_ST)
+#undef SV_ST
+    if (nb >= nwork) break;
+    wb = nb;
   }
+#undef SV_LD
 }
 
-// The direct kernel's map, or false when the placement does not suit it:
-// the lowest 128-byte line must be covered by the column bits and the member
-// bits a lane group owns.
-template <typename R, int K>
-bool direct_geo(int n, const int* q, DirectGeo* g) {
-  typedef direct_plan<R, K> DP;
-  if (n < K + DP::CB) return false;
-  uint64_t gate = 0;
-  for (int i = 0; i < K; ++i) gate |= 1ull << q[i];
-  *g = DirectGeo{};
-  for (int b = 0; b < K; ++b) g->mbit[b] = 1ull << q[K - 1 - b];
-  int c = 0;
-  uint64_t cols = 0;
-  for (int p = 0; p < n && c < DP::CB; ++p)
-    if (!((gate >> p) & 1)) {
-      g->colpos[c++] = (uint32_t)p;
-      cols |= 1ull << p;
-    }
-  uint64_t lanebits = cols;
-  for (int b = 0; (1 << b) < DP::G; ++b) lanebits |= g->mbit[b];
-  const int line_bits = sizeof(R) == 4 ? 4 : 3;  // amplitudes in 128 bytes
-  if ((lanebits & ((1ull << line_bits) - 1)) != ((1ull << line_bits) - 1)) return false;
-  const uint64_t all = (1ull << n) - 1ull;
-  g->rest = all & ~gate & ~cols;
-  return true;
-}
-
-template <typename R, int K>
-hipError_t launch_direct(void* psi, int n, const DirectGeo& g, const void* m, hipStream_t s) {
-  typedef direct_plan<R, K> DP;
-  const uint64_t nwork = 1ull << (n - K - DP::CB);  // column blocks
+template <typename R, int K, bool SWZ>
+hipError_t launch_3m(void* psi, uint64_t nwork, const DenseGeo& g, const void* m, hipStream_t s) {
+  constexpr size_t lds = mfma_lds<R, K>();
   static KernelLaunchCache cache;
-  uint64_t resident = 0;
-  hipError_t e = prepare_launch(cache, (const void*)k_dense_direct<R, K>, 256, 0, &resident);
+  hipError_t e = prepare_launch(cache, (const void*)k_dense_3m<R, K, SWZ>, m3_plan<R, K>::THREADS, lds, nullptr);
   if (e != hipSuccess) return e;
-  const uint64_t per_block = 4 / DP::WPC;
-  uint64_t blocks = (nwork + per_block - 1) / per_block;
-  if (blocks > resident) blocks = resident;
-  hipLaunchKernelGGL((k_dense_direct<R, K>), dim3((unsigned)blocks), dim3(256), 0, s,
+  const uint64_t blocks = nwork < 4096 ? nwork : 4096;
+  hipLaunchKernelGGL((k_dense_3m<R, K, SWZ>), dim3((unsigned)blocks), dim3(m3_plan<R, K>::THREADS), lds, s,
                      (typename mfma_shape<R>::E*)psi, nwork, g, (const R*)m);
   return hipGetLastError();
 }
@@ -806,15 +777,12 @@ hipError_t launch_mfma(void* psi, uint64_t nwork, const DenseGeo& g, const void*
 
 DenseGeo make_geo(int n, int k, const int* q, int nc, int es, int lb);
 
-// Placements whose lowest 128-byte line the direct kernel's lanes cover run
-// without LDS.  Otherwise the swizzled kernel runs when the plain layout would put a wave's 64 lanes
+// The swizzled kernel runs when the plain layout would put a wave's 64 lanes
 // on at most a quarter (complex64 k = 6: a sixteenth) of the LDS bank groups
 // they could use (member bits among the lanes: low qubit placements); the
 // plain kernel addresses its operands more cheaply and runs otherwise.
 template <typename R, int K>
 hipError_t run_mfma(void* psi, int n, const int* q, const void* m, hipStream_t s) {
-  DirectGeo dg;
-  if (direct_geo<R, K>(n, q, &dg)) return launch_direct<R, K>(psi, n, dg, m, s);
   constexpr int NC = mfma_cols<R, K>();
   constexpr int LB = sizeof(R) == 4 ? 1 : 0;
   const uint64_t ngroups = 1ull << (n - K);
@@ -833,8 +801,12 @@ hipError_t run_mfma(void* psi, int n, const int* q, const void* m, hipStream_t s
   // the complex64 k = 6 kernel is matrix-bound: the swizzle's extra address
   // arithmetic pays only against the worst conflicts
   const int factor = (sizeof(R) == 4 && K == 6) ? 16 : 4;
-  if (distinct * factor <= (1 << mfma_shape<R>::ES))
-    return launch_mfma<R, K, true>(psi, nwork, make_geo(n, K, q, NC, mfma_shape<R>::ES, LB), m, s);
+  const bool swz = distinct * factor <= (1 << mfma_shape<R>::ES);
+  if constexpr ((1 << K) >= mfma_shape<R>::BM) {
+    if (swz) return launch_3m<R, K, true>(psi, nwork, make_geo(n, K, q, NC, mfma_shape<R>::ES, LB), m, s);
+    return launch_3m<R, K, false>(psi, nwork, plain, m, s);
+  }
+  if (swz) return launch_mfma<R, K, true>(psi, nwork, make_geo(n, K, q, NC, mfma_shape<R>::ES, LB), m, s);
   return launch_mfma<R, K, false>(psi, nwork, plain, m, s);
 }
 

@@ -82,6 +82,9 @@ enum PassKind { PASS_SWEEP = 0, PASS_TILE = 1, PASS_DENSE = 2, PASS_PERMUTE = 3 
 struct StageHost {
   uint32_t q[kPassRegBitsMax] = {0, 0, 0, 0, 0};  // local bit of each register bit
   uint32_t form = PFORM_NONE;               // PassForm of the 2x2 part
+  uint32_t slot_mask = 0;                   // register bits with a 2x2 (the others hold identities)
+  uint32_t nsub = 0;                        // earlier layers (entries of `mats`; dr kPassNoTable: none)
+  PassSubDev sub[kPassSubMax] = {};
   uint32_t flags = 0;                       // PassStageFlags
   uint32_t slots = 0, u2 = 0, dr = 0;       // entries of `mats`
   std::vector<PassItemDev> items;           // lane items (.mat indexes `mats`)

@@ -24,6 +24,8 @@
 // LDS rows are 128 bytes; the element index is XOR-swizzled (low bits folded
 // with every higher group of bits) so that power-of-two strides between the
 // lanes of a wave fall into distinct banks.
+#include <stddef.h>
+
 #include "sv_device.h"
 #include "sv_kernels.h"
 #include "sv_tile_kernels.h"
@@ -40,12 +42,18 @@ struct Regs {
   static constexpr int NR = 1 << RB;
 };
 
-template <int WB>
+// LDS index of local amplitude x.  Global memory moves 16-byte elements (LB
+// amplitude bits inside one: 1 for complex64, 0 for complex128); the three
+// element bits above them (one 128-byte row of LDS) are XORed with every
+// higher group of three element bits, so that power-of-two strides between
+// the lanes of a wave spread over the banks.  The map is linear over GF(2)
+// and its own inverse, and keeps the amplitudes of one element together.
+template <int LB>
 __device__ __forceinline__ uint32_t swz(uint32_t x) {
-  uint32_t y = x >> WB, h = 0;
+  uint32_t y = x >> (LB + 3), h = 0;
 #pragma unroll
-  for (int k = 0; k * WB < 16; ++k) h ^= y >> (k * WB);
-  return x ^ (h & ((1u << WB) - 1u));
+  for (int k = 0; k < 5; ++k) h ^= y >> (3 * k);
+  return x ^ ((h & 7u) << LB);
 }
 
 template <typename R>
@@ -96,6 +104,25 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
 template <typename P>
 __device__ __forceinline__ P uniform_ptr(P p) {
   return (P)uniform64((uint64_t)p);
+}
+
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// A workgroup barrier without the memory fence of __syncthreads (which
+// would also wait for this wave's global stores): the caller has already
+// waited for the LDS traffic the barrier orders.  The empty asm statements
+// keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// The barrier between the phases of a tile: every lane's LDS reads and
+// writes (and scalar loads) are complete, then all waves meet.
+__device__ __forceinline__ void lds_sync() {
+  wait_lgkm0();
+  lds_barrier();
 }
 
 template <typename R>
@@ -200,7 +227,8 @@ __device__ __forceinline__ void op_u2(cplx<R>* v, cptr<cplx<R>> M) {
 }
 
 // The tensor product of one 2x2 per register bit (4 entries per bit, bit 0
-// first), every bit in form F.
+// first), every bit in form F; bits outside `mask` hold identities and are
+// skipped.
 template <int F, int B, typename R>
 __device__ __forceinline__ void slot(cplx<R>* v, cptr<cplx<R>> M) {
   if constexpr (F == PFORM_UR) op_ur<B>(v, M + 4 * B);
@@ -209,12 +237,14 @@ __device__ __forceinline__ void slot(cplx<R>* v, cptr<cplx<R>> M) {
   else op_u1<B>(v, M + 4 * B);
 }
 template <int F, typename R>
-__device__ __forceinline__ void layer(cplx<R>* v, cptr<cplx<R>> M) {
-  slot<F, 0>(v, M);
-  slot<F, 1>(v, M);
-  slot<F, 2>(v, M);
-  slot<F, 3>(v, M);
-  if constexpr (Regs<R>::RB > 4) slot<F, 4>(v, M);
+__device__ __forceinline__ void layer(cplx<R>* v, cptr<cplx<R>> M, uint32_t mask) {
+  if (mask & 1u) slot<F, 0>(v, M);
+  if (mask & 2u) slot<F, 1>(v, M);
+  if (mask & 4u) slot<F, 2>(v, M);
+  if (mask & 8u) slot<F, 3>(v, M);
+  if constexpr (Regs<R>::RB > 4) {
+    if (mask & 16u) slot<F, 4>(v, M);
+  }
 }
 
 // Angle words of the phase ladder: fixed-point turns, summed modulo one turn.
@@ -321,7 +351,7 @@ __device__ __forceinline__ void stage_rows(const PassStageDev& S, cptr<cplx<R>> 
     for (int i = 0; i < kPassLPTileBits; ++i) acc += ((sel >> i) & 1) ? w[i] : W(0);
     ts[j] = (pred == kPassRowAlways || ((base >> pred) & 1)) ? acc : W(0);
   }
-  __syncthreads();
+  lds_sync();
 }
 
 // Value of selector code c for the lane: local bit c of its group index, or
@@ -437,35 +467,8 @@ struct gelem<float> {
   static constexpr int LB = 1;
 };
 
-// Uniform physical offsets of the per-lane element counter: bit b of the
-// counter is local bit LB + 8 + b; h[0..3] cover a batch of 16, the rest the
-// batch number.
-struct PassOffsets {
-  uint64_t in[4], out[4];
-};
-
-template <int LB>
-__device__ __forceinline__ void pass_offsets(cptr<PassDescDev> P, PassOffsets* po) {
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const uint32_t l = LB + 8 + b;
-    po->in[b] = l < P->m ? 1ull << P->lpos[l] : 0ull;
-    po->out[b] = l < P->m ? 1ull << P->wpos[l] : 0ull;
-  }
-}
-
-template <int U>
-__device__ __forceinline__ uint64_t batch_bits(const uint64_t* h) {
-  return ((U & 1) ? h[0] : 0ull) | ((U & 2) ? h[1] : 0ull) | ((U & 4) ? h[2] : 0ull) | ((U & 8) ? h[3] : 0ull);
-}
-
-template <int U>
-__device__ __forceinline__ uint32_t batch_bits32(const uint32_t* h) {
-  return ((U & 1) ? h[0] : 0u) | ((U & 2) ? h[1] : 0u) | ((U & 4) ? h[2] : 0u) | ((U & 8) ? h[3] : 0u);
-}
-
-// Everything a lane needs to move one tile: the pass, the state, the tile's
-// base index and the uniform offsets of its element counter.
+// Everything a lane needs to move one tile: the pass, the state and the
+// tile's base index.
 template <typename R>
 struct TileRef {
   typename dev_elem<R>::E* psi;
@@ -490,10 +493,9 @@ __device__ __forceinline__ TileRef<R> tile_ref(typename dev_elem<R>::E* psi, int
   return r;
 }
 
-constexpr int kBatch = 16;  // 16-byte loads in flight per lane
+constexpr int kBatch = 16;  // 16-byte elements per lane: 64 KiB tiles
 
-// Lane geometry of a tile: element e = t + 256 j holds local index
-// x = e << LB; local bits LB .. LB+7 come from the lane, the rest from j.
+// Lane geometry of a tile: LDS element slot e = t + 256 u (u < per) of lane t.
 struct LaneGeo {
   uint32_t per;
   bool on;
@@ -505,67 +507,66 @@ __device__ __forceinline__ LaneGeo lane_geo(uint32_t m) {
   return {elems >= (uint32_t)kBlock ? elems / kBlock : 1u, threadIdx.x < elems};
 }
 
+// Physical offset of element slot bit i when the load fills slot e with tile
+// element swz(e) (amplitude index swz(e) << LB): the swizzle is linear, so
+// the address of a slot is the XOR of the offsets of its set bits.  pos =
+// local bit positions (lpos for the load).
 template <int LB>
-__device__ __forceinline__ uint64_t lane_bits(cptr<uint32_t> pos, uint32_t m) {
+__device__ __forceinline__ uint64_t slot_offset(cptr<uint32_t> pos, uint32_t m, uint32_t i) {
+  if (LB + i >= m) return 0ull;
+  uint64_t o = 1ull << pos[LB + i];
+  if (i >= 3) o ^= 1ull << pos[LB + (i - 3) % 3];
+  return o;
+}
+
+// Offsets of the slot bits a lane owns (bits 0..7 of its slot index).
+template <int LB>
+__device__ __forceinline__ uint64_t lane_slot_bits(cptr<uint32_t> pos, uint32_t m) {
   uint64_t r = 0;
-  for (uint32_t j = 0; j < 8 && LB + j < m; ++j)
-    if ((threadIdx.x >> j) & 1u) r |= 1ull << pos[LB + j];
+  for (uint32_t j = 0; j < 8; ++j)
+    if ((threadIdx.x >> j) & 1u) r ^= slot_offset<LB>(pos, m, j);
   return r;
 }
 
-// Issue the loads of the whole tile into buf (no wait).
+// Issue the tile's loads straight into LDS (global_load_lds_dwordx4): slot e
+// of the tile receives tile element swz(e), so the tile lands in LDS in its
+// swizzled layout without passing through registers.  Each instruction of a
+// wave writes 1 KiB of consecutive slots; its 64 lanes read whole 128-byte
+// lines (the swizzle permutes elements within a line).  No wait.
 template <typename R>
-__device__ __forceinline__ void tile_load(const TileRef<R>& T, typename gelem<R>::G* buf) {
+__device__ __forceinline__ void tile_load_lds(const TileRef<R>& T, typename dev_elem<R>::E* tile) {
   typedef typename gelem<R>::G G;
   constexpr int LB = gelem<R>::LB;
   const cptr<PassDescDev> P = T.P;
-  const LaneGeo lg = lane_geo<LB>(P->m);
+  const uint32_t m = P->m;
+  const LaneGeo lg = lane_geo<LB>(m);
   const gptr<const G> gpsi = as_global(reinterpret_cast<const G*>(T.psi));
-  const uint64_t a0 = T.base | lane_bits<LB>(P->lpos, P->m);
-  PassOffsets po;
-  pass_offsets<LB>(P, &po);
-  // unpredicated: elements past the tile (small tiles) re-read the tile base,
-  // so the loads need no branches (and no waits between them)
-#define SV_LD(U)                                                                        \
-  {                                                                                     \
-    const uint64_t ad = (U < lg.per && lg.on) ? (a0 | batch_bits<U>(po.in)) : T.base;  \
-    buf[U] = ldg<G>(gpsi + (ad >> LB));                                                 \
-  }
-  SV_LD(0) SV_LD(1) SV_LD(2) SV_LD(3) SV_LD(4) SV_LD(5) SV_LD(6) SV_LD(7)
-  SV_LD(8) SV_LD(9) SV_LD(10) SV_LD(11) SV_LD(12) SV_LD(13) SV_LD(14) SV_LD(15)
-#undef SV_LD
-}
-
-template <typename R, int WB>
-__device__ __forceinline__ void batch_to_lds(const typename gelem<R>::G* buf, uint32_t j0, const LaneGeo& lg,
-                                             typename dev_elem<R>::E* tile) {
-  typedef typename dev_elem<R>::E E;
-  constexpr int LB = gelem<R>::LB;
+  const uint64_t a0 = T.base | lane_slot_bits<LB>(P->lpos, m);
+  uint64_t hb[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) hb[b] = slot_offset<LB>(P->lpos, m, 8 + b);
+  // the wave's first slot of instruction u: uniform (the LDS destination of
+  // the instruction is wave-uniform; lanes land at consecutive 16 bytes)
+  const uint32_t wslot = (threadIdx.x & ~63u);
+  __attribute__((address_space(3))) G* lds = (__attribute__((address_space(3))) G*)tile;
 #pragma unroll
   for (int u = 0; u < kBatch; ++u)
-    if (j0 + u < lg.per && lg.on) {
-      const uint32_t x = (threadIdx.x + (j0 + u) * kBlock) << LB;
-      if constexpr (LB == 1) {
-        tile[swz<WB>(x)] = E{buf[u].x, buf[u].y};
-        tile[swz<WB>(x | 1u)] = E{buf[u].z, buf[u].w};
-      } else {
-        tile[swz<WB>(x)] = buf[u];
-      }
+    if ((uint32_t)u < lg.per && lg.on) {
+      uint64_t ad = a0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if ((u >> b) & 1) ad ^= hb[b];
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(gpsi + (ad >> LB)),
+                                       (__attribute__((address_space(3))) void*)(lds + wslot + u * kBlock), 16, 0,
+                                       0);
     }
 }
 
-// Write the loaded tile (at most 16 elements per lane: 64 KiB tiles) to LDS.
-template <typename R, int WB>
-__device__ __forceinline__ void tile_fill(const TileRef<R>& T, const typename gelem<R>::G* buf,
-                                          typename dev_elem<R>::E* tile) {
-  const LaneGeo lg = lane_geo<gelem<R>::LB>(T.P->m);
-  batch_to_lds<R, WB>(buf, 0, lg, tile);
-}
-
 // The pass's register stages on the tile in LDS (ends with a barrier).
-template <typename R, int WB, bool LP>
+template <typename R, bool LP>
 __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_elem<R>::E* tile) {
   typedef typename dev_elem<R>::E E;
+  constexpr int LB = gelem<R>::LB;
   const cptr<PassDescDev> P = T.P;
   const cptr<PassStageDev> stages = T.stages;
   const cptr<PassItemDev> items = T.items;
@@ -587,7 +588,7 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
     // the swizzled register bits are kept, not one offset per register
     uint32_t sbit[RB], cbit[RB];
 #pragma unroll
-    for (int b = 0; b < RB; ++b) sbit[b] = swz<WB>(1u << S.q[b]);
+    for (int b = 0; b < RB; ++b) sbit[b] = swz<LB>(1u << S.q[b]);
     // the store writes amplitude r to register index A r ^ c: bit j of r
     // moves the address by the swizzled image of column j
 #pragma unroll
@@ -605,7 +606,7 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
         const uint32_t q = S.qsort[b];
         xg = ((xg >> q) << (q + 1)) | (xg & ((1u << q) - 1u));
       }
-      const uint32_t sx = swz<WB>(xg);
+      const uint32_t sx = swz<LB>(xg);
       cplx<R> v[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -617,12 +618,25 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
         v[r] = cplx<R>{e.x, e.y};
       }
       if (S.flags & PSF_U2) op_u2<R>(v, mats + S.u2);
-      switch (S.form) {
-        case PFORM_UR: layer<PFORM_UR>(v, mats + S.slots); break;
-        case PFORM_UI: layer<PFORM_UI>(v, mats + S.slots); break;
-        case PFORM_RC: layer<PFORM_RC>(v, mats + S.slots); break;
-        case PFORM_U: layer<PFORM_U>(v, mats + S.slots); break;
-        default: break;
+      // the earlier layers (2x2s, then register factors), then the last one;
+      // one copy of the layer code serves all of them
+      const cptr<PassSubDev> subs = (cptr<PassSubDev>)((cptr<uint32_t>)(stages + (P->stage_first + si)) +
+                                                      offsetof(PassStageDev, sub) / 4);
+      for (uint32_t li = 0; li <= S.nsub; ++li) {
+        const bool last = li == S.nsub;
+        const PassSubDev L = last ? PassSubDev{S.form, S.slot_mask, S.slots, kPassNoTable} : cload(subs + li);
+        switch (L.form) {
+          case PFORM_UR: layer<PFORM_UR>(v, mats + L.slots, L.slot_mask); break;
+          case PFORM_UI: layer<PFORM_UI>(v, mats + L.slots, L.slot_mask); break;
+          case PFORM_RC: layer<PFORM_RC>(v, mats + L.slots, L.slot_mask); break;
+          case PFORM_U: layer<PFORM_U>(v, mats + L.slots, L.slot_mask); break;
+          default: break;
+        }
+        if (L.dr != kPassNoTable) {
+          const cptr<cplx<R>> D = mats + L.dr;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) v[r] = cmul(cget(D, r), v[r]);
+        }
       }
       if (S.flags & PSF_LANE) {
         lane_diag<R, LP>(S, items, mats, xg, base, tsum, v);
@@ -658,52 +672,48 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
         tile[o] = e;
       }
     }
-    __syncthreads();
+    lds_sync();
   }
 }
 
-// Store the tile: local bit j goes to physical position wpos[j], a
-// permutation of the positions the tile was loaded from.  When the lowest
-// element bits keep their positions lanes walk the tile in load order;
-// otherwise they walk the destination addresses in the load's order (the
-// same coalesced runs and 16-byte elements whatever the permutation) and
-// gather each element from LDS: the element's k-th address bit holds local
-// bit winv[k].
-template <typename R, int WB>
-__device__ __forceinline__ void tile_store(const TileRef<R>& T, const typename dev_elem<R>::E* tile) {
+// Read the tile for its store into registers: local bit j goes to physical
+// position wpos[j], a permutation of the positions the tile was loaded from.
+// When the lowest element bits keep their positions lanes walk the tile in
+// load order (element x = t + 256 u); otherwise they walk the destination
+// addresses in the load's order (the same coalesced runs and 16-byte
+// elements whatever the permutation) and gather each element from LDS: the
+// element's k-th address bit holds local bit winv[k].
+template <typename R>
+__device__ __forceinline__ void tile_gather(const TileRef<R>& T, const typename dev_elem<R>::E* tile,
+                                            typename gelem<R>::G* out) {
   typedef typename dev_elem<R>::E E;
   typedef typename gelem<R>::G G;
   constexpr int LB = gelem<R>::LB;
   const cptr<PassDescDev> P = T.P;
   const uint32_t m = P->m;
   const LaneGeo lg = lane_geo<LB>(m);
-  const gptr<G> gpsi = as_global(reinterpret_cast<G*>(T.psi));
-  const uint64_t a0 = T.base | lane_bits<LB>(P->lpos, m);
-  PassOffsets po;
-  pass_offsets<LB>(P, &po);
-  if (P->flags & kPassStoreLaneOrder) {  // load order: the low element bits stay in place
-    const uint64_t w0 = T.base | lane_bits<LB>(P->wpos, m);
-#define SV_ST(U)                                                                       \
-    if (U < lg.per && lg.on) {                                                         \
-      const uint32_t x = (threadIdx.x + U * kBlock) << LB;                             \
-      G g;                                                                             \
-      if constexpr (LB == 1) {                                                         \
-        const E e0 = tile[swz<WB>(x)], e1 = tile[swz<WB>(x | 1u)];                     \
-        g = G{e0.x, e0.y, e1.x, e1.y};                                                 \
-      } else {                                                                         \
-        g = tile[swz<WB>(x)];                                                          \
-      }                                                                                \
-      stg<G>(gpsi + ((w0 | batch_bits<U>(po.out)) >> LB), g);                          \
-    }
-    SV_ST(0) SV_ST(1) SV_ST(2) SV_ST(3) SV_ST(4) SV_ST(5) SV_ST(6) SV_ST(7)
-    SV_ST(8) SV_ST(9) SV_ST(10) SV_ST(11) SV_ST(12) SV_ST(13) SV_ST(14) SV_ST(15)
-#undef SV_ST
+  // an opaque copy of the thread index: the addresses below are recomputed
+  // per tile instead of being kept live (or spilled) across the whole loop
+  uint32_t tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  if (P->flags & kPassStoreLaneOrder) {
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if ((uint32_t)u < lg.per && lg.on) {
+        const uint32_t x = (tid + u * kBlock) << LB;
+        if constexpr (LB == 1) {
+          // both amplitudes of the element sit in one 16-byte LDS slot
+          out[u] = *reinterpret_cast<const G*>(tile + swz<LB>(x));
+        } else {
+          out[u] = tile[swz<LB>(x)];
+        }
+      }
     return;
   }
   // LDS index of the lane's element: lane bit j is address bit LB + j
   uint32_t xl = 0;
   for (uint32_t jb = 0; jb < 8 && LB + jb < m; ++jb)
-    if ((threadIdx.x >> jb) & 1u) xl |= 1u << P->winv[LB + jb];
+    if ((tid >> jb) & 1u) xl |= 1u << P->winv[LB + jb];
   uint32_t xo[4];  // LDS offsets of the batch bits
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
@@ -711,42 +721,89 @@ __device__ __forceinline__ void tile_store(const TileRef<R>& T, const typename d
     xo[b] = k < m ? 1u << P->winv[k] : 0u;
   }
   const uint32_t xp = LB ? 1u << P->winv[0] : 0u;  // the element's second amplitude (complex64)
-#define SV_ST(U)                                                                       \
-  if (U < lg.per && lg.on) {                                                           \
-    const uint32_t x = xl | batch_bits32<U>(xo);                                       \
-    G g;                                                                               \
-    if constexpr (LB == 1) {                                                           \
-      const E e0 = tile[swz<WB>(x)], e1 = tile[swz<WB>(x | xp)];                       \
-      g = G{e0.x, e0.y, e1.x, e1.y};                                                   \
-    } else {                                                                           \
-      g = tile[swz<WB>(x)];                                                            \
-    }                                                                                  \
-    stg<G>(gpsi + ((a0 | batch_bits<U>(po.in)) >> LB), g);                             \
-  }
-  SV_ST(0) SV_ST(1) SV_ST(2) SV_ST(3) SV_ST(4) SV_ST(5) SV_ST(6) SV_ST(7)
-  SV_ST(8) SV_ST(9) SV_ST(10) SV_ST(11) SV_ST(12) SV_ST(13) SV_ST(14) SV_ST(15)
-#undef SV_ST
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u)
+    if ((uint32_t)u < lg.per && lg.on) {
+      uint32_t x = xl;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if ((u >> b) & 1) x |= xo[b];
+      if constexpr (LB == 1) {
+        const E e0 = tile[swz<LB>(x)], e1 = tile[swz<LB>(x | xp)];
+        out[u] = G{e0.x, e0.y, e1.x, e1.y};
+      } else {
+        out[u] = tile[swz<LB>(x)];
+      }
+    }
 }
 
-// Persistent loop over tiles, software-pipelined: the next tile's loads are
-// in flight while the current tile runs its stages and is stored.  `next`
-// maps a global tile number to its TileRef.
-template <typename R, int WB, bool LP, typename Src>
+// Store the gathered elements: in load order to the wpos addresses of the
+// lane's element, or in destination order to the lpos addresses.
+template <typename R>
+__device__ __forceinline__ void tile_put(const TileRef<R>& T, const typename gelem<R>::G* g) {
+  typedef typename gelem<R>::G G;
+  constexpr int LB = gelem<R>::LB;
+  const cptr<PassDescDev> P = T.P;
+  const uint32_t m = P->m;
+  const LaneGeo lg = lane_geo<LB>(m);
+  const gptr<G> gpsi = as_global(reinterpret_cast<G*>(T.psi));
+  const cptr<uint32_t> pos = (P->flags & kPassStoreLaneOrder) ? P->wpos : P->lpos;
+  uint64_t a0 = T.base;
+  for (uint32_t j = 0; j < 8 && LB + j < m; ++j)
+    if ((threadIdx.x >> j) & 1u) a0 |= 1ull << pos[LB + j];
+  uint64_t hb[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) hb[b] = LB + 8 + b < (int)m ? 1ull << pos[LB + 8 + b] : 0ull;
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u)
+    if ((uint32_t)u < lg.per && lg.on) {
+      uint64_t ad = a0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if ((u >> b) & 1) ad |= hb[b];
+      stg<G>(gpsi + (ad >> LB), g[u]);
+    }
+}
+
+// s_waitcnt with only the vector-memory counter (gfx9 encoding: expcnt and
+// lgkmcnt at their no-wait values).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Persistent loop over tiles.  Per tile: the tile's loads land in LDS, the
+// stages run, the result is read back into registers, and after a barrier
+// the next tile's loads are issued before this tile's stores, so that the
+// wait for a tile's data never waits for the previous tile's stores (the
+// vector-memory counter retires in issue order).  The two blocks a CU holds
+// overlap one block's memory phase with the other's stages.
+template <typename R, bool LP, typename Src>
 __device__ __forceinline__ void tile_loop(uint64_t total, const Src& src, typename dev_elem<R>::E* tile) {
   typedef typename gelem<R>::G G;
   uint64_t g = xcd_block();
   if (g >= total) return;
-  G buf[kBatch];
-  tile_load<R>(src(g), buf);
+  tile_load_lds<R>(src(g), tile);
+  bool full_prev = false;  // the previous tile stored kBatch elements per lane
   while (true) {
     const uint64_t ng = g + gridDim.x;
-    const TileRef<R> cur = src(g);  // recomputed, not carried: fewer live registers
-    __syncthreads();  // the previous tile's store has read the buffer
-    tile_fill<R, WB>(cur, buf, tile);
-    __syncthreads();
-    if (ng < total) tile_load<R>(src(ng), buf);
-    tile_stages<R, WB, LP>(cur, tile);
-    tile_store<R, WB>(cur, tile);
+    const TileRef<R> cur = src(g);
+    // this tile's loads are older than the previous tile's stores: when that
+    // tile issued kBatch stores per lane, waiting until at most kBatch
+    // operations remain waits for exactly the loads
+    if (full_prev) wait_vm<kBatch>();
+    else wait_vm<0>();
+    lds_barrier();
+    tile_stages<R, LP>(cur, tile);
+    G out[kBatch];
+    tile_gather<R>(cur, tile, out);
+    wait_lgkm0();  // this lane's LDS reads are done
+    lds_barrier();
+    if (ng < total) tile_load_lds<R>(src(ng), tile);
+    asm volatile("" ::: "memory");  // the loads stay ahead of the stores
+    tile_put<R>(cur, out);
+    full_prev = lane_geo<gelem<R>::LB>(cur.P->m).per == (uint32_t)kBatch;
     if (ng >= total) break;
     g = ng;
   }
@@ -765,7 +822,7 @@ struct SingleSrc {
   }
 };
 
-template <typename R, int WB, bool LP>
+template <typename R, bool LP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pass(typename dev_elem<R>::E* __restrict__ psi, int n,
                                                  const PassDescDev* __restrict__ passes, int pi,
                                                  const PassStageDev* __restrict__ stages,
@@ -776,7 +833,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   E* tile = reinterpret_cast<E*>(smem);
   const cptr<PassDescDev> P = as_const(passes + pi);
   const SingleSrc<R> src{psi, n, P, as_const(stages), as_const(items), as_const(mats)};
-  tile_loop<R, WB, LP>(1ull << (n - P->m), src, tile);
+  tile_loop<R, LP>(1ull << (n - P->m), src, tile);
 }
 
 // Many states in one launch: work item i runs pass `pass` of its own program
@@ -802,43 +859,43 @@ struct BatchSrc {
   }
 };
 
-template <typename R, int WB, bool LP>
+template <typename R, bool LP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pass_batch(const BatchItemDev* __restrict__ items, int count,
                                                        uint64_t total_tiles) {
   typedef typename dev_elem<R>::E E;
   extern __shared__ __align__(16) unsigned char smem[];
   E* tile = reinterpret_cast<E*>(smem);
   const BatchSrc<R> src{as_const(items), count};
-  tile_loop<R, WB, LP>(total_tiles, src, tile);
+  tile_loop<R, LP>(total_tiles, src, tile);
 }
 
-template <typename R, int WB, bool LP>
+template <typename R, bool LP>
 hipError_t run(void* psi, int n, int m, const PassDescDev* passes, int pass, const PassStageDev* stages,
                const PassItemDev* items, const void* mats, hipStream_t s) {
   typedef typename dev_elem<R>::E E;
   const size_t lds = ((size_t)1 << m) * sizeof(E);
   static KernelLaunchCache cache;
   uint64_t resident = 0;
-  hipError_t e = prepare_launch(cache, (const void*)k_pass<R, WB, LP>, kBlock, lds, &resident);
+  hipError_t e = prepare_launch(cache, (const void*)k_pass<R, LP>, kBlock, lds, &resident);
   if (e != hipSuccess) return e;
   const uint64_t tiles = 1ull << (n - m);
   const uint64_t blocks = tiles < resident ? tiles : resident;
-  hipLaunchKernelGGL((k_pass<R, WB, LP>), dim3((unsigned)blocks), dim3(kBlock), lds, s, (E*)psi, n, passes, pass, stages,
+  hipLaunchKernelGGL((k_pass<R, LP>), dim3((unsigned)blocks), dim3(kBlock), lds, s, (E*)psi, n, passes, pass, stages,
                      items, (const cplx<R>*)mats);
   return hipGetLastError();
 }
 
-template <typename R, int WB, bool LP>
+template <typename R, bool LP>
 hipError_t run_batch(const BatchItemDev* items, int count, uint64_t total_tiles, int max_m, hipStream_t s) {
   typedef typename dev_elem<R>::E E;
   const size_t lds = ((size_t)1 << max_m) * sizeof(E);
   static KernelLaunchCache cache;
   uint64_t resident = 0;
-  hipError_t e = prepare_launch(cache, (const void*)k_pass_batch<R, WB, LP>, kBlock, lds, &resident);
+  hipError_t e = prepare_launch(cache, (const void*)k_pass_batch<R, LP>, kBlock, lds, &resident);
   if (e != hipSuccess) return e;
   if (total_tiles == 0) return hipSuccess;
   const uint64_t blocks = total_tiles < resident ? total_tiles : resident;
-  hipLaunchKernelGGL((k_pass_batch<R, WB, LP>), dim3((unsigned)blocks), dim3(kBlock), lds, s, items, count, total_tiles);
+  hipLaunchKernelGGL((k_pass_batch<R, LP>), dim3((unsigned)blocks), dim3(kBlock), lds, s, items, count, total_tiles);
   return hipGetLastError();
 }
 
@@ -848,19 +905,19 @@ hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* 
                        const PassStageDev* stages, const PassItemDev* items, const void* mats, bool ladders,
                        hipStream_t s) {
   if (dt == SV_C128)
-    return ladders ? run<double, 3, true>(psi, n, m, passes, pass, stages, items, mats, s)
-                   : run<double, 3, false>(psi, n, m, passes, pass, stages, items, mats, s);
-  return ladders ? run<float, 4, true>(psi, n, m, passes, pass, stages, items, mats, s)
-                 : run<float, 4, false>(psi, n, m, passes, pass, stages, items, mats, s);
+    return ladders ? run<double, true>(psi, n, m, passes, pass, stages, items, mats, s)
+                   : run<double, false>(psi, n, m, passes, pass, stages, items, mats, s);
+  return ladders ? run<float, true>(psi, n, m, passes, pass, stages, items, mats, s)
+                 : run<float, false>(psi, n, m, passes, pass, stages, items, mats, s);
 }
 
 hipError_t launch_pass_batch(sv_dtype dt, const BatchItemDev* items, int count, uint64_t total_tiles, int max_m,
                              bool ladders, hipStream_t s) {
   if (dt == SV_C128)
-    return ladders ? run_batch<double, 3, true>(items, count, total_tiles, max_m, s)
-                   : run_batch<double, 3, false>(items, count, total_tiles, max_m, s);
-  return ladders ? run_batch<float, 4, true>(items, count, total_tiles, max_m, s)
-                 : run_batch<float, 4, false>(items, count, total_tiles, max_m, s);
+    return ladders ? run_batch<double, true>(items, count, total_tiles, max_m, s)
+                   : run_batch<double, false>(items, count, total_tiles, max_m, s);
+  return ladders ? run_batch<float, true>(items, count, total_tiles, max_m, s)
+                 : run_batch<float, false>(items, count, total_tiles, max_m, s);
 }
 
 }  // namespace sv

@@ -171,6 +171,14 @@ struct LayerBuilder {
   uint32_t sel_local = 0;  // local bits that are permutation selectors
   int n_perm = 0;          // permutation gates composed
   int n_members = 0;
+  // earlier layers of the stage: their 2x2s and the diagonal gates (all on
+  // register bits) that follow them
+  struct SubLayer {
+    M2 slot[kPassRegBitsMax];
+    bool on[kPassRegBitsMax];
+    std::vector<Op> diag;
+  };
+  std::vector<SubLayer> subs;
 
   bool f32() const { return dt == SV_C64; }
 
@@ -190,6 +198,7 @@ struct LayerBuilder {
     sel_local = 0;
     n_perm = 0;
     n_members = 0;
+    subs.clear();
   }
 
   int reg(int physq) const {
@@ -251,6 +260,66 @@ struct LayerBuilder {
     for (int j = 0; j < rb; ++j) A[j] = f(A[j]);
     c0 = f(c0);
     for (auto& p : px) p.second = f(p.second);
+  }
+
+  bool perm_pending() const {
+    if (c0 != 0 || !px.empty()) return true;
+    for (int j = 0; j < rb; ++j)
+      if (A[j] != (1u << j)) return true;
+    return false;
+  }
+
+  // A single-qubit gate on q that must follow diagonal gates of the stage on
+  // q: when q and every qubit of those gates can be register bits (and no
+  // permutation is pending), the layer so far and the diagonal gates on
+  // register bits close an earlier layer of the stage (its 2x2s, then their
+  // register factors) and the gate opens the next; false: close the stage.
+  bool start_sub_layer(int q) {
+    if ((int)subs.size() >= kPassSubMax || perm_pending()) return false;
+    // register bits for q and for the qubits the gates on q share with it
+    std::vector<int> need = {q};
+    for (const Op& d : diag) {
+      bool on_q = false;
+      for (int i = 0; i < d.nq; ++i) on_q = on_q || d.q[i] == q;
+      if (!on_q) continue;
+      for (int i = 0; i < d.nq; ++i) need.push_back(d.q[i]);
+    }
+    int missing = 0;
+    for (size_t i = 0; i < need.size(); ++i) {
+      bool dup = false;
+      for (size_t k = 0; k < i; ++k) dup = dup || need[k] == need[i];
+      if (dup || reg(need[i]) >= 0) continue;
+      const int l = loc[need[i]];
+      if (l < 0 || ((sel_local >> l) & 1u)) return false;
+      ++missing;
+    }
+    if ((int)qs.size() + missing > rb) return false;
+    for (int x : need)
+      if (reg(x) < 0) want_reg(x);
+    SubLayer sl;
+    for (int r = 0; r < kPassRegBitsMax; ++r) {
+      sl.slot[r] = slot[r];
+      sl.on[r] = slot_on[r];
+      slot[r] = kIdentity2;
+      slot_on[r] = false;
+    }
+    // the diagonal gates on register bits move into the earlier layer; the
+    // others stay pending (they commute with the gate on q)
+    std::vector<Op> rest;
+    diag_q = 0;
+    for (Op& d : diag) {
+      bool all_reg = true;
+      for (int i = 0; i < d.nq; ++i) all_reg = all_reg && reg(d.q[i]) >= 0;
+      if (all_reg) {
+        sl.diag.push_back(std::move(d));
+      } else {
+        diag_q |= qubit_mask(d);
+        rest.push_back(std::move(d));
+      }
+    }
+    diag = std::move(rest);
+    subs.push_back(std::move(sl));
+    return true;
   }
 
   bool is_perm_gate(const Op& op) const {
@@ -335,7 +404,12 @@ struct LayerBuilder {
     // single-qubit, not diagonal: the 2x2 of its register bit
     const int q = op.q[0];
     int j = reg(q);
-    bool conflict = ((diag_q >> q) & 1ull) || (j >= 0 && ((moved() >> j) & 1u));
+    const bool moved_q = j >= 0 && ((moved() >> j) & 1u);
+    bool conflict = ((diag_q >> q) & 1ull) || moved_q;
+    if (conflict && !moved_q && start_sub_layer(q)) {
+      conflict = false;
+      j = reg(q);
+    }
     if (!conflict && j < 0) {
       j = want_reg(q);
       conflict = j < 0;
@@ -688,8 +762,34 @@ struct LayerBuilder {
     for (int r = 0; r < rb; ++r)
       if (slot_on[r]) {
         form = join_form(form, form_of(slot[r]));
+        sh->slot_mask |= 1u << r;
         ++n_slots;
       }
+    // earlier layers: 2x2s, then the factors of their diagonal gates
+    int n_sub_ops = 0;
+    sh->nsub = (uint32_t)subs.size();
+    for (size_t k = 0; k < subs.size(); ++k) {
+      const SubLayer& sl = subs[k];
+      PassSubDev sd{PFORM_NONE, 0, 0, kPassNoTable};
+      std::vector<cd> e;
+      for (int r = 0; r < rb; ++r) {
+        if (sl.on[r]) {
+          sd.form = join_form(sd.form, form_of(sl.slot[r]));
+          sd.slot_mask |= 1u << r;
+          ++n_sub_ops;
+        }
+        e.insert(e.end(), sl.slot[r].begin(), sl.slot[r].end());
+      }
+      sd.slots = push_entries(sh, e.data(), e.size());
+      if (!sl.diag.empty()) {
+        std::vector<cd> dr(1u << rb, cd(1.0, 0.0));
+        bool any = false;
+        for (const Op& d : sl.diag) encode_exact(sh, d, &dr, &any);
+        sd.dr = push_entries(sh, dr.data(), dr.size());
+        ++n_sub_ops;
+      }
+      sh->sub[k] = sd;
+    }
     if (n_slots) {
       // absent 2x2s are identities, which every form holds
       sh->form = form;
@@ -716,7 +816,8 @@ struct LayerBuilder {
     }
     if (perm) sh->flags |= PSF_PERM;
     encode_rows(sh);
-    sh->n_ops = n_slots + (has_u2 ? 1 : 0) + ((sh->flags & PSF_DR) ? 1 : 0) + (int)sh->items.size() + n_perm;
+    sh->n_ops = n_sub_ops + n_slots + (has_u2 ? 1 : 0) + ((sh->flags & PSF_DR) ? 1 : 0) + (int)sh->items.size() +
+                n_perm;
   }
 
   void close() {
@@ -752,8 +853,12 @@ std::vector<StageHost> build_stages(const std::vector<Op>& ops, const int* loc, 
 double stage_ops(const StageHost& sh, sv_dtype dt) {
   const int rb = pass_reg_bits(dt);
   double ops = (dt == SV_C64 ? 8.0 : 16.0);  // LDS read + write of every amplitude, barrier
-  ops += form_ops(sh.form) * rb;
+  ops += form_ops(sh.form) * __builtin_popcount(sh.slot_mask);
   if (sh.flags & PSF_U2) ops += 32.0;
+  for (uint32_t k = 0; k < sh.nsub; ++k) {
+    ops += form_ops(sh.sub[k].form) * __builtin_popcount(sh.sub[k].slot_mask);
+    if (sh.sub[k].dr != kPassNoTable) ops += 4.0;
+  }
   if (sh.flags & PSF_LANE) ops += 12.0 + 4.0 * (double)sh.items.size();
   else if (sh.flags & PSF_DR) ops += 4.0;
   return ops;

@@ -279,6 +279,13 @@ sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out) {
       for (int r = 0; r < rb; ++r) sd.qsort[r] = srt[r];
       const uint32_t mbase = (uint32_t)pool.size();
       sd.form = sh.form;
+      sd.slot_mask = sh.slot_mask;
+      sd.nsub = sh.nsub;
+      for (uint32_t k = 0; k < sh.nsub; ++k) {
+        sd.sub[k] = sh.sub[k];
+        sd.sub[k].slots += mbase;
+        if (sd.sub[k].dr != kPassNoTable) sd.sub[k].dr += mbase;
+      }
       sd.flags = sh.flags;
       sd.slots = mbase + sh.slots;
       sd.u2 = mbase + sh.u2;

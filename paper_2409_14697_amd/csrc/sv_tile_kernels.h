@@ -23,14 +23,18 @@ inline constexpr int pass_reg_bits(sv_dtype dt) { return dt == SV_C64 ? 5 : 4; }
 // A register stage of a tile pass applies, in this order (each part a block
 // of gates in program order that the planner proved may run in that order):
 //   1. optionally a dense 4x4 on register bits (1, 0)          (PSF_U2)
-//   2. one 2x2 on every register bit: the tensor product of a layer of
+//   2. nsub earlier layers (PassSubDev), each one 2x2 per register bit of
+//      its mask followed by a factor per register index: single-qubit gates
+//      separated by diagonal gates on register bits (the Hadamard and
+//      controlled-phase ladder of a QFT block, say) stay in registers
+//   3. one 2x2 on every register bit: the tensor product of a layer of
 //      single-qubit gates (identity on bits without a gate); `form` says
 //      which entries are nonzero or real, so the kernel runs the cheapest
 //      code that applies all of them
-//   3. a diagonal: a factor per register index (PSF_DR) times per-lane
+//   4. a diagonal: a factor per register index (PSF_DR) times per-lane
 //      factors of the lane items (PSF_LANE): phases and diagonal gates that
 //      involve bits outside the registers
-//   4. a permutation of the register index, r -> A r ^ c(lane) over GF(2)
+//   5. a permutation of the register index, r -> A r ^ c(lane) over GF(2)
 //      (X, CNOT, SWAP: PSF_PERM), which costs nothing: the stage's LDS store
 //      writes amplitude r to the address of register index A r ^ c(lane).
 enum PassForm : uint32_t {
@@ -106,6 +110,15 @@ struct alignas(16) PassItemDev {
 constexpr int kPassStageRowsMax = 256;
 constexpr uint32_t kPassRowAlways = 0xffffffffu;  // row descriptor: no gating tile bit
 
+// An earlier layer of a stage: 2x2s (form, mask and pool entry as for the
+// stage's last layer), then the register factors at pool entry `dr`
+// (kPassNoTable: none).
+constexpr int kPassSubMax = 4;
+constexpr uint32_t kPassNoTable = 0xffffffffu;
+struct PassSubDev {
+  uint32_t form, slot_mask, slots, dr;
+};
+
 struct alignas(16) PassStageDev {
   uint32_t q[kPassRegBitsMax];      // local bit of register bit r (r < rb)
   uint32_t qsort[kPassRegBitsMax];  // the same bits, ascending (group enumeration)
@@ -121,7 +134,9 @@ struct alignas(16) PassStageDev {
   uint32_t row_count;               // <= kPassStageRowsMax
   uint32_t pcol[kPassRegBitsMax];   // permutation: image of register bit j (A e_j)
   uint32_t pconst;                  // permutation: constant XOR
-  uint32_t pad[2];
+  uint32_t slot_mask;               // register bits whose 2x2 is not the identity
+  uint32_t nsub;                    // earlier layers (<= kPassSubMax)
+  PassSubDev sub[kPassSubMax];
 };
 
 // PassDescDev flag: the store can walk the tile in load order (the lowest

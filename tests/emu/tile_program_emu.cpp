@@ -237,6 +237,13 @@ int main() {
       }
       for (uint32_t si = 0; si < D->stage_count; ++si) {
         const PassStageDev S = *pr.stage(D->stage_first + si);
+        if (t == 0 && getenv("SV_EMU_DUMP")) {  // plan structure, for inspection
+          int ni[5] = {0, 0, 0, 0, 0};
+          for (uint32_t k = 0; k < S.item_count; ++k) ++ni[pr.item(S.item_first + k)->type % 5];
+          fprintf(stderr, "pass %zu stage %u: q=%u,%u,%u,%u,%u form %u mask %x flags %x items DG%d D1%d LP%d QG%d px %u rows %u\n",
+                  pi, si, S.q[0], S.q[1], S.q[2], S.q[3], RB > 4 ? S.q[4] : 0, S.form, S.slot_mask, S.flags, ni[0], ni[1],
+                  ni[2], ni[3], S.px_count, S.row_count);
+        }
         // tile sums of rows
         std::vector<uint64_t> ts(S.row_count);
         for (uint32_t j = 0; j < S.row_count; ++j) {
@@ -276,16 +283,25 @@ int main() {
               }
             }
           }
-          if (S.form != PFORM_NONE) {
+          // one layer: a 2x2 per register bit of the mask, in the layer's form
+          auto apply_layer = [&](uint32_t form, uint32_t slots, uint32_t mask) {
+            if (form == PFORM_NONE) return;
             for (int b = 0; b < RB; ++b) {
               cd mm[4];
-              for (int e = 0; e < 4; ++e) mm[e] = pr.entry(S.slots + 4 * b + e);
+              for (int e = 0; e < 4; ++e) mm[e] = pr.entry(slots + 4 * b + e);
               // the form must hold the entries
               for (int e = 0; e < 4; ++e) {
                 const bool diag = e == 0 || e == 3;
-                if (S.form == PFORM_UR && mm[e].imag() != 0) die("UR form with imaginary entry");
-                if (S.form == PFORM_UI && ((diag && mm[e].imag() != 0) || (!diag && mm[e].real() != 0))) die("UI form mismatch");
-                if (S.form == PFORM_RC && diag && mm[e].imag() != 0) die("RC form mismatch");
+                if (form == PFORM_UR && mm[e].imag() != 0) die("UR form with imaginary entry");
+                if (form == PFORM_UI && ((diag && mm[e].imag() != 0) || (!diag && mm[e].real() != 0))) die("UI form mismatch");
+                if (form == PFORM_RC && diag && mm[e].imag() != 0) die("RC form mismatch");
+              }
+              // the kernel skips the bits outside the mask: they must hold
+              // identities
+              if (!((mask >> b) & 1u)) {
+                if (mm[0] != cd(1.0) || mm[1] != cd(0.0) || mm[2] != cd(0.0) || mm[3] != cd(1.0))
+                  die("2x2 outside the slot mask is not the identity");
+                continue;
               }
               for (int r = 0; r < NR; ++r)
                 if (!((r >> b) & 1)) {
@@ -293,6 +309,18 @@ int main() {
                   v[r] = mm[0] * a0 + mm[1] * a1;
                   v[r | (1 << b)] = mm[2] * a0 + mm[3] * a1;
                 }
+            }
+          };
+          if (S.nsub > (uint32_t)kPassSubMax) die("too many earlier layers");
+          for (uint32_t li = 0; li <= S.nsub; ++li) {
+            const bool last = li == S.nsub;
+            const PassSubDev L = last ? PassSubDev{S.form, S.slot_mask, S.slots, kPassNoTable} : S.sub[li];
+            if (!last && L.form == PFORM_NONE && L.dr == kPassNoTable) die("empty earlier layer");
+            if (L.form == PFORM_NONE && L.slot_mask) die("slot mask without a form");
+            apply_layer(L.form, L.slots, L.slot_mask);
+            if (L.dr != kPassNoTable) {
+              if (last) die("last layer with its own table");
+              for (int r = 0; r < NR; ++r) v[r] *= pr.entry(L.dr + r);
             }
           }
           if (S.flags & PSF_LANE) {

@@ -169,8 +169,11 @@ def test_pass_plan_needs_few_passes_for_diagonal_ladders():
     # controlled phases need no locality: the QFT's passes are set by its H gates
     n = 20
     plan = B.Plan(n, "c64", qft_circuit(n), {"mode": "pass"})
-    kinds = [k for k, _, _ in plan.passes()]
-    assert kinds.count(1) <= 2
+    passes = plan.passes()
+    assert len(passes) <= 4
+    # two passes hold the H gates and their phase ladders (a third at most
+    # holds the last few gates)
+    assert sum(1 for k, ops, _ in passes if k == 1 and ops > 10) <= 2
 
 
 def test_fusion_qft_and_haar():

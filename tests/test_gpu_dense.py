@@ -79,12 +79,11 @@ def test_mfma_and_valu_agree_to_fp32(sv):
 
 @pytest.mark.parametrize("dtype,k", [("c128", 3), ("c128", 4), ("c128", 5), ("c128", 6),
                                      ("c64", 4), ("c64", 5), ("c64", 6)])
-def test_dense_register_direct_placements(sv, dtype, k):
-    """Placements whose lowest 128-byte line is covered by the column bits or
-    by the member bits a lane group owns: the matrix-core kernel that loads
-    its operands from HBM straight into registers (no LDS).  N=22, so that
-    waves loop over many column blocks (with the next block's loads in
-    flight) and k = 6 blocks share column blocks; against the oracle."""
+def test_dense_line_covering_placements(sv, dtype, k):
+    """Placements with the highest qubits, and with the lowest physical bits
+    (one 128-byte line) among the gate's qubits next to random higher ones:
+    N=22, so that the persistent blocks loop over many column tiles (with the
+    next tile's loads in flight); against the oracle."""
     n = 22
     rng = np.random.default_rng(70 + k)
     low = [0] if dtype == "c64" else [1, 0]  # member bits the lane groups own, at physical 0 (and 1)
