@@ -299,39 +299,56 @@ __device__ __forceinline__ uint32_t item_rows(const PassItemDev& it) {
 }
 
 // PIT_LP: the phase of the lane's amplitudes whose register bit `a` is 1:
-// the constant word, the row's tile sum (ts[0], the same in every lane) and
-// the words of the lane's set local group bits (xg has zeros at the
-// register positions).
+// the constant word and the words of the lane's set local group bits (xg
+// has zeros at the register positions) -- the lane's part, the same for
+// every tile -- plus the row's tile sum (ts[0], the same in every lane).
 template <typename R>
-__device__ __forceinline__ cplx<R> lp_phase(const PassItemDev& it, cptr<cplx<R>> M, uint32_t xg,
-                                            const typename lp_word<R>::W* ts) {
+__device__ __forceinline__ typename lp_word<R>::W lp_lane_part(const PassItemDev& it, cptr<cplx<R>> M, uint32_t xg) {
   typedef typename lp_word<R>::W W;
   const cptr<W> words = (cptr<W>)M;
-  return lp_word<R>::phase(words[kPassLPConst] + ts[0] + lp_local<R>(words, xg & it.lmask));
+  return words[kPassLPConst] + lp_local<R>(words, xg & it.lmask);
 }
 
 // PIT_QG: row 0 and the constant, then the rows of the local targets set in
-// the lane (tile sum ts[k] plus the row's local words), then the tile-target
-// rows (their tile sums are zero unless the target bit is set).
+// the lane, then the tile-target rows (their tile sums are zero unless the
+// target bit is set).  The lane's part is the constant and the local words
+// of row 0 and of the set local targets' rows; the tile part is the tile
+// sums of row 0, of those rows and of the tile-target rows.
 template <typename R>
-__device__ __forceinline__ cplx<R> qg_phase(const PassItemDev& it, cptr<cplx<R>> M, uint32_t xg,
-                                            const typename lp_word<R>::W* ts) {
+__device__ __forceinline__ typename lp_word<R>::W qg_lane_part(const PassItemDev& it, cptr<cplx<R>> M, uint32_t xg) {
   typedef typename lp_word<R>::W W;
   cptr<W> words = (cptr<W>)M;
   const uint32_t lsel = xg & it.lmask;
-  W t = words[kPassLPConst] + ts[0] + lp_local<R>(words, lsel);
-  uint32_t k = 1;
+  W t = words[kPassLPConst] + lp_local<R>(words, lsel);
 #pragma unroll 1
-  for (uint32_t lt = it.a; lt; lt &= lt - 1u, ++k) {
+  for (uint32_t lt = it.a; lt; lt &= lt - 1u) {
     words += kPassLPWords;
-    const W h = ts[k] + lp_local<R>(words, lsel);
+    const W h = lp_local<R>(words, lsel);
     t += ((xg >> __builtin_ctz(lt)) & 1u) ? h : W(0);
   }
+  return t;
+}
+template <typename R>
+__device__ __forceinline__ typename lp_word<R>::W qg_tile_part(const PassItemDev& it, uint32_t xg,
+                                                                const typename lp_word<R>::W* ts) {
+  typedef typename lp_word<R>::W W;
+  W t = ts[0];
+  uint32_t k = 1;
+#pragma unroll 1
+  for (uint32_t lt = it.a; lt; lt &= lt - 1u, ++k) t += ((xg >> __builtin_ctz(lt)) & 1u) ? ts[k] : W(0);
   const uint32_t end = item_rows(it);
 #pragma unroll 1
   for (; k < end; ++k) t += ts[k];
-  return lp_word<R>::phase(t);
+  return t;
 }
+
+// Fixed-point phase items whose lane parts a block computes once, before its
+// tiles (k_pass): pre[k][t] holds the lane part of the pass's k-th such item
+// for thread t.  Later items compute theirs per tile.
+template <typename R>
+struct pre_cap {
+  static constexpr int N = sizeof(R) == 4 ? 14 : 6;
+};
 
 // Tile sums of the stage's fixed-point rows into ts[] (all threads; ends
 // with a barrier).  Each thread sums whole rows: its 34 tile words are
@@ -391,7 +408,9 @@ __device__ __forceinline__ cplx<R> pick(cptr<cplx<R>> T, uint32_t var, int n) {
 template <typename R, bool LP>
 __device__ __forceinline__ void lane_diag(const PassStageDev& S, cptr<PassItemDev> items, cptr<cplx<R>> mats,
                                           uint32_t xg, uint64_t base, const typename lp_word<R>::W* ts,
+                                          const typename lp_word<R>::W* pre, uint32_t npre, uint32_t* kfix,
                                           cplx<R>* v) {
+  typedef typename lp_word<R>::W W;
   constexpr int RB = Regs<R>::RB, NR = Regs<R>::NR, HALF = NR / 2;
   const cplx<R> one = {R(1), R(0)};
   cplx<R> G = one, f0[RB], f1[RB];
@@ -414,13 +433,17 @@ __device__ __forceinline__ void lane_diag(const PassStageDev& S, cptr<PassItemDe
           f1[b] = cmul(f1[b], e1);
         }
     } else if (LP && it.type == PIT_LP) {
-      const cplx<R> p = lp_phase<R>(it, T, xg, ts + row);
+      const W lane = *kfix < npre ? pre[*kfix * kBlock + threadIdx.x] : lp_lane_part<R>(it, T, xg);
+      ++*kfix;
+      const cplx<R> p = lp_word<R>::phase(lane + ts[row]);
 #pragma unroll
       for (int b = 0; b < RB; ++b)
         if (it.a == (uint32_t)b) f1[b] = cmul(f1[b], p);
       row += 1;
     } else if (LP && it.type == PIT_QG) {
-      G = cmul(G, qg_phase<R>(it, T, xg, ts + row));
+      const W lane = *kfix < npre ? pre[*kfix * kBlock + threadIdx.x] : qg_lane_part<R>(it, T, xg);
+      ++*kfix;
+      G = cmul(G, lp_word<R>::phase(lane + qg_tile_part<R>(it, xg, ts + row)));
       row += item_rows(it);
     }
   }
@@ -563,8 +586,47 @@ __device__ __forceinline__ void tile_load_lds(const TileRef<R>& T, typename dev_
 }
 
 // The pass's register stages on the tile in LDS (ends with a barrier).
+// The lane's group index in a stage: thread t's group with zeros inserted at
+// the register bits (ascending positions qsort).
+template <int RB>
+__device__ __forceinline__ uint32_t group_bits(uint32_t gi, const uint32_t* qsort) {
+  uint32_t xg = gi;
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const uint32_t q = qsort[b];
+    xg = ((xg >> q) << (q + 1)) | (xg & ((1u << q) - 1u));
+  }
+  return xg;
+}
+
+// Lane parts of the pass's first fixed-point phase items (at most cap) into
+// pre[k * kBlock + t]; returns how many.  Valid when every thread owns at
+// most one group per stage (tiles of at most kBlock groups), as in k_pass.
+template <typename R>
+__device__ __forceinline__ uint32_t pre_fill(cptr<PassDescDev> P, cptr<PassStageDev> stages, cptr<PassItemDev> items,
+                                             cptr<cplx<R>> mats, typename lp_word<R>::W* pre, uint32_t cap) {
+  constexpr int RB = Regs<R>::RB;
+  const uint32_t groups = (1u << P->m) >> RB, t = threadIdx.x;
+  uint32_t k = 0;
+  for (uint32_t si = 0; si < P->stage_count && k < cap; ++si) {
+    const PassStageDev S = cload(stages + (P->stage_first + si));
+    if (!(S.flags & PSF_LANE)) continue;
+    const uint32_t xg = group_bits<RB>(t, S.qsort);
+    for (uint32_t i = 0; i < S.item_count && k < cap; ++i) {
+      const PassItemDev it = cload(items + (S.item_first + i));
+      if (it.type != PIT_LP && it.type != PIT_QG) continue;
+      if (t < groups)
+        pre[k * kBlock + t] = it.type == PIT_LP ? lp_lane_part<R>(it, mats + it.mat, xg)
+                                                : qg_lane_part<R>(it, mats + it.mat, xg);
+      ++k;
+    }
+  }
+  return k;
+}
+
 template <typename R, bool LP>
-__device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_elem<R>::E* tile) {
+__device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_elem<R>::E* tile,
+                                            const typename lp_word<R>::W* pre, uint32_t npre) {
   typedef typename dev_elem<R>::E E;
   constexpr int LB = gelem<R>::LB;
   const cptr<PassDescDev> P = T.P;
@@ -577,6 +639,7 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
   constexpr int RB = Regs<R>::RB, NR = Regs<R>::NR;
   typedef typename lp_word<R>::W W;
   __shared__ W tsum[LP ? kPassStageRowsMax : 1];  // tile sums of the stage's fixed-point rows
+  uint32_t kfix = 0;  // fixed-point phase items of the pass so far
   for (uint32_t si = 0; si < P->stage_count; ++si) {
     const PassStageDev S = cload(stages + (P->stage_first + si));
     if constexpr (LP) {
@@ -599,13 +662,17 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
         if ((S.pcol[j] >> b) & 1u) o ^= sbit[b];
       cbit[j] = o;
     }
+    // fixed-point items of this stage (every group of the stage walks them)
+    uint32_t nfix = 0;
+    if constexpr (LP) {
+      if (S.flags & PSF_LANE)
+        for (uint32_t i = 0; i < S.item_count; ++i) {
+          const uint32_t ty = items[S.item_first + i].type;
+          nfix += ty == PIT_LP || ty == PIT_QG;
+        }
+    }
     for (uint32_t gi = t; gi < groups; gi += kBlock) {
-      uint32_t xg = gi;
-#pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        const uint32_t q = S.qsort[b];
-        xg = ((xg >> q) << (q + 1)) | (xg & ((1u << q) - 1u));
-      }
+      const uint32_t xg = group_bits<RB>(gi, S.qsort);
       const uint32_t sx = swz<LB>(xg);
       cplx<R> v[NR];
 #pragma unroll
@@ -639,7 +706,8 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
         }
       }
       if (S.flags & PSF_LANE) {
-        lane_diag<R, LP>(S, items, mats, xg, base, tsum, v);
+        uint32_t kf = kfix;
+        lane_diag<R, LP>(S, items, mats, xg, base, tsum, pre, npre, &kf, v);
       } else if (S.flags & PSF_DR) {
         const cptr<cplx<R>> D = mats + S.dr;
 #pragma unroll
@@ -672,6 +740,7 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
         tile[o] = e;
       }
     }
+    kfix += nfix;
     lds_sync();
   }
 }
@@ -780,7 +849,8 @@ __device__ __forceinline__ void wait_vm() {
 // vector-memory counter retires in issue order).  The two blocks a CU holds
 // overlap one block's memory phase with the other's stages.
 template <typename R, bool LP, typename Src>
-__device__ __forceinline__ void tile_loop(uint64_t total, const Src& src, typename dev_elem<R>::E* tile) {
+__device__ __forceinline__ void tile_loop(uint64_t total, const Src& src, typename dev_elem<R>::E* tile,
+                                          const typename lp_word<R>::W* pre, uint32_t npre) {
   typedef typename gelem<R>::G G;
   uint64_t g = xcd_block();
   if (g >= total) return;
@@ -795,7 +865,7 @@ __device__ __forceinline__ void tile_loop(uint64_t total, const Src& src, typena
     if (full_prev) wait_vm<kBatch>();
     else wait_vm<0>();
     lds_barrier();
-    tile_stages<R, LP>(cur, tile);
+    tile_stages<R, LP>(cur, tile, pre, npre);
     G out[kBatch];
     tile_gather<R>(cur, tile, out);
     wait_lgkm0();  // this lane's LDS reads are done
@@ -833,7 +903,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   E* tile = reinterpret_cast<E*>(smem);
   const cptr<PassDescDev> P = as_const(passes + pi);
   const SingleSrc<R> src{psi, n, P, as_const(stages), as_const(items), as_const(mats)};
-  tile_loop<R, LP>(1ull << (n - P->m), src, tile);
+  typedef typename lp_word<R>::W W;
+  // lane parts of the fixed-point phase items, computed once for all tiles
+  __shared__ W pre[LP ? pre_cap<R>::N * kBlock : 1];
+  uint32_t npre = 0;
+  if constexpr (LP) {
+    npre = pre_fill<R>(P, as_const(stages), as_const(items), as_const(mats), pre, pre_cap<R>::N);
+    wait_lgkm0();  // the table is complete before the first tile's barrier
+  }
+  tile_loop<R, LP>(1ull << (n - P->m), src, tile, pre, npre);
 }
 
 // Many states in one launch: work item i runs pass `pass` of its own program
@@ -866,7 +944,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   extern __shared__ __align__(16) unsigned char smem[];
   E* tile = reinterpret_cast<E*>(smem);
   const BatchSrc<R> src{as_const(items), count};
-  tile_loop<R, LP>(total_tiles, src, tile);
+  tile_loop<R, LP>(total_tiles, src, tile, nullptr, 0);
 }
 
 template <typename R, bool LP>
