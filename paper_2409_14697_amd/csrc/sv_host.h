@@ -89,7 +89,7 @@ struct StageHost {
   uint32_t slots = 0, u2 = 0, dr = 0;       // entries of `mats`
   std::vector<PassItemDev> items;           // lane items (.mat indexes `mats`)
   std::vector<PassItemDev> px;              // permutation terms (PIT_PX)
-  uint32_t pcol[kPassRegBitsMax] = {1, 2, 4, 8, 16};  // register permutation, columns
+  uint32_t colimg[kPassLocalMax] = {};     // store map: column images (local masks)
   uint32_t pconst = 0;
   std::vector<cd> mats;
   std::vector<uint8_t> raw;                 // per entry: 1 = two raw words (write_pool)

@@ -652,16 +652,22 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
     uint32_t sbit[RB], cbit[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) sbit[b] = swz<LB>(1u << S.q[b]);
-    // the store writes amplitude r to register index A r ^ c: bit j of r
-    // moves the address by the swizzled image of column j
+    // the store writes local index x to M x ^ c: register bit j of an
+    // amplitude moves its address by the swizzled image of column q[j]
 #pragma unroll
     for (int j = 0; j < RB; ++j) {
-      uint32_t o = 0;
+      uint32_t img = 0;
 #pragma unroll
-      for (int b = 0; b < RB; ++b)
-        if ((S.pcol[j] >> b) & 1u) o ^= sbit[b];
-      cbit[j] = o;
+      for (int l = 0; l < kPassLocalMax; ++l) img = (uint32_t)l == S.q[j] ? S.colimg[l] : img;
+      cbit[j] = __builtin_amdgcn_readfirstlane(swz<LB>(img));
     }
+    // the constant of the map for this tile (the terms selected by tile bits)
+    uint32_t cmap = S.pconst;
+    for (uint32_t k = 0; k < S.px_count; ++k) {
+      const PassItemDev it = cload(items + (S.px_first + k));
+      if (sel_bit(it.sel & 0xffu, 0u, base)) cmap ^= it.a;
+    }
+    const bool xperm = (S.flags & PSF_XPERM) != 0;
     // fixed-point items of this stage (every group of the stage walks them)
     uint32_t nfix = 0;
     if constexpr (LP) {
@@ -671,8 +677,10 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
           nfix += ty == PIT_LP || ty == PIT_QG;
         }
     }
-    for (uint32_t gi = t; gi < groups; gi += kBlock) {
-      const uint32_t xg = group_bits<RB>(gi, S.qsort);
+    // a tile holds at most kBlock groups: one per thread
+    const bool own = t < groups;
+    {
+      const uint32_t xg = own ? group_bits<RB>(t, S.qsort) : 0u;
       const uint32_t sx = swz<LB>(xg);
       cplx<R> v[NR];
 #pragma unroll
@@ -681,7 +689,7 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
 #pragma unroll
         for (int b = 0; b < RB; ++b)
           if ((r >> b) & 1) o ^= sbit[b];
-        const E e = tile[o];
+        const E e = own ? tile[o] : E{};
         v[r] = cplx<R>{e.x, e.y};
       }
       if (S.flags & PSF_U2) op_u2<R>(v, mats + S.u2);
@@ -713,16 +721,18 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = cmul(cget(D, r), v[r]);
       }
-      // register index of amplitude 0 after the permutation
-      uint32_t c = S.pconst;
-      for (uint32_t k = 0; k < S.px_count; ++k) {
-        const PassItemDev it = cload(items + (S.px_first + k));
-        if (sel_bit(it.sel & 0xffu, xg, base)) c ^= it.a;
-      }
+      // address of the group's register index 0 after the map: M xg ^ c
       uint32_t so = sx;
+      if (S.flags & PSF_PERM) {
+        uint32_t y = cmap;
 #pragma unroll
-      for (int b = 0; b < RB; ++b)
-        if ((c >> b) & 1u) so ^= sbit[b];
+        for (int l = 0; l < kPassLocalMax; ++l)
+          if ((xg >> l) & 1u) y ^= S.colimg[l];
+        so = swz<LB>(y);
+      }
+      // a map that moves amplitudes between groups writes after every
+      // group has been read
+      if (xperm) lds_sync();
       // The store recomputes the offsets from opaque copies of the inputs, so
       // the compiler cannot keep NR offsets live across the stage's work.
       asm volatile("" : "+v"(so));
@@ -737,7 +747,7 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
 #pragma unroll
         for (int b = 0; b < RB; ++b)
           if ((r >> b) & 1) o ^= cbit[b];
-        tile[o] = e;
+        if (own) tile[o] = e;
       }
     }
     kfix += nfix;

@@ -165,10 +165,11 @@ struct LayerBuilder {
   bool slot_on[kPassRegBitsMax] = {};
   std::vector<Op> diag;  // diagonal gates (physical qubits), program order
   uint64_t diag_q = 0;   // physical qubits of the diagonal gates
-  uint32_t A[kPassRegBitsMax];  // permutation r -> A r ^ c0 ^ (px terms): columns
-  uint32_t c0 = 0;
-  std::vector<std::pair<uint32_t, uint32_t>> px;  // (selector code, register mask)
-  uint32_t sel_local = 0;  // local bits that are permutation selectors
+  // the stage's store map of the local index, x -> M x ^ cl ^ (tile terms)
+  // over GF(2): the X, CNOT and SWAP gates of the stage
+  uint32_t Mc[kPassLocalMax];  // column images (local masks)
+  uint32_t cl = 0;
+  std::vector<std::pair<uint32_t, uint32_t>> tterms;  // (tile selector code, local mask)
   int n_perm = 0;          // permutation gates composed
   int n_members = 0;
   // earlier layers of the stage: their 2x2s and the diagonal gates (all on
@@ -189,13 +190,12 @@ struct LayerBuilder {
     for (int r = 0; r < kPassRegBitsMax; ++r) {
       slot[r] = kIdentity2;
       slot_on[r] = false;
-      A[r] = 1u << r;
     }
+    for (int l = 0; l < kPassLocalMax; ++l) Mc[l] = 1u << l;
     diag.clear();
     diag_q = 0;
-    c0 = 0;
-    px.clear();
-    sel_local = 0;
+    cl = 0;
+    tterms.clear();
     n_perm = 0;
     n_members = 0;
     subs.clear();
@@ -214,23 +214,25 @@ struct LayerBuilder {
     return l >= 0 ? (uint32_t)l : kPassTileSel + (uint32_t)physq;
   }
 
-  // register bits the permutation involves (as a source or a destination)
+  // local bits whose value the store map may change
+  uint32_t unstable() const {
+    uint32_t un = cl;
+    for (const auto& t : tterms) un |= t.second;
+    for (int l = 0; l < m; ++l) un |= Mc[l] & ~(1u << l);  // bits that receive another bit
+    for (int l = 0; l < m; ++l)
+      if (!((Mc[l] >> l) & 1u)) un |= 1u << l;
+    return un;
+  }
+  // local bits the store map involves (their value changes or is read)
   uint32_t moved() const {
-    uint32_t mv = c0;
-    for (const auto& t : px) mv |= t.second;
-    for (int j = 0; j < rb; ++j)
-      if (A[j] != (1u << j)) mv |= (1u << j) | A[j];
+    uint32_t mv = unstable();
+    for (int l = 0; l < m; ++l)
+      if (Mc[l] != (1u << l)) mv |= 1u << l;
     return mv;
   }
-  // register bits whose value the permutation may change
-  uint32_t unstable() const {
-    uint32_t un = c0;
-    for (const auto& t : px) un |= t.second;
-    for (int j = 0; j < rb; ++j) {
-      un |= A[j] & ~(1u << j);
-      if (!((A[j] >> j) & 1u)) un |= 1u << j;
-    }
-    return un;
+  bool local_moved(int physq) const {
+    const int l = loc[physq];
+    return l >= 0 && ((moved() >> l) & 1u);
   }
 
   // The register bit of local qubit `physq`, taking a free one if needed;
@@ -239,33 +241,34 @@ struct LayerBuilder {
     const int j = reg(physq);
     if (j >= 0) return j;
     const int l = loc[physq];
-    if (l < 0 || (int)qs.size() >= rb || ((sel_local >> l) & 1u)) return -1;
+    if (l < 0 || (int)qs.size() >= rb) return -1;
     qs.push_back(l);
     return (int)qs.size() - 1;
   }
 
-  // Compose the permutation with a linear map of the register index that
-  // flips bit t when bit c is set (a CNOT on register bits).
+  // Compose the store map with a row operation on the local index: bit t
+  // flips when bit c is set (a CNOT on local bits), or with a swap of two
+  // local bits.
   void compose_cx(int c, int t) {
     auto f = [&](uint32_t x) { return ((x >> c) & 1u) ? x ^ (1u << t) : x; };
-    for (int j = 0; j < rb; ++j) A[j] = f(A[j]);
-    c0 = f(c0);
-    for (auto& p : px) p.second = f(p.second);
+    for (int l = 0; l < m; ++l) Mc[l] = f(Mc[l]);
+    cl = f(cl);
+    for (auto& p : tterms) p.second = f(p.second);
   }
   void compose_swap(int a, int b) {
     auto f = [&](uint32_t x) {
       const uint32_t xa = (x >> a) & 1u, xb = (x >> b) & 1u;
       return (x & ~((1u << a) | (1u << b))) | (xa << b) | (xb << a);
     };
-    for (int j = 0; j < rb; ++j) A[j] = f(A[j]);
-    c0 = f(c0);
-    for (auto& p : px) p.second = f(p.second);
+    for (int l = 0; l < m; ++l) Mc[l] = f(Mc[l]);
+    cl = f(cl);
+    for (auto& p : tterms) p.second = f(p.second);
   }
 
   bool perm_pending() const {
-    if (c0 != 0 || !px.empty()) return true;
-    for (int j = 0; j < rb; ++j)
-      if (A[j] != (1u << j)) return true;
+    if (cl != 0 || !tterms.empty()) return true;
+    for (int l = 0; l < m; ++l)
+      if (Mc[l] != (1u << l)) return true;
     return false;
   }
 
@@ -289,8 +292,7 @@ struct LayerBuilder {
       bool dup = false;
       for (size_t k = 0; k < i; ++k) dup = dup || need[k] == need[i];
       if (dup || reg(need[i]) >= 0) continue;
-      const int l = loc[need[i]];
-      if (l < 0 || ((sel_local >> l) & 1u)) return false;
+      if (loc[need[i]] < 0) return false;
       ++missing;
     }
     if ((int)qs.size() + missing > rb) return false;
@@ -326,69 +328,38 @@ struct LayerBuilder {
     return op.kind == SV_G_X || op.kind == SV_G_CNOT || op.kind == SV_G_SWAP;
   }
 
-  // Try to add a permutation gate to the current stage; false: close first
-  // (a fresh stage always takes it).
-  bool add_perm(const Op& op) {
-    const int free = rb - (int)qs.size();
+  // Add a permutation gate to the current stage's store map (its targets
+  // are local bits of the pass; a CNOT's control may be a tile bit, which
+  // makes a term of the map selected per tile).  Always possible: the map
+  // needs no register bits.
+  void add_perm(const Op& op) {
     if (op.kind == SV_G_X) {
-      const int j = want_reg(op.q[0]);
-      if (j < 0) return false;
-      c0 ^= 1u << j;
-      return true;
+      cl ^= 1u << loc[op.q[0]];
+      return;
     }
     if (op.kind == SV_G_SWAP) {
-      if ((reg(op.q[0]) < 0) + (reg(op.q[1]) < 0) > free) return false;
-      const int a = want_reg(op.q[0]);
-      if (a < 0) return false;
-      const int b = want_reg(op.q[1]);
-      if (b < 0) return false;
-      compose_swap(a, b);
-      return true;
+      compose_swap(loc[op.q[0]], loc[op.q[1]]);
+      return;
     }
-    // CNOT: control q[0], target q[1].  A control outside the registers
-    // becomes a permutation term selected by its bit; a local one is then a
-    // selector, and the register padding needs rb local bits that are not.
-    const int c = op.q[0], lc = loc[c];
-    int jc = reg(c);
-    bool new_sel = jc < 0 && lc >= 0 && !((sel_local >> lc) & 1u);
-    const bool ctrl_reg = new_sel && m - (__builtin_popcount(sel_local) + 1) < rb;
-    if (ctrl_reg) new_sel = false;
-    if ((reg(op.q[1]) < 0) + (ctrl_reg ? 1 : 0) > free) return false;
-    if (ctrl_reg) {
-      jc = want_reg(c);
-      if (jc < 0) return false;
-    }
-    const int jt = want_reg(op.q[1]);
-    if (jt < 0) return false;
-    if (jc >= 0) {
-      compose_cx(jc, jt);
-    } else {
-      px.push_back({src(c), 1u << jt});
-      if (new_sel) sel_local |= 1u << lc;
-    }
-    return true;
+    const int c = op.q[0], lt = loc[op.q[1]];  // CNOT: control q[0], target q[1]
+    if (loc[c] >= 0) compose_cx(loc[c], lt);
+    else tterms.push_back({src(c), 1u << lt});
   }
 
   void add(const Op& op) {
     const OpClass cls = classify(op);
     if (cls == CLS_DIAG) {
-      uint32_t regs = 0;
-      for (int i = 0; i < op.nq; ++i) {
-        const int j = reg(op.q[i]);
-        if (j >= 0) regs |= 1u << j;
-      }
-      if (regs & unstable()) close();
+      uint32_t lbits = 0;
+      for (int i = 0; i < op.nq; ++i)
+        if (loc[op.q[i]] >= 0) lbits |= 1u << loc[op.q[i]];
+      if (lbits & unstable()) close();
       diag.push_back(op);
       diag_q |= qubit_mask(op);
       ++n_members;
       return;
     }
     if (is_perm_gate(op)) {
-      if (!add_perm(op)) {
-        close();
-        const bool ok = add_perm(op);
-        (void)ok;  // a fresh stage always has room for one gate
-      }
+      add_perm(op);
       ++n_perm;
       ++n_members;
       return;
@@ -404,7 +375,7 @@ struct LayerBuilder {
     // single-qubit, not diagonal: the 2x2 of its register bit
     const int q = op.q[0];
     int j = reg(q);
-    const bool moved_q = j >= 0 && ((moved() >> j) & 1u);
+    const bool moved_q = local_moved(q);
     bool conflict = ((diag_q >> q) & 1ull) || moved_q;
     if (conflict && !moved_q && start_sub_layer(q)) {
       conflict = false;
@@ -755,7 +726,7 @@ struct LayerBuilder {
     // pad the register bits with the lowest local bits that are neither
     // register bits nor permutation selectors
     for (int l = 0; (int)qs.size() < rb && l < m; ++l)
-      if (std::find(qs.begin(), qs.end(), l) == qs.end() && !((sel_local >> l) & 1u)) qs.push_back(l);
+      if (std::find(qs.begin(), qs.end(), l) == qs.end()) qs.push_back(l);
     for (int r = 0; r < rb; ++r) sh->q[r] = (uint32_t)qs[r];
     int n_slots = 0;
     uint32_t form = PFORM_NONE;
@@ -802,18 +773,27 @@ struct LayerBuilder {
       sh->u2 = push_entries(sh, u2m.data(), 16);
     }
     encode_diag(sh);
-    bool perm = c0 != 0 || !px.empty();
-    for (int j = 0; j < rb; ++j) {
-      sh->pcol[j] = A[j];
-      perm = perm || A[j] != (1u << j);
+    bool perm = cl != 0 || !tterms.empty();
+    uint32_t regmask = 0;
+    for (int r = 0; r < rb; ++r) regmask |= 1u << qs[r];
+    bool cross = false;  // the map moves amplitudes between groups
+    for (int l = 0; l < kPassLocalMax; ++l) {
+      sh->colimg[l] = l < m ? Mc[l] : 1u << l;
+      if (l < m && Mc[l] != (1u << l)) {
+        perm = true;
+        cross = cross || ((Mc[l] | (1u << l)) & ~regmask);
+      }
     }
-    sh->pconst = c0;
-    for (const auto& t : px) {
+    sh->pconst = cl;
+    cross = cross || (cl & ~regmask);
+    for (const auto& t : tterms) {
       PassItemDev it = item(PIT_PX);
       it.sel = t.first | (kPassNoSel << 8);
       it.a = t.second;
       sh->px.push_back(it);
+      cross = cross || (t.second & ~regmask);
     }
+    if (cross) sh->flags |= PSF_XPERM;
     if (perm) sh->flags |= PSF_PERM;
     encode_rows(sh);
     sh->n_ops = n_sub_ops + n_slots + (has_u2 ? 1 : 0) + ((sh->flags & PSF_DR) ? 1 : 0) + (int)sh->items.size() +

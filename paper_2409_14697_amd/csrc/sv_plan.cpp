@@ -293,7 +293,7 @@ sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out) {
       sd.mat_base = mbase;
       sd.rows = sh.rows;
       sd.row_count = sh.row_count;
-      for (int r = 0; r < kPassRegBitsMax; ++r) sd.pcol[r] = sh.pcol[r];
+      for (int l = 0; l < kPassLocalMax; ++l) sd.colimg[l] = sh.colimg[l];
       sd.pconst = sh.pconst;
       sd.item_first = (uint32_t)items.size();
       sd.item_count = (uint32_t)sh.items.size();

@@ -18,6 +18,7 @@ namespace sv {
 // 5 for complex64, 4 for complex128): register bit r is local bit q[r];
 // groups enumerate the other local bits.
 constexpr int kPassRegBitsMax = 5;
+constexpr int kPassLocalMax = 16;  // local bits of a tile, at most
 inline constexpr int pass_reg_bits(sv_dtype dt) { return dt == SV_C64 ? 5 : 4; }
 
 // A register stage of a tile pass applies, in this order (each part a block
@@ -34,9 +35,12 @@ inline constexpr int pass_reg_bits(sv_dtype dt) { return dt == SV_C64 ? 5 : 4; }
 //   4. a diagonal: a factor per register index (PSF_DR) times per-lane
 //      factors of the lane items (PSF_LANE): phases and diagonal gates that
 //      involve bits outside the registers
-//   5. a permutation of the register index, r -> A r ^ c(lane) over GF(2)
-//      (X, CNOT, SWAP: PSF_PERM), which costs nothing: the stage's LDS store
-//      writes amplitude r to the address of register index A r ^ c(lane).
+//   5. an affine map of the local index, x -> M x ^ c ^ c(tile) over GF(2)
+//      (the stage's X, CNOT and SWAP gates on any local bits: PSF_PERM),
+//      which costs no arithmetic: the stage's LDS store writes the amplitude
+//      of local index x to the address of M x ^ c ^ c(tile).  When the map
+//      moves amplitudes between the lanes' groups (PSF_XPERM) every lane
+//      reads its group before any lane writes.
 enum PassForm : uint32_t {
   PFORM_NONE = 0,  // no 2x2 part
   PFORM_UR = 1,    // every 2x2 real (H, RY)
@@ -49,7 +53,8 @@ enum PassStageFlags : uint32_t {
   PSF_DR = 2,    // factor table over the register index
   PSF_LANE = 4,  // lane items
   PSF_F0 = 8,    // some lane item multiplies the amplitudes whose register bit is 0
-  PSF_PERM = 16  // register permutation at the store
+  PSF_PERM = 16,  // affine map of the local index at the store
+  PSF_XPERM = 32  // ... which moves amplitudes between groups
 };
 enum PassItemType : uint32_t {
   PIT_DG = 0,  // factor on all the lane's amplitudes: table[var] (var from sel)
@@ -75,9 +80,9 @@ enum PassItemType : uint32_t {
                // mask), then one per tile target (ascending physical bit; `tt`
                // is their mask).  lmask / tmask cover every bit with a nonzero
                // word or a row.
-  PIT_PX = 4   // permutation term: when the selector bit is 1, the register
-               // index is XORed with the mask `a` (a CNOT whose control lies
-               // outside the registers)
+  PIT_PX = 4   // term of the store map: when the selector (a tile bit) is 1,
+               // the local index is XORed with the mask `a` (a CNOT whose
+               // control lies outside the tile)
 };
 constexpr int kPassLPLocalBits = 16;
 constexpr int kPassLPTileBits = 34;
@@ -132,8 +137,8 @@ struct alignas(16) PassStageDev {
   uint32_t mat_base;                // the stage's first pool entry
   uint32_t rows;                    // row descriptors: pool entry, from mat_base
   uint32_t row_count;               // <= kPassStageRowsMax
-  uint32_t pcol[kPassRegBitsMax];   // permutation: image of register bit j (A e_j)
-  uint32_t pconst;                  // permutation: constant XOR
+  uint32_t colimg[kPassLocalMax];   // store map: image of local bit l (M e_l, a local mask)
+  uint32_t pconst;                  // store map: constant XOR (local mask)
   uint32_t slot_mask;               // register bits whose 2x2 is not the identity
   uint32_t nsub;                    // earlier layers (<= kPassSubMax)
   PassSubDev sub[kPassSubMax];

@@ -263,6 +263,8 @@ int main() {
         if (__builtin_popcount(regmask) != RB) die("register bits not distinct");
         const uint32_t groups = (1u << m) >> RB;
         const uint32_t gmask = ((1u << m) - 1) & ~regmask;
+        std::vector<cd> nt(1u << m);
+        std::vector<char> written(1u << m, 0);
         for (uint32_t gi = 0; gi < groups; ++gi) {
           const uint32_t xg = (uint32_t)deposit(gi, gmask);
           auto addr = [&](uint32_t r) {
@@ -376,24 +378,28 @@ int main() {
           } else if (S.flags & PSF_DR) {
             for (int r = 0; r < NR; ++r) v[r] *= pr.entry(S.dr + r);
           }
+          // the store map x -> M x ^ c ^ c(tile), into the stage's output
           uint32_t c = S.pconst;
           for (uint32_t k = 0; k < S.px_count; ++k) {
             const PassItemDev it = *pr.item(S.px_first + k);
             if (it.type != PIT_PX) die("px item type");
             const uint32_t sc = it.sel & 0xffu;
-            if (sc < kPassTileSel && ((regmask >> sc) & 1u)) die("px selector is a register bit");
+            if (sc < kPassTileSel) die("store-map term not selected by a tile bit");
             if (sel_bit(sc, xg, base)) c ^= it.a;
           }
-          std::vector<char> seen(NR, 0);
           for (int r = 0; r < NR; ++r) {
-            uint32_t pr2 = c;
-            for (int j = 0; j < RB; ++j)
-              if ((r >> j) & 1) pr2 ^= S.pcol[j];
-            if (pr2 >= (uint32_t)NR) die("permutation leaves the registers");
-            if (seen[pr2]++) die("permutation not a bijection");
-            tile[addr(pr2)] = v[r];
+            const uint32_t x = addr(r);
+            uint32_t y = c;
+            for (uint32_t l = 0; l < m; ++l)
+              if ((x >> l) & 1u) y ^= S.colimg[l];
+            if (y >= (1u << m)) die("store map leaves the tile");
+            if (!(S.flags & PSF_PERM) && y != x) die("store map without PSF_PERM");
+            if (!(S.flags & PSF_XPERM) && (y & ~regmask) != xg) die("map between groups without PSF_XPERM");
+            if (written[y]++) die("store map not a bijection");
+            nt[y] = v[r];
           }
         }
+        tile.swap(nt);
       }
       for (uint32_t x = 0; x < (1u << m); ++x) {
         uint64_t a = base;
