@@ -1,9 +1,9 @@
 """Summarise rocprofv3 output of bench.py into profiles/ (host side, no GPU).
 
 Inputs are the CSV directories of three profiled runs of bench.py:
-  --trace : rocprofv3 --kernel-trace --stats -f csv -d <dir> -o bench -- python bench.py
+  --trace : rocprofv3 --kernel-trace --stats -f csv -d <dir> -o bench -- python bench.py --extras none
   --fetch : rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o bench -- python bench.py --steps 1 --warmup 0
-            --no-cpu-baseline --copy-ceiling
+            --no-cpu-baseline --copy-ceiling --extras none
   --write : the same with --pmc WRITE_SIZE
 Subcommands `trace` (kernel-trace summary of any profiled run) and `mfma`
 (matrix-core utilisation of the dense kernels from a counter run) write
@@ -195,11 +195,11 @@ def main():
     lines = ["# Gate-sweep benchmark, N=30 (complex128 + complex64): rocprofv3 summary", "",
              "Commands (run from the repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first):", "",
              "```",
-             "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o bench -- python bench.py",
+             "rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_trace -o bench -- python bench.py --extras none",
              "rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/prof_fetch -o bench -- python bench.py --steps 1 "
-             "--warmup 0 --no-cpu-baseline --copy-ceiling",
+             "--warmup 0 --no-cpu-baseline --copy-ceiling --extras none",
              "rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/prof_write -o bench -- python bench.py --steps 1 "
-             "--warmup 0 --no-cpu-baseline --copy-ceiling",
+             "--warmup 0 --no-cpu-baseline --copy-ceiling --extras none",
              "python bench_profile.py --trace gpurun_out/prof_trace --fetch gpurun_out/prof_fetch "
              "--write gpurun_out/prof_write",
              "```", "",
