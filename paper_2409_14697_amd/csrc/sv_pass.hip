@@ -227,24 +227,24 @@ __device__ __forceinline__ void op_u2(cplx<R>* v, cptr<cplx<R>> M) {
 }
 
 // The tensor product of one 2x2 per register bit (4 entries per bit, bit 0
-// first), every bit in form F; bits outside `mask` hold identities and are
-// skipped.
-template <int F, int B, typename R>
-__device__ __forceinline__ void slot(cplx<R>* v, cptr<cplx<R>> M) {
-  if constexpr (F == PFORM_UR) op_ur<B>(v, M + 4 * B);
-  else if constexpr (F == PFORM_UI) op_ui<B>(v, M + 4 * B);
-  else if constexpr (F == PFORM_RC) op_rc<B>(v, M + 4 * B);
+// first): bit B in its own form (three bits of `forms` each); bits without a
+// gate are skipped.
+template <int B, typename R>
+__device__ __forceinline__ void slot(cplx<R>* v, cptr<cplx<R>> M, uint32_t forms) {
+  const uint32_t f = pass_form_of(forms, B);
+  if (f == PFORM_NONE) return;
+  if (f == PFORM_UR) op_ur<B>(v, M + 4 * B);
+  else if (f == PFORM_UI) op_ui<B>(v, M + 4 * B);
+  else if (f == PFORM_RC) op_rc<B>(v, M + 4 * B);
   else op_u1<B>(v, M + 4 * B);
 }
-template <int F, typename R>
-__device__ __forceinline__ void layer(cplx<R>* v, cptr<cplx<R>> M, uint32_t mask) {
-  if (mask & 1u) slot<F, 0>(v, M);
-  if (mask & 2u) slot<F, 1>(v, M);
-  if (mask & 4u) slot<F, 2>(v, M);
-  if (mask & 8u) slot<F, 3>(v, M);
-  if constexpr (Regs<R>::RB > 4) {
-    if (mask & 16u) slot<F, 4>(v, M);
-  }
+template <typename R>
+__device__ __forceinline__ void layer(cplx<R>* v, cptr<cplx<R>> M, uint32_t forms) {
+  slot<0>(v, M, forms);
+  slot<1>(v, M, forms);
+  slot<2>(v, M, forms);
+  slot<3>(v, M, forms);
+  if constexpr (Regs<R>::RB > 4) slot<4>(v, M, forms);
 }
 
 // Angle words of the phase ladder: fixed-point turns, summed modulo one turn.
@@ -700,13 +700,7 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
       for (uint32_t li = 0; li <= S.nsub; ++li) {
         const bool last = li == S.nsub;
         const PassSubDev L = last ? PassSubDev{S.form, S.slot_mask, S.slots, kPassNoTable} : cload(subs + li);
-        switch (L.form) {
-          case PFORM_UR: layer<PFORM_UR>(v, mats + L.slots, L.slot_mask); break;
-          case PFORM_UI: layer<PFORM_UI>(v, mats + L.slots, L.slot_mask); break;
-          case PFORM_RC: layer<PFORM_RC>(v, mats + L.slots, L.slot_mask); break;
-          case PFORM_U: layer<PFORM_U>(v, mats + L.slots, L.slot_mask); break;
-          default: break;
-        }
+        if (L.form) layer<R>(v, mats + L.slots, L.form);
         if (L.dr != kPassNoTable) {
           const cptr<cplx<R>> D = mats + L.dr;
 #pragma unroll

@@ -108,15 +108,6 @@ uint32_t form_of(const M2& m) {
   return PFORM_U;
 }
 
-// The form that holds every one of a stage's 2x2s (PFORM_UR and PFORM_UI
-// only when all of them are of that kind).
-uint32_t join_form(uint32_t a, uint32_t b) {
-  if (a == PFORM_NONE) return b;
-  if (a == b) return a;
-  if (a == PFORM_U || b == PFORM_U) return PFORM_U;
-  return PFORM_RC;
-}
-
 // VALU instructions per amplitude of a 2x2 in each form (the kernel applies
 // one 2x2 per register bit).
 double form_ops(uint32_t f) {
@@ -729,10 +720,10 @@ struct LayerBuilder {
       if (std::find(qs.begin(), qs.end(), l) == qs.end()) qs.push_back(l);
     for (int r = 0; r < rb; ++r) sh->q[r] = (uint32_t)qs[r];
     int n_slots = 0;
-    uint32_t form = PFORM_NONE;
+    uint32_t form = 0;  // one PassForm per register bit
     for (int r = 0; r < rb; ++r)
       if (slot_on[r]) {
-        form = join_form(form, form_of(slot[r]));
+        form |= form_of(slot[r]) << (kPassFormBits * r);
         sh->slot_mask |= 1u << r;
         ++n_slots;
       }
@@ -741,11 +732,11 @@ struct LayerBuilder {
     sh->nsub = (uint32_t)subs.size();
     for (size_t k = 0; k < subs.size(); ++k) {
       const SubLayer& sl = subs[k];
-      PassSubDev sd{PFORM_NONE, 0, 0, kPassNoTable};
+      PassSubDev sd{0, 0, 0, kPassNoTable};
       std::vector<cd> e;
       for (int r = 0; r < rb; ++r) {
         if (sl.on[r]) {
-          sd.form = join_form(sd.form, form_of(sl.slot[r]));
+          sd.form |= form_of(sl.slot[r]) << (kPassFormBits * r);
           sd.slot_mask |= 1u << r;
           ++n_sub_ops;
         }
@@ -762,7 +753,7 @@ struct LayerBuilder {
       sh->sub[k] = sd;
     }
     if (n_slots) {
-      // absent 2x2s are identities, which every form holds
+      // absent 2x2s are identities (the kernel skips their bits)
       sh->form = form;
       std::vector<cd> e;
       for (int r = 0; r < rb; ++r) e.insert(e.end(), slot[r].begin(), slot[r].end());
@@ -833,10 +824,10 @@ std::vector<StageHost> build_stages(const std::vector<Op>& ops, const int* loc, 
 double stage_ops(const StageHost& sh, sv_dtype dt) {
   const int rb = pass_reg_bits(dt);
   double ops = (dt == SV_C64 ? 8.0 : 16.0);  // LDS read + write of every amplitude, barrier
-  ops += form_ops(sh.form) * __builtin_popcount(sh.slot_mask);
+  for (int r = 0; r < rb; ++r) ops += form_ops(pass_form_of(sh.form, r));
   if (sh.flags & PSF_U2) ops += 32.0;
   for (uint32_t k = 0; k < sh.nsub; ++k) {
-    ops += form_ops(sh.sub[k].form) * __builtin_popcount(sh.sub[k].slot_mask);
+    for (int r = 0; r < rb; ++r) ops += form_ops(pass_form_of(sh.sub[k].form, r));
     if (sh.sub[k].dr != kPassNoTable) ops += 4.0;
   }
   if (sh.flags & PSF_LANE) ops += 12.0 + 4.0 * (double)sh.items.size();

@@ -29,9 +29,10 @@ inline constexpr int pass_reg_bits(sv_dtype dt) { return dt == SV_C64 ? 5 : 4; }
 //      separated by diagonal gates on register bits (the Hadamard and
 //      controlled-phase ladder of a QFT block, say) stay in registers
 //   3. one 2x2 on every register bit: the tensor product of a layer of
-//      single-qubit gates (identity on bits without a gate); `form` says
-//      which entries are nonzero or real, so the kernel runs the cheapest
-//      code that applies all of them
+//      single-qubit gates (identity on bits without a gate); `form` holds
+//      three bits per register bit (bit r at 3 r) saying which entries of its
+//      2x2 are nonzero or real, so the kernel runs the cheapest code for
+//      each (PFORM_NONE: the bit has no gate and is skipped)
 //   4. a diagonal: a factor per register index (PSF_DR) times per-lane
 //      factors of the lane items (PSF_LANE): phases and diagonal gates that
 //      involve bits outside the registers
@@ -121,13 +122,15 @@ constexpr uint32_t kPassRowAlways = 0xffffffffu;  // row descriptor: no gating t
 constexpr int kPassSubMax = 4;
 constexpr uint32_t kPassNoTable = 0xffffffffu;
 struct PassSubDev {
-  uint32_t form, slot_mask, slots, dr;
+  uint32_t form, slot_mask, slots, dr;  // form: three bits per register bit
 };
+constexpr int kPassFormBits = 3;  // bits of one register bit's PassForm in a form word
+inline constexpr uint32_t pass_form_of(uint32_t word, int r) { return (word >> (kPassFormBits * r)) & 7u; }
 
 struct alignas(16) PassStageDev {
   uint32_t q[kPassRegBitsMax];      // local bit of register bit r (r < rb)
   uint32_t qsort[kPassRegBitsMax];  // the same bits, ascending (group enumeration)
-  uint32_t form;                    // PassForm
+  uint32_t form;                    // PassForm of each register bit (kPassFormBits each, bit 0 lowest)
   uint32_t flags;                   // PassStageFlags
   uint32_t slots;                   // pool entry of the 2x2s: 4 per register bit, bit 0 first
   uint32_t u2;                      // pool entry of the 4x4 (16 entries, row-major)

@@ -286,9 +286,20 @@ int main() {
             }
           }
           // one layer: a 2x2 per register bit of the mask, in the layer's form
-          auto apply_layer = [&](uint32_t form, uint32_t slots, uint32_t mask) {
-            if (form == PFORM_NONE) return;
+          auto apply_layer = [&](uint32_t forms, uint32_t slots, uint32_t mask) {
+            if (forms == 0) return;
+            if (forms >> (kPassFormBits * RB)) die("form word beyond the register bits");
             for (int b = 0; b < RB; ++b) {
+              const uint32_t form = pass_form_of(forms, b);
+              if (form > PFORM_U) die("unknown 2x2 form");
+              if ((form != PFORM_NONE) != (((mask >> b) & 1u) != 0)) die("slot mask and forms disagree");
+              if (form == PFORM_NONE) {
+                // the kernel skips the bit: its entries must be the identity
+                if (pr.entry(slots + 4 * b) != cd(1.0) || pr.entry(slots + 4 * b + 1) != cd(0.0) ||
+                    pr.entry(slots + 4 * b + 2) != cd(0.0) || pr.entry(slots + 4 * b + 3) != cd(1.0))
+                  die("2x2 without a form is not the identity");
+                continue;
+              }
               cd mm[4];
               for (int e = 0; e < 4; ++e) mm[e] = pr.entry(slots + 4 * b + e);
               // the form must hold the entries
@@ -297,13 +308,6 @@ int main() {
                 if (form == PFORM_UR && mm[e].imag() != 0) die("UR form with imaginary entry");
                 if (form == PFORM_UI && ((diag && mm[e].imag() != 0) || (!diag && mm[e].real() != 0))) die("UI form mismatch");
                 if (form == PFORM_RC && diag && mm[e].imag() != 0) die("RC form mismatch");
-              }
-              // the kernel skips the bits outside the mask: they must hold
-              // identities
-              if (!((mask >> b) & 1u)) {
-                if (mm[0] != cd(1.0) || mm[1] != cd(0.0) || mm[2] != cd(0.0) || mm[3] != cd(1.0))
-                  die("2x2 outside the slot mask is not the identity");
-                continue;
               }
               for (int r = 0; r < NR; ++r)
                 if (!((r >> b) & 1)) {
@@ -317,8 +321,8 @@ int main() {
           for (uint32_t li = 0; li <= S.nsub; ++li) {
             const bool last = li == S.nsub;
             const PassSubDev L = last ? PassSubDev{S.form, S.slot_mask, S.slots, kPassNoTable} : S.sub[li];
-            if (!last && L.form == PFORM_NONE && L.dr == kPassNoTable) die("empty earlier layer");
-            if (L.form == PFORM_NONE && L.slot_mask) die("slot mask without a form");
+            if (!last && L.form == 0 && L.dr == kPassNoTable) die("empty earlier layer");
+            if (L.form == 0 && L.slot_mask) die("slot mask without a form");
             apply_layer(L.form, L.slots, L.slot_mask);
             if (L.dr != kPassNoTable) {
               if (last) die("last layer with its own table");
