@@ -95,10 +95,15 @@ typedef struct sv_plan sv_plan;    /* opaque: host-only executable schedule   */
 
 /* Execution strategy of a plan. */
 typedef enum {
-  SV_MODE_AUTO = 0,   /* cost model picks the cheaper of a tile-pass plan and
-                         a one-sweep-per-fused-op plan                       */
+  SV_MODE_AUTO = 0,   /* cost model picks the cheapest of a tile-pass plan,
+                         a matrix-pass plan and a one-sweep-per-fused-op
+                         plan                                              */
   SV_MODE_SWEEP = 1,  /* one full-state sweep per (fused) op                */
-  SV_MODE_PASS = 2    /* LDS in-cache passes that apply many ops per sweep  */
+  SV_MODE_PASS = 2,   /* LDS in-cache passes that apply many ops per sweep  */
+  SV_MODE_MATRIX = 3  /* fused dense ops (Sec. II-B gate fusion) grouped by
+                         locality: each group runs in one in-cache pass
+                         (Sec. II-B, III-B) as matrix-core products on the
+                         tiles; ops that gain nothing grouped run as sweeps */
 } sv_mode;
 
 /* Planner / executor options.  Pass NULL for the defaults that
@@ -186,9 +191,10 @@ sv_status sv_plan_export(const sv_plan *p, size_t op, int32_t *nq, int32_t q[SV_
                          double *m, int32_t *pass);
 
 /* Describe pass `pass`: kind (0 = sweep kernel, 1 = LDS in-cache tile pass,
- * 2 = dense fused kernel, 3 = permutation), number of ops, the number of
- * local qubits of its tile (0 for sweeps) and of register stages (LDS round
- * trips of the tile; 0 for sweeps).  Outputs may be NULL. */
+ * 2 = dense fused kernel, 3 = permutation, 4 = matrix pass), number of ops,
+ * the number of local qubits of its tile (0 for sweeps) and of stages (LDS
+ * round trips of the tile; one per op in a matrix pass; 0 for sweeps).
+ * Outputs may be NULL. */
 sv_status sv_plan_pass_info(const sv_plan *p, size_t pass, int32_t *kind, int32_t *n_ops,
                             int32_t *n_local, int32_t *n_stages);
 

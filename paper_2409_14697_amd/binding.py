@@ -25,7 +25,7 @@ HEADERS = [os.path.join(ROOT, "include", "sv.h"), os.path.join(ROOT, "include", 
 SV_OK, SV_ERR_ARG, SV_ERR_QUBIT, SV_ERR_NOMEM, SV_ERR_DEVICE, SV_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 SV_C64, SV_C128 = 1, 2
 SV_NO_INIT = 1
-MODE = {"auto": 0, "sweep": 1, "pass": 2}
+MODE = {"auto": 0, "sweep": 1, "pass": 2, "matrix": 3}
 KIND = {"MATRIX": 0, "H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "T": 6, "RX": 7, "RY": 8, "RZ": 9, "P": 10,
         "CNOT": 11, "CZ": 12, "SWAP": 13, "CPHASE": 14, "RZZ": 15}
 MAXQ = 6

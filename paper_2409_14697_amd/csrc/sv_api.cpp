@@ -133,7 +133,7 @@ static sv_status validate_opts(const sv_opts& o) {
   if (o.pinned_low_bits < 0 || o.pinned_low_bits > 8)
     return fail(SV_ERR_ARG, "pinned_low_bits %d outside 0..8", o.pinned_low_bits);
   if (o.renorm_interval < 0) return fail(SV_ERR_ARG, "negative renorm_interval");
-  if (o.mode < SV_MODE_AUTO || o.mode > SV_MODE_PASS) return fail(SV_ERR_ARG, "bad mode %d", o.mode);
+  if (o.mode < SV_MODE_AUTO || o.mode > SV_MODE_MATRIX) return fail(SV_ERR_ARG, "bad mode %d", o.mode);
   if (o.max_pass_ops < 0) return fail(SV_ERR_ARG, "negative max_pass_ops");
   return SV_OK;
 }

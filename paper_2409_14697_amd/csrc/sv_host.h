@@ -77,7 +77,7 @@ bool low_args_for(const Op& op, sv_dtype dt, SweepArgs* out);
 double touched_fraction(const Op& op);
 
 // ------------------------------------------------------------------ plan
-enum PassKind { PASS_SWEEP = 0, PASS_TILE = 1, PASS_DENSE = 2, PASS_PERMUTE = 3 };
+enum PassKind { PASS_SWEEP = 0, PASS_TILE = 1, PASS_DENSE = 2, PASS_PERMUTE = 3, PASS_MATRIX = 4 };
 
 struct StageHost {
   uint32_t q[kPassRegBitsMax] = {0, 0, 0, 0, 0};  // local bit of each register bit
@@ -110,10 +110,13 @@ struct Pass {
   int n_local = 0;
   // PASS_SWEEP / PASS_DENSE: the op in physical qubits
   Op phys;
-  // PASS_TILE / PASS_PERMUTE
+  // PASS_TILE / PASS_PERMUTE / PASS_MATRIX
   uint32_t lpos[16] = {0};
   uint32_t wpos[16] = {0};
   std::vector<StageHost> stages;
+  // PASS_MATRIX: stage width k (every stage a dense 2^k x 2^k op: q[0..k-1]
+  // and a 2^k x 2^k matrix at mats entry 0)
+  int mx_k = 0;
 };
 
 // Fill a pass descriptor's local-bit maps and store flags (lmask, lpos, wpos,
@@ -186,6 +189,10 @@ std::vector<Op> fuse_ops(std::vector<Op> in, int n, sv_dtype dt, int kmax, bool 
 // times more locality to pay in later passes; build_plan tries both).
 sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const sv_opts& o, sv_plan* p,
                            bool progress);
+// Matrix passes over a fused op list (logical = physical qubits): runs of
+// ops whose qubits, with the pinned low bits, fit one tile become one pass
+// of matrix-core stages; ops that do not pay off grouped run as sweeps.
+void plan_matrix_passes(const std::vector<Op>& fused, int n, sv_dtype dt, const sv_opts& o, sv_plan* p);
 // Cost of one op run as its own sweep, in full read+write sweeps of the state.
 double op_sweep_cost(const Op& op, sv_dtype dt, bool mfma);
 // Tile size defaults.
@@ -199,11 +206,11 @@ sv_status execute_plan(sv_state* s, const sv_plan* p);
 struct PackedPlan {
   std::vector<unsigned char> host;
   std::vector<size_t> dense_off;   // per pass: offset of its dense matrix (PASS_DENSE)
-  std::vector<int> desc_index;     // per pass: descriptor index (PASS_TILE / PASS_PERMUTE) or -1
+  std::vector<int> desc_index;     // per pass: descriptor index (PASS_TILE / PASS_PERMUTE / PASS_MATRIX) or -1
   std::vector<char> pass_lp;       // per pass: holds fixed-point phase items
   size_t off_desc = 0, off_stage = 0, off_items = 0, off_pool = 0;
   int n_desc = 0, max_m = 0;
 };
-// tile_only: fail with SV_ERR_UNSUPPORTED on sweep and dense passes.
+// tile_only: fail with SV_ERR_UNSUPPORTED on sweep, dense and matrix passes.
 sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out);
 }  // namespace sv

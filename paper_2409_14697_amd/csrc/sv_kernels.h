@@ -89,7 +89,7 @@ hipError_t static_scratch(int device, void** out);
 // devices; the cache is guarded and kept per device.
 struct KernelLaunchCache {
   static constexpr int kMaxDevices = 64;
-  static constexpr int kSizes = 18;  // dynamic LDS sizes 2^0 .. 2^17 bytes
+  static constexpr int kSizes = 19;  // dynamic LDS sizes 2^0 .. 2^18 bytes
   std::mutex mu;
   size_t lds_attr[kMaxDevices] = {};
   uint64_t resident[kMaxDevices][kSizes] = {};

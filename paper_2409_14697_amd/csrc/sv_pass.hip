@@ -518,16 +518,26 @@ __device__ __forceinline__ TileRef<R> tile_ref(typename dev_elem<R>::E* psi, int
 
 constexpr int kBatch = 16;  // 16-byte elements per lane: 64 KiB tiles
 
-// Lane geometry of a tile: LDS element slot e = t + 256 u (u < per) of lane t.
+// Thread geometry of a block of NT threads moving a 64 KiB tile (4096
+// 16-byte elements): TB lane bits, BATCH elements per lane (UB bits).
+template <int NT>
+struct TileThreads {
+  static_assert(NT == 256 || NT == 512, "256 or 512 threads");
+  static constexpr int TB = NT == 512 ? 9 : 8;
+  static constexpr int BATCH = 4096 / NT;
+  static constexpr int UB = 12 - TB;
+};
+
+// Lane geometry of a tile: LDS element slot e = t + NT u (u < per) of lane t.
 struct LaneGeo {
   uint32_t per;
   bool on;
 };
 
-template <int LB>
+template <int LB, int NT = kBlock>
 __device__ __forceinline__ LaneGeo lane_geo(uint32_t m) {
   const uint32_t elems = (1u << m) >> LB;
-  return {elems >= (uint32_t)kBlock ? elems / kBlock : 1u, threadIdx.x < elems};
+  return {elems >= (uint32_t)NT ? elems / NT : 1u, threadIdx.x < elems};
 }
 
 // Physical offset of element slot bit i when the load fills slot e with tile
@@ -542,11 +552,11 @@ __device__ __forceinline__ uint64_t slot_offset(cptr<uint32_t> pos, uint32_t m, 
   return o;
 }
 
-// Offsets of the slot bits a lane owns (bits 0..7 of its slot index).
-template <int LB>
+// Offsets of the slot bits a lane owns (bits 0..TB-1 of its slot index).
+template <int LB, int NT = kBlock>
 __device__ __forceinline__ uint64_t lane_slot_bits(cptr<uint32_t> pos, uint32_t m) {
   uint64_t r = 0;
-  for (uint32_t j = 0; j < 8; ++j)
+  for (uint32_t j = 0; j < (uint32_t)TileThreads<NT>::TB; ++j)
     if ((threadIdx.x >> j) & 1u) r ^= slot_offset<LB>(pos, m, j);
   return r;
 }
@@ -756,24 +766,25 @@ __device__ __forceinline__ void tile_stages(const TileRef<R>& T, typename dev_el
 // addresses in the load's order (the same coalesced runs and 16-byte
 // elements whatever the permutation) and gather each element from LDS: the
 // element's k-th address bit holds local bit winv[k].
-template <typename R>
+template <typename R, int NT = kBlock>
 __device__ __forceinline__ void tile_gather(const TileRef<R>& T, const typename dev_elem<R>::E* tile,
                                             typename gelem<R>::G* out) {
   typedef typename dev_elem<R>::E E;
   typedef typename gelem<R>::G G;
+  typedef TileThreads<NT> TT;
   constexpr int LB = gelem<R>::LB;
   const cptr<PassDescDev> P = T.P;
   const uint32_t m = P->m;
-  const LaneGeo lg = lane_geo<LB>(m);
+  const LaneGeo lg = lane_geo<LB, NT>(m);
   // an opaque copy of the thread index: the addresses below are recomputed
   // per tile instead of being kept live (or spilled) across the whole loop
   uint32_t tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
   if (P->flags & kPassStoreLaneOrder) {
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u)
+    for (int u = 0; u < TT::BATCH; ++u)
       if ((uint32_t)u < lg.per && lg.on) {
-        const uint32_t x = (tid + u * kBlock) << LB;
+        const uint32_t x = (tid + u * NT) << LB;
         if constexpr (LB == 1) {
           // both amplitudes of the element sit in one 16-byte LDS slot
           out[u] = *reinterpret_cast<const G*>(tile + swz<LB>(x));
@@ -785,21 +796,21 @@ __device__ __forceinline__ void tile_gather(const TileRef<R>& T, const typename 
   }
   // LDS index of the lane's element: lane bit j is address bit LB + j
   uint32_t xl = 0;
-  for (uint32_t jb = 0; jb < 8 && LB + jb < m; ++jb)
+  for (uint32_t jb = 0; jb < (uint32_t)TT::TB && LB + jb < m; ++jb)
     if ((tid >> jb) & 1u) xl |= 1u << P->winv[LB + jb];
-  uint32_t xo[4];  // LDS offsets of the batch bits
+  uint32_t xo[TT::UB];  // LDS offsets of the batch bits
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const uint32_t k = LB + 8 + b;
+  for (int b = 0; b < TT::UB; ++b) {
+    const uint32_t k = LB + TT::TB + b;
     xo[b] = k < m ? 1u << P->winv[k] : 0u;
   }
   const uint32_t xp = LB ? 1u << P->winv[0] : 0u;  // the element's second amplitude (complex64)
 #pragma unroll
-  for (int u = 0; u < kBatch; ++u)
+  for (int u = 0; u < TT::BATCH; ++u)
     if ((uint32_t)u < lg.per && lg.on) {
       uint32_t x = xl;
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < TT::UB; ++b)
         if ((u >> b) & 1) x |= xo[b];
       if constexpr (LB == 1) {
         const E e0 = tile[swz<LB>(x)], e1 = tile[swz<LB>(x | xp)];
@@ -812,27 +823,28 @@ __device__ __forceinline__ void tile_gather(const TileRef<R>& T, const typename 
 
 // Store the gathered elements: in load order to the wpos addresses of the
 // lane's element, or in destination order to the lpos addresses.
-template <typename R>
+template <typename R, int NT = kBlock>
 __device__ __forceinline__ void tile_put(const TileRef<R>& T, const typename gelem<R>::G* g) {
   typedef typename gelem<R>::G G;
+  typedef TileThreads<NT> TT;
   constexpr int LB = gelem<R>::LB;
   const cptr<PassDescDev> P = T.P;
   const uint32_t m = P->m;
-  const LaneGeo lg = lane_geo<LB>(m);
+  const LaneGeo lg = lane_geo<LB, NT>(m);
   const gptr<G> gpsi = as_global(reinterpret_cast<G*>(T.psi));
   const cptr<uint32_t> pos = (P->flags & kPassStoreLaneOrder) ? P->wpos : P->lpos;
   uint64_t a0 = T.base;
-  for (uint32_t j = 0; j < 8 && LB + j < m; ++j)
+  for (uint32_t j = 0; j < (uint32_t)TT::TB && LB + j < m; ++j)
     if ((threadIdx.x >> j) & 1u) a0 |= 1ull << pos[LB + j];
-  uint64_t hb[4];
+  uint64_t hb[TT::UB];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) hb[b] = LB + 8 + b < (int)m ? 1ull << pos[LB + 8 + b] : 0ull;
+  for (int b = 0; b < TT::UB; ++b) hb[b] = LB + TT::TB + b < (int)m ? 1ull << pos[LB + TT::TB + b] : 0ull;
 #pragma unroll
-  for (int u = 0; u < kBatch; ++u)
+  for (int u = 0; u < TT::BATCH; ++u)
     if ((uint32_t)u < lg.per && lg.on) {
       uint64_t ad = a0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < TT::UB; ++b)
         if ((u >> b) & 1) ad |= hb[b];
       stg<G>(gpsi + (ad >> LB), g[u]);
     }
@@ -981,7 +993,316 @@ hipError_t run_batch(const BatchItemDev* items, int count, uint64_t total_tiles,
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- matrix passes
+// A matrix pass runs dense fused ops (general gate fusion, Sec. II-B) inside
+// the tiles of one pass (in-cache operation, Sec. II-B / III-B), on the
+// matrix cores.  Stage s views the tile as a 2^K x 2^(m-K) matrix X: rows
+// ("members") are the K local bits of the stage (member bit b = local bit
+// q[b]), columns the other local bits in ascending order.  It computes
+// Y = U X with three real products (Gauss's complex multiplication):
+//   P1 = Ur Xr,  P2 = Ui Xi,  P3 = (Ur + Ui)(Xr + Xi),  Yr = P1 - P2,
+//   Yi = P3 - P1 - P2.
+// Every wave owns whole column blocks, so a stage reads and overwrites its
+// columns in place; stages are separated by a barrier.  A-operand fragments
+// of all stages sit in LDS beside the tile (filled once per block).  The
+// next tile's loads go to registers before the stages run and are written to
+// LDS once the current tile has been read back, so HBM traffic overlaps the
+// matrix-core work; a block is the only one on its CU.
+typedef float mx_f32x16 __attribute__((ext_vector_type(16)));
+typedef double mx_f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct mx_shape;
+template <>
+struct mx_shape<float> {
+  // v_mfma_f32_32x32x2f32: lane l holds A[l % 32][l / 32] and B[l / 32][l % 32];
+  // accumulator register r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
+  static constexpr int BM = 32, BN = 32, BK = 2, NACC = 16;
+  typedef mx_f32x16 acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  static constexpr uint32_t out_u(int r) { return 8 * (r / 4) + r % 4; }  // row: register part
+  static __device__ __forceinline__ uint32_t out_l(uint32_t l) { return 4 * (l / 32); }  // row: lane part
+};
+template <>
+struct mx_shape<double> {
+  // v_mfma_f64_16x16x4f64: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
+  // accumulator register r of lane l is C[l / 16 + 4 r][l % 16]
+  static constexpr int BM = 16, BN = 16, BK = 4, NACC = 4;
+  typedef mx_f64x4 acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static constexpr uint32_t out_u(int r) { return 4 * r; }
+  static __device__ __forceinline__ uint32_t out_l(uint32_t l) { return l / 16; }
+};
+
+template <typename R, int K>
+struct mx_plan {
+  static constexpr int D = 1 << K;
+  static constexpr int RBK = D / mx_shape<R>::BM;  // row blocks
+  static constexpr int KS = D / mx_shape<R>::BK;   // k-steps
+  static constexpr int AF = RBK * KS * 64;         // A-fragment entries of one stage
+  static_assert(RBK >= 1, "a stage fills at least one row block");
+  static_assert(AF == D * D, "one A-fragment entry per matrix entry (matrix_pass_max_stages)");
+};
+
+// Swizzled LDS offset of a member: the XOR of the offsets of its set bits
+// (swz is linear, and members and columns occupy disjoint local bits).
+template <int K>
+__device__ __forceinline__ uint32_t mx_member(uint32_t mem, const uint32_t* sm) {
+  uint32_t o = 0;
+#pragma unroll
+  for (int b = 0; b < K; ++b)
+    if ((mem >> b) & 1u) o ^= sm[b];
+  return o;
+}
+
+// Threads of a matrix-pass block: eight waves, two per SIMD, so that one
+// wave's LDS and vector work overlaps the other's matrix-core products.
+constexpr int kMxThreads = 512;
+
+// Per-stage address table of a matrix pass (uint32 words, byte offsets into
+// the tile; every offset is an XOR of swizzled bit offsets, so offsets of
+// disjoint bit sets combine by XOR), filled once per block:
+//   [kMxBoff + ks]           member BK ks (operand reads, uniform part)
+//   [kMxOoff + rb NACC + r]  member BM rb + out_u(r) (results, uniform part)
+//   [kMxCol + cb]            column BN cb
+//   [kMxLane + 2 l (+ 1)]    lane l: column l % BN with member l / BN (with
+//                            the lane part out_l(l) of the result member)
+constexpr int kMxBoff = 0, kMxOoff = 16, kMxCol = 48, kMxLane = 64, kMxTab = 192;
+static_assert(kMxTab * 4 == kMatrixStageTable, "table size shared with the planner");
+
+template <typename R, int K>
+__device__ __forceinline__ void mx_table(cptr<uint32_t> q, uint32_t m, uint32_t* tab) {
+  typedef mx_shape<R> MS;
+  typedef mx_plan<R, K> MP;
+  constexpr int LB = gelem<R>::LB;
+  constexpr uint32_t EB = sizeof(typename dev_elem<R>::E);
+  uint32_t sm[K], tmask = 0;
+#pragma unroll
+  for (int b = 0; b < K; ++b) {
+    const uint32_t qb = q[b];
+    sm[b] = swz<LB>(1u << qb) * EB;
+    tmask |= 1u << qb;
+  }
+  const uint32_t cmask = ((1u << m) - 1u) & ~tmask;
+  const uint32_t cblocks = (1u << (m - K)) / MS::BN;
+  for (uint32_t t = threadIdx.x; t < (uint32_t)kMxTab; t += kMxThreads) {
+    uint32_t v = 0;
+    if (t < (uint32_t)kMxBoff + MP::KS) {
+      v = mx_member<K>(MS::BK * (t - kMxBoff), sm);
+    } else if (t >= (uint32_t)kMxOoff && t < (uint32_t)kMxOoff + MP::RBK * MS::NACC) {
+      const uint32_t i = t - kMxOoff;
+      v = mx_member<K>(MS::BM * (i / MS::NACC) + MS::out_u((int)(i % MS::NACC)), sm);
+    } else if (t >= (uint32_t)kMxCol && t < (uint32_t)kMxCol + cblocks) {
+      v = swz<LB>((uint32_t)deposit((uint64_t)(t - kMxCol) * MS::BN, cmask)) * EB;
+    } else if (t >= (uint32_t)kMxLane) {
+      const uint32_t l = (t - kMxLane) / 2;
+      const uint32_t col = swz<LB>((uint32_t)deposit(l % MS::BN, cmask)) * EB;
+      v = col ^ mx_member<K>(((t - kMxLane) & 1u) ? MS::out_l(l) : l / MS::BN, sm);
+    }
+    tab[t] = v;
+  }
+}
+
+// One stage on the tile in LDS (no barrier inside).  tab: the stage's
+// address table; am: its A fragments, entry (rb KS + ks) 64 + l =
+// U[BM rb + l % BM][BK ks + l / BM].  Each wave owns whole column blocks.
+template <typename R, int K>
+__device__ __forceinline__ void mx_stage(typename dev_elem<R>::E* tile, const uint32_t* tab, const cplx<R>* am,
+                                         uint32_t m) {
+  typedef mx_shape<R> MS;
+  typedef mx_plan<R, K> MP;
+  typedef typename dev_elem<R>::E E;
+  unsigned char* tb = reinterpret_cast<unsigned char*>(tile);
+  const uint32_t l = threadIdx.x & 63u;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t cblocks = (1u << (m - K)) / MS::BN;
+  const uint32_t lb = tab[kMxLane + 2 * l], lo = tab[kMxLane + 2 * l + 1];
+  for (uint32_t cb = w; cb < cblocks; cb += kMxThreads / 64) {
+    const uint32_t cu = tab[kMxCol + cb];
+    const uint32_t bb = lb ^ cu, bo = lo ^ cu;
+    typename MS::acc_t p1[MP::RBK], p2[MP::RBK], p3[MP::RBK];
+#pragma unroll
+    for (int rb = 0; rb < MP::RBK; ++rb) p1[rb] = p2[rb] = p3[rb] = typename MS::acc_t{};
+#pragma unroll
+    for (int ks = 0; ks < MP::KS; ++ks) {
+      const E x = *reinterpret_cast<const E*>(tb + (bb ^ tab[kMxBoff + ks]));
+      const R xs = x.x + x.y;
+#pragma unroll
+      for (int rb = 0; rb < MP::RBK; ++rb) {
+        const cplx<R> a = am[(rb * MP::KS + ks) * 64 + l];
+        p1[rb] = MS::mma(a.re, x.x, p1[rb]);
+        p2[rb] = MS::mma(a.im, x.y, p2[rb]);
+        p3[rb] = MS::mma(a.re + a.im, xs, p3[rb]);
+      }
+    }
+    // this wave has read every member of its columns: overwrite them
+#pragma unroll
+    for (int rb = 0; rb < MP::RBK; ++rb)
+#pragma unroll
+      for (int r = 0; r < MS::NACC; ++r) {
+        E y;
+        y.x = p1[rb][r] - p2[rb][r];
+        y.y = p3[rb][r] - p1[rb][r] - p2[rb][r];
+        *reinterpret_cast<E*>(tb + (bo ^ tab[kMxOoff + rb * MS::NACC + r])) = y;
+      }
+  }
+}
+
+// Global addresses of a lane's tile elements: register u of lane t is
+// element slot e = t + NT u, which holds tile element swz(e) (the layout
+// tile_load_lds produces).  The same for every tile of a pass but the base.
+template <int NT>
+struct MoveGeo {
+  uint64_t lane;
+  uint64_t hb[TileThreads<NT>::UB];
+  LaneGeo lg;
+};
+
+template <typename R, int NT>
+__device__ __forceinline__ MoveGeo<NT> move_geo(cptr<PassDescDev> P) {
+  constexpr int LB = gelem<R>::LB;
+  typedef TileThreads<NT> TT;
+  MoveGeo<NT> g;
+  const uint32_t m = P->m;
+  g.lane = lane_slot_bits<LB, NT>(P->lpos, m);
+#pragma unroll
+  for (int b = 0; b < TT::UB; ++b) g.hb[b] = slot_offset<LB>(P->lpos, m, TT::TB + b);
+  g.lg = lane_geo<LB, NT>(m);
+  return g;
+}
+
+// Move the tile's elements between HBM and registers.  STORE: write them
+// back to the addresses they were loaded from (a pass whose write positions
+// are its load positions).
+template <typename R, int NT, bool STORE>
+__device__ __forceinline__ void tile_move(const TileRef<R>& T, const MoveGeo<NT>& mg, typename gelem<R>::G* v) {
+  typedef typename gelem<R>::G G;
+  typedef TileThreads<NT> TT;
+  constexpr int LB = gelem<R>::LB;
+  const gptr<G> gpsi = as_global(reinterpret_cast<G*>(T.psi));
+  const uint64_t a0 = T.base | mg.lane;
+  // Loads are not predicated: a lane without element u reads the tile's
+  // first element instead, so that no load result merges with an older value
+  // (which would wait for the load right away).
+#pragma unroll
+  for (int u = 0; u < TT::BATCH; ++u) {
+    uint64_t ad = a0;
+#pragma unroll
+    for (int b = 0; b < TT::UB; ++b)
+      if ((u >> b) & 1) ad ^= mg.hb[b];
+    const bool ok = (uint32_t)u < mg.lg.per && mg.lg.on;
+    if constexpr (STORE) {
+      if (ok) stg<G>(gpsi + (ad >> LB), v[u]);
+    } else {
+      v[u] = ldg<G>((gptr<const G>)(gpsi + ((ok ? ad : T.base) >> LB)));
+    }
+  }
+}
+
+// The tile's element slots to or from registers (register u of lane t = slot t + NT u).
+template <typename R, int NT, bool TO_LDS>
+__device__ __forceinline__ void tile_slots(typename gelem<R>::G* v, typename dev_elem<R>::E* tile, const LaneGeo& lg) {
+  typedef typename gelem<R>::G G;
+  G* slots = reinterpret_cast<G*>(tile);
+#pragma unroll
+  for (int u = 0; u < TileThreads<NT>::BATCH; ++u)
+    if ((uint32_t)u < lg.per && lg.on) {
+      if constexpr (TO_LDS) slots[threadIdx.x + u * NT] = v[u];
+      else v[u] = slots[threadIdx.x + u * NT];
+    }
+}
+
+template <typename R, int K>
+__global__ __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mpass(
+    typename dev_elem<R>::E* __restrict__ psi, int n, const PassDescDev* __restrict__ passes, int pi,
+    const PassStageDev* __restrict__ stages, const cplx<R>* __restrict__ mats) {
+  typedef typename dev_elem<R>::E E;
+  typedef typename gelem<R>::G G;
+  typedef mx_shape<R> MS;
+  typedef mx_plan<R, K> MP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const cptr<PassDescDev> P = as_const(passes + pi);
+  const uint32_t m = P->m, ns = P->stage_count;
+  E* tile = reinterpret_cast<E*>(smem);
+  cplx<R>* am = reinterpret_cast<cplx<R>*>(tile + (1u << m));
+  uint32_t* tab = reinterpret_cast<uint32_t*>(am + ns * MP::AF);
+  const cptr<PassStageDev> st = as_const(stages) + P->stage_first;
+  constexpr int NT = kMxThreads, BATCH = TileThreads<NT>::BATCH;
+  for (uint32_t s = 0; s < ns; ++s) {
+    const uint32_t at = ((cptr<uint32_t>)(st + s))[offsetof(PassStageDev, u2) / 4];
+#pragma unroll
+    for (int j = 0; j < (MP::AF + NT - 1) / NT; ++j) {
+      const uint32_t f = threadIdx.x + j * NT, l = f % 64, ks = (f / 64) % MP::KS, rb = f / (64 * MP::KS);
+      const uint32_t row = MS::BM * rb + l % MS::BM, col = MS::BK * ks + l / MS::BM;
+      if (f < (uint32_t)MP::AF) am[s * MP::AF + f] = mats[at + row * MP::D + col];
+    }
+    mx_table<R, K>((cptr<uint32_t>)(st + s), m, tab + s * kMxTab);  // PassStageDev::q first
+  }
+  const SingleSrc<R> src{psi, n, P, as_const(stages), as_const((const PassItemDev*)nullptr), as_const(mats)};
+  const MoveGeo<NT> mg = move_geo<R, NT>(P);
+  const uint64_t total = 1ull << (n - m);
+  uint64_t g = xcd_block();
+  G nx[BATCH];
+  if (g < total) tile_move<R, NT, false>(src(g), mg, nx);
+  __syncthreads();  // the A fragments and tables are in LDS
+  if (g >= total) return;
+  tile_slots<R, NT, true>(nx, tile, mg.lg);
+  while (true) {
+    const uint64_t ng = g + gridDim.x;
+    const TileRef<R> cur = src(g);
+    lds_sync();  // the tile is in LDS
+    if (ng < total) tile_move<R, NT, false>(src(ng), mg, nx);
+    for (uint32_t s = 0; s < ns; ++s) {
+      mx_stage<R, K>(tile, tab + s * kMxTab, am + s * MP::AF, m);
+      lds_sync();
+    }
+    G out[BATCH];
+    tile_slots<R, NT, false>(out, tile, mg.lg);
+    lds_sync();  // every lane has read the tile
+    if (ng < total) tile_slots<R, NT, true>(nx, tile, mg.lg);
+    // the next tile's LDS writes go first: placed after the stores, their
+    // wait for the loads would also wait for stores
+    asm volatile("" ::: "memory");
+    tile_move<R, NT, true>(cur, mg, out);
+    if (ng >= total) break;
+    g = ng;
+  }
+}
+
+template <typename R, int K>
+hipError_t run_mpass(void* psi, int n, int m, const PassDescDev* passes, int pass, int n_stages,
+                     const PassStageDev* stages, const void* mats, hipStream_t s) {
+  typedef typename dev_elem<R>::E E;
+  const size_t lds = ((size_t)1 << m) * sizeof(E) +
+                     (size_t)n_stages * (mx_plan<R, K>::AF * sizeof(cplx<R>) + kMxTab * sizeof(uint32_t));
+  if (lds > (size_t)kMatrixPassLds) return hipErrorInvalidValue;
+  static KernelLaunchCache cache;
+  uint64_t resident = 0;
+  hipError_t e = prepare_launch(cache, (const void*)k_mpass<R, K>, kMxThreads, lds, &resident);
+  if (e != hipSuccess) return e;
+  const uint64_t tiles = 1ull << (n - m);
+  const uint64_t blocks = tiles < resident ? tiles : resident;
+  hipLaunchKernelGGL((k_mpass<R, K>), dim3((unsigned)blocks), dim3(kMxThreads), lds, s, (E*)psi, n, passes, pass,
+                     stages, (const cplx<R>*)mats);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_matrix_pass(sv_dtype dt, int k, void* psi, int n, int m, const PassDescDev* passes, int pass,
+                              int n_stages, const PassStageDev* stages, const void* mats, hipStream_t s) {
+  if (dt == SV_C64) {
+    if (k != 5) return hipErrorInvalidValue;
+    return run_mpass<float, 5>(psi, n, m, passes, pass, n_stages, stages, mats, s);
+  }
+  if (k == 4) return run_mpass<double, 4>(psi, n, m, passes, pass, n_stages, stages, mats, s);
+  if (k == 5) return run_mpass<double, 5>(psi, n, m, passes, pass, n_stages, stages, mats, s);
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* passes, int pass,
                        const PassStageDev* stages, const PassItemDev* items, const void* mats, bool ladders,

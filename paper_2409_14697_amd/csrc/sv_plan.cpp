@@ -160,6 +160,153 @@ std::vector<Op> fuse_ops(std::vector<Op> in, int n, sv_dtype dt, int kmax, bool 
 
 double op_sweep_cost(const Op& op, sv_dtype dt, bool mfma) { return sweep_cost(op, dt, mfma); }
 
+namespace {
+
+// The op times the identity on `e` further qubits (appended as the least
+// significant bits of the local index).
+Op widened(const Op& o, const int* extra, int e) {
+  Op r;
+  r.kind = SV_G_MATRIX;
+  r.nq = o.nq + e;
+  for (int i = 0; i < o.nq; ++i) r.q[i] = o.q[i];
+  for (int i = 0; i < e; ++i) r.q[o.nq + i] = extra[i];
+  r.n_gates = o.n_gates;
+  const int d = 1 << r.nq, dold = 1 << o.nq, emask = (1 << e) - 1;
+  r.m.assign((size_t)d * d, cd(0.0, 0.0));
+  for (int row = 0; row < d; ++row)
+    for (int col = 0; col < d; ++col)
+      if ((row & emask) == (col & emask)) r.m[(size_t)row * d + col] = o.m[(size_t)(row >> e) * dold + (col >> e)];
+  return r;
+}
+
+// Cost of a matrix pass in full-state sweeps, measured on MI355X at N = 30
+// (both precisions): a fixed part (the tile traffic the stages do not hide)
+// plus 0.84 sweeps per stage of 32 members (the matrix cores at about 0.65
+// of their dense peak), half that for 16 members.
+double matrix_pass_cost(int k, int stages) { return 0.65 + 0.84 * stages * (double)(1 << k) / 32.0; }
+
+// Stage width of a matrix pass for ops of up to k qubits: FP32 products need
+// 32 members, FP64 products 16.
+int matrix_width(sv_dtype dt, int k) { return dt == SV_C64 ? 5 : std::max(4, k); }
+
+}  // namespace
+
+void plan_matrix_passes(const std::vector<Op>& fused, int n, sv_dtype dt, const sv_opts& o, sv_plan* p) {
+  const bool mfma = dt == SV_C64 && o.fp32_mfma;
+  const int m = std::min(n, dt == SV_C64 ? 13 : 12);  // 64 KiB tiles
+  const int pin = std::min(default_pinned_bits(dt), m);
+  // four column blocks of the instruction per stage (one per wave)
+  const int min_cols = dt == SV_C64 ? 7 : 6;
+  p->ops.clear();
+  p->op_pass.clear();
+  p->passes.clear();
+  p->est_cost = 0.0;
+  std::vector<char> done(fused.size(), 0);
+  size_t first = 0;
+  auto emit_sweep = [&](const Op& op) {
+    Pass ps;
+    ps.kind = op.nq >= 3 ? PASS_DENSE : PASS_SWEEP;
+    ps.first_op = (int)p->ops.size();
+    ps.n_ops = 1;
+    ps.phys = op;
+    p->op_pass.push_back((int)p->passes.size());
+    p->ops.push_back(op);
+    p->est_cost += sweep_cost(op, dt, mfma);
+    p->passes.push_back(std::move(ps));
+  };
+  while (true) {
+    while (first < fused.size() && done[first]) ++first;
+    if (first == fused.size()) break;
+    // the longest run of ops (each free of the qubits of the ops skipped
+    // before it, so that it may move ahead of them) whose qubits fit a tile
+    std::vector<char> in_l(n, 0), blocked(n, 0);
+    int count = 0;
+    for (int b = 0; b < pin; ++b) {
+      in_l[b] = 1;
+      ++count;
+    }
+    std::vector<size_t> members;
+    int kw = 0;
+    for (size_t j = first; j < fused.size(); ++j) {
+      if (done[j]) continue;
+      const Op& op = fused[j];
+      bool blk = op.nq > 5;
+      for (int i = 0; i < op.nq; ++i) blk = blk || blocked[op.q[i]];
+      if (!blk) {
+        int extra = 0;
+        for (int i = 0; i < op.nq; ++i) extra += in_l[op.q[i]] ? 0 : 1;
+        const int k2 = matrix_width(dt, std::max(kw, op.nq));
+        if (count + extra <= m && m - k2 >= min_cols &&
+            (int)members.size() < matrix_pass_max_stages(dt, k2, m)) {
+          for (int i = 0; i < op.nq; ++i)
+            if (!in_l[op.q[i]]) {
+              in_l[op.q[i]] = 1;
+              ++count;
+            }
+          members.push_back(j);
+          kw = k2;
+          continue;
+        }
+      }
+      for (int i = 0; i < op.nq; ++i) blocked[op.q[i]] = 1;
+    }
+    double as_sweeps = 0.0;
+    for (size_t j : members) as_sweeps += sweep_cost(fused[j], dt, mfma);
+    const double cost = members.empty() ? 0.0 : matrix_pass_cost(kw, (int)members.size());
+    if (members.empty() || cost >= as_sweeps) {
+      emit_sweep(fused[first]);
+      done[first] = 1;
+      continue;
+    }
+    // the tile: the group's qubits, the pinned bits, then the lowest others
+    for (int b = 0; b < n && count < m; ++b)
+      if (!in_l[b]) {
+        in_l[b] = 1;
+        ++count;
+      }
+    Pass ps;
+    ps.kind = PASS_MATRIX;
+    ps.first_op = (int)p->ops.size();
+    ps.n_ops = (int)members.size();
+    ps.n_local = m;
+    ps.mx_k = kw;
+    int loc[64];
+    for (int b = 0; b < 64; ++b) loc[b] = -1;
+    int jl = 0;
+    for (int b = 0; b < n; ++b)
+      if (in_l[b]) {
+        ps.lpos[jl] = ps.wpos[jl] = (uint32_t)b;
+        loc[b] = jl++;
+      }
+    const int pass_id = (int)p->passes.size();
+    for (size_t j : members) {
+      const Op& op = fused[j];
+      // widen to kw qubits with the lowest tile qubits the op does not use
+      int extra[6], e = 0;
+      for (int jj = 0; jj < m && op.nq + e < kw; ++jj) {
+        const int x = (int)ps.lpos[jj];
+        bool used = false;
+        for (int i = 0; i < op.nq; ++i) used = used || op.q[i] == x;
+        if (!used) extra[e++] = x;
+      }
+      const Op w = e ? widened(op, extra, e) : op;
+      StageHost sh;
+      // member bit b is op qubit q[kw - 1 - b] (q[0] is the most significant)
+      for (int b = 0; b < kw; ++b) sh.q[b] = (uint32_t)loc[w.q[kw - 1 - b]];
+      sh.u2 = 0;
+      sh.mats = w.m;
+      sh.raw.assign(sh.mats.size(), 0);
+      sh.n_ops = 1;
+      ps.stages.push_back(std::move(sh));
+      p->ops.push_back(op);
+      p->op_pass.push_back(pass_id);
+      done[j] = 1;
+    }
+    p->est_cost += matrix_pass_cost(kw, (int)members.size());
+    p->passes.push_back(std::move(ps));
+  }
+}
+
 sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const sv_opts& o, sv_plan* p) {
   p->n = n;
   p->dt = dt;
@@ -173,6 +320,10 @@ sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const
   raw.reserve(n_gates);
   for (size_t i = 0; i < n_gates; ++i) raw.push_back(op_from_gate(g[i]));
 
+  if (o.mode == SV_MODE_MATRIX) {
+    plan_matrix_passes(fuse_ops(raw, n, dt, o.max_fuse_qubits, mfma), n, dt, o, p);
+    return SV_OK;
+  }
   // in-cache passes need a tile of at least 2^(register bits + 1) amplitudes
   const bool tiles_ok = n > pass_reg_bits(dt);
   if (o.mode != SV_MODE_SWEEP && tiles_ok) {
@@ -197,15 +348,22 @@ sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const
       p->est_cost = tp.est_cost;
       return SV_OK;
     }
-    // SV_MODE_AUTO: keep the tile plan unless one-sweep-per-op is cheaper
+    // SV_MODE_AUTO: the cheapest of the tile plan, the matrix-pass plan and
+    // one sweep per fused op
     std::vector<Op> fused = fuse_ops(raw, n, dt, o.max_fuse_qubits, mfma);
     double sweep_total = 0.0;
     for (const Op& op : fused) sweep_total += sweep_cost(op, dt, mfma);
-    if (tp.est_cost <= sweep_total) {
-      p->ops = std::move(tp.ops);
-      p->op_pass = std::move(tp.op_pass);
-      p->passes = std::move(tp.passes);
-      p->est_cost = tp.est_cost;
+    sv_plan mq;
+    mq.n = n;
+    mq.dt = dt;
+    mq.opts = o;
+    plan_matrix_passes(fused, n, dt, o, &mq);
+    sv_plan* best = tp.est_cost <= mq.est_cost ? &tp : &mq;
+    if (best->est_cost <= sweep_total) {
+      p->ops = std::move(best->ops);
+      p->op_pass = std::move(best->op_pass);
+      p->passes = std::move(best->passes);
+      p->est_cost = best->est_cost;
       return SV_OK;
     }
     p->ops = std::move(fused);
@@ -260,7 +418,7 @@ sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out) {
   std::vector<uint8_t> pool_raw;
   for (size_t i = 0; i < p->passes.size(); ++i) {
     const Pass& ps = p->passes[i];
-    if (ps.kind == PASS_DENSE || ps.kind == PASS_SWEEP) {
+    if (ps.kind == PASS_DENSE || ps.kind == PASS_SWEEP || (tile_only && ps.kind == PASS_MATRIX)) {
       if (tile_only)
         return fail(SV_ERR_UNSUPPORTED, "program needs a plan of in-cache tile passes only (build it with mode PASS)");
       if (ps.kind == PASS_DENSE) out->dense_off[i] = put_cd(ps.phys.m.data(), ps.phys.m.size(), nullptr);
@@ -273,10 +431,12 @@ sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out) {
     if (!fill_pass_maps(ps, p->dt, &d)) return fail(SV_ERR_UNSUPPORTED, "internal: pass write map is not a permutation");
     for (const StageHost& sh : ps.stages) {
       PassStageDev sd{};
+      // register bits of a tile stage, members of a matrix stage
+      const int nq = ps.kind == PASS_MATRIX ? ps.mx_k : rb;
       uint32_t srt[kPassRegBitsMax];
-      for (int r = 0; r < rb; ++r) sd.q[r] = srt[r] = sh.q[r];
-      std::sort(srt, srt + rb);
-      for (int r = 0; r < rb; ++r) sd.qsort[r] = srt[r];
+      for (int r = 0; r < nq; ++r) sd.q[r] = srt[r] = sh.q[r];
+      std::sort(srt, srt + nq);
+      for (int r = 0; r < nq; ++r) sd.qsort[r] = srt[r];
       const uint32_t mbase = (uint32_t)pool.size();
       sd.form = sh.form;
       sd.slot_mask = sh.slot_mask;
@@ -345,6 +505,15 @@ sv_status execute_plan(sv_state* s, const sv_plan* p) {
       sv_status st = run_op_sweep(s, ps.phys, db + pk.dense_off[i], p->opts.fp32_mfma != 0);
       if (st != SV_OK) return st;
       if (renorm > 0 && ++since >= renorm) {
+        if (sv_status r = renormalize(s)) return r;
+        since = 0;
+      }
+    } else if (ps.kind == PASS_MATRIX) {
+      SV_LAUNCH(launch_matrix_pass(s->dt, ps.mx_k, s->ptr, s->n, ps.n_local, (const PassDescDev*)(db + pk.off_desc),
+                                   pk.desc_index[i], (int)ps.stages.size(), (const PassStageDev*)(db + pk.off_stage),
+                                   db + pk.off_pool, s->stream),
+                s->stream);
+      if (renorm > 0 && (since += ps.n_ops) >= renorm) {
         if (sv_status r = renormalize(s)) return r;
         since = 0;
       }

@@ -186,6 +186,28 @@ hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* 
                        const PassStageDev* stages, const PassItemDev* items, const void* mats, bool ladders,
                        hipStream_t s);
 
+// --- matrix passes -----------------------------------------------------------
+// A matrix pass applies its stages, each a dense 2^k x 2^k op on k local bits
+// of the tile, on the matrix cores (complex64: k = 5, FP32 MFMA; complex128:
+// k = 4 or 5, FP64 MFMA).  Stage s (PassStageDev stage_first + s): q[b] = the
+// local bit of member bit b (b = 0 least significant), u2 = pool entry of the
+// matrix (row-major, rows and columns indexed by members).  Every other
+// PassStageDev field is unused.  The tile and the A fragments of all stages
+// share one block's LDS, kMatrixPassLds bytes at most; 2^(m-k) must be at
+// least four column blocks of the instruction (complex64 m >= 12; complex128
+// m >= k + 6).  The write-back uses the descriptor's wpos like a tile pass.
+constexpr int kMatrixPassLds = 160 * 1024;
+constexpr int kMatrixStageTable = 768;  // bytes of a stage's address table
+// Stages of width k that fit beside a tile of 2^m amplitudes (A fragments:
+// 2^k x 2^k complex entries per stage, and the stage's address table).
+inline int matrix_pass_max_stages(sv_dtype dt, int k, int m) {
+  const size_t eb = dt == SV_C64 ? 8 : 16;
+  const size_t tile = ((size_t)1 << m) * eb, stage = ((size_t)1 << (2 * k)) * eb + kMatrixStageTable;
+  return tile >= (size_t)kMatrixPassLds ? 0 : (int)(((size_t)kMatrixPassLds - tile) / stage);
+}
+hipError_t launch_matrix_pass(sv_dtype dt, int k, void* psi, int n, int m, const PassDescDev* passes, int pass,
+                              int n_stages, const PassStageDev* stages, const void* mats, hipStream_t s);
+
 // --- dense k-qubit fused gate (3 <= k <= 6) ---------------------------------
 // m_dev: device copy of the 2^k x 2^k matrix, row-major interleaved, in the
 // state's precision (double for SV_C128, float for SV_C64).  mfma: complex64

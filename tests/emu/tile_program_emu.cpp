@@ -35,6 +35,8 @@ sv_status run_op_sweep(sv_state*, const Op&, const void*, bool) { return SV_ERR_
 sv_status renormalize(sv_state*) { return SV_ERR_DEVICE; }
 hipError_t launch_pass(sv_dtype, void*, int, int, const PassDescDev*, int, const PassStageDev*, const PassItemDev*,
                        const void*, bool, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t launch_matrix_pass(sv_dtype, int, void*, int, int, const PassDescDev*, int, int, const PassStageDev*,
+                              const void*, hipStream_t) { return hipErrorInvalidValue; }
 static std::string g_err;
 sv_status fail(sv_status st, const char* fmt, ...) {
   char buf[512];

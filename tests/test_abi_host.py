@@ -12,7 +12,7 @@ import oracle
 from oracle import sv_oracle as so
 from paper_2409_14697_amd import binding as B
 from svgen import (Gate, fused_haar_circuit, layered_circuit, qaoa_circuit, qft_circuit, brickwork_circuit,
-                   gaussian_state_np)
+                   gaussian_state_np, haar_unitary)
 
 
 def test_library_exports_every_header_symbol():
@@ -137,7 +137,7 @@ CIRCUITS = {
 
 
 @pytest.mark.parametrize("name", sorted(CIRCUITS))
-@pytest.mark.parametrize("mode", ["pass", "auto", "sweep"])
+@pytest.mark.parametrize("mode", ["pass", "auto", "sweep", "matrix"])
 @pytest.mark.parametrize("lds", [0, 6, 9])
 def test_pass_plans_replay_circuit(name, mode, lds):
     n = 12
@@ -149,9 +149,42 @@ def test_pass_plans_replay_circuit(name, mode, lds):
     passes = plan.passes()
     assert len(passes) == n_passes
     for kind, nops, nloc in passes:
-        assert kind in (0, 1, 2, 3)
+        assert kind in (0, 1, 2, 3, 4)
         if kind in (1, 3):
             assert nloc == (lds or 12) or nloc == n
+        if kind == 4:  # matrix passes: 64 KiB tiles whatever lds_qubits says
+            assert nloc == min(n, 13)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_matrix_plans_group_local_ops(dtype):
+    """Matrix-pass plans: exported ops replay the circuit (grouping moves an op
+    only past ops on other qubits), every group fits one tile with the pinned
+    low qubits, and each pass has one stage per op."""
+    n, m, pin = 22, (13 if dtype == "c64" else 12), (4 if dtype == "c64" else 3)
+    rng = np.random.default_rng(5)
+    gates = []
+    for _ in range(5):
+        pool = list(range(pin)) + [int(x) for x in rng.choice(np.arange(pin, n), m - pin, replace=False)]
+        for _ in range(3):
+            k = int(rng.integers(2, 6))
+            qs = tuple(int(x) for x in rng.choice(pool, k, replace=False))
+            gates.append(Gate("MATRIX", qs, matrix=haar_unitary(1 << k, rng)))
+    plan = B.Plan(n, dtype, gates, {"mode": "matrix", "max_fuse_qubits": 0})
+    psi = gaussian_state_np(n, 2)
+    assert np.max(np.abs(_replay(plan, n, psi) - oracle.run(gates, psi0=psi))) < 1e-12
+    ex = plan.export()
+    passes = plan.passes(stages=True)
+    assert sum(1 for p in passes if p[0] == 4) >= 2
+    for pi, (kind, nops, nloc, nst) in enumerate(passes):
+        if kind != 4:
+            continue
+        assert nloc == m and nst == nops
+        qs = set(range(pin))
+        for q, _, p in ex:
+            if p == pi:
+                qs |= set(q)
+        assert len(qs) <= m
 
 
 def test_qft_swaps_become_relabels():
