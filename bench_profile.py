@@ -117,7 +117,7 @@ def mfma_summary(argv):
     seen = {}
     for r in rows:
         if r["Counter_Name"] != "SQ_VALU_MFMA_BUSY_CYCLES" or not any(
-                k in r["Kernel_Name"] for k in ("k_dense_mfma", "k_dense_3m")):
+                k in r["Kernel_Name"] for k in ("k_dense_mfma", "k_dense_3m", "k_mpass")):
             continue
         key = (r["Dispatch_Id"], short(r["Kernel_Name"]))
         seen.setdefault(key, [0.0, (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9])
@@ -139,6 +139,12 @@ def mfma_summary(argv):
         rtype = name.split("<")[1].split(",")[0].strip()
         dur = statistics.mean(d["dur"])
         busy = statistics.mean(b / (SIMDS * t * CLOCK_HZ) for b, t in zip(d["busy"], d["dur"]))
+        if "k_mpass" in name:
+            # a matrix pass runs several ops per dispatch (one per stage): the
+            # counters give its matrix-core busy fraction; its algorithmic rate
+            # is in the profiled run's own report
+            lines.append(f"| `{name}` | {len(d['dur'])} | {dur * 1e3:.3f} | {busy:.3f} | - | - | - |")
+            continue
         tflops = 8.0 * 2.0 ** (args.n + k) / dur / 1e12
         done = tflops * (0.75 if "k_dense_3m" in name else 1.0)
         lines.append(f"| `{name}` | {len(d['dur'])} | {dur * 1e3:.3f} | {busy:.3f} | {tflops:.1f} | "
