@@ -1121,6 +1121,14 @@ __device__ __forceinline__ void mx_stage(typename dev_elem<R>::E* tile, const ui
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t cblocks = (1u << (m - K)) / MS::BN;
   const uint32_t lb = tab[kMxLane + 2 * l], lo = tab[kMxLane + 2 * l + 1];
+  // the result offsets are read with the operands' and held in registers:
+  // read next to their stores, each would cost a wait on the LDS queue
+  constexpr int NO = MP::RBK * MS::NACC;
+  uint32_t oo[NO];
+#pragma unroll
+  for (int j = 0; j < NO; ++j) oo[j] = tab[kMxOoff + j];
+#pragma unroll
+  for (int j = 0; j < NO; ++j) asm volatile("" : "+v"(oo[j]));
   for (uint32_t cb = w; cb < cblocks; cb += kMxThreads / 64) {
     const uint32_t cu = tab[kMxCol + cb];
     const uint32_t bb = lb ^ cu, bo = lo ^ cu;
@@ -1147,7 +1155,7 @@ __device__ __forceinline__ void mx_stage(typename dev_elem<R>::E* tile, const ui
         E y;
         y.x = p1[rb][r] - p2[rb][r];
         y.y = p3[rb][r] - p1[rb][r] - p2[rb][r];
-        *reinterpret_cast<E*>(tb + (bo ^ tab[kMxOoff + rb * MS::NACC + r])) = y;
+        *reinterpret_cast<E*>(tb + (bo ^ oo[rb * MS::NACC + r])) = y;
       }
   }
 }
