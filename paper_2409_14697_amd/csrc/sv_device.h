@@ -65,6 +65,25 @@ __device__ __forceinline__ uint64_t xcd_block() {
   return (b % 8) * (nb / 8) + b / 8;
 }
 
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// A workgroup barrier without the memory fence of __syncthreads (which
+// would also wait for this wave's global stores): the caller has already
+// waited for the LDS traffic the barrier orders.  The empty asm statements
+// keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// The barrier between the phases of a tile: every lane's LDS reads and
+// writes (and scalar loads) are complete, then all waves meet.
+__device__ __forceinline__ void lds_sync() {
+  wait_lgkm0();
+  lds_barrier();
+}
+
 // Memory element types: one load/store instruction moves one element.
 //   dbl2 : one complex128 amplitude (16 B)
 //   flt2 : one complex64 amplitude (8 B)

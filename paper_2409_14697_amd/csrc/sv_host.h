@@ -187,8 +187,10 @@ std::vector<Op> fuse_ops(std::vector<Op> in, int n, sv_dtype dt, int kmax, bool 
 // progress: every pass's write-back also moves data toward the position the
 // remaining relabelings give it (fewer permutation passes at the end, at
 // times more locality to pay in later passes; build_plan tries both).
+// reserve: local bits each pass keeps free of its gates, for data moving
+// toward its final position (smaller gate blocks, fewer permutation passes).
 sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const sv_opts& o, sv_plan* p,
-                           bool progress);
+                           bool progress, int reserve = 0);
 // Matrix passes over a fused op list (logical = physical qubits): runs of
 // ops whose qubits, with the pinned low bits, fit one tile become one pass
 // of matrix-core stages; ops that do not pay off grouped run as sweeps.

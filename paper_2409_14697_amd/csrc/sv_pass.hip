@@ -106,25 +106,6 @@ __device__ __forceinline__ P uniform_ptr(P p) {
   return (P)uniform64((uint64_t)p);
 }
 
-__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
-
-// A workgroup barrier without the memory fence of __syncthreads (which
-// would also wait for this wave's global stores): the caller has already
-// waited for the LDS traffic the barrier orders.  The empty asm statements
-// keep the compiler from moving memory accesses across it.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
-
-// The barrier between the phases of a tile: every lane's LDS reads and
-// writes (and scalar loads) are complete, then all waves meet.
-__device__ __forceinline__ void lds_sync() {
-  wait_lgkm0();
-  lds_barrier();
-}
-
 template <typename R>
 __device__ __forceinline__ cplx<R> cget(cptr<cplx<R>> M, uint32_t i) {
   return cplx<R>{M[i].re, M[i].im};

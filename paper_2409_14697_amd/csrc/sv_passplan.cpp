@@ -924,7 +924,7 @@ std::vector<std::vector<int>> dest_cycles(const std::vector<int>& d) {
 }  // namespace
 
 sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const sv_opts& o, sv_plan* p,
-                           bool progress) {
+                           bool progress, int reserve) {
   int m = o.lds_qubits ? o.lds_qubits : default_lds_qubits(dt);
   // 64 KiB tiles: two blocks per CU, and 16 elements of 16 bytes per lane
   const int m_max = dt == SV_C128 ? 12 : 13;
@@ -1005,7 +1005,8 @@ sv_status plan_tile_passes(const std::vector<Op>& ops, int n, sv_dtype dt, const
         const int k = locality(op, q);
         int extra = 0;
         for (int i = 0; i < k; ++i) extra += in_l[mp.phys[q[i]]] ? 0 : 1;
-        if (count + extra <= m) {
+        // the reserve never keeps a pass from taking its first op
+        if (count + extra <= (members.empty() ? m : m - reserve)) {
           for (int i = 0; i < k; ++i)
             if (!in_l[mp.phys[q[i]]]) {
               in_l[mp.phys[q[i]]] = 1;

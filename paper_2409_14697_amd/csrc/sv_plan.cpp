@@ -341,6 +341,18 @@ sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const
     tq.dt = dt;
     tq.opts = o;
     if (plan_tile_passes(light, n, dt, o, &tq, true) == SV_OK && tq.est_cost < tp.est_cost) tp = std::move(tq);
+    // with relabelings (SWAPs) ahead, gate blocks that leave a few local bits
+    // to moving data can save permutation passes at the end
+    bool relabels = false;
+    for (const Op& op : light) relabels = relabels || (o.reorder && op.kind == SV_G_SWAP);
+    for (int reserve = 1; relabels && reserve <= 3; ++reserve) {
+      sv_plan tr;
+      tr.n = n;
+      tr.dt = dt;
+      tr.opts = o;
+      if (plan_tile_passes(light, n, dt, o, &tr, true, reserve) == SV_OK && tr.est_cost < tp.est_cost)
+        tp = std::move(tr);
+    }
     if (o.mode == SV_MODE_PASS) {
       p->ops = std::move(tp.ops);
       p->op_pass = std::move(tp.op_pass);

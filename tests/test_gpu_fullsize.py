@@ -183,7 +183,8 @@ def test_circuit_benchmark_n32_properties(sv):
     ref[0] = 1.0
     err = max_err(got, ref)
     print(f"brickwork d40 + inverse at N=32 complex64: max amplitude error {err:.3e}", flush=True)
-    assert err <= 1e-4, err
+    # measured 1.5e-8 (matrix passes, FP32 products): the FP32 bar holds
+    assert err <= 1e-5, err
     st.close()
     torch.cuda.empty_cache()
 
