@@ -1235,31 +1235,33 @@ __global__ __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(2, 2
   const MoveGeo<NT> mg = move_geo<R, NT>(P);
   const uint64_t total = 1ull << (n - m);
   uint64_t g = xcd_block();
-  G nx[BATCH];
+  // Per tile: the next tile's loads go out first, the previous tile's
+  // stores after the first stage, so neither burst waits behind the other in
+  // the memory queue while the stages could run.
+  G nx[BATCH], out[BATCH];
   if (g < total) tile_move<R, NT, false>(src(g), mg, nx);
   __syncthreads();  // the A fragments and tables are in LDS
   if (g >= total) return;
   tile_slots<R, NT, true>(nx, tile, mg.lg);
+  uint64_t prev = total;  // tile whose results wait in `out` (none yet)
   while (true) {
     const uint64_t ng = g + gridDim.x;
-    const TileRef<R> cur = src(g);
     lds_sync();  // the tile is in LDS
     if (ng < total) tile_move<R, NT, false>(src(ng), mg, nx);
     for (uint32_t s = 0; s < ns; ++s) {
       mx_stage<R, K>(tile, tab + s * kMxTab, am + s * MP::AF, m);
+      if (s == 0 && prev < total) tile_move<R, NT, true>(src(prev), mg, out);
       lds_sync();
     }
-    G out[BATCH];
+    if (ns == 0 && prev < total) tile_move<R, NT, true>(src(prev), mg, out);  // (a pass has stages)
     tile_slots<R, NT, false>(out, tile, mg.lg);
     lds_sync();  // every lane has read the tile
-    if (ng < total) tile_slots<R, NT, true>(nx, tile, mg.lg);
-    // the next tile's LDS writes go first: placed after the stores, their
-    // wait for the loads would also wait for stores
-    asm volatile("" ::: "memory");
-    tile_move<R, NT, true>(cur, mg, out);
+    prev = g;
     if (ng >= total) break;
+    tile_slots<R, NT, true>(nx, tile, mg.lg);
     g = ng;
   }
+  tile_move<R, NT, true>(src(prev), mg, out);
 }
 
 template <typename R, int K>
