@@ -1056,20 +1056,26 @@ constexpr int kMxBoff = 0, kMxOoff = 16, kMxCol = 48, kMxLane = 64, kMxTab = 192
 static_assert(kMxTab * 4 == kMatrixStageTable, "table size shared with the planner");
 
 template <typename R, int K>
-__device__ __forceinline__ void mx_table(cptr<uint32_t> q, uint32_t m, uint32_t* tab) {
+__device__ __forceinline__ void mx_table(cptr<uint32_t> sd, uint32_t m, uint32_t* tab) {
   typedef mx_shape<R> MS;
   typedef mx_plan<R, K> MP;
   constexpr int LB = gelem<R>::LB;
   constexpr uint32_t EB = sizeof(typename dev_elem<R>::E);
-  uint32_t sm[K], tmask = 0;
+  constexpr int LBN = MS::BN == 32 ? 5 : 4;  // lane bits of a column block
+  const cptr<uint32_t> q = sd + offsetof(PassStageDev, q) / 4;
+  const cptr<uint32_t> col = sd + offsetof(PassStageDev, colimg) / 4;  // column bit j: local bit col[j]
+  uint32_t sm[K];
 #pragma unroll
-  for (int b = 0; b < K; ++b) {
-    const uint32_t qb = q[b];
-    sm[b] = swz<LB>(1u << qb) * EB;
-    tmask |= 1u << qb;
-  }
-  const uint32_t cmask = ((1u << m) - 1u) & ~tmask;
-  const uint32_t cblocks = (1u << (m - K)) / MS::BN;
+  for (int b = 0; b < K; ++b) sm[b] = swz<LB>(1u << q[b]) * EB;
+  const uint32_t nc = m - K;  // column bits
+  const uint32_t cblocks = (1u << nc) / MS::BN;
+  // offset of the column bits `v` taken from column bit `first` on
+  auto cols = [&](uint32_t v, uint32_t first, uint32_t nbits) {
+    uint32_t o = 0;
+    for (uint32_t j = 0; j < nbits; ++j)
+      if ((v >> j) & 1u) o ^= swz<LB>(1u << col[first + j]) * EB;
+    return o;
+  };
   for (uint32_t t = threadIdx.x; t < (uint32_t)kMxTab; t += kMxThreads) {
     uint32_t v = 0;
     if (t < (uint32_t)kMxBoff + MP::KS) {
@@ -1078,11 +1084,10 @@ __device__ __forceinline__ void mx_table(cptr<uint32_t> q, uint32_t m, uint32_t*
       const uint32_t i = t - kMxOoff;
       v = mx_member<K>(MS::BM * (i / MS::NACC) + MS::out_u((int)(i % MS::NACC)), sm);
     } else if (t >= (uint32_t)kMxCol && t < (uint32_t)kMxCol + cblocks) {
-      v = swz<LB>((uint32_t)deposit((uint64_t)(t - kMxCol) * MS::BN, cmask)) * EB;
+      v = cols(t - kMxCol, LBN, nc - LBN);
     } else if (t >= (uint32_t)kMxLane) {
       const uint32_t l = (t - kMxLane) / 2;
-      const uint32_t col = swz<LB>((uint32_t)deposit(l % MS::BN, cmask)) * EB;
-      v = col ^ mx_member<K>(((t - kMxLane) & 1u) ? MS::out_l(l) : l / MS::BN, sm);
+      v = cols(l % MS::BN, 0, LBN) ^ mx_member<K>(((t - kMxLane) & 1u) ? MS::out_l(l) : l / MS::BN, sm);
     }
     tab[t] = v;
   }
@@ -1229,7 +1234,7 @@ __global__ __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(2, 2
       const uint32_t row = MS::BM * rb + l % MS::BM, col = MS::BK * ks + l / MS::BM;
       if (f < (uint32_t)MP::AF) am[s * MP::AF + f] = mats[at + row * MP::D + col];
     }
-    mx_table<R, K>((cptr<uint32_t>)(st + s), m, tab + s * kMxTab);  // PassStageDev::q first
+    mx_table<R, K>((cptr<uint32_t>)(st + s), m, tab + s * kMxTab);
   }
   const SingleSrc<R> src{psi, n, P, as_const(stages), as_const((const PassItemDev*)nullptr), as_const(mats)};
   const MoveGeo<NT> mg = move_geo<R, NT>(P);
@@ -1249,10 +1254,21 @@ __global__ __launch_bounds__(kMxThreads) __attribute__((amdgpu_waves_per_eu(2, 2
     lds_sync();  // the tile is in LDS
     if (ng < total) tile_move<R, NT, false>(src(ng), mg, nx);
     for (uint32_t s = 0; s < ns; ++s) {
+      if (s > 0) {
+        const uint32_t fl = ((cptr<uint32_t>)(st + s))[offsetof(PassStageDev, flags) / 4];
+        if (fl & kMatrixStageSync) {
+          lds_sync();
+        } else {
+          // the stage reads only what this wave wrote: its own LDS writes
+          // are done, no other wave is waited for
+          wait_lgkm0();
+          asm volatile("" ::: "memory");
+        }
+      }
       mx_stage<R, K>(tile, tab + s * kMxTab, am + s * MP::AF, m);
       if (s == 0 && prev < total) tile_move<R, NT, true>(src(prev), mg, out);
-      lds_sync();
     }
+    lds_sync();  // every wave's results are in LDS
     if (ns == 0 && prev < total) tile_move<R, NT, true>(src(prev), mg, out);  // (a pass has stages)
     tile_slots<R, NT, false>(out, tile, mg.lg);
     lds_sync();  // every lane has read the tile

@@ -185,6 +185,59 @@ Op widened(const Op& o, const int* extra, int e) {
 // of their dense peak), half that for 16 members.
 double matrix_pass_cost(int k, int stages) { return 0.65 + 0.84 * stages * (double)(1 << k) / 32.0; }
 
+// Column orders and barriers of a matrix pass's stages: runs of consecutive
+// stages share three wave bits that are a member of none of them (so each
+// wave keeps its elements through the run and no barrier separates the
+// run's stages); a run ends where no three such bits remain.
+void assign_matrix_columns(Pass& ps, sv_dtype dt) {
+  const int m = ps.n_local, kw = ps.mx_k;
+  const int lane_bits = dt == SV_C64 ? 5 : 4;  // log2 of the instruction's columns
+  const int nwb = std::min(3, m - kw - lane_bits);  // wave bits: kMatrixWaves = 2^3
+  const uint32_t all = (1u << m) - 1u;
+  auto targets = [&](const StageHost& sh) {
+    uint32_t t = 0;
+    for (int b = 0; b < kw; ++b) t |= 1u << sh.q[b];
+    return t;
+  };
+  size_t s0 = 0;
+  while (s0 < ps.stages.size()) {
+    uint32_t free = all & ~targets(ps.stages[s0]);
+    size_t s1 = s0 + 1;
+    while (s1 < ps.stages.size() && __builtin_popcount(free & ~targets(ps.stages[s1])) >= nwb) {
+      free &= ~targets(ps.stages[s1]);
+      ++s1;
+    }
+    uint32_t wave = 0;  // the highest nwb free bits
+    for (int b = m - 1, left = nwb; b >= 0 && left > 0; --b)
+      if ((free >> b) & 1u) {
+        wave |= 1u << b;
+        --left;
+      }
+    for (size_t si = s0; si < s1; ++si) {
+      StageHost& sh = ps.stages[si];
+      const uint32_t rest = all & ~targets(sh) & ~wave;
+      int j = 0, taken = 0;
+      for (int b = 0; b < m && taken < lane_bits; ++b)
+        if ((rest >> b) & 1u) {
+          sh.colimg[j++] = (uint32_t)b;
+          ++taken;
+        }
+      for (int b = 0; b < m; ++b)
+        if ((wave >> b) & 1u) sh.colimg[j++] = (uint32_t)b;
+      for (int b = 0, skip = lane_bits; b < m; ++b)
+        if ((rest >> b) & 1u) {
+          if (skip > 0) {
+            --skip;
+            continue;
+          }
+          sh.colimg[j++] = (uint32_t)b;
+        }
+      sh.flags = (si == s0 && si > 0) ? kMatrixStageSync : 0u;
+    }
+    s0 = s1;
+  }
+}
+
 // Stage width of a matrix pass for ops of up to k qubits: FP32 products need
 // 32 members, FP64 products 16.
 int matrix_width(sv_dtype dt, int k) { return dt == SV_C64 ? 5 : std::max(4, k); }
@@ -302,6 +355,7 @@ void plan_matrix_passes(const std::vector<Op>& fused, int n, sv_dtype dt, const 
       p->op_pass.push_back(pass_id);
       done[j] = 1;
     }
+    assign_matrix_columns(ps, dt);
     p->est_cost += matrix_pass_cost(kw, (int)members.size());
     p->passes.push_back(std::move(ps));
   }

@@ -196,6 +196,16 @@ hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* 
 // share one block's LDS, kMatrixPassLds bytes at most; 2^(m-k) must be at
 // least four column blocks of the instruction (complex64 m >= 12; complex128
 // m >= k + 6).  The write-back uses the descriptor's wpos like a tile pass.
+// Column order of a matrix stage: colimg[j] = the local bit of column bit j
+// (the columns are the tile's other local bits: first the lane bits, log2 of
+// the instruction's column count, then the wave bits, then the rest); wave w
+// of kMatrixWaves owns the columns whose wave bits spell w.  Stage flag
+// kMatrixStageSync: a barrier precedes the stage.  Consecutive stages without
+// it have the same wave bits, none of them a member bit of either stage, so
+// every wave keeps the same elements and runs those stages without waiting
+// for the others.
+constexpr uint32_t kMatrixStageSync = 1;
+constexpr int kMatrixWaves = 8;
 constexpr int kMatrixPassLds = 160 * 1024;
 constexpr int kMatrixStageTable = 768;  // bytes of a stage's address table
 // Stages of width k that fit beside a tile of 2^m amplitudes (A fragments:
