@@ -190,6 +190,34 @@ def test_circuit_benchmark_n32_properties(sv):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_matrix_passes_n30_brickwork_and_inverse(sv, dtype):
+    """N=30 brickwork depth 10 and its inverse, each planned as matrix passes
+    (different groupings of different fused ops), return |0..0>: every
+    amplitude of 4096 samples (and index 0) within the precision's bar."""
+    import torch
+    n = 30
+    brick = brickwork_circuit(n, 10, seed=5)
+    st = sv.StateVector(n, dtype)
+    st.init_basis(0)
+    for gates in (brick, inverse(brick)):
+        plan = sv.Plan(n, dtype, gates, {"mode": "matrix"})
+        assert 4 in [k for k, _, _ in plan.passes()]
+        st.apply_plan(plan)
+        plan.close()
+    st.sync()
+    rng = np.random.default_rng(12)
+    idx = np.concatenate([[0], rng.integers(1, 1 << n, size=4095, dtype=np.int64)])
+    got = read(st.tensor, idx)
+    ref = np.zeros(idx.shape, dtype=np.complex128)
+    ref[0] = 1.0
+    err = max_err(got, ref)
+    print(f"matrix passes, brickwork d10 + inverse at N=30 {dtype}: max amplitude error {err:.3e}", flush=True)
+    assert err <= (1e-12 if dtype == "c128" else 1e-5), err
+    st.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_tensor_product_layers_n30_pairs(sv, dtype):
     """Three layers of Haar single-qubit gates on all 30 qubits, with the same
     CNOT matching after the first two, in tile passes (register stages apply
