@@ -979,16 +979,19 @@ hipError_t run_batch(const BatchItemDev* items, int count, uint64_t total_tiles,
 // the tiles of one pass (in-cache operation, Sec. II-B / III-B), on the
 // matrix cores.  Stage s views the tile as a 2^K x 2^(m-K) matrix X: rows
 // ("members") are the K local bits of the stage (member bit b = local bit
-// q[b]), columns the other local bits in ascending order.  It computes
-// Y = U X with three real products (Gauss's complex multiplication):
+// q[b]), columns the other local bits in the stage's column order (lane
+// bits, wave bits, the rest).  It computes Y = U X with three real products
+// (Gauss's complex multiplication):
 //   P1 = Ur Xr,  P2 = Ui Xi,  P3 = (Ur + Ui)(Xr + Xi),  Yr = P1 - P2,
 //   Yi = P3 - P1 - P2.
-// Every wave owns whole column blocks, so a stage reads and overwrites its
-// columns in place; stages are separated by a barrier.  A-operand fragments
-// of all stages sit in LDS beside the tile (filled once per block).  The
-// next tile's loads go to registers before the stages run and are written to
-// LDS once the current tile has been read back, so HBM traffic overlaps the
-// matrix-core work; a block is the only one on its CU.
+// Every wave owns whole column blocks (those whose wave bits spell its
+// index), so a stage reads and overwrites its columns in place; a barrier
+// separates two stages only when their wave bits differ.  A-operand
+// fragments and address tables of all stages sit in LDS beside the tile
+// (filled once per block).  The next tile's loads go to registers while the
+// stages run and are written to LDS once the current tile has been read
+// back; a tile's stores go out after the next tile's first stage.  A block
+// (eight waves, two per SIMD) is the only one on its CU.
 typedef float mx_f32x16 __attribute__((ext_vector_type(16)));
 typedef double mx_f64x4 __attribute__((ext_vector_type(4)));
 

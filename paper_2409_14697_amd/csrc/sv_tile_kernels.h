@@ -191,11 +191,13 @@ hipError_t launch_pass(sv_dtype dt, void* psi, int n, int m, const PassDescDev* 
 // of the tile, on the matrix cores (complex64: k = 5, FP32 MFMA; complex128:
 // k = 4 or 5, FP64 MFMA).  Stage s (PassStageDev stage_first + s): q[b] = the
 // local bit of member bit b (b = 0 least significant), u2 = pool entry of the
-// matrix (row-major, rows and columns indexed by members).  Every other
-// PassStageDev field is unused.  The tile and the A fragments of all stages
-// share one block's LDS, kMatrixPassLds bytes at most; 2^(m-k) must be at
-// least four column blocks of the instruction (complex64 m >= 12; complex128
-// m >= k + 6).  The write-back uses the descriptor's wpos like a tile pass.
+// matrix (row-major, rows and columns indexed by members), colimg and flags
+// as below.  Every other PassStageDev field is unused.  The tile and the A
+// fragments of all stages share one block's LDS, kMatrixPassLds bytes at
+// most; 2^(m-k) must be at least four column blocks of the instruction
+// (complex64 m >= 12; complex128 m >= k + 6).  The write-back stores every
+// element where it was loaded from (the planner gives matrix passes
+// wpos = lpos).
 // Column order of a matrix stage: colimg[j] = the local bit of column bit j
 // (the columns are the tile's other local bits: first the lane bits, log2 of
 // the instruction's column count, then the wave bits, then the rest); wave w
