@@ -495,6 +495,9 @@ sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out) {
     d.stage_first = (uint32_t)stages.size();
     d.stage_count = (uint32_t)ps.stages.size();
     if (!fill_pass_maps(ps, p->dt, &d)) return fail(SV_ERR_UNSUPPORTED, "internal: pass write map is not a permutation");
+    if (ps.kind == PASS_MATRIX)  // the matrix-pass kernel stores where it loaded
+      for (int j = 0; j < ps.n_local; ++j)
+        if (ps.wpos[j] != ps.lpos[j]) return fail(SV_ERR_UNSUPPORTED, "internal: matrix pass with a write map");
     for (const StageHost& sh : ps.stages) {
       PassStageDev sd{};
       // register bits of a tile stage, members of a matrix stage
