@@ -168,7 +168,7 @@ int main() {
   o.max_fuse_qubits = 5;
   o.reorder = 1;
   o.fp32_mfma = 1;
-  o.mode = mode == "pass" ? SV_MODE_PASS : mode == "sweep" ? SV_MODE_SWEEP : SV_MODE_AUTO;
+  o.mode = mode == "pass" ? SV_MODE_PASS : mode == "sweep" ? SV_MODE_SWEEP : mode == "matrix" ? SV_MODE_MATRIX : SV_MODE_AUTO;
   o.lds_qubits = lds;
   sv_plan p;
   if (build_plan(n, dt, gates.data(), gates.size(), o, &p) != SV_OK) die(g_err.c_str());
@@ -236,6 +236,69 @@ int main() {
         for (uint32_t j = 0; j < m; ++j)
           if ((x >> j) & 1) a |= 1ull << D->lpos[j];
         tile[x] = psi[a];
+      }
+      if (ps.kind == PASS_MATRIX) {
+        // Matrix stages: a dense 2^K x 2^K op on the member bits q[]; the
+        // column order puts lane bits, then wave bits first; a stage without
+        // the barrier flag must leave every element with the wave that held it.
+        const int K = ps.mx_k, D2 = 1 << K;
+        const int lane_bits = dt == SV_C64 ? 5 : 4;
+        const int nc = (int)m - K, nwb = std::min(3, nc - lane_bits);
+        if (nc < lane_bits + 2) die("matrix stage: too few column bits");
+        for (uint32_t j = 0; j < m; ++j)
+          if (D->wpos[j] != D->lpos[j]) die("matrix pass with a write map");
+        std::vector<int> owner(1u << m, -1);
+        for (uint32_t si = 0; si < D->stage_count; ++si) {
+          const PassStageDev& S = *pr.stage(D->stage_first + si);
+          uint32_t tmask = 0;
+          for (int b = 0; b < K; ++b) {
+            if (S.q[b] >= m || ((tmask >> S.q[b]) & 1u)) die("matrix stage: bad member bits");
+            tmask |= 1u << S.q[b];
+          }
+          uint32_t cmask = 0;
+          for (int j = 0; j < nc; ++j) {
+            if (S.colimg[j] >= m || ((cmask >> S.colimg[j]) & 1u) || ((tmask >> S.colimg[j]) & 1u))
+              die("matrix stage: column order is not the other local bits");
+            cmask |= 1u << S.colimg[j];
+          }
+          std::vector<int> own(1u << m);
+          for (uint32_t x = 0; x < (1u << m); ++x) {
+            int w = 0;
+            for (int j = 0; j < nwb; ++j) w |= (int)((x >> S.colimg[lane_bits + j]) & 1u) << j;
+            own[x] = w;
+            if (si > 0 && !(S.flags & kMatrixStageSync) && owner[x] != w)
+              die("matrix stage without a barrier moves an element to another wave");
+          }
+          owner.swap(own);
+          std::vector<cd> xin(D2), yout(D2);
+          for (uint32_t b0 = 0; b0 < (1u << m); ++b0) {
+            if (b0 & tmask) continue;
+            for (int r = 0; r < D2; ++r) {
+              uint32_t x = b0;
+              for (int b = 0; b < K; ++b)
+                if ((r >> b) & 1) x |= 1u << S.q[b];
+              xin[r] = tile[x];
+            }
+            for (int r = 0; r < D2; ++r) {
+              cd acc = 0;
+              for (int c = 0; c < D2; ++c) acc += pr.entry(S.u2 + (uint32_t)(r * D2 + c)) * xin[c];
+              yout[r] = acc;
+            }
+            for (int r = 0; r < D2; ++r) {
+              uint32_t x = b0;
+              for (int b = 0; b < K; ++b)
+                if ((r >> b) & 1) x |= 1u << S.q[b];
+              tile[x] = yout[r];
+            }
+          }
+        }
+        for (uint32_t x = 0; x < (1u << m); ++x) {
+          uint64_t a = base;
+          for (uint32_t j = 0; j < m; ++j)
+            if ((x >> j) & 1) a |= 1ull << D->lpos[j];
+          psi[a] = tile[x];
+        }
+        continue;
       }
       for (uint32_t si = 0; si < D->stage_count; ++si) {
         const PassStageDev S = *pr.stage(D->stage_first + si);

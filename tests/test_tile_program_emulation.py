@@ -156,6 +156,31 @@ def test_tile_program_model_permutations_exact(emu, dtype):
         assert np.array_equal(out, oracle.run(gates, psi0=psi)), lds
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("name", ["brickwork", "grouped"])
+def test_matrix_pass_model_matches_oracle(emu, name, dtype):
+    """Matrix passes as packed for the kernel (member bits, pool matrices,
+    column orders, barrier flags): the host model applies the stages and
+    checks that a stage without a barrier keeps every element with its
+    wave, against the oracle.  N = 14: two tiles."""
+    n = 14
+    rng = np.random.default_rng(3)
+    if name == "brickwork":
+        gates = brickwork_circuit(n, 12, seed=2)
+    else:
+        gates = []
+        pin = 4 if dtype == "c64" else 3
+        for _ in range(4):
+            pool = list(range(pin)) + [int(x) for x in rng.choice(np.arange(pin, n), 8, replace=False)]
+            for _ in range(3):
+                k = int(rng.integers(2, 6))
+                qs = tuple(int(x) for x in rng.choice(pool, k, replace=False))
+                gates.append(Gate("MATRIX", qs, matrix=haar_unitary(1 << k, rng)))
+    psi = gaussian_state_np(n, 6)
+    out = run_emu(emu, n, dtype, "matrix", 0, gates, psi)
+    assert np.max(np.abs(out - oracle.run(gates, psi0=psi))) <= TOL[dtype], (name, dtype)
+
+
 def test_tile_program_model_under_sanitizers():
     """The planner and packer sources, built with AddressSanitizer and
     UndefinedBehaviorSanitizer into the host model, plan and run a mixed
