@@ -501,12 +501,15 @@ def _cpu_threads():
 
 
 def serve_roofline(st, dt):
-    """Roofline of the batched pass kernel: whichever of HBM bytes and VALU
-    flops (both algorithmic, per second of launch time) is nearer its peak."""
+    """Roofline of the batched step (the batched tile-pass kernel plus the
+    launches of matrix, dense and sweep passes of the step): whichever of HBM
+    bytes and VALU flops (both algorithmic: each state read and written once
+    per pass, the gates' flops; per second of step time) is nearer its peak."""
     peak_flops = PEAK_VALU_TFLOPS[dt]
     hbm = st["GBs"] / PEAK_HBM_GBS
     alu = st["TFLOPs"] / peak_flops
-    common = {"kernel": "k_pass_batch", "mean_launch_us": round(st["mean_launch_us"], 2),
+    common = {"kernel": "batched step (k_pass_batch; k_mpass / dense / sweep launches)",
+              "mean_launch_us": round(st["mean_launch_us"], 2),
               "hbm_frac": round(hbm, 4), "alu_frac": round(alu, 4)}
     if alu > hbm:
         return dict({"bound": "alu", "achieved": round(st["TFLOPs"], 2), "peak": peak_flops, "unit": "TFLOP/s",
@@ -543,7 +546,7 @@ def serve_bench(args, requests_by_dtype):
         prep_s = time.perf_counter() - t0
 
         def run(rate, budget=None, timed=False):
-            eng = DeviceEngine(dt, time_launches=timed)
+            eng = DeviceEngine(dt, time_launches=timed, matrix_qubits=args.matrix_qubits)
             srv = Server(eng, budget or free_budget(0.8), max_active=args.max_active,
                          plan_workers=min(16, _cpu_threads()))
             res = srv.run(jobs_from_marshalled(reqs, marshalled, rate))
@@ -553,7 +556,7 @@ def serve_bench(args, requests_by_dtype):
             return res, stats
         # warm-up: allocator, kernels, planner threads
         warm = max(1, min(32, len(reqs) // 8))
-        eng = DeviceEngine(dt)
+        eng = DeviceEngine(dt, matrix_qubits=args.matrix_qubits)
         Server(eng, free_budget(0.8), plan_workers=4).run(jobs_from_marshalled(reqs[:warm], marshalled[:warm], None))
         eng.close()
         closed, _ = run(None)
@@ -573,7 +576,7 @@ def serve_bench(args, requests_by_dtype):
             out["cpu_baseline"] = serve_cpu_baseline(reqs)
     out["config"] = {"workload": f"serving: requests N~U{{12..{args.nmax}}}, depth~U{{20..200}} layer pairs "
                                  f"(seed 5), Poisson arrivals at {args.rate_fraction} x closed-loop throughput, "
-                                 f"budget 0.8 x free HBM"}
+                                 f"budget 0.8 x free HBM, AUTO plans from N={args.matrix_qubits}"}
     return out
 
 
@@ -694,6 +697,8 @@ def main():
                     help="default workload's serving part: dtype:requests list")
     ap.add_argument("--nmax", type=int, default=26, help="serve workload: largest request N")
     ap.add_argument("--max-active", type=int, default=512, help="serve workload: slot cap")
+    ap.add_argument("--matrix-qubits", type=int, default=24,
+                    help="serve workload: requests of at least this many qubits use AUTO plans (0: tile passes only)")
     ap.add_argument("--rate-fraction", type=float, default=0.8, help="serve workload: arrival rate / saturated rate")
     ap.add_argument("--contention-gib", type=float, default=0.0,
                     help="serve workload: also run with this HBM budget (GiB)")

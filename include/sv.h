@@ -204,6 +204,11 @@ sv_status sv_plan_pass_info(const sv_plan *p, size_t pass, int32_t *kind, int32_
  * and 0 for a permutation.  Errors: SV_ERR_ARG. */
 sv_status sv_plan_pass_flops(const sv_plan *p, size_t pass, double *flops_per_amp);
 
+/* The same for every pass at once: flops_per_amp[i] for each pass i (host
+ * memory of `count` doubles, count >= the plan's number of passes; entries
+ * beyond it are not written).  Errors: SV_ERR_ARG. */
+sv_status sv_plan_flops(const sv_plan *p, double *flops_per_amp, size_t count);
+
 /* Kernel ops of tile pass `pass` after register staging: *n_ops ops in
  * total (per register stage: one per single-qubit gate of its tensor-product
  * layer, one for a dense two-qubit gate, one for its register-index factor
@@ -279,20 +284,22 @@ const char *sv_last_error(void);
 
 /* ---- Serving: device-resident programs and batched passes ---------------
  * A request loop keeps many states resident and advances all of them with one
- * kernel launch per step (continuous batching): each launch runs the next
+ * step per pass (continuous batching): one kernel launch runs the next
  * in-cache tile pass of every active state, so requests admitted later join
- * the next launch and their work overlaps with older ones on the device. */
-typedef struct sv_program sv_program;  /* tile-pass program of one plan, in device memory */
+ * the next launch and their work overlaps with older ones on the device;
+ * a state whose next pass is a matrix, dense or sweep pass runs it as a
+ * launch of its own in the same step. */
+typedef struct sv_program sv_program;  /* the passes of one plan, in device memory */
 typedef struct sv_batcher sv_batcher;  /* launches one pass of many states at once        */
 
 /* Device bytes a program of plan p occupies (for a caller-owned buffer).
  * Errors: SV_ERR_ARG, SV_ERR_UNSUPPORTED (see sv_program_create). */
 sv_status sv_program_bytes(const sv_plan *p, size_t *bytes);
 
-/* Upload the tile-pass program of plan p, stream-ordered on hip_stream (NULL
- * = null stream).  The plan must consist only of in-cache tile passes (mode
- * SV_MODE_PASS, n >= 5, gates of at most 2 qubits); otherwise
- * SV_ERR_UNSUPPORTED.
+/* Upload the program of plan p (any mode: tile, permutation, matrix, dense
+ * and sweep passes), stream-ordered on hip_stream (NULL = null stream).  A
+ * program does not renormalise: the plan's renorm_interval is not applied
+ * to complex64 states run through a batcher.
  *   dev_buf : NULL -> the library allocates the device copy and frees it in
  *             sv_program_destroy; otherwise caller device memory of at least
  *             sv_program_bytes(p) bytes, 256-byte aligned, kept alive while
@@ -314,8 +321,9 @@ sv_status sv_program_destroy(sv_program *prog);
 /* A batcher owns its stream and small descriptor buffers. */
 sv_status sv_batcher_create(void *hip_stream, sv_batcher **out);
 
-/* One launch: for every i < count, run pass pass_index[i] of programs[i] on
- * states[i].  All states and programs must share one dtype; states[i] must
+/* One step: for every i < count, run pass pass_index[i] of programs[i] on
+ * states[i] -- the tile and permutation passes of all items in one launch,
+ * each matrix, dense or sweep pass in a launch of its own.  All states and programs must share one dtype; states[i] must
  * have programs[i]'s qubit count; a state may appear at most once.  Work is
  * enqueued on the batcher's stream: the caller orders it against other work
  * on the states (e.g. by creating the states on the same stream).  A state's

@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   POINTER(c_int32)]),
         "sv_plan_destroy": (S, [c_void_p]),
         "sv_plan_pass_flops": (S, [c_void_p, c_size_t, POINTER(c_double)]),
+        "sv_plan_flops": (S, [c_void_p, POINTER(c_double), c_size_t]),
         "sv_plan_pass_ops": (S, [c_void_p, c_size_t, POINTER(c_int32), POINTER(c_int32)]),
         "sv_apply_plan": (S, [c_void_p, c_void_p]),
         "sv_apply_circuit": (S, [c_void_p, POINTER(SvGate), c_size_t, POINTER(SvOpts)]),
@@ -245,15 +246,13 @@ class Plan:
         return out
 
     def pass_flops(self) -> List[float]:
-        """Algorithmic real flops per amplitude of every pass (sv_plan_pass_flops)."""
+        """Algorithmic real flops per amplitude of every pass (sv_plan_flops,
+        one call: the pass query sv_plan_pass_flops per pass gives the same)."""
         lib = load_library()
         _, n_passes = self.info()
-        out = []
-        f = c_double()
-        for i in range(n_passes):
-            check(lib.sv_plan_pass_flops(self._h, i, byref(f)))
-            out.append(f.value)
-        return out
+        buf = (c_double * max(1, n_passes))()
+        check(lib.sv_plan_flops(self._h, buf, n_passes))
+        return list(buf[:n_passes])
 
     def close(self):
         if self._h:

@@ -1,4 +1,5 @@
 // C ABI of the state-vector core (declared in include/sv.h).
+#include <algorithm>
 #include <cstdarg>
 #include <cstdlib>
 #include <cstdio>
@@ -329,17 +330,36 @@ sv_status sv_plan_pass_info(const sv_plan* p, size_t pass, int32_t* kind, int32_
   return SV_OK;
 }
 
+namespace {
+// Flops per amplitude of every pass, filled once per plan by one sweep over
+// its ops (later queries are O(1) per pass).
+const std::vector<double>& plan_flops(const sv_plan* p) {
+  sv_plan::FlopsCache& fc = *p->flops;
+  std::call_once(fc.once, [p, &fc]() {
+    fc.per_pass.assign(p->passes.size(), 0.0);
+    for (size_t i = 0; i < p->ops.size(); ++i) {
+      const OpClass c = classify(p->ops[i]);
+      fc.per_pass[(size_t)p->op_pass[i]] += c == CLS_PERM ? 0.0 : c == CLS_DIAG ? 6.0 : 8.0 * (double)(1 << p->ops[i].nq);
+    }
+  });
+  return fc.per_pass;
+}
+}  // namespace
+
 sv_status sv_plan_pass_flops(const sv_plan* p, size_t pass, double* flops_per_amp) {
   clear_error();
   if (!p || !flops_per_amp) return fail(SV_ERR_ARG, "null argument");
   if (pass >= p->passes.size()) return fail(SV_ERR_ARG, "pass %zu out of range", pass);
-  double f = 0.0;
-  for (size_t i = 0; i < p->ops.size(); ++i) {
-    if (p->op_pass[i] != (int)pass) continue;
-    const OpClass c = classify(p->ops[i]);
-    f += c == CLS_PERM ? 0.0 : c == CLS_DIAG ? 6.0 : 8.0 * (double)(1 << p->ops[i].nq);
-  }
-  *flops_per_amp = f;
+  *flops_per_amp = plan_flops(p)[pass];
+  return SV_OK;
+}
+
+sv_status sv_plan_flops(const sv_plan* p, double* flops_per_amp, size_t count) {
+  clear_error();
+  if (!p || !flops_per_amp) return fail(SV_ERR_ARG, "null argument");
+  if (count < p->passes.size()) return fail(SV_ERR_ARG, "room for %zu passes, plan has %zu", count, p->passes.size());
+  const std::vector<double>& f = plan_flops(p);
+  std::copy(f.begin(), f.end(), flops_per_amp);
   return SV_OK;
 }
 

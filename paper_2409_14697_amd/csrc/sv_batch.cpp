@@ -1,5 +1,7 @@
-// Serving support: device-resident tile-pass programs and the batcher that
-// runs one pass of many states per kernel launch (continuous batching).
+// Serving support: device-resident programs and the batcher that runs one
+// pass of many states per step (continuous batching): the tile and
+// permutation passes of all states in one launch, matrix, dense and sweep
+// passes as launches of their own.
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -11,7 +13,12 @@ struct sv_program {
   sv_dtype dt = SV_C128;
   int n_passes = 0;
   int max_m = 0;
+  bool mfma = true;           // complex64 dense passes on the FP32 matrix cores
   std::vector<int> pass_m;    // local qubits of each pass
+  std::vector<int> pass_kind;  // PassKind of each pass
+  std::vector<int> pass_mx_k;  // PASS_MATRIX: stage width
+  std::vector<int> pass_stages;  // PASS_MATRIX: stages
+  std::vector<sv::Op> pass_op;   // PASS_SWEEP / PASS_DENSE: the op in physical qubits
   sv::PackedPlan packed;      // device image, kept for the async upload
   void* dev = nullptr;
   bool owned = false;
@@ -35,15 +42,51 @@ struct sv_batcher {
 namespace sv {
 namespace {
 
-// Pack the plan's tile passes into the program's device image.
+// Pack the plan's passes into the program's device image.
 sv_status pack_program(const sv_plan* p, sv_program* prog) {
-  if (sv_status st = pack_plan(p, true, &prog->packed)) return st;
+  if (sv_status st = pack_plan(p, &prog->packed)) return st;
   prog->n = p->n;
   prog->dt = p->dt;
-  prog->n_passes = prog->packed.n_desc;
+  prog->n_passes = (int)p->passes.size();
   prog->max_m = prog->packed.max_m;
+  prog->mfma = p->opts.fp32_mfma != 0;
   prog->pass_m.clear();
-  for (const Pass& ps : p->passes) prog->pass_m.push_back(ps.n_local);
+  prog->pass_kind.clear();
+  prog->pass_mx_k.clear();
+  prog->pass_stages.clear();
+  prog->pass_op.clear();
+  for (const Pass& ps : p->passes) {
+    prog->pass_m.push_back(ps.n_local);
+    prog->pass_kind.push_back(ps.kind);
+    prog->pass_mx_k.push_back(ps.mx_k);
+    prog->pass_stages.push_back((int)ps.stages.size());
+    prog->pass_op.push_back(ps.kind == PASS_SWEEP || ps.kind == PASS_DENSE ? ps.phys : Op());
+  }
+  return SV_OK;
+}
+
+// One pass of one state as its own launch on `stream`: matrix, dense and
+// sweep passes (the batched kernel runs tile and permutation passes).
+sv_status run_single_pass(const sv_program* p, int pass, sv_state* s, hipStream_t stream) {
+  unsigned char* pd = (unsigned char*)p->dev;
+  const int kind = p->pass_kind[pass];
+  if (kind == PASS_MATRIX) {
+    SV_LAUNCH(launch_matrix_pass(s->dt, p->pass_mx_k[pass], s->ptr, s->n, p->pass_m[pass],
+                                 (const PassDescDev*)(pd + p->packed.off_desc), p->packed.desc_index[pass],
+                                 p->pass_stages[pass], (const PassStageDev*)(pd + p->packed.off_stage),
+                                 pd + p->packed.off_pool, stream),
+              stream);
+    return SV_OK;
+  }
+  const Op& op = p->pass_op[pass];
+  if (kind == PASS_DENSE) {
+    SV_LAUNCH(launch_dense_kq(s->dt, s->ptr, s->n, op.nq, op.q, pd + p->packed.dense_off[pass], p->mfma, stream),
+              stream);
+    return SV_OK;
+  }
+  SweepArgs a;
+  if (!low_args_for(op, s->dt, &a)) sweep_args_for(op, &a);
+  SV_LAUNCH(launch_sweep(s->dt, s->ptr, s->n, a, stream), stream);
   return SV_OK;
 }
 
@@ -148,7 +191,9 @@ sv_status sv_batcher_run(sv_batcher* b, int count, sv_state* const* states, cons
   if (!b) return fail(SV_ERR_ARG, "null batcher");
   if (count <= 0) return count == 0 ? SV_OK : fail(SV_ERR_ARG, "negative count");
   if (!states || !programs || !pass_index) return fail(SV_ERR_ARG, "null array");
-  std::vector<BatchItemDev> items((size_t)count);
+  std::vector<BatchItemDev> items;
+  items.reserve((size_t)count);
+  std::vector<int> single;  // items whose pass runs as a launch of its own
   uint64_t tiles = 0;
   int max_m = 0;
   bool ladders = false;
@@ -164,8 +209,14 @@ sv_status sv_batcher_run(sv_batcher* b, int count, sv_state* const* states, cons
       return fail(SV_ERR_ARG, "item %d: pass %d out of range (%d passes)", i, pass_index[i], p->n_passes);
     for (int j = 0; j < i; ++j)
       if (states[j] == s) return fail(SV_ERR_ARG, "state %d appears twice in one batch", i);
+    const int kind = p->pass_kind[pass_index[i]];
+    if (kind != PASS_TILE && kind != PASS_PERMUTE) {
+      single.push_back(i);
+      continue;
+    }
     const int m = p->pass_m[pass_index[i]];
-    BatchItemDev& it = items[i];
+    items.emplace_back();
+    BatchItemDev& it = items.back();
     unsigned char* pd = (unsigned char*)p->dev;
     it.psi = s->ptr;
     it.passes = (const PassDescDev*)(pd + p->packed.off_desc);
@@ -174,11 +225,14 @@ sv_status sv_batcher_run(sv_batcher* b, int count, sv_state* const* states, cons
     it.mats = pd + p->packed.off_pool;
     it.tile_begin = tiles;
     it.n = s->n;
-    it.pass = pass_index[i];
+    it.pass = p->packed.desc_index[pass_index[i]];
     tiles += 1ull << (s->n - m);
     max_m = std::max(max_m, m);
     ladders = ladders || p->packed.pass_lp[pass_index[i]];
   }
+  for (int i : single)
+    if (sv_status st = run_single_pass(programs[i], pass_index[i], states[i], b->stream)) return st;
+  if (items.empty()) return SV_OK;
   const size_t bytes = items.size() * sizeof(BatchItemDev);
   const int k = b->next;
   b->next = (b->next + 1) % sv_batcher::kSlots;
@@ -205,7 +259,8 @@ sv_status sv_batcher_run(sv_batcher* b, int count, sv_state* const* states, cons
   }
   std::memcpy(b->host[k], items.data(), bytes);
   SV_HIP_TRY(hipMemcpyAsync(b->dev[k], b->host[k], bytes, hipMemcpyHostToDevice, b->stream));
-  SV_LAUNCH(launch_pass_batch(dt, (const BatchItemDev*)b->dev[k], count, tiles, max_m, ladders, b->stream), b->stream);
+  SV_LAUNCH(launch_pass_batch(dt, (const BatchItemDev*)b->dev[k], (int)items.size(), tiles, max_m, ladders, b->stream),
+            b->stream);
   SV_HIP_TRY(hipEventRecord(b->done[k], b->stream));
   b->used[k] = true;
   return SV_OK;

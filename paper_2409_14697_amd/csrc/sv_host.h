@@ -6,6 +6,8 @@
 #include <stdint.h>
 
 #include <complex>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -142,6 +144,12 @@ struct sv_plan {
   std::vector<sv::Pass> passes;
   size_t n_gates_in = 0;
   double est_cost = 0.0;          // planner's estimate, in full-state sweeps
+  // algorithmic flops per amplitude of every pass, filled by the first query
+  struct FlopsCache {
+    std::once_flag once;
+    std::vector<double> per_pass;
+  };
+  std::unique_ptr<FlopsCache> flops = std::make_unique<FlopsCache>();
 };
 
 struct sv_state {
@@ -213,6 +221,5 @@ struct PackedPlan {
   size_t off_desc = 0, off_stage = 0, off_items = 0, off_pool = 0;
   int n_desc = 0, max_m = 0;
 };
-// tile_only: fail with SV_ERR_UNSUPPORTED on sweep, dense and matrix passes.
-sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out);
+sv_status pack_plan(const sv_plan* p, PackedPlan* out);
 }  // namespace sv

@@ -451,7 +451,7 @@ sv_status build_plan(int n, sv_dtype dt, const sv_gate* g, size_t n_gates, const
   return SV_OK;
 }
 
-sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out) {
+sv_status pack_plan(const sv_plan* p, PackedPlan* out) {
   if (!p || (p->dt != SV_C64 && p->dt != SV_C128)) return fail(SV_ERR_ARG, "bad plan");
   const bool f32 = p->dt == SV_C64;
   const size_t scal = f32 ? sizeof(float) : sizeof(double);
@@ -484,9 +484,7 @@ sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out) {
   std::vector<uint8_t> pool_raw;
   for (size_t i = 0; i < p->passes.size(); ++i) {
     const Pass& ps = p->passes[i];
-    if (ps.kind == PASS_DENSE || ps.kind == PASS_SWEEP || (tile_only && ps.kind == PASS_MATRIX)) {
-      if (tile_only)
-        return fail(SV_ERR_UNSUPPORTED, "program needs a plan of in-cache tile passes only (build it with mode PASS)");
+    if (ps.kind == PASS_DENSE || ps.kind == PASS_SWEEP) {
       if (ps.kind == PASS_DENSE) out->dense_off[i] = put_cd(ps.phys.m.data(), ps.phys.m.size(), nullptr);
       continue;
     }
@@ -555,7 +553,7 @@ sv_status pack_plan(const sv_plan* p, bool tile_only, PackedPlan* out) {
 
 sv_status execute_plan(sv_state* s, const sv_plan* p) {
   PackedPlan pk;
-  if (sv_status st = pack_plan(p, false, &pk)) return st;
+  if (sv_status st = pack_plan(p, &pk)) return st;
   void* dev = nullptr;
   if (!pk.host.empty()) {
     sv_status st = upload(s, pk.host.data(), pk.host.size(), &dev);

@@ -268,12 +268,13 @@ def _done_future(fn, *args):
 
 # ----------------------------------------------------------------- device engine
 class DeviceEngine:
-    """Runs jobs on the GPU through the library: tile-pass plans (sv_fuse,
-    mode PASS), device-resident programs, the batched pass launch and the
-    batched marginal reduction.  All device work goes to one stream."""
+    """Runs jobs on the GPU through the library: plans (sv_fuse), device-resident
+    programs, the batched pass step and the batched marginal reduction.  All
+    device work goes to one stream."""
 
     def __init__(self, dtype: str = "c64", probs_qubits: int = 16, inflight: int = 3, keep_states: bool = False,
-                 lds_qubits: int = 0, max_pass_ops: int = 64, time_launches: bool = False):
+                 lds_qubits: int = 0, max_pass_ops: int = 64, time_launches: bool = False,
+                 matrix_qubits: int = 24):
         import torch
         from . import binding as B
         if dtype not in ELEM_BYTES:
@@ -292,6 +293,11 @@ class DeviceEngine:
         # completes in a single launch
         self.opts = {"mode": "pass", "lds_qubits": lds_qubits, "max_pass_ops": max_pass_ops}
         self.tile_qubits = lds_qubits or (13 if dtype == "c64" else 12)
+        # states of at least matrix_qubits qubits are planned in mode AUTO:
+        # fused dense ops in matrix passes where the cost model prefers them
+        # (each such pass is a launch of its own within the batched step; at
+        # these sizes one state fills the device by itself)
+        self.matrix_qubits = matrix_qubits
         self.stream = torch.cuda.current_stream()
         self.batcher = B.Batcher(self.stream)
         self.launch_events: collections.deque = collections.deque()
@@ -301,9 +307,26 @@ class DeviceEngine:
     # worker thread: host planning only
     def prepare(self, job: Job) -> Job:
         B = self.B
-        opts = self.opts if job.n > self.tile_qubits else dict(self.opts, max_pass_ops=0)
+        if job.n <= self.tile_qubits:
+            opts = dict(self.opts, max_pass_ops=0)
+        elif self.matrix_qubits and job.n >= self.matrix_qubits:
+            opts = dict(self.opts, mode="auto")
+        else:
+            opts = self.opts
         plan = B.Plan.from_array(job.n, self.dtype, job.gates, job.n_gates, opts)
-        job.handle = {"plan": plan, "flops": plan.pass_flops() if self.time_launches else None}
+        flops = None
+        if self.time_launches:
+            flops = plan.pass_flops()
+            if opts["mode"] != "pass":
+                # count the gates' flops (one-qubit runs merged, as tile passes
+                # apply them) spread over the passes, not the products of the
+                # fused blocks, so that plan forms compare on one basis
+                ref = B.Plan.from_array(job.n, self.dtype, job.gates, job.n_gates,
+                                        {"mode": "sweep", "max_fuse_qubits": 1})
+                total = sum(ref.pass_flops())
+                ref.close()
+                flops = [total / len(flops)] * len(flops)
+        job.handle = {"plan": plan, "flops": flops}
         job.n_passes = plan.info()[1]
         job.footprint = (1 << job.n) * self.elem_bytes + _round_up(plan.program_bytes(), 512) \
             + (8 << min(job.n, self.probs_qubits))

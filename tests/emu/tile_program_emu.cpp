@@ -173,7 +173,7 @@ int main() {
   sv_plan p;
   if (build_plan(n, dt, gates.data(), gates.size(), o, &p) != SV_OK) die(g_err.c_str());
   PackedPlan pk;
-  if (pack_plan(&p, false, &pk) != SV_OK) die(g_err.c_str());
+  if (pack_plan(&p, &pk) != SV_OK) die(g_err.c_str());
   Prog pr{&pk.host, &pk, dt == SV_C64, 0, 0, 0};
   const size_t esz = dt == SV_C64 ? 8 : 16;
   pr.pool_entries = pk.n_desc ? (pk.host.size() - pk.off_pool) / esz : 0;

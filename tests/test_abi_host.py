@@ -275,3 +275,31 @@ def test_planning_time_is_bounded():
         dt = time.perf_counter() - t0
         assert plan.info()[0] > 0
         assert dt < 2.0, (mode, dt)
+
+
+def test_pass_flops_count_each_gate_class():
+    """Flops per amplitude: 8 * 2^k for a dense k-qubit op, 6 for a diagonal
+    op, 0 for a permutation; the one-call array form equals the per-pass
+    query, and a plan of one-qubit-merged sweeps counts what the tile-pass
+    plan of the same circuit counts."""
+    rng = np.random.default_rng(3)
+    gates = [Gate("H", (0,)), Gate("RZ", (1,), 0.3), Gate("CNOT", (0, 2)), Gate("CZ", (1, 3)),
+             Gate("RX", (2,), 0.7), Gate("MATRIX", (0, 1, 3), matrix=haar_unitary(8, rng)), Gate("SWAP", (1, 2))]
+    plan = B.Plan(6, "c128", gates, {"mode": "sweep", "max_fuse_qubits": 0})
+    flops = plan.pass_flops()
+    assert flops == [16.0, 6.0, 0.0, 6.0, 16.0, 64.0, 0.0]
+    lib = B.load_library()
+    one = ctypes.c_double()
+    for i, f in enumerate(flops):
+        B.check(lib.sv_plan_pass_flops(plan._h, i, ctypes.byref(one)))
+        assert one.value == f
+    short = (ctypes.c_double * 3)()
+    with pytest.raises(B.SvError):
+        B.check(lib.sv_plan_flops(plan._h, short, 3))
+    plan.close()
+    lay = layered_circuit(16, n_layer_pairs=6, seed=2)
+    tile = B.Plan(16, "c64", lay, {"mode": "pass"})
+    light = B.Plan(16, "c64", lay, {"mode": "sweep", "max_fuse_qubits": 1})
+    assert sum(tile.pass_flops()) == sum(light.pass_flops()) > 0
+    tile.close()
+    light.close()

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from svgen import layered_circuit, qft_circuit, serving_requests
+from svgen import brickwork_circuit, layered_circuit, qft_circuit, serving_requests
 from tests.gpu_util import TOL, max_err, to_host
 
 pytestmark = pytest.mark.gpu
@@ -68,6 +68,45 @@ def test_batched_pass_launch_matches_oracle_and_single_plans(sv, dtype, family):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batched_steps_with_matrix_dense_and_sweep_passes(sv, dtype):
+    """Programs of every pass kind in one batch: each step runs the tile and
+    permutation passes of all states in one launch and every matrix, dense or
+    sweep pass as a launch of its own.  Each state matches the oracle and,
+    bitwise, the same plan applied alone."""
+    import torch
+    cases = [(9, "sweep", brickwork_circuit(9, 4, seed=1)),
+             (14, "matrix", brickwork_circuit(14, 10, seed=2)),
+             (16, "sweep", layered_circuit(16, n_layer_pairs=2, seed=3)),
+             (17, "pass", layered_circuit(17, n_layer_pairs=4, seed=4)),
+             (18, "matrix", brickwork_circuit(18, 10, seed=5)),
+             (20, "auto", brickwork_circuit(20, 8, seed=6))]
+    plans = [sv.Plan(n, dtype, g, {"mode": mode}) for n, mode, g in cases]
+    kinds = {k for p in plans for k, _, _ in p.passes()}
+    assert {0, 1, 2, 4} <= kinds, kinds  # sweep, tile, dense and matrix passes
+    progs = [sv.Program(p) for p in plans]
+    states = [sv.StateVector(n, dtype) for n, _, _ in cases]
+    b = sv.Batcher()
+    step = 0
+    while True:
+        live = [i for i in range(len(cases)) if step < progs[i].n_passes]
+        if not live:
+            break
+        b.run([states[i] for i in live], [progs[i] for i in live], [step] * len(live))
+        step += 1
+    torch.cuda.synchronize()
+    for i, (n, mode, g) in enumerate(cases):
+        out = to_host(states[i].tensor)
+        assert max_err(out, oracle.run(g, n=n)) <= TOL[dtype], (n, mode)
+        single = sv.StateVector(n, dtype)
+        single.apply_plan(plans[i])
+        single.sync()
+        assert np.array_equal(to_host(single.tensor), out), (n, mode)
+        single.close()
+    for x in states + progs + plans + [b]:
+        x.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_batcher_rejects_bad_batches(sv, dtype):
     from paper_2409_14697_amd import binding as B
     other = "c64" if dtype == "c128" else "c128"
@@ -90,19 +129,15 @@ def test_batcher_rejects_bad_batches(sv, dtype):
     import torch
     torch.cuda.synchronize()
     assert np.array_equal(to_host(s8.tensor), before)
-    # a plan with a dense sweep pass cannot become a program
-    with pytest.raises(B.SvError) as e:
-        sv.Program(sv.Plan(8, dtype, layered_circuit(8, n_layer_pairs=2, seed=1), {"mode": "sweep"}))
-    assert e.value.status == B.SV_ERR_UNSUPPORTED
     for x in (s8, s9, s8o, pa, pb, b):
         x.close()
 
 
-def _serve(sv, dtype, requests, rate, budget=None, keep_states=True, max_active=64):
+def _serve(sv, dtype, requests, rate, budget=None, keep_states=True, max_active=64, matrix_qubits=24):
     from paper_2409_14697_amd import binding as B
     from paper_2409_14697_amd.serve import DeviceEngine, Server, free_budget, make_jobs
     jobs = make_jobs(requests, rate, B.make_gates)
-    eng = DeviceEngine(dtype, keep_states=keep_states, max_pass_ops=24)
+    eng = DeviceEngine(dtype, keep_states=keep_states, max_pass_ops=24, matrix_qubits=matrix_qubits)
     srv = Server(eng, budget or free_budget(0.5), max_active=max_active, plan_workers=4)
     res = srv.run(jobs)
     eng.close()
@@ -124,6 +159,21 @@ def test_serving_loop_results_match_oracle(sv, dtype, rate):
         assert max_err(j.probs, low_probs_ref(ref, r.n)) <= PROB_TOL[dtype], (r.rid, r.n)
         if r.n <= tile:  # the whole circuit in one LDS-resident pass: one launch
             assert j.n_passes == 1, (r.rid, r.n, j.n_passes)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_serving_loop_with_auto_plans(sv, dtype):
+    """Requests of at least 15 qubits planned in mode AUTO (matrix, dense and
+    sweep passes next to tile passes) served in one loop with smaller ones."""
+    reqs = serving_requests(16, seed=12, n_range=(10, 19), depth_range=(4, 16))
+    res, jobs = _serve(sv, dtype, reqs, None, matrix_qubits=15)
+    s = res.summary()
+    assert s["completed"] == len(reqs) and s["errors"] == 0 and s["rejected"] == 0
+    assert any(r.n >= 15 for r in reqs)
+    for r, j in zip(reqs, jobs):
+        ref = oracle.run(r.circuit(), n=r.n)
+        assert max_err(to_host(j.handle["tensor"]), ref) <= TOL[dtype], (r.rid, r.n)
+        assert max_err(j.probs, low_probs_ref(ref, r.n)) <= PROB_TOL[dtype], (r.rid, r.n)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
