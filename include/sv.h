@@ -293,7 +293,8 @@ typedef struct sv_program sv_program;  /* the passes of one plan, in device memo
 typedef struct sv_batcher sv_batcher;  /* launches one pass of many states at once        */
 
 /* Device bytes a program of plan p occupies (for a caller-owned buffer).
- * Errors: SV_ERR_ARG, SV_ERR_UNSUPPORTED (see sv_program_create). */
+ * Errors: SV_ERR_ARG, SV_ERR_UNSUPPORTED (a pass the packer cannot encode:
+ * an internal planner failure, not expected for plans sv_fuse returns). */
 sv_status sv_program_bytes(const sv_plan *p, size_t *bytes);
 
 /* Upload the program of plan p (any mode: tile, permutation, matrix, dense
@@ -305,7 +306,8 @@ sv_status sv_program_bytes(const sv_plan *p, size_t *bytes);
  *             sv_program_bytes(p) bytes, 256-byte aligned, kept alive while
  *             work that uses the program may run.
  * The program keeps its own host copy; the plan may be destroyed at once.
- * Errors: SV_ERR_ARG, SV_ERR_UNSUPPORTED, SV_ERR_NOMEM, SV_ERR_DEVICE. */
+ * Errors: SV_ERR_ARG, SV_ERR_UNSUPPORTED (as sv_program_bytes), SV_ERR_NOMEM,
+ * SV_ERR_DEVICE. */
 sv_status sv_program_create(const sv_plan *p, void *dev_buf, size_t buf_bytes, void *hip_stream,
                             sv_program **out);
 

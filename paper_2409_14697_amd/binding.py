@@ -196,7 +196,7 @@ class Plan:
         return self._h
 
     def program_bytes(self) -> int:
-        """Device bytes of this plan's tile-pass program (sv_program_bytes)."""
+        """Device bytes of this plan's program (sv_program_bytes)."""
         nb = c_size_t()
         check(load_library().sv_program_bytes(self._h, byref(nb)))
         return nb.value
@@ -363,7 +363,7 @@ class StateVector:
 
 # ------------------------------------------------------------------ serving
 class Program:
-    """A plan's tile-pass program resident in device memory (sv_program_*).
+    """A plan's program (all its passes) resident in device memory (sv_program_*).
 
     With buffer=None the program's bytes live in a uint8 torch tensor of the
     caching allocator (no hipMalloc once the allocator is warm); the tensor is
@@ -406,7 +406,9 @@ class Program:
 
 
 class Batcher:
-    """One kernel launch runs one tile pass of many states (sv_batcher_*)."""
+    """One step runs one pass of many states (sv_batcher_*): their tile and
+    permutation passes in one kernel launch, matrix, dense and sweep passes as
+    launches of their own."""
 
     def __init__(self, stream=None):
         import torch
