@@ -331,7 +331,8 @@ sv_status sv_batcher_create(void *hip_stream, sv_batcher **out);
  * on the states (e.g. by creating the states on the same stream).  A state's
  * result depends only on its own program -- bitwise the same in any batch.
  * Errors: SV_ERR_ARG (count, null entries, mismatched n/dtype, pass index out
- * of range), SV_ERR_NOMEM, SV_ERR_DEVICE. */
+ * of range; checked before anything is enqueued), SV_ERR_NOMEM, SV_ERR_DEVICE
+ * (the passes of some items may already be enqueued). */
 sv_status sv_batcher_run(sv_batcher *b, int count, sv_state *const *states, const sv_program *const *programs,
                          const int32_t *pass_index);
 

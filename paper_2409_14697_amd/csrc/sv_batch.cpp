@@ -85,7 +85,8 @@ sv_status run_single_pass(const sv_program* p, int pass, sv_state* s, hipStream_
     return SV_OK;
   }
   SweepArgs a;
-  if (!low_args_for(op, s->dt, &a)) sweep_args_for(op, &a);
+  if (!low_args_for(op, s->dt, &a) && !sweep_args_for(op, &a))
+    return fail(SV_ERR_UNSUPPORTED, "internal: sweep pass of a %d-qubit op", op.nq);
   SV_LAUNCH(launch_sweep(s->dt, s->ptr, s->n, a, stream), stream);
   return SV_OK;
 }
