@@ -121,7 +121,7 @@ sv_status sv_program_create(const sv_plan* p, void* dev_buf, size_t buf_bytes, v
     if (dev_buf) {
       if (buf_bytes < bytes) st = fail(SV_ERR_ARG, "program buffer of %zu bytes, %zu needed", buf_bytes, bytes);
       prog->dev = dev_buf;
-    } else if (hipMalloc(&prog->dev, bytes) != hipSuccess) {
+    } else if (hipMalloc(&prog->dev, std::max<size_t>(bytes, 256)) != hipSuccess) {  // sweep-only programs hold 0 bytes
       prog->dev = nullptr;
       st = fail(SV_ERR_NOMEM, "cannot allocate %zu bytes for the program", bytes);
     } else {

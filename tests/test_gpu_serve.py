@@ -177,6 +177,23 @@ def test_serving_loop_with_auto_plans(sv, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_serving_tiny_requests(sv, dtype):
+    """Requests of 1..5 qubits (too small for a tile: their programs hold
+    sweep and dense passes only; 1-2 qubits: no program bytes at all) served
+    with 6..9-qubit ones, against the oracle."""
+    from svgen.circuits import Request
+    reqs = [Request(i, n, 3 + i % 4, 40 + i, 0.0) for i, n in enumerate((1, 2, 3, 4, 5, 1, 3, 5))]
+    reqs += [Request(10 + i, n, 4, 60 + i, 0.0) for i, n in enumerate((6, 7, 8, 9))]
+    res, jobs = _serve(sv, dtype, reqs, None)
+    s = res.summary()
+    assert s["completed"] == len(reqs) and s["errors"] == 0 and s["rejected"] == 0
+    for r, j in zip(reqs, jobs):
+        ref = oracle.run(r.circuit(), n=r.n)
+        assert max_err(to_host(j.handle["tensor"]), ref) <= TOL[dtype], (r.rid, r.n)
+        assert max_err(j.probs, low_probs_ref(ref, r.n)) <= PROB_TOL[dtype], (r.rid, r.n)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_serving_alone_equals_in_mix_bitwise(sv, dtype):
     reqs = serving_requests(16, seed=12, n_range=(6, 17), depth_range=(2, 10))
     _, mixed = _serve(sv, dtype, reqs, None)
