@@ -52,18 +52,74 @@ void apply_left(std::vector<cd>& m, int k, const int* uq, const Op& g) {
   }
   int gmask = 0;
   for (int j = 0; j < g.nq; ++j) gmask |= 1 << pos[j];
-  std::vector<cd> in(dg), out(dg);
-  std::vector<int> idx(dg);
-  for (int c = 0; c < d; ++c) {
+  cd in[1 << SV_MAX_GATE_QUBITS], out[1 << SV_MAX_GATE_QUBITS];
+  int idx[1 << SV_MAX_GATE_QUBITS];
+  if (g.nq == 1) {
+    // the common case: two rows mix.  The products and sums are those of the
+    // general loop below, written on real parts (same roundings), so that the
+    // column loop has no branches
+    const double g0r = g.m[0].real(), g0i = g.m[0].imag(), g1r = g.m[1].real(), g1i = g.m[1].imag();
+    const double g2r = g.m[2].real(), g2i = g.m[2].imag(), g3r = g.m[3].real(), g3i = g.m[3].imag();
+    const int b0 = 1 << pos[0];
+    for (int base = 0; base < d; ++base) {
+      if (base & b0) continue;
+      double* r0 = reinterpret_cast<double*>(m.data() + (size_t)base * d);
+      double* r1 = reinterpret_cast<double*>(m.data() + (size_t)(base | b0) * d);
+      for (int c = 0; c < d; ++c) {
+        const double ar = r0[2 * c], ai = r0[2 * c + 1], br = r1[2 * c], bi = r1[2 * c + 1];
+        r0[2 * c] = (0.0 + (g0r * ar - g0i * ai)) + (g1r * br - g1i * bi);
+        r0[2 * c + 1] = (0.0 + (g0r * ai + g0i * ar)) + (g1r * bi + g1i * br);
+        r1[2 * c] = (0.0 + (g2r * ar - g2i * ai)) + (g3r * br - g3i * bi);
+        r1[2 * c + 1] = (0.0 + (g2r * ai + g2i * ar)) + (g3r * bi + g3i * br);
+      }
+    }
+    return;
+  }
+  if (g.nq == 2) {  // four rows mix; the same sums as the general loop
+    double gr[16], gi[16];
+    for (int e = 0; e < 16; ++e) {
+      gr[e] = g.m[e].real();
+      gi[e] = g.m[e].imag();
+    }
+    const int bh = 1 << pos[0], bl = 1 << pos[1];  // r = 2 (bit of q[0]) + (bit of q[1])
     for (int base = 0; base < d; ++base) {
       if (base & gmask) continue;
-      for (int r = 0; r < dg; ++r) {
-        int i = base;
-        for (int j = 0; j < g.nq; ++j)
-          if ((r >> (g.nq - 1 - j)) & 1) i |= 1 << pos[j];
-        idx[r] = i;
-        in[r] = m[(size_t)i * d + c];
+      double* row[4] = {reinterpret_cast<double*>(m.data() + (size_t)base * d),
+                        reinterpret_cast<double*>(m.data() + (size_t)(base | bl) * d),
+                        reinterpret_cast<double*>(m.data() + (size_t)(base | bh) * d),
+                        reinterpret_cast<double*>(m.data() + (size_t)(base | bh | bl) * d)};
+      for (int c = 0; c < d; ++c) {
+        double xr[4], xi[4];
+        for (int s = 0; s < 4; ++s) {
+          xr[s] = row[s][2 * c];
+          xi[s] = row[s][2 * c + 1];
+        }
+        for (int r = 0; r < 4; ++r) {
+          double yr = 0.0, yi = 0.0;
+          for (int s = 0; s < 4; ++s) {
+            const double ur = gr[4 * r + s], ui = gi[4 * r + s];
+            yr = yr + (ur * xr[s] - ui * xi[s]);
+            yi = yi + (ur * xi[s] + ui * xr[s]);
+          }
+          row[r][2 * c] = yr;
+          row[r][2 * c + 1] = yi;
+        }
       }
+    }
+    return;
+  }
+  // rows of one group (base: the rows with g's bits clear) mix; the group's
+  // row indices are found once and every column is updated in turn
+  for (int base = 0; base < d; ++base) {
+    if (base & gmask) continue;
+    for (int r = 0; r < dg; ++r) {
+      int i = base;
+      for (int j = 0; j < g.nq; ++j)
+        if ((r >> (g.nq - 1 - j)) & 1) i |= 1 << pos[j];
+      idx[r] = i;
+    }
+    for (int c = 0; c < d; ++c) {
+      for (int r = 0; r < dg; ++r) in[r] = m[(size_t)idx[r] * d + c];
       for (int r = 0; r < dg; ++r) {
         cd y = 0.0;
         for (int s = 0; s < dg; ++s) y += g.m[(size_t)r * dg + s] * in[s];
@@ -122,6 +178,16 @@ std::vector<Op> fuse_ops(std::vector<Op> in, int n, sv_dtype dt, int kmax, bool 
     if (width >= 1 && cand >= 0 && union_size(out[cand], op) <= width &&
         !(op.kind == SV_G_SWAP && width < 2)) {
       Op& prev = out[cand];
+      if (prev.nq >= 3 && union_size(prev, op) == prev.nq) {
+        // no new qubit: a dense op keeps its width and cost, so the merge
+        // always pays; the product is formed in place (as `merged` would)
+        prev.kind = SV_G_MATRIX;
+        prev.theta = 0.0;
+        apply_left(prev.m, prev.nq, prev.q, op);
+        prev.n_gates += op.n_gates;
+        for (int j = 0; j < op.nq; ++j) last[op.q[j]] = cand;
+        continue;
+      }
       Op m = merged(prev, op);
       if (sweep_cost(m, dt, mfma) <= sweep_cost(prev, dt, mfma) + sweep_cost(op, dt, mfma) + 1e-12) {
         prev = std::move(m);
