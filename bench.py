@@ -102,6 +102,30 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def circuit_source_hash() -> str:
+    """Hash of the sources that decide the circuit benchmark's kernels and plans."""
+    h = hashlib.sha256()
+    for f in ("sv_pass.hip", "sv_dense.hip", "sv_sweep.hip", "sv_tile_kernels.h", "sv_device.h", "sv_kernels.h",
+              "sv_plan.cpp", "sv_passplan.cpp", "sv_gates.cpp"):
+        with open(os.path.join(ROOT, "paper_2409_14697_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_circuit_traffic():
+    """Per-kernel HBM bytes per launch of the circuit benchmark (committed
+    rocprofv3 counter summary); None when absent or taken on other sources."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "circuit_traffic_n32_c64.json")) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    if d.get("source_hash") != circuit_source_hash():
+        return None
+    return {k: {"launches": v["launches"], "bytes_per_launch": v["bytes_per_launch"],
+                "of_read_plus_write": v["of_read_plus_write"]} for k, v in d["kernels"].items()}
+
+
 def load_traffic(kernel_key: str):
     """HBM bytes per launch of `kernel_key` from the committed rocprofv3 counter
     summary (FETCH_SIZE / WRITE_SIZE scaled by a copy kernel of known size);
@@ -358,6 +382,10 @@ def circuit_bench(args, n: int = 32):
     out["seconds"] = round(total, 5)
     out["config"] = {"workload": f"N={n} complex64, brickwork depth 40 (seed 3) + QFT", "mode": args.mode,
                      "steps": steps, "warmup": warmup}
+    # HBM bytes per launch of each kernel from the committed counter runs
+    # (a pass reads and writes the state once: of_read_plus_write = 1)
+    if n == 32 and args.mode == "auto":
+        out["kernel_traffic"] = load_circuit_traffic()
     return out
 
 

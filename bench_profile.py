@@ -5,8 +5,9 @@ Inputs are the CSV directories of three profiled runs of bench.py:
   --fetch : rocprofv3 --pmc FETCH_SIZE -f csv -d <dir> -o bench -- python bench.py --steps 1 --warmup 0
             --no-cpu-baseline --copy-ceiling --extras none
   --write : the same with --pmc WRITE_SIZE
-Subcommands `trace` (kernel-trace summary of any profiled run) and `mfma`
-(matrix-core utilisation of the dense kernels from a counter run) write
+Subcommands `trace` (kernel-trace summary of any profiled run), `mfma`
+(matrix-core utilisation of the dense kernels from a counter run) and
+`circuit` (HBM traffic per launch of the circuit benchmark's kernels) write
 their own summaries.
 Outputs:
   profiles/gate_sweep_n30.md              per-kernel durations (kernel trace) and
@@ -155,7 +156,63 @@ def mfma_summary(argv):
     print(f"wrote {args.out}")
 
 
+def circuit_traffic(argv):
+    """HBM traffic per launch of the circuit benchmark's kernels (N=32
+    complex64): bench_profile.py circuit --fetch D --write D, the counter runs
+    of `bench.py --workload circuit --steps 1 --warmup 0`.  FETCH_SIZE and
+    WRITE_SIZE are scaled by the copy-kernel factors recorded in
+    profiles/gate_sweep_counters_n30.json (same counters, same device);
+    writes profiles/circuit_traffic_n32_c64.{md,json}."""
+    import bench
+    ap = argparse.ArgumentParser(prog="bench_profile.py circuit")
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    args = ap.parse_args(argv)
+    with open(os.path.join(ROOT, "profiles", "gate_sweep_counters_n30.json")) as f:
+        cal = json.load(f)["copy_calibration"]
+    f_fetch, f_write = cal["fetch_factor"], cal["write_factor"]
+    fetch, write = counters(args.fetch, "FETCH_SIZE"), counters(args.write, "WRITE_SIZE")
+    two_s = 2.0 * float(1 << args.n) * 8.0  # read + write of the complex64 state
+    kernels = {}
+    for sym, vals in fetch.items():
+        if sym not in write or not sym.startswith("k_"):
+            continue
+        fk, wk = statistics.mean(vals), statistics.mean(write[sym])
+        b = (fk * f_fetch + wk * f_write) * 1024.0
+        kernels[sym] = {"launches": len(vals), "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+                        "bytes_per_launch": round(b), "of_read_plus_write": round(b / two_s, 4)}
+    with open(os.path.join(args.out, "circuit_traffic_n32_c64.json"), "w") as f:
+        json.dump({"source_hash": bench.circuit_source_hash(), "n_qubits": args.n, "dtype": "c64",
+                   "copy_calibration": {"fetch_factor": f_fetch, "write_factor": f_write},
+                   "read_plus_write_bytes": two_s, "kernels": kernels}, f, indent=1, sort_keys=True)
+    lines = ["# Circuit benchmark, N=32 complex64: HBM traffic per kernel launch (rocprofv3 counters)", "",
+             "Commands (from the repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "```",
+             "rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/prof_cfetch -o bench -- python bench.py --workload circuit "
+             "--steps 1 --warmup 0",
+             "rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/prof_cwrite -o bench -- python bench.py --workload circuit "
+             "--steps 1 --warmup 0",
+             "python bench_profile.py circuit --fetch gpurun_out/prof_cfetch --write gpurun_out/prof_cwrite",
+             "```", "",
+             f"Bytes = FETCH_SIZE x {f_fetch:.3f} + WRITE_SIZE x {f_write:.3f} (KiB per dispatch; the factors that turn "
+             "the copy kernel's counters into its known bytes, from the gate-sweep counter runs). A pass reads and "
+             f"writes the 32 GiB state once: {two_s:.4g} bytes. Kernel source hash: `{bench.circuit_source_hash()}`.", "",
+             "| kernel | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes / launch | of read + write |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for sym, k in sorted(kernels.items(), key=lambda kv: -kv[1]["bytes_per_launch"] * kv[1]["launches"]):
+        lines.append(f"| `{sym}` | {k['launches']} | {k['fetch_kib']:.0f} | {k['write_kib']:.0f} | "
+                     f"{k['bytes_per_launch']:.4g} | {k['of_read_plus_write']:.4f} |")
+    with open(os.path.join(args.out, "circuit_traffic_n32_c64.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {args.out}/circuit_traffic_n32_c64.md and .json")
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "circuit":
+        circuit_traffic(sys.argv[2:])
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "trace":
         trace_summary(sys.argv[2:])
         return
