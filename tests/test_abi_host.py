@@ -303,3 +303,6 @@ def test_pass_flops_count_each_gate_class():
     assert sum(tile.pass_flops()) == sum(light.pass_flops()) > 0
     tile.close()
     light.close()
+    empty = B.Plan(4, "c64", [], {"mode": "auto"})
+    assert empty.info() == (0, 0) and empty.pass_flops() == [] and empty.program_bytes() == 0
+    empty.close()
